@@ -1,0 +1,112 @@
+"""Brute-force dense operators and the full Lindblad master equation -- oracle.
+
+Test infrastructure only (see the package header).  Every operator is built
+as an explicit N x N matrix from single-mode d x d matrices with numpy.kron in
+the order transmon (x) resonator (x) filter, independently of the slicing
+code in ``lowrank``.  The master equation is the one of supplement S1.A
+(eq. "master_equation", dissipator eq. "lindblad_dissipator"):
+
+    d rho/dt = -i [H, rho] + sum_k ( L_k rho L_k^ - 1/2 {L_k^ L_k, rho} ).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import pulses
+
+
+def annihilation(d):
+    """<n-1| b |n> = sqrt(n)."""
+    return np.diag(np.sqrt(np.arange(1, d, dtype=np.float64)), 1).astype(np.complex128)
+
+
+def _embed(model, op, mode):
+    Iq = np.eye(model.d_q)
+    Ir = np.eye(model.d_r)
+    If = np.eye(model.d_f)
+    mats = [Iq, Ir, If]
+    mats[mode] = op
+    return np.kron(mats[0], np.kron(mats[1], mats[2]))
+
+
+def operators(model):
+    """Dense b, a, f (annihilation) on the full space."""
+    b = _embed(model, annihilation(model.d_q), 0)
+    a = _embed(model, annihilation(model.d_r), 1)
+    f = _embed(model, annihilation(model.d_f), 2)
+    return b, a, f
+
+
+def hamiltonian(model, d_t):
+    """Dense H(t) for the drive coefficient d_t."""
+    b, a, f = operators(model)
+    nq = b.conj().T @ b
+    Nn = nq.shape[0]
+    I = np.eye(Nn)
+    H = (model.w_q * nq + 0.5 * model.alpha * nq @ (nq - I)
+         + model.w_r * a.conj().T @ a + model.w_f * f.conj().T @ f)
+    H = H + model.g * (b + b.conj().T) @ (a + a.conj().T)
+    H = H + model.G * (a + a.conj().T) @ (f + f.conj().T)
+    H = H + d_t * (f + f.conj().T)
+    return H
+
+
+def jump_operators(model):
+    b, _, f = operators(model)
+    return [np.sqrt(model.kappa_f) * f, np.sqrt(model.gamma_1) * b]
+
+
+def lindbladian(model, pulse, t, rho):
+    """Right-hand side of the master equation on a dense rho."""
+    d_t = pulses.drive(pulse, t) if pulse is not None else 0.0
+    H = hamiltonian(model, d_t)
+    out = -1j * (H @ rho - rho @ H)
+    for L in jump_operators(model):
+        LdL = L.conj().T @ L
+        out = out + L @ rho @ L.conj().T - 0.5 * (LdL @ rho + rho @ LdL)
+    return out
+
+
+def lowrank_rhs_pinv(model, pulse, t, B):
+    """Literal low-rank right-hand side with dense matrices and numpy's pinv:
+    -i H B + 1/2 sum_k [ L_k B (pinv(B) L_k B)^ - L_k^ L_k B ]."""
+    d_t = pulses.drive(pulse, t) if pulse is not None else 0.0
+    H = hamiltonian(model, d_t)
+    Bp = np.linalg.pinv(B)
+    out = -1j * (H @ B)
+    for L in jump_operators(model):
+        LB = L @ B
+        out = out + 0.5 * (LB @ (Bp @ LB).conj().T - L.conj().T @ L @ B)
+    return out
+
+
+def observables(model, rho):
+    """Same record as lowrank.observables, computed from a dense rho."""
+    b, a, f = operators(model)
+    ea = np.trace(a @ rho)
+    ef = np.trace(f @ rho)
+    tr = np.trace(rho).real
+    tr2 = np.trace(rho @ rho).real
+    Pq = []
+    for k in range(model.d_q):
+        Pk = np.zeros((model.d_q, model.d_q))
+        Pk[k, k] = 1.0
+        Pq.append(np.trace(_embed(model, Pk, 0) @ rho).real)
+    return np.concatenate([[ea.real, ea.imag, ef.real, ef.imag, tr, tr2], Pq])
+
+
+def integrate(model, pulse, t0, dt, nsteps, rho0, obs_stride=0):
+    """Classic RK4 on the dense rho with the same stage times as the low-rank path."""
+    rho = np.array(rho0, dtype=np.complex128, copy=True)
+    fun = lambda t, X: lindbladian(model, pulse, t, X)  # noqa: E731
+    rec = [observables(model, rho)] if obs_stride > 0 else []
+    for n in range(nsteps):
+        t = t0 + n * dt
+        k1 = fun(t, rho)
+        k2 = fun(t + 0.5 * dt, rho + (0.5 * dt) * k1)
+        k3 = fun(t + 0.5 * dt, rho + (0.5 * dt) * k2)
+        k4 = fun(t + dt, rho + dt * k3)
+        rho = rho + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+        if obs_stride > 0 and (n + 1) % obs_stride == 0:
+            rec.append(observables(model, rho))
+    return rho, (np.array(rec) if rec else np.zeros((0, 6 + model.d_q)))

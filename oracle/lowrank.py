@@ -1,0 +1,188 @@
+"""Low-rank Lindblad equation of motion, classic RK4 and observables -- oracle.
+
+Test infrastructure only (see the package header).  Plain FP64 numpy.
+
+Notation (supplement S1.A): the density matrix is rho = m m^ (eq.
+"lowrank_diagonal") with m = B an N x M matrix whose columns are
+sqrt(p_j) psi_j.  Its equation of motion (eq. "nosse") is
+
+    dB/dt = -i H B + O[B],
+    O[B]  = 1/2 sum_k [ L_k B (B^+ L_k B)^  -  L_k^ L_k B ],
+    B^+   = (B^ B)^-1 B^        (Moore-Penrose inverse of the tall factor)
+
+where the factor 1/2 multiplies both terms (the reading for which
+O B^ + B O^ reproduces the dissipator of eq. "lindblad_dissipator").
+
+The operators act mode-wise on the state tensor T[i_q, i_r, i_f, j] (B
+reshaped, basis index n = (i_q d_r + i_r) d_f + i_f).  The anti-Hermitian
+part -1/2 sum_k L_k^ L_k is diagonal for L_1 = sqrt(kappa_f) f and
+L_2 = sqrt(gamma_1) b and is folded into H_eff = H - i/2 (kappa_f n_f + gamma_1 n_q),
+so that  dB/dt = -i H_eff B + 1/2 sum_k Y_k X_k^  with
+
+    Y_k = L_k B,   G = B^ B,   C_k = B^ Y_k,   X_k = G^-1 C_k  (= B^+ L_k B).
+
+G^-1 C_k is evaluated through the Cholesky factor G = R R^ and two triangular
+solves; a non-positive pivot raises GramNotPD.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+from . import pulses
+
+
+class GramNotPD(ArithmeticError):
+    """B^ B is not Hermitian positive definite (Cholesky pivot <= 0)."""
+
+
+# ---------------------------------------------------------------- operators
+
+def _as_tensor(model, B):
+    return B.reshape(model.d_q, model.d_r, model.d_f, B.shape[1])
+
+
+def lower(T, axis):
+    """Annihilation operator along `axis`: (b T)[n] = sqrt(n+1) T[n+1]."""
+    d = T.shape[axis]
+    out = np.zeros_like(T)
+    shape = [1] * T.ndim
+    shape[axis] = d - 1
+    coef = np.sqrt(np.arange(1, d, dtype=np.float64)).reshape(shape)
+    dst = [slice(None)] * T.ndim
+    src = [slice(None)] * T.ndim
+    dst[axis] = slice(0, d - 1)
+    src[axis] = slice(1, d)
+    out[tuple(dst)] = coef * T[tuple(src)]
+    return out
+
+
+def raise_(T, axis):
+    """Creation operator along `axis`: (b^ T)[n] = sqrt(n) T[n-1]."""
+    d = T.shape[axis]
+    out = np.zeros_like(T)
+    shape = [1] * T.ndim
+    shape[axis] = d - 1
+    coef = np.sqrt(np.arange(1, d, dtype=np.float64)).reshape(shape)
+    dst = [slice(None)] * T.ndim
+    src = [slice(None)] * T.ndim
+    dst[axis] = slice(1, d)
+    src[axis] = slice(0, d - 1)
+    out[tuple(dst)] = coef * T[tuple(src)]
+    return out
+
+
+def quadrature(T, axis):
+    """(b + b^) along `axis`."""
+    return lower(T, axis) + raise_(T, axis)
+
+
+def diag_heff(model):
+    """Diagonal of H_eff on the (d_q, d_r, d_f) grid (complex)."""
+    q = np.arange(model.d_q, dtype=np.float64)[:, None, None]
+    r = np.arange(model.d_r, dtype=np.float64)[None, :, None]
+    f = np.arange(model.d_f, dtype=np.float64)[None, None, :]
+    h = (model.w_q * q + 0.5 * model.alpha * q * (q - 1.0)
+         + model.w_r * r + model.w_f * f)
+    return h - 0.5j * (model.kappa_f * f + model.gamma_1 * q)
+
+
+def apply_heff(model, d_t, B):
+    """Z = H_eff(t) B, with d_t the drive coefficient d(t)."""
+    T = _as_tensor(model, B)
+    Z = diag_heff(model)[..., None] * T
+    Z = Z + model.g * quadrature(quadrature(T, 0), 1)
+    Z = Z + model.G * quadrature(quadrature(T, 1), 2)
+    Z = Z + d_t * quadrature(T, 2)
+    return Z.reshape(B.shape)
+
+
+def apply_jumps(model, B):
+    """[Y_1, Y_2] = [sqrt(kappa_f) f B, sqrt(gamma_1) b B]."""
+    T = _as_tensor(model, B)
+    Y1 = np.sqrt(model.kappa_f) * lower(T, 2)
+    Y2 = np.sqrt(model.gamma_1) * lower(T, 0)
+    return [Y1.reshape(B.shape), Y2.reshape(B.shape)]
+
+
+# ---------------------------------------------------------------- RHS
+
+def gram_solve(G, C_list):
+    """X_k = G^-1 C_k through the Cholesky factor of G (lower R, G = R R^)."""
+    try:
+        R = np.linalg.cholesky(G)
+    except np.linalg.LinAlgError as exc:
+        raise GramNotPD(str(exc)) from None
+    if not np.all(np.isfinite(R)) or np.any(np.real(np.diag(R)) <= 0.0):
+        raise GramNotPD("non-positive pivot")
+    out = []
+    for C in C_list:
+        Y = scipy.linalg.solve_triangular(R, C, lower=True)
+        out.append(scipy.linalg.solve_triangular(R.conj().T, Y, lower=False))
+    return out
+
+
+def rhs(model, pulse, t, B):
+    """dB/dt at time t (equation of motion of supplement S1.A)."""
+    d_t = pulses.drive(pulse, t) if pulse is not None else 0.0
+    Z = apply_heff(model, d_t, B)
+    Y = apply_jumps(model, B)
+    Bh = B.conj().T
+    G = Bh @ B
+    C = [Bh @ Yk for Yk in Y]
+    X = gram_solve(G, C)
+    dB = -1j * Z
+    for Yk, Xk in zip(Y, X):
+        dB = dB + 0.5 * (Yk @ Xk.conj().T)
+    return dB
+
+
+# ---------------------------------------------------------------- observables
+
+OBS_HEADER = ("re_a", "im_a", "re_f", "im_f", "tr_rho", "tr_rho2")
+
+
+def observables(model, B):
+    """[Re<a>, Im<a>, Re<f>, Im<f>, tr rho, tr rho^2, P_q(0..d_q-1)].
+
+    <O> = tr(O rho) = sum_j b_j^ O b_j (unnormalised); tr rho^2 = ||B^ B||_F^2
+    (since tr (B B^)^2 = tr (B^ B)^2); P_q(k) = tr(|k><k|_q rho).
+    """
+    T = _as_tensor(model, B)
+    a = np.sum(T.conj() * lower(T, 1))
+    f = np.sum(T.conj() * lower(T, 2))
+    tr = np.sum(np.abs(T) ** 2)
+    G = B.conj().T @ B
+    tr2 = np.sum(np.abs(G) ** 2)
+    Pq = np.sum(np.abs(T) ** 2, axis=(1, 2, 3))
+    return np.concatenate([[a.real, a.imag, f.real, f.imag, tr, tr2], Pq])
+
+
+# ---------------------------------------------------------------- RK4
+
+def rk4_step(fun, t, dt, B):
+    k1 = fun(t, B)
+    k2 = fun(t + 0.5 * dt, B + (0.5 * dt) * k1)
+    k3 = fun(t + 0.5 * dt, B + (0.5 * dt) * k2)
+    k4 = fun(t + dt, B + dt * k3)
+    return B + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+
+
+def integrate(model, pulse, t0, dt, nsteps, B0, obs_stride=0):
+    """Classic fixed-step RK4 from B(t0) = B0 over nsteps steps of dt.
+
+    Step n runs from t_n = t0 + n dt.  Observables are recorded at step 0 and
+    after every obs_stride-th step; returns (B(t0 + nsteps dt), obs) with obs
+    of shape (nsteps // obs_stride + 1, 6 + d_q) (empty if obs_stride == 0).
+    """
+    B = np.array(B0, dtype=np.complex128, copy=True)
+    fun = lambda t, X: rhs(model, pulse, t, X)  # noqa: E731
+    rec = []
+    if obs_stride > 0:
+        rec.append(observables(model, B))
+    for n in range(nsteps):
+        B = rk4_step(fun, t0 + n * dt, dt, B)
+        if obs_stride > 0 and (n + 1) % obs_stride == 0:
+            rec.append(observables(model, B))
+    obs = np.array(rec) if rec else np.zeros((0, 6 + model.d_q))
+    return B, obs
