@@ -1,0 +1,144 @@
+/*
+ * lr.h -- C ABI of the MI355X low-rank Lindblad readout integrator.
+ *
+ * What is computed (the paper's supplement S1.A, eq. "lowrank_diagonal" and
+ * eq. "nosse"): the density matrix is kept as rho = B B^ with B an N x M
+ * complex factor, and B follows
+ *
+ *     dB/dt = -i H(t) B + O[B],
+ *     O[B]  = 1/2 sum_k [ L_k B (B^+ L_k B)^  -  L_k^ L_k B ],   B^+ = (B^B)^-1 B^
+ *
+ * for the transmon-resonator-filter readout model (main text, Hamiltonian
+ * eq. "hamiltonianpurcell", master equation eq. "hamiltonian") in the form
+ *
+ *     H(t) = w_q n_q + alpha/2 n_q(n_q-1) + w_r n_r + w_f n_f
+ *            + g (b+b^)(a+a^) + G (a+a^)(f+f^) + d(t) (f+f^),
+ *     L_1 = sqrt(kappa_f) f,   L_2 = sqrt(gamma_1) b,
+ *
+ * integrated by classic fixed-step RK4.  Each right-hand side evaluation
+ * applies H_eff = H - i/2 sum_k L_k^ L_k and L_k mode-wise, forms the Gram
+ * G = B^ B and C_k = B^ L_k B, solves G X_k = C_k by Cholesky in FP64 and
+ * assembles dB/dt = -i H_eff B + 1/2 sum_k (L_k B) X_k^.
+ *
+ * Units: rad/ns and ns.  Basis index n = (i_q d_r + i_r) d_f + i_f.
+ *
+ * Memory and ownership.  B is passed as device memory, column-major N x M,
+ * interleaved complex FP64 (lr_c64): element (n, j) at d_B[n + N*j].  The
+ * caller owns every device buffer (B, dB, observation records, workspace);
+ * the library owns only host-side descriptors created by lr_init and freed
+ * by lr_destroy, and never frees caller memory.  All calls that take device
+ * pointers enqueue work on the stream given to lr_bind and return without
+ * waiting; errors found on the device (non-positive Gram pivot, non-finite
+ * state) are reported by lr_status, which synchronises the stream.
+ * Argument errors are reported synchronously by the return code and nothing
+ * is enqueued.  No call throws across the ABI.
+ */
+#ifndef LR_H
+#define LR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } lr_c64;
+
+/* Model parameters (rad/ns).  d_q >= 2 (g and e must exist), d_r, d_f >= 1. */
+typedef struct {
+  int32_t d_q, d_r, d_f;
+  int32_t reserved;
+  double  w_q, alpha, w_r, w_f;   /* Duffing transmon w_q n + alpha/2 n(n-1); bare modes */
+  double  g, G;                   /* g (b+b^)(a+a^),  G (a+a^)(f+f^)                    */
+  double  kappa_f, gamma_1;       /* L_1 = sqrt(kappa_f) f,  L_2 = sqrt(gamma_1) b      */
+} lr_model_t;
+
+/* Drive coefficient d(t) multiplying (f + f^).
+ *   LR_PULSE_FLATTOP:    d(t) = amp w(t) cos(w_d t)
+ *   LR_PULSE_PIECEWISE6: d(t) = sum_{s=1,2} A_s w_s(t) cos((w_d + Delta_s) t + phi_s),
+ *                        p = {A_1, phi_1, Delta_1, A_2, phi_2, Delta_2}
+ * w(t) = r(t) r(T-t) with r(x) = 0 (x<0), (1-cos(pi x/t_ramp))/2 (0<=x<t_ramp), 1 else;
+ * w_1 = r(t)(1-c(t)), w_2 = r(T-t) c(t), c a cosine cross-fade of length t_ramp
+ * centred at T/2.  Every amplitude must satisfy |A| < 2 pi 0.4 rad/ns (the
+ * drive bound of supplement S3.B-C), else LR_ERR_PULSE. */
+enum { LR_PULSE_FLATTOP = 0, LR_PULSE_PIECEWISE6 = 1 };
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  double  w_d, amp, t_ramp, T;
+  double  p[6];
+} lr_pulse_t;
+
+/* Arithmetic of the operator applications and Gram products.  The Cholesky
+ * solve and the RK4 accumulation of B are FP64 in every mode. */
+enum { LR_FP64 = 0, LR_FP32 = 1, LR_BF16X3 = 2 };
+
+enum {
+  LR_OK = 0,
+  LR_ERR_ARG = -1,          /* invalid argument (dims, M, sizes, null pointers)   */
+  LR_ERR_OOM = -2,          /* workspace smaller than lr_workspace_bytes          */
+  LR_ERR_HIP = -3,          /* a HIP runtime call failed                          */
+  LR_ERR_GRAM_NOT_PD = -4,  /* Cholesky pivot of B^B <= 0 (device, via lr_status) */
+  LR_ERR_NONFINITE = -5,    /* non-finite B or Gram (device, via lr_status)       */
+  LR_ERR_PULSE = -6,        /* drive amplitude above the bound, or bad kind       */
+  LR_ERR_STATE = -7         /* call order (e.g. no workspace bound)               */
+};
+
+typedef struct lr_ctx lr_ctx_t;
+
+/* Create a context for one trajectory shape.  Rejects dims < 1, d_q < 2,
+ * M < 1, M > N, M > LR_MAX_M, unknown precision.  Host allocation only. */
+#define LR_MAX_M 32
+int lr_init(lr_ctx_t** ctx, const lr_model_t* model, int32_t M, int32_t precision);
+
+/* Exact device workspace size in bytes for this context (256-byte aligned
+ * start required).  Used for admission by HBM footprint. */
+size_t lr_workspace_bytes(const lr_ctx_t* ctx);
+
+/* Attach caller-owned device workspace (>= lr_workspace_bytes) and a HIP
+ * stream (hipStream_t, may be NULL for the default stream). */
+int lr_bind(lr_ctx_t* ctx, void* d_workspace, size_t bytes, void* stream);
+
+/* One right-hand side evaluation dB = f(t, B) (supplement S1.A, eq. "nosse").
+ * d_B and d_dB: device, column-major N x M lr_c64; they must not overlap. */
+int lr_rhs(lr_ctx_t* ctx, const lr_pulse_t* pulse, double t, const lr_c64* d_B, lr_c64* d_dB);
+
+/* Classic RK4 from B(t0) over nsteps steps of dt (step n starts at t0 + n dt).
+ * d_B: device, in B(t0), out B(t0 + nsteps dt).  If obs_stride > 0, d_obs
+ * (device, double) receives (nsteps / obs_stride + 1) records of
+ * LR_OBS_LEN(d_q) doubles: at step 0 and after every obs_stride-th step.
+ * Rejects dt <= 0, nsteps < 0, obs_stride < 0, a bad pulse. */
+int lr_integrate(lr_ctx_t* ctx, const lr_pulse_t* pulse, double t0, double dt, int64_t nsteps,
+                 lr_c64* d_B, int32_t obs_stride, double* d_obs);
+
+/* Observation record of B (device) into d_out (device, LR_OBS_LEN(d_q) doubles):
+ *   [Re<a>, Im<a>, Re<f>, Im<f>, tr rho, tr rho^2, P_q(0), ..., P_q(d_q-1)]
+ * with <O> = tr(O rho) unnormalised (main text beta = tr(rho f); populations of
+ * supplement eq. "transmon_ionization"), tr rho^2 = ||B^B||_F^2. */
+#define LR_OBS_LEN(d_q) (6 + (d_q))
+int lr_observables(lr_ctx_t* ctx, const lr_c64* d_B, double* d_out);
+
+/* Synchronise the bound stream and return the first device-side error of the
+ * last lr_integrate / lr_rhs / lr_observables (LR_OK if none); *failed_step
+ * (may be NULL) receives the RK step index at which it occurred. */
+int lr_status(lr_ctx_t* ctx, int64_t* failed_step);
+
+/* Kernel timing telemetry.  While enabled, every launch of the streaming
+ * stage kernel and of the Gram solve kernel made by lr_integrate is bracketed
+ * by HIP events on the bound stream (up to the first LR_PROFILE_MAX launches
+ * of each after enabling; enabling again resets the counters).
+ * lr_profile_read synchronises the stream and returns the summed kernel
+ * times (ms) and launch counts. */
+#define LR_PROFILE_MAX 4096
+int lr_profile_enable(lr_ctx_t* ctx, int32_t on);
+int lr_profile_read(lr_ctx_t* ctx, double* stage_ms, int64_t* stage_launches, double* solve_ms,
+                    int64_t* solve_launches);
+
+const char* lr_strerror(int code);
+void lr_destroy(lr_ctx_t* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LR_H */

@@ -1,0 +1,329 @@
+// Host side of the C ABI declared in include/lr.h: argument validation,
+// workspace layout and the launch sequence of one RK4 integration.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lr.h"
+#include "lr_kernels.hip"
+
+using lrk::TrajDev;
+
+struct lr_ctx {
+  lr_model_t model;
+  int M = 0, prec = 0;
+  int N = 0, L = 0, rt = 1, ntiles = 0;
+  size_t off_traj = 0, off_tilemap = 0, off_rt = 0, off_Bb = 0, off_S0 = 0, off_S1 = 0, off_acc = 0,
+         off_W = 0, off_part = 0, off_misc = 0, total = 0;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  TrajDev base{};
+  // kernel timing telemetry
+  bool prof = false;
+  std::vector<hipEvent_t> ev_stage, ev_solve;  // start/stop pairs
+  int64_t n_stage = 0, n_solve = 0;
+};
+
+namespace {
+
+constexpr double kDriveBound = 2.0 * M_PI * 0.4;  // |amplitude| < 2 pi 400 MHz
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int check_pulse(const lr_pulse_t* p) {
+  if (!p) return LR_ERR_ARG;
+  if (p->kind != LR_PULSE_FLATTOP && p->kind != LR_PULSE_PIECEWISE6) return LR_ERR_PULSE;
+  if (!(std::isfinite(p->w_d) && std::isfinite(p->T) && std::isfinite(p->t_ramp)) || p->t_ramp < 0.0)
+    return LR_ERR_PULSE;
+  if (p->kind == LR_PULSE_FLATTOP) {
+    if (!(std::fabs(p->amp) < kDriveBound)) return LR_ERR_PULSE;
+  } else {
+    for (int i = 0; i < 6; ++i)
+      if (!std::isfinite(p->p[i])) return LR_ERR_PULSE;
+    if (!(std::fabs(p->p[0]) < kDriveBound) || !(std::fabs(p->p[3]) < kDriveBound)) return LR_ERR_PULSE;
+  }
+  return LR_OK;
+}
+
+void set_pulse(TrajDev& v, const lr_pulse_t* p) {
+  v.pkind = p->kind;
+  v.w_d = p->w_d;
+  v.amp = p->amp;
+  v.t_ramp = p->t_ramp;
+  v.T = p->T;
+  for (int i = 0; i < 6; ++i) v.p[i] = p->p[i];
+}
+
+TrajDev* dev_traj(const lr_ctx* c) { return reinterpret_cast<TrajDev*>(c->ws + c->off_traj); }
+int2* dev_tilemap(const lr_ctx* c) { return reinterpret_cast<int2*>(c->ws + c->off_tilemap); }
+int* dev_rt(const lr_ctx* c) { return reinterpret_cast<int*>(c->ws + c->off_rt); }
+
+size_t stage_lds_bytes(const lr_ctx* c) {
+  return (size_t)(2 * c->M * c->M + c->rt * c->L * c->M) * sizeof(double2);
+}
+
+int launch_ok() { return hipGetLastError() == hipSuccess ? LR_OK : LR_ERR_HIP; }
+
+// Event pair slot for the next timed launch, or -1.
+int prof_slot(lr_ctx* c, std::vector<hipEvent_t>& ev, int64_t& n) {
+  if (!c->prof || n >= LR_PROFILE_MAX) return -1;
+  const size_t need = 2 * (size_t)(n + 1);
+  while (ev.size() < need) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    ev.push_back(e);
+  }
+  return (int)(n++);
+}
+
+void launch_stage(lr_ctx* c, int s, int mode) {
+  const int k = prof_slot(c, c->ev_stage, c->n_stage);
+  if (k >= 0) (void)hipEventRecord(c->ev_stage[2 * k], c->stream);
+  hipLaunchKernelGGL(lrk::k_stage, dim3(c->ntiles), dim3(lrk::kWG), stage_lds_bytes(c), c->stream, dev_traj(c),
+                     dev_tilemap(c), dev_rt(c), s, mode);
+  if (k >= 0) (void)hipEventRecord(c->ev_stage[2 * k + 1], c->stream);
+}
+
+void launch_solve(lr_ctx* c, int wpar, int advance, int mode) {
+  const int k = prof_slot(c, c->ev_solve, c->n_solve);
+  if (k >= 0) (void)hipEventRecord(c->ev_solve[2 * k], c->stream);
+  hipLaunchKernelGGL(lrk::k_solve, dim3(1), dim3(lrk::kWG), 0, c->stream, dev_traj(c), wpar, advance, mode);
+  if (k >= 0) (void)hipEventRecord(c->ev_solve[2 * k + 1], c->stream);
+}
+
+double prof_sum(const std::vector<hipEvent_t>& ev, int64_t n) {
+  double tot = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) == hipSuccess) tot += ms;
+  }
+  return tot;
+}
+
+int grid_for(const lr_ctx* c) {
+  const long long e = (long long)c->N * c->M;
+  long long g = (e + lrk::kWG - 1) / lrk::kWG;
+  if (g > 4096) g = 4096;
+  return (int)g;
+}
+
+// Enqueue: descriptor, reset, B -> internal, Gram of B, solve (W for stage 0).
+int prologue(lr_ctx* c, const TrajDev& v, const lr_c64* d_B) {
+  hipLaunchKernelGGL(lrk::k_set_traj, dim3(1), dim3(1), 0, c->stream, dev_traj(c), v);
+  hipLaunchKernelGGL(lrk::k_reset, dim3(1), dim3(64), 0, c->stream, dev_traj(c), 1);
+  hipLaunchKernelGGL(lrk::k_to_internal, dim3(grid_for(c)), dim3(lrk::kWG), 0, c->stream, dev_traj(c), 0,
+                     reinterpret_cast<const double2*>(d_B), c->base.Bb);
+  launch_stage(c, 0, lrk::MODE_GRAM);
+  return launch_ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lr_strerror(int code) {
+  switch (code) {
+    case LR_OK: return "ok";
+    case LR_ERR_ARG: return "invalid argument";
+    case LR_ERR_OOM: return "workspace too small";
+    case LR_ERR_HIP: return "HIP runtime error";
+    case LR_ERR_GRAM_NOT_PD: return "Gram matrix B^B not positive definite (Cholesky pivot <= 0)";
+    case LR_ERR_NONFINITE: return "non-finite state";
+    case LR_ERR_PULSE: return "invalid pulse (unknown kind or amplitude above 2*pi*0.4 rad/ns)";
+    case LR_ERR_STATE: return "invalid call order (no workspace bound)";
+    default: return "unknown error";
+  }
+}
+
+int lr_init(lr_ctx_t** out, const lr_model_t* m, int32_t M, int32_t precision) {
+  if (!out || !m) return LR_ERR_ARG;
+  *out = nullptr;
+  if (m->d_q < 2 || m->d_r < 1 || m->d_f < 1) return LR_ERR_ARG;
+  const long long N = (long long)m->d_q * m->d_r * m->d_f;
+  if (N > (1LL << 26)) return LR_ERR_ARG;
+  if (M < 1 || M > LR_MAX_M || M > N) return LR_ERR_ARG;
+  if (precision != LR_FP64) return LR_ERR_ARG;
+  const double vals[] = {m->w_q, m->alpha, m->w_r, m->w_f, m->g, m->G, m->kappa_f, m->gamma_1};
+  for (double x : vals)
+    if (!std::isfinite(x)) return LR_ERR_ARG;
+  if (m->kappa_f < 0.0 || m->gamma_1 < 0.0) return LR_ERR_ARG;
+  const int L = m->d_q * m->d_f;
+  if ((long long)L * M > lrk::kMaxTileElems) return LR_ERR_ARG;
+
+  lr_ctx* c = new (std::nothrow) lr_ctx();
+  if (!c) return LR_ERR_OOM;
+  c->model = *m;
+  c->M = M;
+  c->prec = precision;
+  c->N = (int)N;
+  c->L = L;
+  int rt = 1;
+  if (const char* e = std::getenv("LR_TILE_LAYERS")) rt = std::atoi(e);
+  const int rt_max = lrk::kMaxTileElems / (L * M);
+  if (rt < 1) rt = 1;
+  if (rt > rt_max) rt = rt_max;
+  if (rt > m->d_r) rt = m->d_r;
+  c->rt = rt;
+  c->ntiles = (m->d_r + rt - 1) / rt;
+
+  const size_t a = 256, nm = (size_t)N * M * sizeof(double2), mm = (size_t)M * M * sizeof(double2);
+  size_t o = 0;
+  c->off_traj = o;    o = align_up(o + sizeof(TrajDev), a);
+  c->off_tilemap = o; o = align_up(o + (size_t)c->ntiles * sizeof(int2), a);
+  c->off_rt = o;      o = align_up(o + sizeof(int), a);
+  c->off_Bb = o;      o = align_up(o + nm, a);
+  c->off_S0 = o;      o = align_up(o + nm, a);
+  c->off_S1 = o;      o = align_up(o + nm, a);
+  c->off_acc = o;     o = align_up(o + nm, a);
+  c->off_W = o;       o = align_up(o + 4 * mm, a);
+  c->off_part = o;    o = align_up(o + (size_t)c->ntiles * 3 * mm, a);
+  c->off_misc = o;    o = align_up(o + 64, a);
+  c->total = o;
+
+  TrajDev& b = c->base;
+  b.d_q = m->d_q; b.d_r = m->d_r; b.d_f = m->d_f; b.M = M;
+  b.N = (int)N; b.L = L; b.ntiles = c->ntiles; b.obs_stride = 0;
+  b.nsteps = 0;
+  b.w_q = m->w_q; b.alpha = m->alpha; b.w_r = m->w_r; b.w_f = m->w_f;
+  b.g = m->g; b.G = m->G; b.kappa = m->kappa_f; b.gamma = m->gamma_1;
+  *out = c;
+  return LR_OK;
+}
+
+size_t lr_workspace_bytes(const lr_ctx_t* c) { return c ? c->total : 0; }
+
+int lr_bind(lr_ctx_t* c, void* d_ws, size_t bytes, void* stream) {
+  if (!c || !d_ws) return LR_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return LR_ERR_ARG;
+  if (bytes < c->total) return LR_ERR_OOM;
+  c->ws = static_cast<char*>(d_ws);
+  c->stream = static_cast<hipStream_t>(stream);
+  TrajDev& b = c->base;
+  b.Bb = reinterpret_cast<double2*>(c->ws + c->off_Bb);
+  b.S0 = reinterpret_cast<double2*>(c->ws + c->off_S0);
+  b.S1 = reinterpret_cast<double2*>(c->ws + c->off_S1);
+  b.acc = reinterpret_cast<double2*>(c->ws + c->off_acc);
+  b.W = reinterpret_cast<double2*>(c->ws + c->off_W);
+  b.part = reinterpret_cast<double2*>(c->ws + c->off_part);
+  b.step = reinterpret_cast<int64_t*>(c->ws + c->off_misc);
+  b.fail_step = reinterpret_cast<int64_t*>(c->ws + c->off_misc + 8);
+  b.fro2 = reinterpret_cast<double*>(c->ws + c->off_misc + 16);
+  b.status = reinterpret_cast<int32_t*>(c->ws + c->off_misc + 24);
+  b.obs = nullptr;
+
+  // static tile map of this shape (one entry per workgroup of k_stage)
+  int2* tm = new (std::nothrow) int2[c->ntiles];
+  if (!tm) return LR_ERR_OOM;
+  for (int t = 0; t < c->ntiles; ++t) tm[t] = make_int2(0, t);
+  hipError_t e1 = hipMemcpyAsync(dev_tilemap(c), tm, sizeof(int2) * c->ntiles, hipMemcpyHostToDevice, c->stream);
+  hipError_t e2 = hipMemcpyAsync(dev_rt(c), &c->rt, sizeof(int), hipMemcpyHostToDevice, c->stream);
+  hipError_t e3 = hipStreamSynchronize(c->stream);
+  delete[] tm;
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return LR_ERR_HIP;
+  return LR_OK;
+}
+
+int lr_rhs(lr_ctx_t* c, const lr_pulse_t* pulse, double t, const lr_c64* d_B, lr_c64* d_dB) {
+  if (!c || !d_B || !d_dB || !std::isfinite(t)) return LR_ERR_ARG;
+  if (!c->ws) return LR_ERR_STATE;
+  if (int e = check_pulse(pulse)) return e;
+  TrajDev v = c->base;
+  set_pulse(v, pulse);
+  v.t0 = t;
+  v.dt = 0.0;
+  v.nsteps = 0;
+  if (int e = prologue(c, v, d_B)) return e;
+  launch_solve(c, 0, 0, lrk::MODE_RHS);
+  launch_stage(c, 0, lrk::MODE_RHS);
+  hipLaunchKernelGGL(lrk::k_to_abi, dim3(grid_for(c)), dim3(lrk::kWG), 0, c->stream, dev_traj(c), 0,
+                     c->base.acc, reinterpret_cast<double2*>(d_dB));
+  return launch_ok();
+}
+
+int lr_integrate(lr_ctx_t* c, const lr_pulse_t* pulse, double t0, double dt, int64_t nsteps, lr_c64* d_B,
+                 int32_t obs_stride, double* d_obs) {
+  if (!c || !d_B || !std::isfinite(t0) || !(dt > 0.0) || !std::isfinite(dt) || nsteps < 0 || obs_stride < 0)
+    return LR_ERR_ARG;
+  if (obs_stride > 0 && !d_obs) return LR_ERR_ARG;
+  if (!c->ws) return LR_ERR_STATE;
+  if (int e = check_pulse(pulse)) return e;
+  TrajDev v = c->base;
+  set_pulse(v, pulse);
+  v.t0 = t0;
+  v.dt = dt;
+  v.nsteps = nsteps;
+  v.obs = obs_stride > 0 ? d_obs : nullptr;
+  v.obs_stride = obs_stride;
+  if (int e = prologue(c, v, d_B)) return e;
+  launch_solve(c, 0, 0, lrk::MODE_RHS);
+  if (obs_stride > 0)
+    hipLaunchKernelGGL(lrk::k_obs, dim3(1), dim3(lrk::kWG), 0, c->stream, dev_traj(c), (double*)nullptr);
+  for (int64_t n = 0; n < nsteps; ++n) {
+    for (int s = 0; s < 4; ++s) {
+      launch_stage(c, s, lrk::MODE_STEP);
+      launch_solve(c, (s + 1) & 1, s == 3, lrk::MODE_STEP);
+    }
+    if (obs_stride > 0 && (n + 1) % obs_stride == 0)
+      hipLaunchKernelGGL(lrk::k_obs, dim3(1), dim3(lrk::kWG), 0, c->stream, dev_traj(c), (double*)nullptr);
+    if ((n & 1023) == 1023 && hipGetLastError() != hipSuccess) return LR_ERR_HIP;
+  }
+  hipLaunchKernelGGL(lrk::k_to_abi, dim3(grid_for(c)), dim3(lrk::kWG), 0, c->stream, dev_traj(c), 0,
+                     c->base.Bb, reinterpret_cast<double2*>(d_B));
+  return launch_ok();
+}
+
+int lr_observables(lr_ctx_t* c, const lr_c64* d_B, double* d_out) {
+  if (!c || !d_B || !d_out) return LR_ERR_ARG;
+  if (!c->ws) return LR_ERR_STATE;
+  TrajDev v = c->base;
+  v.pkind = 0;
+  v.nsteps = 0;
+  if (int e = prologue(c, v, d_B)) return e;
+  launch_solve(c, 0, 0, lrk::MODE_GRAM);
+  hipLaunchKernelGGL(lrk::k_obs, dim3(1), dim3(lrk::kWG), 0, c->stream, dev_traj(c), d_out);
+  return launch_ok();
+}
+
+int lr_status(lr_ctx_t* c, int64_t* failed_step) {
+  if (!c) return LR_ERR_ARG;
+  if (!c->ws) return LR_ERR_STATE;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LR_ERR_HIP;
+  int32_t st = 0;
+  int64_t fs = -1;
+  if (hipMemcpy(&st, c->base.status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return LR_ERR_HIP;
+  if (hipMemcpy(&fs, c->base.fail_step, sizeof(fs), hipMemcpyDeviceToHost) != hipSuccess) return LR_ERR_HIP;
+  if (failed_step) *failed_step = fs;
+  return st;
+}
+
+int lr_profile_enable(lr_ctx_t* c, int32_t on) {
+  if (!c) return LR_ERR_ARG;
+  c->prof = on != 0;
+  c->n_stage = c->n_solve = 0;
+  return LR_OK;
+}
+
+int lr_profile_read(lr_ctx_t* c, double* stage_ms, int64_t* stage_launches, double* solve_ms,
+                    int64_t* solve_launches) {
+  if (!c) return LR_ERR_ARG;
+  if (c->stream && hipStreamSynchronize(c->stream) != hipSuccess) return LR_ERR_HIP;
+  if (!c->stream && hipDeviceSynchronize() != hipSuccess) return LR_ERR_HIP;
+  if (stage_ms) *stage_ms = prof_sum(c->ev_stage, c->n_stage);
+  if (stage_launches) *stage_launches = c->n_stage;
+  if (solve_ms) *solve_ms = prof_sum(c->ev_solve, c->n_solve);
+  if (solve_launches) *solve_launches = c->n_solve;
+  return LR_OK;
+}
+
+void lr_destroy(lr_ctx_t* c) {
+  if (!c) return;
+  for (hipEvent_t e : c->ev_stage) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->ev_solve) (void)hipEventDestroy(e);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Device-side descriptors and small helpers shared by the HIP kernels.
+//
+// Internal state layout ("layer-major"): row index
+//     rho = (i_r * d_q + i_q) * d_f + i_f,   element (rho, j) at rho * M + j,
+// interleaved complex.  One resonator layer (all i_q, i_f for a fixed i_r) is
+// the contiguous block of L * M elements, L = d_q * d_f.  The jump operators
+// (f on the filter, b on the transmon) never leave a layer, so Gram and cross
+// products of a run of whole layers need no neighbours; only the resonator
+// quadrature (a + a^) couples a layer to the layers above and below.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lrk {
+
+constexpr int kWG = 256;          // threads per workgroup of the streaming kernels
+constexpr int kMaxM = 32;         // largest supported rank
+constexpr int kMaxTileElems = 2048;  // rows*M of one tile (LDS budget: 32 KB of FP64 complex)
+constexpr int kMaxElemsPerThread = kMaxTileElems / kWG;
+
+enum Mode : int { MODE_STEP = 0, MODE_RHS = 1, MODE_GRAM = 2 };
+
+struct TrajDev {
+  // shape
+  int32_t d_q, d_r, d_f, M;
+  int32_t N, L, ntiles, obs_stride;
+  int64_t nsteps;
+  // model (rad/ns)
+  double w_q, alpha, w_r, w_f, g, G, kappa, gamma;
+  // drive
+  int32_t pkind, pad0;
+  double w_d, amp, t_ramp, T, p[6];
+  // time grid
+  double t0, dt;
+  // device buffers, internal layout
+  double2* Bb;     // base state B_n (overwritten by B_{n+1} at the last stage)
+  double2* S0;     // stage inputs (ping-pong)
+  double2* S1;
+  double2* acc;    // k1 + 2 k2 + 2 k3
+  double2* W;      // [2 parity][2 jump][M*M]  W_k = (G^-1 C_k)^
+  double2* part;   // [ntiles][3][M*M] Gram / cross-product partials per tile
+  double* obs;     // caller's observation records (may be null)
+  double* fro2;    // ||B^B||_F^2 of the last reduced Gram
+  int64_t* step;   // device step counter
+  int32_t* status; // first device error (0 = none)
+  int64_t* fail_step;
+};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+// conj(a) * b
+__device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 cscale(double s, double2 a) {
+  return make_double2(s * a.x, s * a.y);
+}
+__device__ __forceinline__ double2 cfma(double s, double2 a, double2 acc) {
+  return make_double2(fma(s, a.x, acc.x), fma(s, a.y, acc.y));
+}
+
+// Cosine ramp r(x) of the flat-top window.
+__device__ __forceinline__ double ramp_up(double x, double t_r) {
+  if (x < 0.0) return 0.0;
+  if (x >= t_r) return 1.0;
+  return 0.5 * (1.0 - cos(M_PI * x / t_r));
+}
+
+// Drive coefficient d(t) multiplying (f + f^).
+__device__ inline double drive_at(const TrajDev& T, double t) {
+  if (T.pkind == 0) {
+    return T.amp * ramp_up(t, T.t_ramp) * ramp_up(T.T - t, T.t_ramp) * cos(T.w_d * t);
+  }
+  const double a = 0.5 * T.T - 0.5 * T.t_ramp;
+  double c;
+  if (t <= a) c = 0.0;
+  else if (t >= a + T.t_ramp) c = 1.0;
+  else c = 0.5 * (1.0 - cos(M_PI * (t - a) / T.t_ramp));
+  const double w1 = ramp_up(t, T.t_ramp) * (1.0 - c);
+  const double w2 = ramp_up(T.T - t, T.t_ramp) * c;
+  return T.p[0] * w1 * cos((T.w_d + T.p[2]) * t + T.p[1]) +
+         T.p[3] * w2 * cos((T.w_d + T.p[5]) * t + T.p[4]);
+}
+
+}  // namespace lrk

@@ -1,0 +1,224 @@
+"""Thin ctypes binding of the C ABI in include/lr.h (argument marshalling only).
+
+Every step of the integration runs in the HIP library ``liblr.so`` built by
+``paper_2508_18114_amd.build``; this module only converts Python values into
+the ABI's structs and device pointers.  PyTorch provides device memory and
+the stream.  Importing this module fails loudly if the library is missing.
+
+Device arrays: a factor B (N x M, column-major as the ABI requires) is held
+in a torch complex128 CUDA tensor of shape (M, N) (row j = column j of B);
+use ``to_device`` / ``from_device`` to move numpy (N, M) arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import inputs as _inp
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblr.so")
+
+LR_OK = 0
+LR_ERR_ARG = -1
+LR_ERR_OOM = -2
+LR_ERR_HIP = -3
+LR_ERR_GRAM_NOT_PD = -4
+LR_ERR_NONFINITE = -5
+LR_ERR_PULSE = -6
+LR_ERR_STATE = -7
+LR_MAX_M = 32
+
+# every symbol include/lr.h declares
+EXPORTS = ("lr_init", "lr_workspace_bytes", "lr_bind", "lr_rhs", "lr_integrate",
+           "lr_observables", "lr_status", "lr_profile_enable", "lr_profile_read",
+           "lr_strerror", "lr_destroy")
+
+
+class LrError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {lr_strerror(code)} ({code})")
+        self.code = code
+
+
+class lr_model_t(ctypes.Structure):
+    _fields_ = [("d_q", ctypes.c_int32), ("d_r", ctypes.c_int32), ("d_f", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("w_q", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("w_r", ctypes.c_double), ("w_f", ctypes.c_double),
+                ("g", ctypes.c_double), ("G", ctypes.c_double),
+                ("kappa_f", ctypes.c_double), ("gamma_1", ctypes.c_double)]
+
+
+class lr_pulse_t(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("w_d", ctypes.c_double), ("amp", ctypes.c_double),
+                ("t_ramp", ctypes.c_double), ("T", ctypes.c_double),
+                ("p", ctypes.c_double * 6)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library {LIB_PATH} is missing: build it with "
+                          "`python -m paper_2508_18114_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "lr_init": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lr_model_t), i32, i32]),
+        "lr_workspace_bytes": (sz, [vp]),
+        "lr_bind": (ctypes.c_int, [vp, vp, sz, vp]),
+        "lr_rhs": (ctypes.c_int, [vp, ctypes.POINTER(lr_pulse_t), dbl, vp, vp]),
+        "lr_integrate": (ctypes.c_int, [vp, ctypes.POINTER(lr_pulse_t), dbl, dbl, i64, vp, i32, vp]),
+        "lr_observables": (ctypes.c_int, [vp, vp, vp]),
+        "lr_status": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
+        "lr_profile_enable": (ctypes.c_int, [vp, i32]),
+        "lr_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64),
+                                           ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
+        "lr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "lr_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def model_struct(m: _inp.ModelParams) -> lr_model_t:
+    return lr_model_t(m.d_q, m.d_r, m.d_f, 0, m.w_q, m.alpha, m.w_r, m.w_f,
+                      m.g, m.G, m.kappa_f, m.gamma_1)
+
+
+def pulse_struct(p: _inp.PulseParams) -> lr_pulse_t:
+    return lr_pulse_t(p.kind, 0, p.w_d, p.amp, p.t_ramp, p.T, (ctypes.c_double * 6)(*p.p))
+
+
+# ---------------------------------------------------------------- raw ABI
+
+def lr_strerror(code: int) -> str:
+    return _lib.lr_strerror(code).decode()
+
+
+def lr_init(model: _inp.ModelParams, M: int, precision: int = _inp.FP64) -> int:
+    h = ctypes.c_void_p()
+    ms = model_struct(model)
+    rc = _lib.lr_init(ctypes.byref(h), ctypes.byref(ms), M, precision)
+    if rc != LR_OK:
+        raise LrError(rc, "lr_init")
+    return h.value
+
+
+def lr_workspace_bytes(ctx: int) -> int:
+    return int(_lib.lr_workspace_bytes(ctx))
+
+
+def lr_bind(ctx: int, d_ws: int, nbytes: int, stream: int) -> int:
+    return _lib.lr_bind(ctx, d_ws, nbytes, stream)
+
+
+def lr_rhs(ctx: int, pulse: _inp.PulseParams, t: float, d_B: int, d_dB: int) -> int:
+    ps = pulse_struct(pulse)
+    return _lib.lr_rhs(ctx, ctypes.byref(ps), t, d_B, d_dB)
+
+
+def lr_integrate(ctx: int, pulse: _inp.PulseParams, t0: float, dt: float, nsteps: int,
+                 d_B: int, obs_stride: int, d_obs: int) -> int:
+    ps = pulse_struct(pulse)
+    return _lib.lr_integrate(ctx, ctypes.byref(ps), t0, dt, nsteps, d_B, obs_stride, d_obs)
+
+
+def lr_observables(ctx: int, d_B: int, d_out: int) -> int:
+    return _lib.lr_observables(ctx, d_B, d_out)
+
+
+def lr_status(ctx: int):
+    fs = ctypes.c_int64(-1)
+    rc = _lib.lr_status(ctx, ctypes.byref(fs))
+    return rc, fs.value
+
+
+def lr_profile_enable(ctx: int, on: bool) -> int:
+    return _lib.lr_profile_enable(ctx, 1 if on else 0)
+
+
+def lr_profile_read(ctx: int):
+    """-> (rc, stage_ms, stage_launches, solve_ms, solve_launches)"""
+    sm, sl, vm, vl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+    rc = _lib.lr_profile_read(ctx, ctypes.byref(sm), ctypes.byref(sl), ctypes.byref(vm), ctypes.byref(vl))
+    return rc, sm.value, sl.value, vm.value, vl.value
+
+
+def lr_destroy(ctx: int) -> None:
+    _lib.lr_destroy(ctx)
+
+
+# ---------------------------------------------------------------- helpers
+
+def to_device(B: np.ndarray, device="cuda"):
+    """numpy (N, M) complex -> torch (M, N) complex128 device tensor (column-major B)."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(B, dtype=np.complex128).T)).to(device)
+
+
+def from_device(t) -> np.ndarray:
+    """torch (M, N) device tensor -> numpy (N, M)."""
+    return t.detach().cpu().numpy().T.copy()
+
+
+def obs_len(model: _inp.ModelParams) -> int:
+    return 6 + model.d_q
+
+
+class Context:
+    """One trajectory shape bound to torch-owned workspace on the current stream."""
+
+    def __init__(self, model: _inp.ModelParams, M: int, precision: int = _inp.FP64, stream=None):
+        import torch
+        self.model, self.M, self.precision = model, M, precision
+        self.handle = lr_init(model, M, precision)
+        nbytes = lr_workspace_bytes(self.handle)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        rc = lr_bind(self.handle, base + off, nbytes, self.stream.cuda_stream)
+        if rc != LR_OK:
+            raise LrError(rc, "lr_bind")
+
+    def _check(self, rc, where):
+        if rc != LR_OK:
+            raise LrError(rc, where)
+
+    def rhs(self, pulse, t, B_dev, dB_dev):
+        self._check(lr_rhs(self.handle, pulse, t, B_dev.data_ptr(), dB_dev.data_ptr()), "lr_rhs")
+
+    def integrate(self, pulse, t0, dt, nsteps, B_dev, obs_stride=0, obs_dev=None):
+        d_obs = obs_dev.data_ptr() if obs_dev is not None else 0
+        self._check(lr_integrate(self.handle, pulse, t0, dt, nsteps, B_dev.data_ptr(), obs_stride, d_obs),
+                    "lr_integrate")
+
+    def observables(self, B_dev, out_dev):
+        self._check(lr_observables(self.handle, B_dev.data_ptr(), out_dev.data_ptr()), "lr_observables")
+
+    def status(self):
+        return lr_status(self.handle)
+
+    def new_obs(self, nsteps, obs_stride):
+        import torch
+        n = nsteps // obs_stride + 1 if obs_stride > 0 else 0
+        return torch.zeros((n, obs_len(self.model)), dtype=torch.float64, device="cuda")
+
+    def close(self):
+        if self.handle:
+            lr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

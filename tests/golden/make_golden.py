@@ -1,0 +1,58 @@
+"""Write the cached oracle trajectories used by the full-size parity tests.
+
+Calls only the CPU oracle and the seeded input generators.  Usage:
+
+    OMP_NUM_THREADS=1 python tests/golden/make_golden.py [small|paper_size|all]
+
+Outputs (numpy .npz, one per named workload):
+    tests/golden/config_small.npz       dims (4,10,5),  M=4,  1e4 steps of 1e-3 ns
+    tests/golden/config_paper_size.npz  dims (8,50,5),  M=20, 8e4 steps of 5e-4 ns
+each holding obs_g, obs_e (observable records every `stride` steps), the
+stride, dt, and the readout figures of merit from the g/e pair.
+"""
+import os
+import sys
+import time
+from multiprocessing import Pool
+
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
+
+import numpy as np  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import loss, lowrank  # noqa: E402
+from paper_2508_18114_amd import inputs as I  # noqa: E402
+
+STRIDES = {"small": 100, "paper_size": 200}
+
+
+def _run(args):
+    name, idx = args
+    traj = (I.config_small() if name == "small" else I.config_paper_size())[idx]
+    t0 = time.time()
+    _, obs = lowrank.integrate(traj.model, traj.pulse, 0.0, traj.dt, traj.nsteps,
+                               traj.B0(), obs_stride=STRIDES[name])
+    return obs, time.time() - t0
+
+
+def make(name):
+    trajs = I.config_small() if name == "small" else I.config_paper_size()
+    with Pool(2) as pool:
+        (obs_g, tg), (obs_e, te) = pool.map(_run, [(name, 0), (name, 1)])
+    tr = trajs[0]
+    h = STRIDES[name] * tr.dt
+    fm = loss.readout_loss(obs_g, obs_e, h, tr.model.kappa_f, tr.model.gamma_1)
+    out = os.path.join(HERE, f"config_{name}.npz")
+    np.savez(out, obs_g=obs_g, obs_e=obs_e, stride=STRIDES[name], dt=tr.dt,
+             nsteps=tr.nsteps, seconds_g=tg, seconds_e=te,
+             **{k: v for k, v in fm.items()})
+    print(name, "written", out, f"{tg:.1f}s/{te:.1f}s", fm, flush=True)
+
+
+if __name__ == "__main__":
+    which = sys.argv[1] if len(sys.argv) > 1 else "all"
+    for nm in (["small", "paper_size"] if which == "all" else [which]):
+        make(nm)

@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (FP64 on both sides; only the summation order differs):
+  right-hand side   |d dB| <= 1e-11 * max|dB|                  (normwise over the factor)
+  <a>, <f>          |d|    <= 1e-8 * max(1, max|<a>|, max|<f>|)
+  P_q, tr rho, tr rho^2   |d| <= 1e-10
+  SNR               relative 1e-8 when SNR > 1e-3, else absolute 1e-11
+The trajectory bounds are those of the FP64 parity contract; the measured
+errors are printed so that they can be compared with the bound.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import loss, lowrank
+from paper_2508_18114_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def lr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2508_18114_amd import lr as _lr
+    return _lr
+
+
+def _rand_B(N, M, seed, scales=None):
+    r = np.random.default_rng(seed)
+    B = r.standard_normal((N, M)) + 1j * r.standard_normal((N, M))
+    if scales is not None:
+        B = B * np.asarray(scales)[None, :]
+    return B
+
+
+def _gpu_rhs(lr, model, M, pulse, t, B):
+    import torch
+    ctx = lr.Context(model, M)
+    dB = torch.empty((M, model.N), dtype=torch.complex128, device="cuda")
+    ctx.rhs(pulse, t, lr.to_device(B), dB)
+    rc, _ = ctx.status()
+    assert rc == lr.LR_OK, lr.lr_strerror(rc)
+    return lr.from_device(dB)
+
+
+def _gpu_integrate(lr, model, M, pulse, dt, nsteps, B0, stride, t0=0.0):
+    ctx = lr.Context(model, M)
+    Bd = lr.to_device(B0)
+    obs = ctx.new_obs(nsteps, stride)
+    ctx.integrate(pulse, t0, dt, nsteps, Bd, stride, obs)
+    rc, fs = ctx.status()
+    assert rc == lr.LR_OK, (lr.lr_strerror(rc), fs)
+    return lr.from_device(Bd), obs.cpu().numpy()
+
+
+def _obs_errors(got, ref):
+    fa = max(1.0, np.max(np.abs(ref[:, 0:4])))
+    e_field = np.max(np.abs(got[:, 0:4] - ref[:, 0:4])) / fa
+    e_pop = np.max(np.abs(got[:, 4:] - ref[:, 4:]))
+    return e_field, e_pop
+
+
+def _assert_obs(got, ref, what):
+    assert got.shape == ref.shape, (got.shape, ref.shape)
+    e_field, e_pop = _obs_errors(got, ref)
+    print(f"[parity] {what}: field err {e_field:.3e} (tol 1e-8), populations err {e_pop:.3e} (tol 1e-10)")
+    assert e_field <= 1e-8
+    assert e_pop <= 1e-10
+
+
+# ------------------------------------------------------------ right-hand side
+
+@pytest.mark.parametrize("dims,M", [((3, 4, 3), 3), ((2, 5, 3), 1), ((2, 2, 2), 8), ((4, 10, 5), 4),
+                                    ((8, 50, 5), 20), ((8, 75, 5), 32), ((8, 13, 5), 7)])
+def test_rhs_matches_oracle(lr, dims, M):
+    m = I.readout_model(*dims).replace(kappa_f=0.7, gamma_1=0.3)
+    p = I.flattop_pulse(0.09, 6.0)
+    B = _rand_B(m.N, M, 1, scales=np.logspace(0, -3, M))
+    for t in (0.0, 1.3, 3.7):
+        ref = lowrank.rhs(m, p, t, B)
+        got = _gpu_rhs(lr, m, M, p, t, B)
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        print(f"[parity] rhs dims={dims} M={M} t={t}: rel err {err:.3e}")
+        assert err <= 1e-11
+
+
+def test_rhs_padded_initial_state(lr):
+    """The rank-padded B0 (columns of norm 1e-6) of the paper-size workload."""
+    tr = I.config_paper_size()[1]
+    B0 = tr.B0()
+    for t in (0.0, 5.0, 20.0):
+        ref = lowrank.rhs(tr.model, tr.pulse, t, B0)
+        got = _gpu_rhs(lr, tr.model, tr.M, tr.pulse, t, B0)
+        colref = np.linalg.norm(ref, axis=0)
+        colerr = np.linalg.norm(got - ref, axis=0)
+        err = np.max(colerr / np.maximum(colref, 1e-300))
+        print(f"[parity] rhs padded B0 t={t}: max column rel err {err:.3e}")
+        assert err <= 1e-9
+
+
+def test_rhs_piecewise_pulse(lr):
+    m = I.readout_model(3, 6, 4)
+    p = I.draw_piecewise6(I.rng(3), 12.0)
+    B = _rand_B(m.N, 5, 2)
+    for t in (0.7, 5.9, 6.0, 6.3, 11.5):
+        ref = lowrank.rhs(m, p, t, B)
+        got = _gpu_rhs(lr, m, 5, p, t, B)
+        assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+# ------------------------------------------------------------ observables
+
+def test_observables_match_oracle(lr):
+    import torch
+    for dims, M in [((4, 10, 5), 4), ((8, 50, 5), 20), ((3, 1, 2), 2)]:
+        m = I.readout_model(*dims)
+        B = _rand_B(m.N, M, 4)
+        ctx = lr.Context(m, M)
+        out = torch.zeros(lr.obs_len(m), dtype=torch.float64, device="cuda")
+        ctx.observables(lr.to_device(B), out)
+        assert ctx.status()[0] == lr.LR_OK
+        ref = lowrank.observables(m, B)
+        got = out.cpu().numpy()
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12 * np.max(np.abs(ref)))
+
+
+# ------------------------------------------------------------ integration
+
+def test_integrate_short_ragged(lr):
+    """Several tiles, ragged observation stride, piecewise drive, mixed column scales."""
+    m = I.readout_model(3, 7, 4).replace(kappa_f=0.5, gamma_1=0.05)
+    p = I.draw_piecewise6(I.rng(5), 0.6)
+    B0 = _rand_B(m.N, 5, 6, scales=[1.0, 0.3, 0.1, 0.05, 0.01])
+    B0 /= np.linalg.norm(B0)
+    dt, n, stride = 1e-3, 203, 7
+    Bo, ref = lowrank.integrate(m, p, 0.0, dt, n, B0, obs_stride=stride)
+    Bg, got = _gpu_integrate(lr, m, 5, p, dt, n, B0, stride)
+    _assert_obs(got, ref, "short ragged")
+    assert np.max(np.abs(Bg - Bo)) <= 1e-10
+
+
+def test_integrate_nonzero_t0(lr):
+    m = I.readout_model(2, 5, 3)
+    p = I.flattop_pulse(0.1, 3.0, t_ramp=1.0)
+    B0 = I.initial_state(m, 3, "e", seed=7, scale=1e-3)
+    Bo, ref = lowrank.integrate(m, p, 0.8, 1e-3, 300, B0, obs_stride=50)
+    Bg, got = _gpu_integrate(lr, m, 3, p, 1e-3, 300, B0, 50, t0=0.8)
+    _assert_obs(got, ref, "t0 = 0.8")
+
+
+def _golden(name):
+    path = os.path.join(HERE, "golden", f"config_{name}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return np.load(path)
+
+
+def _check_config(lr, name, trajs):
+    gd = _golden(name)
+    stride = int(gd["stride"])
+    obs = {}
+    for tr, key in zip(trajs, ("obs_g", "obs_e")):
+        _, got = _gpu_integrate(lr, tr.model, tr.M, tr.pulse, tr.dt, tr.nsteps, tr.B0(), stride)
+        _assert_obs(got, gd[key], f"{name} {tr.which}")
+        obs[key] = got
+    tr = trajs[0]
+    fm = loss.readout_loss(obs["obs_g"], obs["obs_e"], stride * tr.dt, tr.model.kappa_f, tr.model.gamma_1)
+    snr_ref = float(gd["snr"])
+    d = abs(fm["snr"] - snr_ref)
+    print(f"[parity] {name} SNR gpu {fm['snr']:.12e} oracle {snr_ref:.12e} eps_sep {fm['eps_sep']:.6e}")
+    assert d <= (1e-8 * snr_ref if snr_ref > 1e-3 else 1e-11)
+    assert abs(fm["ionisation"] - float(gd["ionisation"])) <= 1e-10
+
+
+def test_integrate_config_small(lr):
+    """dims (4,10,5), M = 4, 1e4 RK4 steps of 1e-3 ns, g and e, against the cached oracle run."""
+    _check_config(lr, "small", I.config_small())
+
+
+def test_integrate_config_paper_size(lr):
+    """dims (8,50,5) (N = 2000), M = 20, 8e4 RK4 steps of 5e-4 ns, g and e, against the cached oracle run."""
+    _check_config(lr, "paper_size", I.config_paper_size())
+
+
+# ------------------------------------------------------------ edge cases
+
+def test_zero_steps_and_degenerate_shapes(lr):
+    m = I.readout_model(2, 3, 2)
+    B0 = _rand_B(m.N, 4, 8)
+    p = I.flattop_pulse(0.05, 1.0)
+    Bg, got = _gpu_integrate(lr, m, 4, p, 1e-3, 0, B0, 5)
+    assert np.array_equal(Bg, B0)
+    np.testing.assert_allclose(got[0], lowrank.observables(m, B0), rtol=1e-12)
+    # M = N (full rank) and M = 1; a single resonator layer; stride > nsteps
+    for dims, M in [((2, 3, 2), 12), ((2, 3, 2), 1), ((3, 1, 4), 3)]:
+        mm = I.readout_model(*dims).replace(kappa_f=0.4, gamma_1=0.1)
+        B0 = _rand_B(mm.N, M, 9)
+        B0 /= np.linalg.norm(B0)
+        Bo, ref = lowrank.integrate(mm, p, 0.0, 1e-3, 40, B0, obs_stride=50)
+        Bg, got = _gpu_integrate(lr, mm, M, p, 1e-3, 40, B0, 50)
+        _assert_obs(got, ref, f"dims {dims} M {M}")
+        assert np.max(np.abs(Bg - Bo)) <= 1e-12
+
+
+def test_device_errors_are_reported(lr):
+    m = I.readout_model(2, 3, 2)
+    p = I.flattop_pulse(0.05, 1.0)
+    B0 = _rand_B(m.N, 3, 10)
+    B0[:, 1] = 0.0
+    ctx = lr.Context(m, 3)
+    Bd = lr.to_device(B0)
+    ctx.integrate(p, 0.0, 1e-3, 5, Bd, 0, None)
+    rc, fs = ctx.status()
+    assert rc == lr.LR_ERR_GRAM_NOT_PD and fs == 0
+    B1 = _rand_B(m.N, 3, 11)
+    B1[4, 2] = np.nan
+    ctx.integrate(p, 0.0, 1e-3, 5, lr.to_device(B1), 0, None)
+    rc, fs = ctx.status()
+    assert rc == lr.LR_ERR_NONFINITE and fs == 0
+    # the context is usable again afterwards
+    B2 = _rand_B(m.N, 3, 12)
+    ctx.integrate(p, 0.0, 1e-3, 5, lr.to_device(B2), 0, None)
+    assert ctx.status()[0] == lr.LR_OK
+    # argument errors are synchronous
+    bad = I.flattop_pulse(0.5, 1.0)   # 0.5 GHz > 0.4 GHz bound
+    assert lr.lr_integrate(ctx.handle, bad, 0.0, 1e-3, 5, lr.to_device(B2).data_ptr(), 0, 0) == lr.LR_ERR_PULSE
+    assert lr.lr_integrate(ctx.handle, p, 0.0, 0.0, 5, lr.to_device(B2).data_ptr(), 0, 0) == lr.LR_ERR_ARG
+
+
+def test_deterministic_replay(lr):
+    """Same inputs twice: bitwise-equal state and records (fixed reduction order)."""
+    tr = I.config_small()[1]
+    a = _gpu_integrate(lr, tr.model, tr.M, tr.pulse, tr.dt, 500, tr.B0(), 10)
+    b = _gpu_integrate(lr, tr.model, tr.M, tr.pulse, tr.dt, 500, tr.B0(), 10)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
