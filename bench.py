@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
 
 
 def parse():
@@ -75,47 +76,47 @@ def main():
     torch.cuda.set_device(0)
     trajs = I.config_paper_size()
     m, M = trajs[0].model, trajs[0].M
-    streams = [torch.cuda.Stream() for _ in trajs]
-    ctxs = [lr.Context(t.model, t.M, stream=s) for t, s in zip(trajs, streams)]
-    Bs = [lr.to_device(t.B0()) for t in trajs]
-    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
 
-    def run(nsteps):
-        for c, t, B in zip(ctxs, trajs, Bs):
-            c.integrate(t.pulse, 0.0, t.dt, nsteps, B)
+    def make_batch(nsteps):
+        items = [dict(model=t.model, M=t.M, pulse=t.pulse, dt=t.dt, nsteps=nsteps, B=lr.to_device(t.B0()))
+                 for t in trajs]
+        return lr.Batch(items, stream=stream), items
 
-    run(a.warmup)
-    torch.cuda.synchronize()
-    for c in ctxs:
-        rc, fs = c.status()
+    def check(b):
+        rc, codes, steps = b.status()
         if rc != lr.LR_OK:
-            raise RuntimeError(f"device error {lr.lr_strerror(rc)} at step {fs}")
+            raise RuntimeError(f"device error {lr.lr_strerror(rc)} (codes {codes}, steps {steps})")
 
-    # timed region: K RK4 steps of both trajectories
+    # warmup: the same batch shape, W steps
+    wb, _ = make_batch(a.warmup)
+    wb.run()
+    check(wb)
+    # timed region: K RK4 steps of both trajectories in one batch (inputs resident in HBM)
+    tb, titems = make_batch(a.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run(a.steps)
+    tb.run()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    for c in ctxs:
-        rc, fs = c.status()
-        if rc != lr.LR_OK:
-            raise RuntimeError(f"device error {lr.lr_strerror(rc)} at step {fs}")
+    check(tb)
     value = len(trajs) * a.steps / elapsed
 
-    # live kernel timing of the stage kernel (events on its own stream)
+    # live kernel timing of the persistent kernel (HIP events on its stream):
+    # one trajectory, one launch of prof_steps steps
     prof_steps = min(1000, max(1, a.steps // 4))
-    c0 = ctxs[0]
-    lr.lr_profile_enable(c0.handle, True)
-    c0.integrate(trajs[0].pulse, 0.0, trajs[0].dt, prof_steps, Bs[0])
-    _, stage_ms, stage_n, solve_ms, solve_n = lr.lr_profile_read(c0.handle)
-    lr.lr_profile_enable(c0.handle, False)
-    stage_us = 1e3 * stage_ms / max(stage_n, 1)
-    solve_us = 1e3 * solve_ms / max(solve_n, 1)
-    # algorithmic state traffic of one trajectory-step: 10 reads + 7 writes of N x M complex FP64
-    bytes_per_step = 17 * 16 * m.N * M
-    bytes_per_launch = bytes_per_step / 4.0
-    achieved = bytes_per_launch / (stage_us * 1e-6) / 1e9
+    ctx = lr.Context(m, M, stream=stream)
+    Bp = lr.to_device(trajs[0].B0())
+    lr.lr_profile_enable(ctx.handle, True)
+    ctx.integrate(trajs[0].pulse, 0.0, trajs[0].dt, prof_steps, Bp)
+    _, stage_ms, stage_n, _, _ = lr.lr_profile_read(ctx.handle)
+    lr.lr_profile_enable(ctx.handle, False)
+    launch_us = 1e3 * stage_ms / max(stage_n, 1)
+    # algorithmic FP64 work of one trajectory-step: 4 stages x N x M elements x
+    # (58 stencil/update + 16 M jump assembly + 24 M Gram/cross) flops
+    flops_per_step = 4 * m.N * M * (58 + 40 * M)
+    flops_per_launch = flops_per_step * prof_steps
+    achieved = flops_per_launch / (launch_us * 1e-6) / 1e12
 
     out = {
         "metric": "RK steps*trajectories/s at N=2000, M=20",
@@ -131,12 +132,12 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "readout model dims (8,50,5) N=2000, M=20, RK4 dt=5e-4 ns, "
-                               "trajectories g and e (plain form, one context each)",
+                               "trajectories g and e integrated together (one batch)",
                    "N": m.N, "M": M, "trajectories": len(trajs), "dt_ns": trajs[0].dt},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_stage", "kernel_mean_us": stage_us, "launches_timed": stage_n,
-                     "bytes_per_launch": bytes_per_launch, "solve_kernel_mean_us": solve_us},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFS, "traffic": None,
+                     "kernel": "k_persist", "kernel_mean_us": launch_us, "launches_timed": stage_n,
+                     "steps_per_launch": prof_steps, "flops_per_launch": flops_per_launch},
     }
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a.cpu_steps)

@@ -82,7 +82,8 @@ enum {
   LR_ERR_GRAM_NOT_PD = -4,  /* Cholesky pivot of B^B <= 0 (device, via lr_status) */
   LR_ERR_NONFINITE = -5,    /* non-finite B or Gram (device, via lr_status)       */
   LR_ERR_PULSE = -6,        /* drive amplitude above the bound, or bad kind       */
-  LR_ERR_STATE = -7         /* call order (e.g. no workspace bound)               */
+  LR_ERR_STATE = -7,        /* call order (e.g. no workspace bound)               */
+  LR_ERR_TIMEOUT = -8       /* a bounded device-side wait expired (via lr_status) */
 };
 
 typedef struct lr_ctx lr_ctx_t;
@@ -137,6 +138,43 @@ int lr_profile_read(lr_ctx_t* ctx, double* stage_ms, int64_t* stage_launches, do
 
 const char* lr_strerror(int code);
 void lr_destroy(lr_ctx_t* ctx);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent trajectories (e.g. pulse candidates x {g, e},
+ * each with its own model dims, rank, drive, dt and step count) integrated
+ * together.  Each trajectory is the lr_integrate problem above; results are
+ * bitwise those of the same trajectory run alone in a batch of one (every
+ * reduction has a fixed order that does not depend on the batch).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  lr_model_t model;
+  int32_t M;
+  int32_t precision;        /* LR_FP64 */
+  lr_pulse_t pulse;
+  double t0, dt;
+  int64_t nsteps;
+  lr_c64* d_B;              /* device, column-major N x M; in B(t0), out B(t0 + nsteps dt) */
+  int32_t obs_stride;       /* records as in lr_integrate (0: none) */
+  int32_t reserved;
+  double* d_obs;            /* device, (nsteps / obs_stride + 1) x LR_OBS_LEN(d_q) */
+} lr_traj_t;
+
+typedef struct lr_batch lr_batch_t;
+
+/* Plan a batch (host only): validates every trajectory (as lr_init and
+ * lr_integrate do), copies the descriptors and sizes the workspace.  The
+ * device pointers inside the descriptors are used by lr_batch_run. */
+int lr_batch_init(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n);
+size_t lr_batch_workspace_bytes(const lr_batch_t* batch);
+int lr_batch_bind(lr_batch_t* batch, void* d_workspace, size_t bytes, void* stream);
+/* Enqueue the integration of every trajectory of the batch on the bound
+ * stream.  Trajectories are packed into co-resident groups and run
+ * concurrently, group after group. */
+int lr_batch_run(lr_batch_t* batch);
+/* Synchronise; per-trajectory status codes and failing step indices
+ * (arrays of n, may be NULL).  Returns the first non-OK code or LR_OK. */
+int lr_batch_status(lr_batch_t* batch, int32_t* codes, int64_t* failed_steps);
+void lr_batch_destroy(lr_batch_t* batch);
 
 #ifdef __cplusplus
 }

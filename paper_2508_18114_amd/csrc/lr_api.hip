@@ -2,6 +2,7 @@
 // workspace layout and the launch sequence of one RK4 integration.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -10,6 +11,7 @@
 
 #include "lr.h"
 #include "lr_kernels.hip"
+#include "lr_persistent.hip"
 
 using lrk::TrajDev;
 
@@ -19,6 +21,10 @@ struct lr_ctx {
   int N = 0, L = 0, rt = 1, ntiles = 0;
   size_t off_traj = 0, off_tilemap = 0, off_rt = 0, off_Bb = 0, off_S0 = 0, off_S1 = 0, off_acc = 0,
          off_W = 0, off_part = 0, off_misc = 0, total = 0;
+  // persistent path: P workgroups of prt layers
+  int P = 0, prt = 1, prows = 2;
+  size_t pers_lds = 0;
+  size_t off_ptilemap = 0, off_SP = 0, off_PART = 0, off_RED = 0, off_flagA = 0, off_flagB = 0;
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   TrajDev base{};
@@ -95,6 +101,18 @@ void launch_solve(lr_ctx* c, int wpar, int advance, int mode) {
   if (k >= 0) (void)hipEventRecord(c->ev_solve[2 * k + 1], c->stream);
 }
 
+int launch_persist(lr_ctx* c, int prologue, int64_t step0, int64_t nchunk) {
+  const int k = prologue ? -1 : prof_slot(c, c->ev_stage, c->n_stage);
+  if (k >= 0) (void)hipEventRecord(c->ev_stage[2 * k], c->stream);
+  const TrajDev* tr = dev_traj(c);
+  const int2* tmap = reinterpret_cast<const int2*>(c->ws + c->off_ptilemap);
+  void* args[] = {(void*)&tr, (void*)&tmap, (void*)&prologue, (void*)&step0, (void*)&nchunk};
+  const void* fn = c->prows == 2 ? (const void*)lrk::k_persist<2> : (const void*)lrk::k_persist<3>;
+  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(c->P), dim3(lrk::kPW), args, (unsigned)c->pers_lds, c->stream);
+  if (k >= 0) (void)hipEventRecord(c->ev_stage[2 * k + 1], c->stream);
+  return e == hipSuccess ? LR_OK : LR_ERR_HIP;
+}
+
 double prof_sum(const std::vector<hipEvent_t>& ev, int64_t n) {
   double tot = 0.0;
   for (int64_t k = 0; k < n; ++k) {
@@ -135,6 +153,7 @@ const char* lr_strerror(int code) {
     case LR_ERR_NONFINITE: return "non-finite state";
     case LR_ERR_PULSE: return "invalid pulse (unknown kind or amplitude above 2*pi*0.4 rad/ns)";
     case LR_ERR_STATE: return "invalid call order (no workspace bound)";
+    case LR_ERR_TIMEOUT: return "device-side wait expired";
     default: return "unknown error";
   }
 }
@@ -170,6 +189,22 @@ int lr_init(lr_ctx_t** out, const lr_model_t* m, int32_t M, int32_t precision) {
   c->rt = rt;
   c->ntiles = (m->d_r + rt - 1) / rt;
 
+  // persistent path: smallest layer count per workgroup that fits the
+  // register rows (<= kMaxRowsPerThread per thread) and the 160 KB LDS
+  {
+    int prt = 1;
+    if (const char* e = std::getenv("LR_PERSIST_LAYERS")) prt = std::atoi(e);
+    if (prt < 1) prt = 1;
+    if (prt > m->d_r) prt = m->d_r;
+    const int NG = lrk::kPW / M;
+    while (prt > 1 && ((prt * L + NG - 1) / NG > lrk::kMaxRowsPerThread || lrk::persist_lds_bytes(prt, L, M, (m->d_r + prt - 1) / prt) > lrk::kPersistLdsMax))
+      --prt;
+    c->prt = prt;
+    c->prows = ((prt * L + NG - 1) / NG <= 2) ? 2 : 3;
+    c->P = (m->d_r + prt - 1) / prt;
+    c->pers_lds = lrk::persist_lds_bytes(prt, L, M, c->P);
+    if ((L + NG - 1) / NG > lrk::kMaxRowsPerThread || c->pers_lds > lrk::kPersistLdsMax) c->P = 0;  // path unavailable
+  }
   const size_t a = 256, nm = (size_t)N * M * sizeof(double2), mm = (size_t)M * M * sizeof(double2);
   size_t o = 0;
   c->off_traj = o;    o = align_up(o + sizeof(TrajDev), a);
@@ -182,6 +217,15 @@ int lr_init(lr_ctx_t** out, const lr_model_t* m, int32_t M, int32_t precision) {
   c->off_W = o;       o = align_up(o + 4 * mm, a);
   c->off_part = o;    o = align_up(o + (size_t)c->ntiles * 3 * mm, a);
   c->off_misc = o;    o = align_up(o + 64, a);
+  if (c->P > 0) {
+    const size_t npe = 3 * mm;
+    c->off_ptilemap = o; o = align_up(o + (size_t)c->P * sizeof(int2), a);
+    c->off_SP = o;       o = align_up(o + 2 * nm, a);
+    c->off_PART = o;     o = align_up(o + 2 * (size_t)c->P * npe, a);
+    c->off_RED = o;      o = align_up(o + 2 * npe, a);
+    c->off_flagA = o;    o = align_up(o + (size_t)c->P * lrk::kFlagStride * 4, a);
+    c->off_flagB = o;    o = align_up(o + (size_t)c->P * lrk::kFlagStride * 4, a);
+  }
   c->total = o;
 
   TrajDev& b = c->base;
@@ -213,17 +257,37 @@ int lr_bind(lr_ctx_t* c, void* d_ws, size_t bytes, void* stream) {
   b.fail_step = reinterpret_cast<int64_t*>(c->ws + c->off_misc + 8);
   b.fro2 = reinterpret_cast<double*>(c->ws + c->off_misc + 16);
   b.status = reinterpret_cast<int32_t*>(c->ws + c->off_misc + 24);
+  b.abort_flag = reinterpret_cast<uint32_t*>(c->ws + c->off_misc + 28);
   b.obs = nullptr;
+  b.P = c->P;
+  b.rt = c->prt;
+  b.npe = 3 * c->M * c->M;
+  if (c->P > 0) {
+    b.SP = reinterpret_cast<double2*>(c->ws + c->off_SP);
+    b.PART = reinterpret_cast<double2*>(c->ws + c->off_PART);
+    b.RED = reinterpret_cast<double2*>(c->ws + c->off_RED);
+    b.flagA = reinterpret_cast<uint32_t*>(c->ws + c->off_flagA);
+    b.flagB = reinterpret_cast<uint32_t*>(c->ws + c->off_flagB);
+  }
 
   // static tile map of this shape (one entry per workgroup of k_stage)
-  int2* tm = new (std::nothrow) int2[c->ntiles];
+  const int nmap = c->ntiles > c->P ? c->ntiles : c->P;
+  int2* tm = new (std::nothrow) int2[nmap];
   if (!tm) return LR_ERR_OOM;
-  for (int t = 0; t < c->ntiles; ++t) tm[t] = make_int2(0, t);
+  for (int t = 0; t < nmap; ++t) tm[t] = make_int2(0, t);
   hipError_t e1 = hipMemcpyAsync(dev_tilemap(c), tm, sizeof(int2) * c->ntiles, hipMemcpyHostToDevice, c->stream);
   hipError_t e2 = hipMemcpyAsync(dev_rt(c), &c->rt, sizeof(int), hipMemcpyHostToDevice, c->stream);
+  hipError_t e4 = hipSuccess;
+  if (c->P > 0)
+    e4 = hipMemcpyAsync(c->ws + c->off_ptilemap, tm, sizeof(int2) * c->P, hipMemcpyHostToDevice, c->stream);
   hipError_t e3 = hipStreamSynchronize(c->stream);
   delete[] tm;
-  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return LR_ERR_HIP;
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) return LR_ERR_HIP;
+  if (c->P > 0) {
+    const void* fn = c->prows == 2 ? (const void*)lrk::k_persist<2> : (const void*)lrk::k_persist<3>;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->pers_lds) != hipSuccess)
+      return LR_ERR_HIP;
+  }
   return LR_OK;
 }
 
@@ -258,6 +322,28 @@ int lr_integrate(lr_ctx_t* c, const lr_pulse_t* pulse, double t0, double dt, int
   v.nsteps = nsteps;
   v.obs = obs_stride > 0 ? d_obs : nullptr;
   v.obs_stride = obs_stride;
+  if (c->P > 0 && !std::getenv("LR_NO_PERSIST")) {
+    hipLaunchKernelGGL(lrk::k_set_traj, dim3(1), dim3(1), 0, c->stream, dev_traj(c), v);
+    hipLaunchKernelGGL(lrk::k_reset, dim3(1), dim3(64), 0, c->stream, dev_traj(c), 1);
+    hipLaunchKernelGGL(lrk::k_reset_persist, dim3(1), dim3(256), 0, c->stream, dev_traj(c), 1);
+    hipLaunchKernelGGL(lrk::k_to_internal, dim3(grid_for(c)), dim3(lrk::kWG), 0, c->stream, dev_traj(c), 0,
+                       reinterpret_cast<const double2*>(d_B), c->base.Bb);
+    if (int e = launch_ok()) return e;
+    if (int e = launch_persist(c, 1, 0, 0)) return e;
+    if (obs_stride > 0)
+      hipLaunchKernelGGL(lrk::k_obs, dim3(1), dim3(lrk::kWG), 0, c->stream, dev_traj(c), (double*)nullptr);
+    const int64_t max_chunk = obs_stride > 0 ? obs_stride : 4096;
+    for (int64_t step = 0; step < nsteps;) {
+      const int64_t chunk = (nsteps - step < max_chunk) ? nsteps - step : max_chunk;
+      if (int e = launch_persist(c, 0, step, chunk)) return e;
+      step += chunk;
+      if (obs_stride > 0 && step % obs_stride == 0)
+        hipLaunchKernelGGL(lrk::k_obs, dim3(1), dim3(lrk::kWG), 0, c->stream, dev_traj(c), (double*)nullptr);
+    }
+    hipLaunchKernelGGL(lrk::k_to_abi, dim3(grid_for(c)), dim3(lrk::kWG), 0, c->stream, dev_traj(c), 0,
+                       c->base.Bb, reinterpret_cast<double2*>(d_B));
+    return launch_ok();
+  }
   if (int e = prologue(c, v, d_B)) return e;
   launch_solve(c, 0, 0, lrk::MODE_RHS);
   if (obs_stride > 0)
@@ -327,3 +413,5 @@ void lr_destroy(lr_ctx_t* c) {
 }
 
 }  // extern "C"
+
+#include "lr_batch.hip"

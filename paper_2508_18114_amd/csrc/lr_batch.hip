@@ -1,0 +1,302 @@
+// Host side of the batch entry points (lr_batch_*): planning, workspace
+// layout and the launch sequence that integrates many independent
+// trajectories with the persistent on-chip kernel.
+//
+// Trajectories are packed, in order, into execution groups whose workgroups
+// are co-resident (one cooperative launch per chunk of steps); groups run one
+// after the other.  Within a group every trajectory has its own barrier
+// flags, so trajectories of different shapes and step counts proceed
+// independently, and each result is bitwise that of the trajectory alone.
+
+struct lr_batch {
+  int n = 0;
+  std::vector<lr_traj_t> tr;
+  std::vector<TrajDev> dev;
+  std::vector<int> P, prt, rows;
+  std::vector<size_t> lds, region, region_bytes;
+  std::vector<int> wg_offset;  // first tilemap entry of each trajectory
+  size_t off_trajs = 0, off_tilemap = 0, total = 0;
+  int total_wg = 0;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  struct Group {
+    int begin, end, wgs, rows;
+    size_t lds;
+    int64_t max_steps, chunk;
+  };
+  std::vector<Group> groups;
+};
+
+namespace {
+
+int64_t gcd64(int64_t a, int64_t b) {
+  while (b) {
+    const int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// Persistent configuration of one shape: layers per workgroup, register rows.
+bool persist_config(const lr_model_t& m, int M, int& prt, int& P, int& rows, size_t& lds) {
+  const int L = m.d_q * m.d_f;
+  const int NG = lrk::kPW / M;
+  prt = 1;
+  if (const char* e = std::getenv("LR_PERSIST_LAYERS")) prt = std::atoi(e);
+  if (prt < 1) prt = 1;
+  if (prt > m.d_r) prt = m.d_r;
+  while (prt > 1 && ((prt * L + NG - 1) / NG > lrk::kMaxRowsPerThread ||
+                     lrk::persist_lds_bytes(prt, L, M, (m.d_r + prt - 1) / prt) > lrk::kPersistLdsMax))
+    --prt;
+  P = (m.d_r + prt - 1) / prt;
+  while (P > 256 && prt < m.d_r) {  // one cooperative launch must hold the trajectory
+    ++prt;
+    P = (m.d_r + prt - 1) / prt;
+  }
+  rows = ((prt * L + NG - 1) / NG <= 2) ? 2 : 3;
+  lds = lrk::persist_lds_bytes(prt, L, M, P);
+  return (prt * L + NG - 1) / NG <= lrk::kMaxRowsPerThread && lds <= lrk::kPersistLdsMax && P <= 256;
+}
+
+int check_model(const lr_model_t& m, int M, int precision) {
+  if (m.d_q < 2 || m.d_r < 1 || m.d_f < 1) return LR_ERR_ARG;
+  const long long N = (long long)m.d_q * m.d_r * m.d_f;
+  if (N > (1LL << 26)) return LR_ERR_ARG;
+  if (M < 1 || M > LR_MAX_M || M > N) return LR_ERR_ARG;
+  if (precision != LR_FP64) return LR_ERR_ARG;
+  const double vals[] = {m.w_q, m.alpha, m.w_r, m.w_f, m.g, m.G, m.kappa_f, m.gamma_1};
+  for (double x : vals)
+    if (!std::isfinite(x)) return LR_ERR_ARG;
+  if (m.kappa_f < 0.0 || m.gamma_1 < 0.0) return LR_ERR_ARG;
+  return LR_OK;
+}
+
+const void* persist_fn(int rows) {
+  return rows == 2 ? (const void*)lrk::k_persist<2> : (const void*)lrk::k_persist<3>;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lr_batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n) {
+  if (!out || !trajs || n < 1) return LR_ERR_ARG;
+  *out = nullptr;
+  lr_batch* b = new (std::nothrow) lr_batch();
+  if (!b) return LR_ERR_OOM;
+  b->n = n;
+  b->tr.assign(trajs, trajs + n);
+  b->dev.resize(n);
+  b->P.resize(n);
+  b->prt.resize(n);
+  b->rows.resize(n);
+  b->lds.resize(n);
+  b->region.resize(n);
+  b->region_bytes.resize(n);
+  b->wg_offset.resize(n);
+  const size_t a = 256;
+  size_t o = 0;
+  b->off_trajs = o;
+  o = align_up(o + sizeof(TrajDev) * (size_t)n, a);
+  int wg = 0;
+  for (int t = 0; t < n; ++t) {
+    const lr_traj_t& x = b->tr[t];
+    int e = check_model(x.model, x.M, x.precision);
+    if (!e) e = check_pulse(&x.pulse);
+    if (!e && (!x.d_B || !std::isfinite(x.t0) || !(x.dt > 0.0) || !std::isfinite(x.dt) || x.nsteps < 0 ||
+               x.obs_stride < 0 || (x.obs_stride > 0 && !x.d_obs)))
+      e = LR_ERR_ARG;
+    if (!e && !persist_config(x.model, x.M, b->prt[t], b->P[t], b->rows[t], b->lds[t])) e = LR_ERR_ARG;
+    if (e) {
+      delete b;
+      return e;
+    }
+    b->wg_offset[t] = wg;
+    wg += b->P[t];
+  }
+  b->total_wg = wg;
+  b->off_tilemap = o;
+  o = align_up(o + sizeof(int2) * (size_t)wg, a);
+  for (int t = 0; t < n; ++t) {
+    const lr_traj_t& x = b->tr[t];
+    const size_t N = (size_t)x.model.d_q * x.model.d_r * x.model.d_f;
+    const size_t nm = N * x.M * sizeof(double2), npe = 3 * (size_t)x.M * x.M * sizeof(double2);
+    const size_t P = b->P[t];
+    size_t r = 0;
+    r = align_up(r + nm, a);                               // Bb
+    r = align_up(r + 2 * nm, a);                           // SP
+    r = align_up(r + 2 * P * npe, a);                      // PART
+    r = align_up(r + 2 * npe, a);                          // RED
+    r = align_up(r + P * lrk::kFlagStride * 4, a);         // flagA
+    r = align_up(r + P * lrk::kFlagStride * 4, a);         // flagB
+    r = align_up(r + 64, a);                               // step, fail_step, fro2, status, abort
+    b->region[t] = o;
+    b->region_bytes[t] = r;
+    o += r;
+  }
+  b->total = o;
+  *out = b;
+  return LR_OK;
+}
+
+size_t lr_batch_workspace_bytes(const lr_batch_t* b) { return b ? b->total : 0; }
+
+int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
+  if (!b || !d_ws) return LR_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return LR_ERR_ARG;
+  if (bytes < b->total) return LR_ERR_OOM;
+  b->ws = static_cast<char*>(d_ws);
+  b->stream = static_cast<hipStream_t>(stream);
+  const size_t a = 256;
+  std::vector<int2> tmap((size_t)b->total_wg);
+  for (int t = 0; t < b->n; ++t) {
+    const lr_traj_t& x = b->tr[t];
+    const lr_model_t& m = x.model;
+    const size_t N = (size_t)m.d_q * m.d_r * m.d_f;
+    const size_t nm = N * x.M * sizeof(double2), npe = 3 * (size_t)x.M * x.M * sizeof(double2);
+    const size_t P = b->P[t];
+    char* base = b->ws + b->region[t];
+    size_t r = 0;
+    TrajDev& v = b->dev[t];
+    v = TrajDev{};
+    v.d_q = m.d_q; v.d_r = m.d_r; v.d_f = m.d_f; v.M = x.M;
+    v.N = (int)N; v.L = m.d_q * m.d_f; v.ntiles = 0; v.obs_stride = x.obs_stride;
+    v.nsteps = x.nsteps;
+    v.w_q = m.w_q; v.alpha = m.alpha; v.w_r = m.w_r; v.w_f = m.w_f;
+    v.g = m.g; v.G = m.G; v.kappa = m.kappa_f; v.gamma = m.gamma_1;
+    set_pulse(v, &x.pulse);
+    v.t0 = x.t0;
+    v.dt = x.dt;
+    v.Bb = reinterpret_cast<double2*>(base + r);        r = align_up(r + nm, a);
+    v.SP = reinterpret_cast<double2*>(base + r);        r = align_up(r + 2 * nm, a);
+    v.PART = reinterpret_cast<double2*>(base + r);      r = align_up(r + 2 * P * npe, a);
+    v.RED = reinterpret_cast<double2*>(base + r);       r = align_up(r + 2 * npe, a);
+    v.flagA = reinterpret_cast<uint32_t*>(base + r);    r = align_up(r + P * lrk::kFlagStride * 4, a);
+    v.flagB = reinterpret_cast<uint32_t*>(base + r);    r = align_up(r + P * lrk::kFlagStride * 4, a);
+    v.step = reinterpret_cast<int64_t*>(base + r);
+    v.fail_step = reinterpret_cast<int64_t*>(base + r + 8);
+    v.fro2 = reinterpret_cast<double*>(base + r + 16);
+    v.status = reinterpret_cast<int32_t*>(base + r + 24);
+    v.abort_flag = reinterpret_cast<uint32_t*>(base + r + 28);
+    v.obs = x.obs_stride > 0 ? x.d_obs : nullptr;
+    v.P = (int)P;
+    v.rt = b->prt[t];
+    v.npe = 3 * x.M * x.M;
+    for (int w = 0; w < (int)P; ++w) tmap[(size_t)b->wg_offset[t] + w] = make_int2(t, w);
+  }
+  hipError_t e1 = hipMemcpyAsync(b->ws + b->off_trajs, b->dev.data(), sizeof(TrajDev) * (size_t)b->n,
+                                 hipMemcpyHostToDevice, b->stream);
+  hipError_t e2 = hipMemcpyAsync(b->ws + b->off_tilemap, tmap.data(), sizeof(int2) * tmap.size(),
+                                 hipMemcpyHostToDevice, b->stream);
+  hipError_t e3 = hipStreamSynchronize(b->stream);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return LR_ERR_HIP;
+
+  // execution groups of co-resident workgroups
+  int dev_id = 0, ncu = 0;
+  if (hipGetDevice(&dev_id) != hipSuccess) return LR_ERR_HIP;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess) return LR_ERR_HIP;
+  size_t max_lds = 0;
+  for (int t = 0; t < b->n; ++t) max_lds = std::max(max_lds, b->lds[t]);
+  for (int rows = 2; rows <= 3; ++rows)
+    if (hipFuncSetAttribute(persist_fn(rows), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) !=
+        hipSuccess)
+      return LR_ERR_HIP;
+  auto capacity = [&](int rows, size_t lds) -> int {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_fn(rows), lrk::kPW, lds) != hipSuccess)
+      return 0;
+    return per_cu * ncu;
+  };
+  b->groups.clear();
+  int t = 0;
+  while (t < b->n) {
+    lr_batch::Group g{t, t, 0, 2, 0, 0, 0};
+    while (t < b->n) {
+      const int rows = std::max(g.rows, b->rows[t]);
+      const size_t lds = std::max(g.lds, b->lds[t]);
+      const int cap = capacity(rows, lds);
+      if (g.wgs + b->P[t] > cap) {
+        if (g.end == g.begin) return LR_ERR_ARG;  // a single trajectory that cannot be co-resident
+        break;
+      }
+      g.rows = rows;
+      g.lds = lds;
+      g.wgs += b->P[t];
+      g.max_steps = std::max(g.max_steps, b->tr[t].nsteps);
+      const int64_t s = b->tr[t].obs_stride;
+      if (s > 0) g.chunk = g.chunk ? gcd64(g.chunk, s) : s;
+      g.end = ++t;
+    }
+    if (g.chunk == 0) g.chunk = 4096;
+    b->groups.push_back(g);
+  }
+  return LR_OK;
+}
+
+int lr_batch_run(lr_batch_t* b) {
+  if (!b) return LR_ERR_ARG;
+  if (!b->ws) return LR_ERR_STATE;
+  TrajDev* trajs = reinterpret_cast<TrajDev*>(b->ws + b->off_trajs);
+  const int2* tmap = reinterpret_cast<const int2*>(b->ws + b->off_tilemap);
+  hipLaunchKernelGGL(lrk::k_reset, dim3((b->n + 63) / 64), dim3(64), 0, b->stream, trajs, b->n);
+  hipLaunchKernelGGL(lrk::k_reset_persist, dim3(b->n), dim3(256), 0, b->stream, trajs, b->n);
+  for (int t = 0; t < b->n; ++t) {
+    const TrajDev& v = b->dev[t];
+    long long e = (long long)v.N * v.M;
+    const int grid = (int)std::min<long long>((e + lrk::kWG - 1) / lrk::kWG, 4096);
+    hipLaunchKernelGGL(lrk::k_to_internal, dim3(grid), dim3(lrk::kWG), 0, b->stream, trajs, t,
+                       reinterpret_cast<const double2*>(b->tr[t].d_B), v.Bb);
+  }
+  if (hipGetLastError() != hipSuccess) return LR_ERR_HIP;
+  for (const auto& g : b->groups) {
+    const TrajDev* gtr = trajs;
+    const int2* gmap = tmap + b->wg_offset[g.begin];
+    auto launch = [&](int prologue, int64_t step0, int64_t nchunk) -> int {
+      void* args[] = {(void*)&gtr, (void*)&gmap, (void*)&prologue, (void*)&step0, (void*)&nchunk};
+      return hipLaunchCooperativeKernel(persist_fn(g.rows), dim3(g.wgs), dim3(lrk::kPW), args, (unsigned)g.lds,
+                                        b->stream) == hipSuccess
+                 ? LR_OK
+                 : LR_ERR_HIP;
+    };
+    if (int e = launch(1, 0, 0)) return e;
+    hipLaunchKernelGGL(lrk::k_obs, dim3(g.end - g.begin), dim3(lrk::kWG), 0, b->stream, trajs + g.begin,
+                       (double*)nullptr);
+    for (int64_t step = 0; step < g.max_steps;) {
+      const int64_t chunk = std::min(g.chunk, g.max_steps - step);
+      if (int e = launch(0, step, chunk)) return e;
+      step += chunk;
+      hipLaunchKernelGGL(lrk::k_obs, dim3(g.end - g.begin), dim3(lrk::kWG), 0, b->stream, trajs + g.begin,
+                         (double*)nullptr);
+    }
+  }
+  for (int t = 0; t < b->n; ++t) {
+    const TrajDev& v = b->dev[t];
+    long long e = (long long)v.N * v.M;
+    const int grid = (int)std::min<long long>((e + lrk::kWG - 1) / lrk::kWG, 4096);
+    hipLaunchKernelGGL(lrk::k_to_abi, dim3(grid), dim3(lrk::kWG), 0, b->stream, trajs, t, v.Bb,
+                       reinterpret_cast<double2*>(b->tr[t].d_B));
+  }
+  return hipGetLastError() == hipSuccess ? LR_OK : LR_ERR_HIP;
+}
+
+int lr_batch_status(lr_batch_t* b, int32_t* codes, int64_t* failed_steps) {
+  if (!b) return LR_ERR_ARG;
+  if (!b->ws) return LR_ERR_STATE;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return LR_ERR_HIP;
+  int first = LR_OK;
+  for (int t = 0; t < b->n; ++t) {
+    int32_t st = 0;
+    int64_t fs = -1;
+    if (hipMemcpy(&st, b->dev[t].status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return LR_ERR_HIP;
+    if (hipMemcpy(&fs, b->dev[t].fail_step, sizeof(fs), hipMemcpyDeviceToHost) != hipSuccess) return LR_ERR_HIP;
+    if (codes) codes[t] = st;
+    if (failed_steps) failed_steps[t] = fs;
+    if (first == LR_OK && st != LR_OK) first = st;
+  }
+  return first;
+}
+
+void lr_batch_destroy(lr_batch_t* b) { delete b; }
+
+}  // extern "C"

@@ -44,7 +44,29 @@ struct TrajDev {
   int64_t* step;   // device step counter
   int32_t* status; // first device error (0 = none)
   int64_t* fail_step;
+  // persistent (on-chip) path: P workgroups of rt layers each
+  int32_t P, rt;
+  int32_t npe, pad1;    // entries of one Gram/cross partial (3 M^2)
+  double2* SP;          // [2 parity][N*M] published stage states (tile boundary layers)
+  double2* PART;        // [2 parity][P][npe] per-workgroup partials
+  double2* RED;         // [2 parity][npe] reduced G, C_1, C_2
+  uint32_t* flagA;      // [P * kFlagStride] "partials of stage g published" = g + 1
+  uint32_t* flagB;      // [P * kFlagStride] "reduction of stage g done"     = g + 1
+  uint32_t* abort_flag; // set when a bounded wait expires
 };
+
+constexpr int kFlagStride = 32;    // one 128-byte line per flag
+
+// Global-address-space views of descriptor pointers: loads and stores through
+// them compile to global_* instead of flat_* instructions (flat accesses also
+// count against the LDS wait counter and would serialise LDS traffic behind
+// global memory latency).
+typedef __attribute__((address_space(1))) double2 g_double2;
+typedef __attribute__((address_space(1))) double g_double;
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef __attribute__((address_space(1))) int32_t g_i32;
+typedef __attribute__((address_space(1))) int64_t g_i64;
+constexpr uint32_t kSpinLimit = 1u << 20;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -75,7 +97,7 @@ __device__ __forceinline__ double ramp_up(double x, double t_r) {
 }
 
 // Drive coefficient d(t) multiplying (f + f^).
-__device__ inline double drive_at(const TrajDev& T, double t) {
+__device__ __forceinline__ double drive_at(const TrajDev& T, double t) {
   if (T.pkind == 0) {
     return T.amp * ramp_up(t, T.t_ramp) * ramp_up(T.T - t, T.t_ramp) * cos(T.w_d * t);
   }

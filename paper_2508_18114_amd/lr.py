@@ -28,12 +28,15 @@ LR_ERR_GRAM_NOT_PD = -4
 LR_ERR_NONFINITE = -5
 LR_ERR_PULSE = -6
 LR_ERR_STATE = -7
+LR_ERR_TIMEOUT = -8
 LR_MAX_M = 32
 
 # every symbol include/lr.h declares
 EXPORTS = ("lr_init", "lr_workspace_bytes", "lr_bind", "lr_rhs", "lr_integrate",
            "lr_observables", "lr_status", "lr_profile_enable", "lr_profile_read",
-           "lr_strerror", "lr_destroy")
+           "lr_strerror", "lr_destroy",
+           "lr_batch_init", "lr_batch_workspace_bytes", "lr_batch_bind", "lr_batch_run",
+           "lr_batch_status", "lr_batch_destroy")
 
 
 class LrError(RuntimeError):
@@ -58,6 +61,13 @@ class lr_pulse_t(ctypes.Structure):
                 ("p", ctypes.c_double * 6)]
 
 
+class lr_traj_t(ctypes.Structure):
+    _fields_ = [("model", lr_model_t), ("M", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("pulse", lr_pulse_t), ("t0", ctypes.c_double), ("dt", ctypes.c_double),
+                ("nsteps", ctypes.c_int64), ("d_B", ctypes.c_void_p), ("obs_stride", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("d_obs", ctypes.c_void_p)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library {LIB_PATH} is missing: build it with "
@@ -76,6 +86,12 @@ def _load():
         "lr_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64),
                                            ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
         "lr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "lr_batch_init": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lr_traj_t), i32]),
+        "lr_batch_workspace_bytes": (sz, [vp]),
+        "lr_batch_bind": (ctypes.c_int, [vp, vp, sz, vp]),
+        "lr_batch_run": (ctypes.c_int, [vp]),
+        "lr_batch_status": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
+        "lr_batch_destroy": (None, [vp]),
         "lr_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -156,6 +172,39 @@ def lr_destroy(ctx: int) -> None:
     _lib.lr_destroy(ctx)
 
 
+def lr_batch_init(trajs) -> int:
+    """trajs: sequence of lr_traj_t."""
+    arr = (lr_traj_t * len(trajs))(*trajs)
+    h = ctypes.c_void_p()
+    rc = _lib.lr_batch_init(ctypes.byref(h), arr, len(trajs))
+    if rc != LR_OK:
+        raise LrError(rc, "lr_batch_init")
+    return h.value
+
+
+def lr_batch_workspace_bytes(batch: int) -> int:
+    return int(_lib.lr_batch_workspace_bytes(batch))
+
+
+def lr_batch_bind(batch: int, d_ws: int, nbytes: int, stream: int) -> int:
+    return _lib.lr_batch_bind(batch, d_ws, nbytes, stream)
+
+
+def lr_batch_run(batch: int) -> int:
+    return _lib.lr_batch_run(batch)
+
+
+def lr_batch_status(batch: int, n: int):
+    codes = (ctypes.c_int32 * n)()
+    steps = (ctypes.c_int64 * n)()
+    rc = _lib.lr_batch_status(batch, codes, steps)
+    return rc, list(codes), list(steps)
+
+
+def lr_batch_destroy(batch: int) -> None:
+    _lib.lr_batch_destroy(batch)
+
+
 # ---------------------------------------------------------------- helpers
 
 def to_device(B: np.ndarray, device="cuda"):
@@ -215,6 +264,55 @@ class Context:
     def close(self):
         if self.handle:
             lr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def traj_struct(model, M, pulse, t0, dt, nsteps, B_dev, obs_stride=0, obs_dev=None,
+                precision=_inp.FP64) -> lr_traj_t:
+    return lr_traj_t(model_struct(model), M, precision, pulse_struct(pulse), t0, dt, nsteps,
+                     B_dev.data_ptr(), obs_stride, 0, obs_dev.data_ptr() if obs_dev is not None else 0)
+
+
+class Batch:
+    """A batch of trajectories bound to torch-owned workspace on one stream.
+
+    items: sequence of dicts with keys model, M, pulse, dt, nsteps, B (device
+    tensor (M, N) complex128), and optionally t0, obs_stride, obs (device
+    tensor).  The tensors must stay alive while the batch is used.
+    """
+
+    def __init__(self, items, stream=None):
+        import torch
+        self.items = list(items)
+        ts = [traj_struct(it["model"], it["M"], it["pulse"], it.get("t0", 0.0), it["dt"], it["nsteps"],
+                          it["B"], it.get("obs_stride", 0), it.get("obs")) for it in self.items]
+        self.handle = lr_batch_init(ts)
+        nbytes = lr_batch_workspace_bytes(self.handle)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        rc = lr_batch_bind(self.handle, base + off, nbytes, self.stream.cuda_stream)
+        if rc != LR_OK:
+            raise LrError(rc, "lr_batch_bind")
+
+    def run(self):
+        rc = lr_batch_run(self.handle)
+        if rc != LR_OK:
+            raise LrError(rc, "lr_batch_run")
+
+    def status(self):
+        return lr_batch_status(self.handle, len(self.items))
+
+    def close(self):
+        if self.handle:
+            lr_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

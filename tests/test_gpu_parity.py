@@ -238,3 +238,57 @@ def test_deterministic_replay(lr):
     a = _gpu_integrate(lr, tr.model, tr.M, tr.pulse, tr.dt, 500, tr.B0(), 10)
     b = _gpu_integrate(lr, tr.model, tr.M, tr.pulse, tr.dt, 500, tr.B0(), 10)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# ------------------------------------------------------------ batches
+
+def _batch_items(lr, specs):
+    items = []
+    for (dims, M, which, nsteps, stride, pseed) in specs:
+        m = I.readout_model(*dims).replace(kappa_f=0.5, gamma_1=0.02)
+        p = I.draw_piecewise6(I.rng(pseed), nsteps * 1e-3)
+        B0 = I.initial_state(m, M, which, seed=pseed, scale=1e-3)
+        it = dict(model=m, M=M, pulse=p, dt=1e-3, nsteps=nsteps, B0=B0, B=lr.to_device(B0),
+                  obs_stride=stride)
+        if stride:
+            import torch
+            it["obs"] = torch.zeros((nsteps // stride + 1, 6 + dims[0]), dtype=torch.float64, device="cuda")
+        items.append(it)
+    return items
+
+
+BATCH_SPECS = [((4, 10, 5), 4, "g", 120, 10, 1), ((3, 7, 4), 6, "e", 97, 0, 2), ((8, 13, 5), 20, "e", 60, 20, 3),
+               ((2, 5, 3), 1, "g", 150, 25, 4), ((4, 10, 5), 4, "e", 120, 10, 5)]
+
+
+def test_batch_equals_single_runs_bitwise(lr):
+    """Trajectories of different shapes, lengths and strides in one batch give
+    bitwise the states and records of the same trajectories run alone."""
+    items = _batch_items(lr, BATCH_SPECS)
+    b = lr.Batch(items)
+    b.run()
+    rc, codes, _ = b.status()
+    assert rc == lr.LR_OK, codes
+    for it in items:
+        ctx = lr.Context(it["model"], it["M"])
+        Bd = lr.to_device(it["B0"])
+        obs = ctx.new_obs(it["nsteps"], it["obs_stride"]) if it["obs_stride"] else None
+        ctx.integrate(it["pulse"], 0.0, it["dt"], it["nsteps"], Bd, it["obs_stride"], obs)
+        assert ctx.status()[0] == lr.LR_OK
+        assert np.array_equal(lr.from_device(Bd), lr.from_device(it["B"]))
+        if obs is not None:
+            assert np.array_equal(obs.cpu().numpy(), it["obs"].cpu().numpy())
+
+
+def test_batch_matches_oracle(lr):
+    items = _batch_items(lr, BATCH_SPECS[:3])
+    b = lr.Batch(items)
+    b.run()
+    assert b.status()[0] == lr.LR_OK
+    for it in items:
+        Bo, ref = lowrank.integrate(it["model"], it["pulse"], 0.0, it["dt"], it["nsteps"], it["B0"],
+                                    obs_stride=it["obs_stride"])
+        got_B = lr.from_device(it["B"])
+        assert np.max(np.abs(got_B - Bo)) <= 1e-12
+        if it["obs_stride"]:
+            _assert_obs(it["obs"].cpu().numpy(), ref, f"batch dims {it['model'].d_q, it['model'].d_r}")
