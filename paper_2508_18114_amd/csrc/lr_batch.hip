@@ -20,7 +20,7 @@ struct lr_batch {
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   struct Group {
-    int begin, end, wgs, rows;
+    int begin, end, wgs, rows, ge;
     size_t lds;
     int64_t max_steps, chunk;
   };
@@ -72,9 +72,7 @@ int check_model(const lr_model_t& m, int M, int precision) {
   return LR_OK;
 }
 
-const void* persist_fn(int rows) {
-  return rows == 2 ? (const void*)lrk::k_persist<2> : (const void*)lrk::k_persist<3>;
-}
+const void* persist_fn(int rows, int ge) { return lrk::persist_kernel(rows, ge); }
 
 }  // namespace
 
@@ -199,28 +197,31 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
   size_t max_lds = 0;
   for (int t = 0; t < b->n; ++t) max_lds = std::max(max_lds, b->lds[t]);
   for (int rows = 2; rows <= 3; ++rows)
-    if (hipFuncSetAttribute(persist_fn(rows), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) !=
-        hipSuccess)
-      return LR_ERR_HIP;
-  auto capacity = [&](int rows, size_t lds) -> int {
+    for (int ge = 1; ge <= 2; ++ge)
+      if (hipFuncSetAttribute(persist_fn(rows, ge), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) !=
+          hipSuccess)
+        return LR_ERR_HIP;
+  auto capacity = [&](int rows, int ge, size_t lds) -> int {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_fn(rows), lrk::kPW, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_fn(rows, ge), lrk::kPW, lds) != hipSuccess)
       return 0;
     return per_cu * ncu;
   };
   b->groups.clear();
   int t = 0;
   while (t < b->n) {
-    lr_batch::Group g{t, t, 0, 2, 0, 0, 0};
+    lr_batch::Group g{t, t, 0, 2, 1, 0, 0, 0};
     while (t < b->n) {
       const int rows = std::max(g.rows, b->rows[t]);
+      const int ge = std::max(g.ge, lrk::persist_ge(b->tr[t].M));
       const size_t lds = std::max(g.lds, b->lds[t]);
-      const int cap = capacity(rows, lds);
+      const int cap = capacity(rows, ge, lds);
       if (g.wgs + b->P[t] > cap) {
         if (g.end == g.begin) return LR_ERR_ARG;  // a single trajectory that cannot be co-resident
         break;
       }
       g.rows = rows;
+      g.ge = ge;
       g.lds = lds;
       g.wgs += b->P[t];
       g.max_steps = std::max(g.max_steps, b->tr[t].nsteps);
@@ -254,7 +255,7 @@ int lr_batch_run(lr_batch_t* b) {
     const int2* gmap = tmap + b->wg_offset[g.begin];
     auto launch = [&](int prologue, int64_t step0, int64_t nchunk) -> int {
       void* args[] = {(void*)&gtr, (void*)&gmap, (void*)&prologue, (void*)&step0, (void*)&nchunk};
-      return hipLaunchCooperativeKernel(persist_fn(g.rows), dim3(g.wgs), dim3(lrk::kPW), args, (unsigned)g.lds,
+      return hipLaunchCooperativeKernel(persist_fn(g.rows, g.ge), dim3(g.wgs), dim3(lrk::kPW), args, (unsigned)g.lds,
                                         b->stream) == hipSuccess
                  ? LR_OK
                  : LR_ERR_HIP;

@@ -88,6 +88,21 @@ __device__ __forceinline__ double2 cscale(double s, double2 a) {
 __device__ __forceinline__ double2 cfma(double s, double2 a, double2 acc) {
   return make_double2(fma(s, a.x, acc.x), fma(s, a.y, acc.y));
 }
+// acc + a * b and acc + conj(a) * b as four fused multiply-adds
+__device__ __forceinline__ double2 cmac(double2 acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+__device__ __forceinline__ double2 cjmac(double2 acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+  return acc;
+}
 
 // Cosine ramp r(x) of the flat-top window.
 __device__ __forceinline__ double ramp_up(double x, double t_r) {

@@ -35,9 +35,9 @@ constexpr size_t kPersistLdsMax = 159 * 1024;  // dynamic LDS (160 KB less the s
 
 // Dynamic LDS bytes of k_persist for rt layers of L rows at rank M and P
 // workgroups: stage input with halos, W, slice-reduction buffer, pivot
-// row/column (double buffered), per-row jump coefficients.
+// row/column (double buffered), per-row jump coefficients, square-root table.
 __host__ __device__ inline size_t persist_lds_bytes(int rt, int L, int M, int P) {
-  return (size_t)((rt + 2) * L * M + 2 * M * M + 3 * M * M + P + 2 * 4 * M) * 16 + (size_t)2 * rt * L * 8;
+  return (size_t)((rt + 2) * L * M + 2 * M * M + 3 * M * M + P + 8 * M) * 16 + (size_t)(2 * rt * L + L + rt + 1) * 8;
 }
 
 // agent-coherent 16-byte store / load (two 64-bit atomic accesses)
@@ -103,45 +103,66 @@ __device__ __forceinline__ void publish_boundary(const double2* tile, g_double2*
   }
 }
 
+// v + (v of lane l ^ 32): the two halves of a wave; both lanes get the same
+// bits (the sum is commutative)
+__device__ __forceinline__ double2 add_wave_halves(double2 v) {
+  return make_double2(v.x + __shfl_xor(v.x, 32), v.y + __shfl_xor(v.y, 32));
+}
+
 // Gram / cross partials of the tile (rows x M in LDS) -> dst[3 M^2]:
 //   G[i][j]   = sum_rho conj(O[rho][i]) O[rho][j]
 //   C_1[i][j] = sum_rho conj(O[rho][i]) sqrt(kappa (f+1)) O[rho+1][j]      (f+1 < d_f)
 //   C_2[i][j] = sum_rho conj(O[rho][i]) sqrt(gamma (q+1)) O[rho+d_f][j]    (q+1 < d_q)
 // c1row / c2row hold those coefficients per row and 0 where the jump leaves
 // the mode (the row read there is a finite neighbour in the tile or halo).
-// With PAIR, rows are taken in pairs with separate accumulators (fixed
-// order either way).
-template <bool PAIR>
+// Lanes l and l + 32 of a wave own the entries (i0, j), (i0 + 1, j) of all
+// three matrices; each sums one half of the rows (in order) and the halves
+// are added across the wave.  Consecutive lanes of a half take consecutive
+// j, so the row reads of a half are bank-conflict free.  Every lane of the
+// block takes the same number of passes, so both partners are always present.
 __device__ __forceinline__ void persist_partials(const TrajDev& T, const double2* tile, int R, const double* c1row,
                                                  const double* c2row, g_double2* dst) {
   const int M = T.M, MM = M * M, d_f = T.d_f;
-  for (int o = threadIdx.x; o < MM; o += kPW) {
-    const int i = o / M, jj = o - i * M;
-    double2 g0 = make_double2(0.0, 0.0), a10 = g0, a20 = g0, g1 = g0, a11 = g0, a21 = g0;
-    int rl = 0;
-    if (PAIR)
-    for (; rl + 2 <= R; rl += 2) {
-      const double2 oi0 = tile[rl * M + i], oi1 = tile[(rl + 1) * M + i];
-      const double2 oj0 = tile[rl * M + jj], oj1 = tile[(rl + 1) * M + jj];
-      const double2 f0 = tile[(rl + 1) * M + jj], f1 = tile[(rl + 2) * M + jj];
-      const double2 q0 = tile[(rl + d_f) * M + jj], q1 = tile[(rl + 1 + d_f) * M + jj];
-      const double c10 = c1row[rl], c11 = c1row[rl + 1], c20 = c2row[rl], c21 = c2row[rl + 1];
-      g0 = cadd(g0, cconjmul(oi0, oj0));
-      g1 = cadd(g1, cconjmul(oi1, oj1));
-      a10 = cfma(c10, cconjmul(oi0, f0), a10);
-      a11 = cfma(c11, cconjmul(oi1, f1), a11);
-      a20 = cfma(c20, cconjmul(oi0, q0), a20);
-      a21 = cfma(c21, cconjmul(oi1, q1), a21);
+  const int nu = ((M + 1) >> 1) * M;   // (i pair, j) units
+  const int Rh = (R + 1) >> 1;
+  const int lane = threadIdx.x & 63, h = lane >> 5;
+  for (int u0 = 0; u0 < nu; u0 += kPW / 2) {
+    const int uu = u0 + (int)(threadIdx.x >> 6) * 32 + (lane & 31);
+    const bool valid = uu < nu;
+    const int u = valid ? uu : 0;
+    const int ip = u / M, j = u - ip * M;
+    const int i0 = 2 * ip, i1 = min(i0 + 1, M - 1);
+    const int ra = h ? Rh : 0, rb = h ? R : Rh;
+    double2 g0 = make_double2(0.0, 0.0), g1 = g0, a0 = g0, a1 = g0, b0 = g0, b1 = g0;
+    for (int r = ra; r < rb; ++r) {
+      const double2* row = tile + r * M;
+      const double2 x0 = row[i0], x1 = row[i1], y = row[j];
+      const double2 yf = cscale(c1row[r], row[M + j]);
+      const double2 yq = cscale(c2row[r], row[d_f * M + j]);
+      g0 = cjmac(g0, x0, y);
+      g1 = cjmac(g1, x1, y);
+      a0 = cjmac(a0, x0, yf);
+      a1 = cjmac(a1, x1, yf);
+      b0 = cjmac(b0, x0, yq);
+      b1 = cjmac(b1, x1, yq);
     }
-    for (; rl < R; ++rl) {
-      const double2 oi0 = tile[rl * M + i];
-      g0 = cadd(g0, cconjmul(oi0, tile[rl * M + jj]));
-      a10 = cfma(c1row[rl], cconjmul(oi0, tile[(rl + 1) * M + jj]), a10);
-      a20 = cfma(c2row[rl], cconjmul(oi0, tile[(rl + d_f) * M + jj]), a20);
+    g0 = add_wave_halves(g0);
+    g1 = add_wave_halves(g1);
+    a0 = add_wave_halves(a0);
+    a1 = add_wave_halves(a1);
+    b0 = add_wave_halves(b0);
+    b1 = add_wave_halves(b1);
+    if (valid && h == 0) {
+      const int o0 = i0 * M + j;
+      st_ag(dst + o0, g0);
+      st_ag(dst + MM + o0, a0);
+      st_ag(dst + 2 * MM + o0, b0);
+      if (i0 + 1 < M) {
+        st_ag(dst + o0 + M, g1);
+        st_ag(dst + MM + o0 + M, a1);
+        st_ag(dst + 2 * MM + o0 + M, b1);
+      }
     }
-    st_ag(dst + o, cadd(g0, g1));
-    st_ag(dst + MM + o, cadd(a10, a11));
-    st_ag(dst + 2 * MM + o, cadd(a20, a21));
   }
 }
 
@@ -157,111 +178,145 @@ __device__ __forceinline__ double pivot_rcp(double p) {
 // W_k = X_k^ with X_k = G^-1 C_k (G Hermitian positive definite), in two
 // parallel phases:
 //   1. in-place Gauss-Jordan inversion of G without pivoting: M pivot steps,
-//      each a rank-1 update of every entry from the pivot row and column (one
-//      barrier per pivot).  Its pivots are those of the Cholesky factorisation
-//      G = L D L^ (D_k > 0 iff G is positive definite); a non-positive pivot
-//      is reported like a failed Cholesky.
+//      each taking every entry off the pivot row and column to
+//      x - G[i][k] G[k][j] / p, the pivot row to x / p, the pivot column to
+//      -x / p and the pivot to 1 / p (one barrier per pivot; every thread
+//      owns at most GE entries).  Its pivots are those of the Cholesky
+//      factorisation G = L D L^ (D_k > 0 iff G is positive definite); a
+//      non-positive pivot is reported like a failed Cholesky.  The pivot is
+//      taken as the real part of the diagonal entry and its inverse stored
+//      exactly real (G is Hermitian; any imaginary part is rounding).
 //   2. W_k[i][j] = sum_l conj(C_k[l][i]) (G^-1)[l][j]  (= (G^-1 C_k)^ since
 //      G^-1 is Hermitian), every entry independent.
-// G entries live in registers (thread t owns flat entries t, t + kPW);
-// C_k and G^-1 go through LDS.  solve_load issues the loads of the reduced
-// G, C_k so that their latency overlaps other work; solve_run finishes.
-constexpr int kGE = 2;  // ceil(M^2 / kPW) for M <= 32
-constexpr int kCE = 4;  // ceil(2 M^2 / kPW)
+// G entries live in registers (thread t owns flat entries t + u kPW); C_k and
+// G^-1 go through LDS.  solve_load issues the loads of the reduced G, C_k so
+// that their latency overlaps other work; solve_run finishes.
 
+// GE = entries of G and of C_1, C_2 per thread: 1 for M^2 <= 512, 2 for
+// M^2 <= 1024.
+template <int GE>
 struct SolveRegs {
-  double2 g[kGE];
-  double2 c[kCE];
+  double2 g[GE];
+  double2 c[2 * GE];
 };
 
-__device__ __forceinline__ void solve_load(const g_double2* red, int M, SolveRegs& S) {
+template <int GE>
+__device__ __forceinline__ void solve_load(const g_double2* red, int M, SolveRegs<GE>& S) {
   const int MM = M * M;
 #pragma unroll
-  for (int u = 0; u < kGE; ++u) S.g[u] = ld_ag(red + min((int)threadIdx.x + u * kPW, MM - 1));
+  for (int u = 0; u < GE; ++u) S.g[u] = ld_ag(red + min((int)threadIdx.x + u * kPW, MM - 1));
 #pragma unroll
-  for (int u = 0; u < kCE; ++u) S.c[u] = ld_ag(red + MM + min((int)threadIdx.x + u * kPW, 2 * MM - 1));
+  for (int u = 0; u < 2 * GE; ++u) S.c[u] = ld_ag(red + MM + min((int)threadIdx.x + u * kPW, 2 * MM - 1));
 }
 
-// Cs (2 M^2) and Gi (M^2) are LDS scratch; prow, pcol hold 2 x M each.
-// Writes W_k to Wl.  Returns -1, the first non-positive pivot, or -2 for a
-// non-finite input.
-__device__ __forceinline__ int solve_run(SolveRegs& S, double2* prow, double2* pcol, double2* Cs, double2* Gi,
-                                         double2* Wl, int M, int* nonfinite_flag) {
+// Cs (2 M^2) and Gi (M^2) are LDS scratch; prow and pcol hold 2 x M entries.  nonfinite_flag is an LDS word that the caller zeroed before
+// a barrier that precedes this call; bad_flag is LDS scratch.  Writes W_k to
+// Wl.  Returns -1, the first non-positive pivot, or -2 for a non-finite
+// input.  LB = l values per batch of loads in the W product (register
+// budget).
+template <int GE, int LB>
+__device__ __forceinline__ int solve_run(SolveRegs<GE>& S, double2* prow, double2* pcol, double2* Cs, double2* Gi,
+                                         double2* Wl, int M, int* nonfinite_flag, int* bad_flag) {
   const int MM = M * M;
   const int tid = threadIdx.x;
   int bad_local = 0;
 #pragma unroll
-  for (int u = 0; u < kGE; ++u)
+  for (int u = 0; u < GE; ++u)
     if (tid + u * kPW < MM && (!isfinite(S.g[u].x) || !isfinite(S.g[u].y))) bad_local = 1;
 #pragma unroll
-  for (int u = 0; u < kCE; ++u) {
+  for (int u = 0; u < 2 * GE; ++u) {
     const int o = tid + u * kPW;
     if (o < 2 * MM) {
       if (!isfinite(S.c[u].x) || !isfinite(S.c[u].y)) bad_local = 1;
       Cs[o] = S.c[u];
     }
   }
-  if (tid == 0) *nonfinite_flag = 0;
-  __syncthreads();
-  if (bad_local) *nonfinite_flag = 1;
-  __syncthreads();
-  if (*nonfinite_flag) return -2;
+  if (bad_local) *nonfinite_flag = 1;  // seen after the first pivot barrier
 
-  int gi[kGE], gj[kGE];
+  int gi[GE], gj[GE];
+  bool own[GE];
 #pragma unroll
-  for (int u = 0; u < kGE; ++u) {
-    const int o = min(tid + u * kPW, MM - 1);
-    gi[u] = o / M;
-    gj[u] = o - gi[u] * M;
+  for (int u = 0; u < GE; ++u) {
+    const int o = tid + u * kPW;
+    own[u] = o < MM;
+    const int oc = min(o, MM - 1);
+    gi[u] = oc / M;
+    gj[u] = oc - gi[u] * M;
   }
-  const int nu = (MM + kPW - 1) / kPW;
+  int bad = -1;
   for (int k = 0; k < M; ++k) {
-    double2* pr = prow + (k & 1) * M;
-    double2* pc = pcol + (k & 1) * M;
+    double2* pr = prow + (k & 1) * M;  // row k of the current matrix
+    double2* pc = pcol + (k & 1) * M;  // column k
 #pragma unroll
-    for (int u = 0; u < kGE; ++u) {
-      if (u < nu && tid + u * kPW < MM) {
+    for (int u = 0; u < GE; ++u) {
+      if (own[u]) {
         if (gi[u] == k) pr[gj[u]] = S.g[u];
         if (gj[u] == k) pc[gi[u]] = S.g[u];
       }
     }
     __syncthreads();
+    // pivot, pivot column and pivot row entries read together
     const double piv = pr[k].x;
-    if (!(piv > 0.0)) return k;  // uniform: every thread read the same pivot
-    const double inv = pivot_rcp(piv);
+    double2 a[GE], b[GE];
 #pragma unroll
-    for (int u = 0; u < kGE; ++u) {
-      if (u < nu) {
-        const double2 a = pc[gi[u]], bkj = pr[gj[u]];
-        const bool ri = gi[u] == k, cj = gj[u] == k;
-        double2 v;
-        if (ri && cj) v = make_double2(inv, 0.0);
-        else if (ri) v = cscale(inv, S.g[u]);
-        else if (cj) v = cscale(-inv, S.g[u]);
-        else {
-          const double2 t = cscale(inv, cmul(a, bkj));
-          v = make_double2(S.g[u].x - t.x, S.g[u].y - t.y);
-        }
-        S.g[u] = v;
-      }
+    for (int u = 0; u < GE; ++u) {
+      a[u] = pc[gi[u]];
+      b[u] = pr[gj[u]];
+    }
+    const bool pos = piv > 0.0;  // uniform: every thread read the same pivot
+    if (!pos && bad < 0) bad = k;
+    const double inv = pivot_rcp(pos ? piv : 1.0);
+#pragma unroll
+    for (int u = 0; u < GE; ++u) {
+      const bool ri = gi[u] == k, cj = gj[u] == k;
+      const double2 x = S.g[u];
+      const double2 t = cmul(a[u], b[u]);
+      double2 v = make_double2(fma(-inv, t.x, x.x), fma(-inv, t.y, x.y));
+      const double sc = cj ? -inv : inv;
+      v = (ri || cj) ? make_double2(sc * x.x, sc * x.y) : v;
+      v = (ri && cj) ? make_double2(inv, 0.0) : v;
+      S.g[u] = v;
     }
   }
 #pragma unroll
-  for (int u = 0; u < kGE; ++u)
-    if (tid + u * kPW < MM) Gi[tid + u * kPW] = S.g[u];
+  for (int u = 0; u < GE; ++u)
+    if (own[u]) Gi[tid + u * kPW] = S.g[u];
+  if (tid == 0) *bad_flag = bad;
   __syncthreads();
-  // W_k[i][j] = sum_l conj(C_k[l][i]) Gi[l][j]
-  for (int o = tid; o < 2 * MM; o += kPW) {
-    const int kk = o / MM, ij = o - kk * MM, i = ij / M, j = ij - i * M;
-    const double2* C = Cs + kk * MM;
-    double2 s0 = make_double2(0.0, 0.0), s1 = s0;
+  if (*nonfinite_flag) return -2;
+  if (*bad_flag >= 0) return *bad_flag;
+  // W_k[i][j] = sum_l conj(C_k[l][i]) Gi[l][j]; the entry (i, j) of both
+  // jumps per thread, LB l per batch of loads, two accumulators each
+  for (int o = tid; o < MM; o += kPW) {
+    const int i = o / M, j = o - i * M;
+    const double2* C1 = Cs + i;
+    const double2* C2 = Cs + MM + i;
+    const double2* Gc = Gi + j;
+    double2 w1a = make_double2(0.0, 0.0), w1b = w1a, w2a = w1a, w2b = w1a;
     int l = 0;
-    for (; l + 2 <= M; l += 2) {
-      s0 = cadd(s0, cconjmul(C[l * M + i], Gi[l * M + j]));
-      s1 = cadd(s1, cconjmul(C[(l + 1) * M + i], Gi[(l + 1) * M + j]));
+    for (; l + LB <= M; l += LB) {
+      double2 g[LB], c1[LB], c2[LB];
+#pragma unroll
+      for (int v = 0; v < LB; ++v) {
+        g[v] = Gc[(l + v) * M];
+        c1[v] = C1[(l + v) * M];
+        c2[v] = C2[(l + v) * M];
+      }
+#pragma unroll
+      for (int v = 0; v < LB; v += 2) {
+        w1a = cjmac(w1a, c1[v], g[v]);
+        w2a = cjmac(w2a, c2[v], g[v]);
+        w1b = cjmac(w1b, c1[v + 1], g[v + 1]);
+        w2b = cjmac(w2b, c2[v + 1], g[v + 1]);
+      }
     }
-    if (l < M) s0 = cadd(s0, cconjmul(C[l * M + i], Gi[l * M + j]));
-    Wl[o] = cadd(s0, s1);
+    for (; l < M; ++l) {
+      const double2 g = Gc[l * M];
+      w1a = cjmac(w1a, C1[l * M], g);
+      w2a = cjmac(w2a, C2[l * M], g);
+    }
+    Wl[o] = cadd(w1a, w1b);
+    Wl[MM + o] = cadd(w2a, w2b);
   }
   __syncthreads();
   return -1;
@@ -283,14 +338,16 @@ __device__ __forceinline__ double gram_fro2(const g_double2* red, int MM, double
   return tot;
 }
 
-template <int ROWS>
+template <int ROWS, int GE>
 __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ trajs,
                                                  const int2* __restrict__ tilemap, int prologue, int64_t step0,
                                                  int64_t nchunk) {
   extern __shared__ double2 lds[];
   __shared__ int s_ok;
   __shared__ int s_nonfinite;
+  __shared__ int s_bad;
   __shared__ double s_part[kPW / 64];
+  __shared__ double s_drv[2];
 
   const int2 tm = tilemap[blockIdx.x];
   const TrajDev& T = trajs[tm.x];
@@ -309,11 +366,14 @@ __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ tra
   double2* SL = lds;                              // (rt + 2) L M: [halo | tile | halo]
   double2* tile = SL + LM;
   double2* Wl = SL + (size_t)(rt + 2) * LM;       // 2 M^2
-  double2* RB = Wl + 2 * MM;                      // 3 M^2 + P   (slice reduction)
-  double2* prow = RB + 3 * MM + P;                // 2 x 3M
-  double2* pcol = prow + 6 * M;                   // 2 x M
-  double* c1row = reinterpret_cast<double*>(pcol + 2 * M);
+  double2* RB = Wl + 2 * MM;                      // 3 M^2 + P: slice reduction; C_k, G^-1 in the solve
+  double2* prow = RB + 3 * MM + P;                // 2 x M
+  double2* pcol = prow + 4 * M;                   // 2 x M
+  double* c1row = reinterpret_cast<double*>(pcol + 4 * M);
   double* c2row = c1row + rt * L;
+  double* sqt = c2row + rt * L;                   // sqrt(n), n < nq; then sqrt(r0 + k), k <= rt
+  const int nq = max(d_q, d_f);
+  const double* sqr = sqt + nq;
 
   // halo layers start at zero: the jump partials read one neighbour row past
   // the tile edge with a zero coefficient
@@ -323,6 +383,7 @@ __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ tra
     c1row[rl] = f + 1 < d_f ? sqrt(T.kappa * (double)(f + 1)) : 0.0;
     c2row[rl] = q + 1 < d_q ? sqrt(T.gamma * (double)(q + 1)) : 0.0;
   }
+  for (int n = tid; n < nq + rt + 1; n += kPW) sqt[n] = sqrt((double)(n < nq ? n : r0 + (n - nq)));
 
   // element mapping: column j, rows rg, rg + NG, ...
   const int NG = kPW / M;
@@ -330,9 +391,14 @@ __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ tra
   const bool active = rg < NG;
 
   double2 base[ROWS], acc[ROWS], o_new[ROWS];
+  int rq[ROWS], rf[ROWS], rr[ROWS];  // mode indices (q, f, r - r0) of the thread's rows
 #pragma unroll
   for (int k = 0; k < ROWS; ++k) {
     const int rl = rg + k * NG;
+    const int lr = rl / L, rem = rl - lr * L;
+    rq[k] = rem / d_f;
+    rf[k] = rem - rq[k] * d_f;
+    rr[k] = lr;
     base[k] = make_double2(0.0, 0.0);
     acc[k] = base[k];
     o_new[k] = base[k];
@@ -350,30 +416,39 @@ __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ tra
   const int e0 = w * cs, e1 = min(npe, e0 + cs), ne = max(0, e1 - e0);
 
   // slice reduction of the partials of parity `par`: all loads in flight at
-  // once into LDS, then a fixed-order sum over the workgroups per entry
+  // once into LDS; then each entry is summed by a 16-lane group (lane l adds
+  // workgroups l, l + 16, ... in order, then a butterfly over the group), so
+  // the order depends on P only
   auto reduce_slice = [&](int par) {
     const g_double2* src = PARTg + (size_t)par * P * npe;
     const int nit = ne * P;
-    for (int base_it = 0; base_it < nit; base_it += 4 * kPW) {
-      double2 v[4];
+    for (int base_it = 0; base_it < nit; base_it += 8 * kPW) {
+      double2 v[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         const int it = min(base_it + tid + u * kPW, nit - 1);
         const int pp = it / ne, e = it - pp * ne;
         v[u] = ld_ag(src + (size_t)pp * npe + e0 + e);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         const int it = base_it + tid + u * kPW;
         if (it < nit) RB[it] = v[u];
       }
     }
     __syncthreads();
     g_double2* dst = REDg + (size_t)par * npe + e0;
-    for (int e = tid; e < ne; e += kPW) {
-      double2 s = make_double2(0.0, 0.0);
-      for (int pp = 0; pp < P; ++pp) s = cadd(s, RB[pp * ne + e]);
-      st_ag(dst + e, s);
+    const int sub = tid & 15, grp = tid >> 4;
+    for (int eb = 0; eb < ne; eb += kPW / 16) {
+      const int e = eb + grp, ec = min(e, ne - 1);
+      double2 sum = make_double2(0.0, 0.0);
+      for (int pp = sub; pp < P; pp += 16) sum = cadd(sum, RB[pp * ne + ec]);
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) {
+        sum.x += __shfl_xor(sum.x, off, 16);
+        sum.y += __shfl_xor(sum.y, off, 16);
+      }
+      if (sub == 0 && e < ne) st_ag(dst + e, sum);
     }
   };
   auto load_halo = [&](int par) {
@@ -408,7 +483,7 @@ __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ tra
     const int64_t g = 4 * step0;
     const int p = (int)(g & 1);
     __syncthreads();
-    persist_partials<ROWS == 2>(T, tile, R, c1row, c2row, PARTg + ((size_t)p * P + w) * npe);
+    persist_partials(T, tile, R, c1row, c2row, PARTg + ((size_t)p * P + w) * npe);
     publish_boundary(tile, SPg + (size_t)p * NMn, row0, R, L, M);
     flag_arrive(myA, (uint32_t)(g + 1));
     bool ok = flag_wait(T, flagA, (uint32_t)(g + 1), &s_ok);
@@ -435,6 +510,12 @@ __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ tra
   // of its input are in global memory
   load_halo((int)((4 * step0) & 1));
   const double dt = T.dt;
+  // time of stage s of step n: t_n + c_s dt with c = 0, 1/2, 1/2, 1
+  auto stage_time = [&](int64_t step, int s) {
+    const double c = (s == 0) ? 0.0 : (s == 3 ? 1.0 : 0.5);
+    return T.t0 + (double)step * dt + c * dt;
+  };
+  if (tid == 0) s_drv[0] = drive_at(T, stage_time(step0, 0));
   const int64_t nrun = max((int64_t)0, min(nchunk, T.nsteps - step0));  // trajectories of a batch end apart
   bool ok = true;
   bool failed = false;
@@ -444,13 +525,12 @@ __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ tra
     for (int s = 0; s < 4; ++s) {
       const int64_t g = 4 * step + s;
       const int p = (int)(g & 1);
-      const double cs_ = (s == 0) ? 0.0 : (s == 3 ? 1.0 : 0.5);
-      const double t = T.t0 + (double)step * dt + cs_ * dt;
-      const double drv = drive_at(T, t);
-      __syncthreads();  // stage input tile and halo in LDS
+      if (tid == 0) s_nonfinite = 0;
+      __syncthreads();  // stage input tile and halo, drive value in LDS
+      const double drv = s_drv[s & 1];
 
       // (1) loads of the reduced G, C_k in flight while Z = H_eff(t) S is formed
-      SolveRegs SR;
+      SolveRegs<GE> SR;
       solve_load(REDg + (size_t)p * npe, M, SR);
       double2 z[ROWS];
 #pragma unroll
@@ -458,40 +538,45 @@ __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ tra
         const int rl = rg + k * NG;
         z[k] = make_double2(0.0, 0.0);
         if (active && rl < R) {
-          const int rho = row0 + rl;
-          const int r = rho / L, rem = rho - r * L, q = rem / d_f, f = rem - q * d_f;
+          // opaque per stage: values derived from the row indices are formed
+          // here rather than held in registers across the whole chunk
+          int q = rq[k], f = rf[k], rk = rr[k];
+          asm volatile("" : "+v"(q), "+v"(f), "+v"(rk));
+          const int r = r0 + rk;
           const double2* col = tile + j;  // row offsets relative to the tile (halo at -L, +R)
           const double2 b = col[rl * M];
           const double hr = T.w_q * q + 0.5 * T.alpha * q * (q - 1) + T.w_r * r + T.w_f * f;
           const double hi = -0.5 * (T.kappa * f + T.gamma * q);
+          // sqrt(max(n, n +- 1)) of each mode: sqrt(n) downwards, sqrt(n + 1) upwards
+          const double sq0 = sqt[q], sq1 = sqt[min(q + 1, nq - 1)];
+          const double sf0 = sqt[f], sf1 = sqt[min(f + 1, nq - 1)];
+          const double sr0 = sqr[rk], sr1 = sqr[rk + 1];
+          const bool rlo = r > 0, rhi = r + 1 < d_r;
           double2 zz = cmul(make_double2(hr, hi), b);
-          for (int dq = -1; dq <= 1; dq += 2) {
-            const int qq = q + dq;
-            if (qq < 0 || qq >= d_q) continue;
-            const double cq = sqrt((double)max(q, qq));
-            for (int dr = -1; dr <= 1; dr += 2) {
-              const int rr = r + dr;
-              if (rr < 0 || rr >= d_r) continue;
-              zz = cfma(T.g * cq * sqrt((double)max(r, rr)), col[(rl + dq * d_f + dr * L) * M], zz);
-            }
+          if (q > 0) {
+            if (rlo) zz = cfma(T.g * sq0 * sr0, col[(rl - d_f - L) * M], zz);
+            if (rhi) zz = cfma(T.g * sq0 * sr1, col[(rl - d_f + L) * M], zz);
           }
-          for (int df = -1; df <= 1; df += 2) {
-            const int ff = f + df;
-            if (ff < 0 || ff >= d_f) continue;
-            const double cf = sqrt((double)max(f, ff));
-            for (int dr = -1; dr <= 1; dr += 2) {
-              const int rr = r + dr;
-              if (rr < 0 || rr >= d_r) continue;
-              zz = cfma(T.G * cf * sqrt((double)max(r, rr)), col[(rl + dr * L + df) * M], zz);
-            }
-            zz = cfma(drv * cf, col[(rl + df) * M], zz);
+          if (q + 1 < d_q) {
+            if (rlo) zz = cfma(T.g * sq1 * sr0, col[(rl + d_f - L) * M], zz);
+            if (rhi) zz = cfma(T.g * sq1 * sr1, col[(rl + d_f + L) * M], zz);
+          }
+          if (f > 0) {
+            if (rlo) zz = cfma(T.G * sf0 * sr0, col[(rl - L - 1) * M], zz);
+            if (rhi) zz = cfma(T.G * sf0 * sr1, col[(rl + L - 1) * M], zz);
+            zz = cfma(drv * sf0, col[(rl - 1) * M], zz);
+          }
+          if (f + 1 < d_f) {
+            if (rlo) zz = cfma(T.G * sf1 * sr0, col[(rl - L + 1) * M], zz);
+            if (rhi) zz = cfma(T.G * sf1 * sr1, col[(rl + L + 1) * M], zz);
+            zz = cfma(drv * sf1, col[(rl + 1) * M], zz);
           }
           z[k] = zz;
         }
       }
       // (2) W_k of this stage input
       {
-        const int bad = solve_run(SR, prow, pcol, RB, RB + 2 * MM, Wl, M, &s_nonfinite);
+        const int bad = solve_run<GE, ROWS == 2 ? 4 : 2>(SR, prow, pcol, RB, RB + 2 * MM, Wl, M, &s_nonfinite, &s_bad);
         if (bad != -1) {
           if (tid == 0) report(T, bad == -2 ? -5 /* LR_ERR_NONFINITE */ : -4 /* LR_ERR_GRAM_NOT_PD */, step);
           failed = true;
@@ -499,50 +584,65 @@ __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ tra
         }
       }
 
-      // (3) k = -i Z + 1/2 sum_k (L_k S) W_k ; RK4 stage update
+      // (3) k = -i Z + 1/2 sum_k (L_k S) W_k ; RK4 stage update.  The jump
+      // term of a row is c1 (S W_1)[rho+1, j] + c2 (S W_2)[rho+d_f, j] (the
+      // coefficient is 0 where the jump leaves the mode); the W entries of
+      // column j are loaded once for all rows of the thread.
+      {
+        const double2* y1[ROWS];
+        const double2* y2[ROWS];
+        double2 s1[ROWS], s2[ROWS];
 #pragma unroll
-      for (int k = 0; k < ROWS; ++k) {
-        const int rl = rg + k * NG;
-        if (active && rl < R) {
-          const double2 zz = z[k];
-          // jump assembly: c1 (S W_1)[rho+1, j] + c2 (S W_2)[rho+d_f, j]; the
-          // coefficient is 0 where the jump leaves the mode
-          const double2* y1 = tile + (rl + 1) * M;
-          const double2* y2 = tile + (rl + d_f) * M;
-          const double2* W1 = Wl + j;
-          const double2* W2 = Wl + MM + j;
-          double2 s1a = make_double2(0.0, 0.0), s1b = s1a, s2a = s1a, s2b = s1a;
-          int i = 0;
-          // two accumulator pairs where registers allow (three rows per thread
-          // would spill)
-          if (ROWS == 2)
+        for (int k = 0; k < ROWS; ++k) {
+          const int rl = min(rg + k * NG, R - 1);  // rows past the tile read a valid row, unused
+          y1[k] = tile + (rl + 1) * M;
+          y2[k] = tile + (rl + d_f) * M;
+          s1[k] = make_double2(0.0, 0.0);
+          s2[k] = s1[k];
+        }
+        const double2* W1 = Wl + j;
+        const double2* W2 = Wl + MM + j;
+        int i = 0;
+        if (ROWS == 2)
           for (; i + 2 <= M; i += 2) {
-            s1a = cadd(s1a, cmul(y1[i], W1[i * M]));
-            s1b = cadd(s1b, cmul(y1[i + 1], W1[(i + 1) * M]));
-            s2a = cadd(s2a, cmul(y2[i], W2[i * M]));
-            s2b = cadd(s2b, cmul(y2[i + 1], W2[(i + 1) * M]));
+            const double2 w1a = W1[i * M], w1b = W1[(i + 1) * M], w2a = W2[i * M], w2b = W2[(i + 1) * M];
+#pragma unroll
+            for (int k = 0; k < ROWS; ++k) {
+              s1[k] = cmac(cmac(s1[k], y1[k][i], w1a), y1[k][i + 1], w1b);
+              s2[k] = cmac(cmac(s2[k], y2[k][i], w2a), y2[k][i + 1], w2b);
+            }
           }
-          for (; i < M; ++i) {
-            s1a = cadd(s1a, cmul(y1[i], W1[i * M]));
-            s2a = cadd(s2a, cmul(y2[i], W2[i * M]));
+        for (; i < M; ++i) {
+          const double2 w1a = W1[i * M], w2a = W2[i * M];
+#pragma unroll
+          for (int k = 0; k < ROWS; ++k) {
+            s1[k] = cmac(s1[k], y1[k][i], w1a);
+            s2[k] = cmac(s2[k], y2[k][i], w2a);
           }
-          const double2 a = cfma(c2row[rl], cadd(s2a, s2b), cscale(c1row[rl], cadd(s1a, s1b)));
-          const double2 kk = make_double2(zz.y + 0.5 * a.x, -zz.x + 0.5 * a.y);
-          double2 o;
-          if (s == 0) {
-            acc[k] = kk;
-            o = cfma(0.5 * dt, kk, base[k]);
-          } else if (s == 1) {
-            acc[k] = cfma(2.0, kk, acc[k]);
-            o = cfma(0.5 * dt, kk, base[k]);
-          } else if (s == 2) {
-            acc[k] = cfma(2.0, kk, acc[k]);
-            o = cfma(dt, kk, base[k]);
-          } else {
-            base[k] = cfma(dt / 6.0, cadd(acc[k], kk), base[k]);
-            o = base[k];
+        }
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k) {
+          const int rl = rg + k * NG;
+          if (active && rl < R) {
+            const double2 zz = z[k];
+            const double2 a = cfma(c2row[rl], s2[k], cscale(c1row[rl], s1[k]));
+            const double2 kk = make_double2(zz.y + 0.5 * a.x, -zz.x + 0.5 * a.y);
+            double2 o;
+            if (s == 0) {
+              acc[k] = kk;
+              o = cfma(0.5 * dt, kk, base[k]);
+            } else if (s == 1) {
+              acc[k] = cfma(2.0, kk, acc[k]);
+              o = cfma(0.5 * dt, kk, base[k]);
+            } else if (s == 2) {
+              acc[k] = cfma(2.0, kk, acc[k]);
+              o = cfma(dt, kk, base[k]);
+            } else {
+              base[k] = cfma(dt / 6.0, cadd(acc[k], kk), base[k]);
+              o = base[k];
+            }
+            o_new[k] = o;
           }
-          o_new[k] = o;
         }
       }
       __syncthreads();  // every thread is done reading the stage input
@@ -555,11 +655,13 @@ __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ tra
 
       // (4) partials and boundary layers of the next stage input
       const int pn = p ^ 1;
-      persist_partials<ROWS == 2>(T, tile, R, c1row, c2row, PARTg + ((size_t)pn * P + w) * npe);
+      persist_partials(T, tile, R, c1row, c2row, PARTg + ((size_t)pn * P + w) * npe);
       publish_boundary(tile, SPg + (size_t)pn * NMn, row0, R, L, M);
 
-      // (5) group barriers around the slice reduction
+      // (5) group barriers around the slice reduction; a wave that does not
+      // poll computes the drive value of the next stage meanwhile
       flag_arrive(myA, (uint32_t)(g + 2));
+      if (tid == 64) s_drv[(s + 1) & 1] = drive_at(T, s == 3 ? stage_time(step + 1, 0) : stage_time(step, s + 1));
       ok = flag_wait(T, flagA, (uint32_t)(g + 2), &s_ok);
       if (!ok) break;
       load_halo(pn);
@@ -586,6 +688,13 @@ __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ tra
   } else if (w == 0 && tid == 0) {
     *T.step = step0 + n;
   }
+}
+
+// Kernel variant for ROWS rows per thread and rank M.
+inline int persist_ge(int M) { return M * M > kPW ? 2 : 1; }
+inline const void* persist_kernel(int rows, int ge) {
+  if (rows <= 2) return ge <= 1 ? (const void*)k_persist<2, 1> : (const void*)k_persist<2, 2>;
+  return ge <= 1 ? (const void*)k_persist<3, 1> : (const void*)k_persist<3, 2>;
 }
 
 // Zero the barrier flags and the abort flag of every trajectory of a batch.
