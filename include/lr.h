@@ -125,12 +125,13 @@ int lr_observables(lr_ctx_t* ctx, const lr_c64* d_B, double* d_out);
  * (may be NULL) receives the RK step index at which it occurred. */
 int lr_status(lr_ctx_t* ctx, int64_t* failed_step);
 
-/* Kernel timing telemetry.  While enabled, every launch of the streaming
- * stage kernel and of the Gram solve kernel made by lr_integrate is bracketed
- * by HIP events on the bound stream (up to the first LR_PROFILE_MAX launches
- * of each after enabling; enabling again resets the counters).
- * lr_profile_read synchronises the stream and returns the summed kernel
- * times (ms) and launch counts. */
+/* Kernel timing telemetry.  While enabled, every launch of the integrator's
+ * main kernel made by lr_integrate -- a chunk of steps of the persistent
+ * on-chip kernel, or one stage of the multi-kernel fallback -- and of the
+ * fallback's Gram solve kernel is bracketed by HIP events on the bound
+ * stream (up to the first LR_PROFILE_MAX launches of each after enabling;
+ * enabling again resets the counters).  lr_profile_read synchronises the
+ * stream and returns the summed kernel times (ms) and launch counts. */
 #define LR_PROFILE_MAX 4096
 int lr_profile_enable(lr_ctx_t* ctx, int32_t on);
 int lr_profile_read(lr_ctx_t* ctx, double* stage_ms, int64_t* stage_launches, double* solve_ms,
@@ -174,6 +175,13 @@ int lr_batch_run(lr_batch_t* batch);
 /* Synchronise; per-trajectory status codes and failing step indices
  * (arrays of n, may be NULL).  Returns the first non-OK code or LR_OK. */
 int lr_batch_status(lr_batch_t* batch, int32_t* codes, int64_t* failed_steps);
+/* Kernel timing of a batch: while enabled, every chunk launch of the
+ * persistent kernel made by lr_batch_run is bracketed by HIP events on the
+ * bound stream (the first LR_PROFILE_MAX launches after enabling; enabling
+ * again resets the count).  lr_batch_profile_read synchronises the stream and
+ * returns the summed kernel time (ms) and the launch count. */
+int lr_batch_profile_enable(lr_batch_t* batch, int32_t on);
+int lr_batch_profile_read(lr_batch_t* batch, double* ms, int64_t* launches);
 void lr_batch_destroy(lr_batch_t* batch);
 
 #ifdef __cplusplus

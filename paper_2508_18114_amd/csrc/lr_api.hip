@@ -106,8 +106,8 @@ int launch_persist(lr_ctx* c, int prologue, int64_t step0, int64_t nchunk) {
   if (k >= 0) (void)hipEventRecord(c->ev_stage[2 * k], c->stream);
   const TrajDev* tr = dev_traj(c);
   const int2* tmap = reinterpret_cast<const int2*>(c->ws + c->off_ptilemap);
-  void* args[] = {(void*)&tr, (void*)&tmap, (void*)&prologue, (void*)&step0, (void*)&nchunk};
-  const void* fn = lrk::persist_kernel(c->prows, lrk::persist_ge(c->M));
+  void* args[] = {(void*)&tr, (void*)&tmap, (void*)&step0, (void*)&nchunk};
+  const void* fn = lrk::persist_kernel(c->prows, lrk::persist_ge(c->M), prologue != 0);
   hipError_t e = hipLaunchCooperativeKernel(fn, dim3(c->P), dim3(lrk::kPW), args, (unsigned)c->pers_lds, c->stream);
   if (k >= 0) (void)hipEventRecord(c->ev_stage[2 * k + 1], c->stream);
   return e == hipSuccess ? LR_OK : LR_ERR_HIP;
@@ -284,9 +284,11 @@ int lr_bind(lr_ctx_t* c, void* d_ws, size_t bytes, void* stream) {
   delete[] tm;
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) return LR_ERR_HIP;
   if (c->P > 0) {
-    const void* fn = lrk::persist_kernel(c->prows, lrk::persist_ge(c->M));
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->pers_lds) != hipSuccess)
-      return LR_ERR_HIP;
+    for (int pro = 0; pro < 2; ++pro) {
+      const void* fn = lrk::persist_kernel(c->prows, lrk::persist_ge(c->M), pro != 0);
+      if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->pers_lds) != hipSuccess)
+        return LR_ERR_HIP;
+    }
   }
   return LR_OK;
 }

@@ -25,6 +25,9 @@ struct lr_batch {
     int64_t max_steps, chunk;
   };
   std::vector<Group> groups;
+  bool prof = false;
+  std::vector<hipEvent_t> ev;  // start/stop pairs of timed chunk launches
+  int64_t n_ev = 0;
 };
 
 namespace {
@@ -72,7 +75,7 @@ int check_model(const lr_model_t& m, int M, int precision) {
   return LR_OK;
 }
 
-const void* persist_fn(int rows, int ge) { return lrk::persist_kernel(rows, ge); }
+const void* persist_fn(int rows, int ge, bool prologue = false) { return lrk::persist_kernel(rows, ge, prologue); }
 
 }  // namespace
 
@@ -198,9 +201,10 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
   for (int t = 0; t < b->n; ++t) max_lds = std::max(max_lds, b->lds[t]);
   for (int rows = 2; rows <= 3; ++rows)
     for (int ge = 1; ge <= 2; ++ge)
-      if (hipFuncSetAttribute(persist_fn(rows, ge), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) !=
-          hipSuccess)
-        return LR_ERR_HIP;
+      for (int pro = 0; pro < 2; ++pro)
+        if (hipFuncSetAttribute(persist_fn(rows, ge, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)max_lds) != hipSuccess)
+          return LR_ERR_HIP;
   auto capacity = [&](int rows, int ge, size_t lds) -> int {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_fn(rows, ge), lrk::kPW, lds) != hipSuccess)
@@ -254,11 +258,21 @@ int lr_batch_run(lr_batch_t* b) {
     const TrajDev* gtr = trajs;
     const int2* gmap = tmap + b->wg_offset[g.begin];
     auto launch = [&](int prologue, int64_t step0, int64_t nchunk) -> int {
-      void* args[] = {(void*)&gtr, (void*)&gmap, (void*)&prologue, (void*)&step0, (void*)&nchunk};
-      return hipLaunchCooperativeKernel(persist_fn(g.rows, g.ge), dim3(g.wgs), dim3(lrk::kPW), args, (unsigned)g.lds,
-                                        b->stream) == hipSuccess
-                 ? LR_OK
-                 : LR_ERR_HIP;
+      void* args[] = {(void*)&gtr, (void*)&gmap, (void*)&step0, (void*)&nchunk};
+      int64_t k = -1;
+      if (b->prof && !prologue && b->n_ev < LR_PROFILE_MAX) {
+        while ((int64_t)b->ev.size() < 2 * (b->n_ev + 1)) {
+          hipEvent_t e;
+          if (hipEventCreate(&e) != hipSuccess) return LR_ERR_HIP;
+          b->ev.push_back(e);
+        }
+        k = b->n_ev++;
+        (void)hipEventRecord(b->ev[2 * k], b->stream);
+      }
+      const hipError_t err = hipLaunchCooperativeKernel(persist_fn(g.rows, g.ge, prologue != 0), dim3(g.wgs),
+                                                        dim3(lrk::kPW), args, (unsigned)g.lds, b->stream);
+      if (k >= 0) (void)hipEventRecord(b->ev[2 * k + 1], b->stream);
+      return err == hipSuccess ? LR_OK : LR_ERR_HIP;
     };
     if (int e = launch(1, 0, 0)) return e;
     hipLaunchKernelGGL(lrk::k_obs, dim3(g.end - g.begin), dim3(lrk::kWG), 0, b->stream, trajs + g.begin,
@@ -298,6 +312,31 @@ int lr_batch_status(lr_batch_t* b, int32_t* codes, int64_t* failed_steps) {
   return first;
 }
 
-void lr_batch_destroy(lr_batch_t* b) { delete b; }
+int lr_batch_profile_enable(lr_batch_t* b, int32_t on) {
+  if (!b) return LR_ERR_ARG;
+  b->prof = on != 0;
+  b->n_ev = 0;
+  return LR_OK;
+}
+
+int lr_batch_profile_read(lr_batch_t* b, double* ms, int64_t* launches) {
+  if (!b) return LR_ERR_ARG;
+  if (b->stream && hipStreamSynchronize(b->stream) != hipSuccess) return LR_ERR_HIP;
+  if (!b->stream && hipDeviceSynchronize() != hipSuccess) return LR_ERR_HIP;
+  double tot = 0.0;
+  for (int64_t k = 0; k < b->n_ev; ++k) {
+    float x = 0.0f;
+    if (hipEventElapsedTime(&x, b->ev[2 * k], b->ev[2 * k + 1]) == hipSuccess) tot += x;
+  }
+  if (ms) *ms = tot;
+  if (launches) *launches = b->n_ev;
+  return LR_OK;
+}
+
+void lr_batch_destroy(lr_batch_t* b) {
+  if (!b) return;
+  for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+  delete b;
+}
 
 }  // extern "C"

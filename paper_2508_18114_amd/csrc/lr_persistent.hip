@@ -338,10 +338,11 @@ __device__ __forceinline__ double gram_fro2(const g_double2* red, int MM, double
   return tot;
 }
 
+// The kernel body: the prologue (partials and reduction of the initial stage
+// input, no step) or a chunk of nchunk RK4 steps from step0.
 template <int ROWS, int GE>
-__global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ trajs,
-                                                 const int2* __restrict__ tilemap, int prologue, int64_t step0,
-                                                 int64_t nchunk) {
+__device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, const int2* __restrict__ tilemap,
+                                             int prologue, int64_t step0, int64_t nchunk) {
   extern __shared__ double2 lds[];
   __shared__ int s_ok;
   __shared__ int s_nonfinite;
@@ -690,9 +691,27 @@ __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ tra
   }
 }
 
+// Chunk of RK4 steps (the integrator proper) and prologue, as separate
+// kernels so that timing tools see the step kernel alone.
+template <int ROWS, int GE>
+__global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ trajs,
+                                                 const int2* __restrict__ tilemap, int64_t step0, int64_t nchunk) {
+  persist_body<ROWS, GE>(trajs, tilemap, 0, step0, nchunk);
+}
+template <int ROWS, int GE>
+__global__ __launch_bounds__(kPW) void k_persist_prologue(const TrajDev* __restrict__ trajs,
+                                                          const int2* __restrict__ tilemap, int64_t step0,
+                                                          int64_t /* nchunk: same signature as k_persist */) {
+  persist_body<ROWS, GE>(trajs, tilemap, 1, step0, 0);
+}
+
 // Kernel variant for ROWS rows per thread and rank M.
 inline int persist_ge(int M) { return M * M > kPW ? 2 : 1; }
-inline const void* persist_kernel(int rows, int ge) {
+inline const void* persist_kernel(int rows, int ge, bool prologue) {
+  if (prologue) {
+    if (rows <= 2) return ge <= 1 ? (const void*)k_persist_prologue<2, 1> : (const void*)k_persist_prologue<2, 2>;
+    return ge <= 1 ? (const void*)k_persist_prologue<3, 1> : (const void*)k_persist_prologue<3, 2>;
+  }
   if (rows <= 2) return ge <= 1 ? (const void*)k_persist<2, 1> : (const void*)k_persist<2, 2>;
   return ge <= 1 ? (const void*)k_persist<3, 1> : (const void*)k_persist<3, 2>;
 }

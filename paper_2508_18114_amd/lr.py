@@ -36,7 +36,7 @@ EXPORTS = ("lr_init", "lr_workspace_bytes", "lr_bind", "lr_rhs", "lr_integrate",
            "lr_observables", "lr_status", "lr_profile_enable", "lr_profile_read",
            "lr_strerror", "lr_destroy",
            "lr_batch_init", "lr_batch_workspace_bytes", "lr_batch_bind", "lr_batch_run",
-           "lr_batch_status", "lr_batch_destroy")
+           "lr_batch_status", "lr_batch_profile_enable", "lr_batch_profile_read", "lr_batch_destroy")
 
 
 class LrError(RuntimeError):
@@ -91,6 +91,8 @@ def _load():
         "lr_batch_bind": (ctypes.c_int, [vp, vp, sz, vp]),
         "lr_batch_run": (ctypes.c_int, [vp]),
         "lr_batch_status": (ctypes.c_int, [vp, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
+        "lr_batch_profile_enable": (ctypes.c_int, [vp, i32]),
+        "lr_batch_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
         "lr_batch_destroy": (None, [vp]),
         "lr_destroy": (None, [vp]),
     }
@@ -201,6 +203,17 @@ def lr_batch_status(batch: int, n: int):
     return rc, list(codes), list(steps)
 
 
+def lr_batch_profile_enable(batch: int, on: bool) -> int:
+    return _lib.lr_batch_profile_enable(batch, 1 if on else 0)
+
+
+def lr_batch_profile_read(batch: int):
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    rc = _lib.lr_batch_profile_read(batch, ctypes.byref(ms), ctypes.byref(n))
+    return rc, ms.value, n.value
+
+
 def lr_batch_destroy(batch: int) -> None:
     _lib.lr_batch_destroy(batch)
 
@@ -309,6 +322,18 @@ class Batch:
 
     def status(self):
         return lr_batch_status(self.handle, len(self.items))
+
+    def profile(self, on=True):
+        rc = lr_batch_profile_enable(self.handle, on)
+        if rc != LR_OK:
+            raise LrError(rc, "lr_batch_profile_enable")
+
+    def profile_read(self):
+        """(summed kernel ms, launches) of the timed persistent-kernel chunks."""
+        rc, ms, n = lr_batch_profile_read(self.handle)
+        if rc != LR_OK:
+            raise LrError(rc, "lr_batch_profile_read")
+        return ms, n
 
     def close(self):
         if self.handle:
