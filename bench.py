@@ -36,6 +36,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-compare", action="store_true", help="skip the batched / single / dense comparisons")
     ap.add_argument("--cpu-steps", type=int, default=2000, help="oracle steps per trajectory in the CPU sample")
     return ap.parse_args()
 
@@ -63,6 +64,74 @@ def cpu_baseline(nsteps):
     return {"value": 2 * nsteps / wall, "unit": "RK steps*trajectories/s", "cores": 2, "kind": "oracle",
             "sample": f"{nsteps} RK4 steps of each of the g and e trajectories at N=2000, M=20 "
                       f"(one process and one BLAS thread each; {wall:.1f} s wall incl. process start)"}
+
+
+def comparisons(lr, I, torch, stream, plain_value):
+    """Throughput of the other forms on the same GPU (bounded samples)."""
+    out = {}
+    trajs = I.config_paper_size()
+    m, M = trajs[0].model, trajs[0].M
+
+    def run_batch(tr_list, nsteps_cap):
+        items = [dict(model=t.model, M=t.M, pulse=t.pulse, dt=t.dt, nsteps=min(t.nsteps, nsteps_cap),
+                      B=lr.to_device(t.B0())) for t in tr_list]
+        b = lr.Batch(items, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        rc, codes, _ = b.status()
+        if rc != lr.LR_OK:
+            raise RuntimeError(f"batch failed: {lr.lr_strerror(rc)}")
+        return sum(it["nsteps"] for it in items) / el, el
+
+    # plain single trajectory (one Context, trajectory g)
+    steps = 2000
+    ctx = lr.Context(m, M, stream=stream)
+    B = lr.to_device(trajs[0].B0())
+    ctx.integrate(trajs[0].pulse, 0.0, trajs[0].dt, 200, B)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.integrate(trajs[0].pulse, 0.0, trajs[0].dt, steps, B)
+    torch.cuda.synchronize()
+    single = steps / (time.perf_counter() - t0)
+    out["plain_single"] = {"value": single, "unit": "RK steps*trajectories/s",
+                           "workload": f"one trajectory (g), N={m.N}, M={M}, {steps} steps"}
+    # batched, same shape: 16 piecewise pulses x {g, e} at N=2000, M=20
+    npulse, steps = 16, 1000
+    v, el = run_batch(I.batch_uniform(npulse), steps)
+    out["batched_same_shape"] = {"value": v, "unit": "RK steps*trajectories/s",
+                                 "vs_plain_g_e": v / plain_value, "vs_plain_single": v / single,
+                                 "workload": f"{2 * npulse} trajectories ({npulse} piecewise pulses x g/e), "
+                                             f"N=2000, M=20, {steps} steps each, one batch ({el:.2f} s)"}
+    # batched mixed shapes: the 512 trajectories of the batched configuration, capped step count
+    steps = 150
+    c4 = I.config_batched()
+    v, el = run_batch(c4, steps)
+    out["batched_mixed_c4_sample"] = {"value": v, "unit": "RK steps*trajectories/s",
+                                      "workload": f"{len(c4)} trajectories, N in {{1000,1520,2000,3000}}, "
+                                                  f"M in [8,32], first {steps} steps of each ({el:.2f} s)"}
+    # dense full-Lindblad RK4 at the same N, dt
+    N = m.N
+    rho = torch.zeros((N, N), dtype=torch.complex128, device="cuda")
+    n0 = I.basis_index(m, 0, 0, 0)
+    rho[n0, n0] = 1.0
+    ws = lr.dense_integrate(m, trajs[0].pulse, 0.0, trajs[0].dt, 2, rho)
+    dsteps = 20
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lr.dense_integrate(m, trajs[0].pulse, 0.0, trajs[0].dt, dsteps, rho, workspace=ws)
+    torch.cuda.synchronize()
+    dms = 1e3 * (time.perf_counter() - t0) / dsteps
+    nfull = trajs[0].nsteps
+    out["dense_lindblad_gpu"] = {
+        "ms_per_step": dms, "unit": "ms per RK4 step (one trajectory)",
+        "full_trajectory_s": dms * nfull / 1e3, "lowrank_plain_single_full_trajectory_s": nfull / single,
+        "speedup_lowrank_vs_dense": (dms * 1e-3) * single,
+        "workload": f"dense rho {N}x{N} FP64, same model/drive/dt, {dsteps} steps timed; full trajectory = "
+                    f"{nfull} steps (extrapolated)"}
+    return out
 
 
 def main():
@@ -138,6 +207,8 @@ def main():
                      "steps_per_launch": steps_per_launch, "trajectories_per_launch": len(trajs),
                      "flops_per_launch": flops_per_launch},
     }
+    if not a.no_compare:
+        out["comparisons"] = comparisons(lr, I, torch, stream, value)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -137,6 +137,37 @@ int lr_profile_enable(lr_ctx_t* ctx, int32_t on);
 int lr_profile_read(lr_ctx_t* ctx, double* stage_ms, int64_t* stage_launches, double* solve_ms,
                     int64_t* solve_launches);
 
+/* Readout figures of merit of a g/e pair from their observation series
+ * (Supplement S3.A eqs. "SNR", "separation_error", "assignment_error"; S3.B
+ * eqs. "transmon_ionization", "loss_function"):
+ *   SNR       = sqrt(2 eta kappa_f int_0^tau |<f>_e - <f>_g|^2 dt)
+ *   eps_sep   = erfc(SNR / 2) / 2,   eps_decay = tau gamma_1 / 2,   eps_a = eps_sep + eps_decay
+ *   T         = (1 / tau) sum_{g,e} sum_{k = 2}^{d_q - 1} int_0^tau P_q(k) dt
+ *   Lambda    = log10(eps_a + T)
+ * d_obs_g, d_obs_e: device, nsamples (>= 2) records of LR_OBS_LEN(d_q)
+ * doubles as written by lr_integrate, sampled every h ns (tau = h
+ * (nsamples - 1)); integrals are composite trapezoids on that grid.
+ * d_out: device, 6 doubles {SNR, eps_sep, eps_decay, eps_a, T, Lambda}.
+ * Enqueued on `stream` (NULL: the null stream); LR_ERR_ARG for invalid
+ * arguments. */
+int lr_readout_loss(const double* d_obs_g, const double* d_obs_e, int64_t nsamples, int32_t d_q, double h,
+                    double kappa_f, double gamma_1, double eta, double* d_out, void* stream);
+
+/* Dense full-Lindblad comparison solve (Supplement S1.A, eq.
+ * "master_equation" with the dissipator of eq. "lindblad_dissipator"): the
+ * same model, drive and classic RK4 stage times as lr_integrate, on the full
+ * N x N density matrix instead of the low-rank factor.
+ * d_rho: device, row-major N x N interleaved complex FP64 in the basis order
+ * of B (n = (q d_r + r) d_f + f), Hermitian; in rho(t0), out rho(t0 + nsteps
+ * dt).  d_workspace: device, >= lr_dense_workspace_bytes(m) bytes (4 N^2
+ * complex), owned by the caller.  obs_stride / d_obs: records as in
+ * lr_integrate, computed from rho.  Enqueued on `stream`; N <= 16384.
+ * Returns LR_ERR_ARG / LR_ERR_PULSE for invalid arguments. */
+size_t lr_dense_workspace_bytes(const lr_model_t* m);
+int lr_dense_integrate(const lr_model_t* m, const lr_pulse_t* pulse, double t0, double dt, int64_t nsteps,
+                       lr_c64* d_rho, int32_t obs_stride, double* d_obs, void* d_workspace, size_t bytes,
+                       void* stream);
+
 const char* lr_strerror(int code);
 void lr_destroy(lr_ctx_t* ctx);
 

@@ -12,6 +12,8 @@
 #include "lr.h"
 #include "lr_kernels.hip"
 #include "lr_persistent.hip"
+#include "lr_loss.hip"
+#include "lr_dense.hip"
 
 using lrk::TrajDev;
 
@@ -405,6 +407,68 @@ int lr_profile_read(lr_ctx_t* c, double* stage_ms, int64_t* stage_launches, doub
   if (solve_ms) *solve_ms = prof_sum(c->ev_solve, c->n_solve);
   if (solve_launches) *solve_launches = c->n_solve;
   return LR_OK;
+}
+
+int lr_readout_loss(const double* d_obs_g, const double* d_obs_e, int64_t nsamples, int32_t d_q, double h,
+                    double kappa_f, double gamma_1, double eta, double* d_out, void* stream) {
+  if (!d_obs_g || !d_obs_e || !d_out || nsamples < 2 || d_q < 2) return LR_ERR_ARG;
+  if (!(std::isfinite(h) && h > 0.0 && std::isfinite(kappa_f) && kappa_f >= 0.0 && std::isfinite(gamma_1) &&
+        gamma_1 >= 0.0 && std::isfinite(eta) && eta >= 0.0))
+    return LR_ERR_ARG;
+  hipLaunchKernelGGL(lrk::k_readout_loss, dim3(1), dim3(lrk::kLossWG), 0, (hipStream_t)stream, d_obs_g, d_obs_e,
+                     nsamples, (int)LR_OBS_LEN(d_q), (int)d_q, h, kappa_f, gamma_1, eta, d_out);
+  return hipGetLastError() == hipSuccess ? LR_OK : LR_ERR_HIP;
+}
+
+size_t lr_dense_workspace_bytes(const lr_model_t* m) {
+  if (!m || m->d_q < 1 || m->d_r < 1 || m->d_f < 1) return 0;
+  const size_t N = (size_t)m->d_q * m->d_r * m->d_f;
+  return 4 * N * N * sizeof(double2);
+}
+
+int lr_dense_integrate(const lr_model_t* m, const lr_pulse_t* pulse, double t0, double dt, int64_t nsteps,
+                       lr_c64* d_rho, int32_t obs_stride, double* d_obs, void* d_workspace, size_t bytes,
+                       void* stream) {
+  if (!m || !d_rho || !d_workspace || m->d_q < 1 || m->d_r < 1 || m->d_f < 1) return LR_ERR_ARG;
+  const long long Nl = (long long)m->d_q * m->d_r * m->d_f;
+  if (Nl > 16384) return LR_ERR_ARG;
+  if (bytes < lr_dense_workspace_bytes(m)) return LR_ERR_ARG;
+  if (!(std::isfinite(dt) && dt > 0.0 && std::isfinite(t0)) || nsteps < 0) return LR_ERR_ARG;
+  if (obs_stride < 0 || (obs_stride > 0 && !d_obs)) return LR_ERR_ARG;
+  if (int e = check_pulse(pulse)) return e;
+  const double vals[] = {m->w_q, m->alpha, m->w_r, m->w_f, m->g, m->G, m->kappa_f, m->gamma_1};
+  for (double x : vals)
+    if (!std::isfinite(x)) return LR_ERR_ARG;
+  if (m->kappa_f < 0.0 || m->gamma_1 < 0.0) return LR_ERR_ARG;
+  const int N = (int)Nl;
+  lrk::DenseDev D{m->d_q, m->d_r, m->d_f, N, m->w_q, m->alpha, m->w_r, m->w_f, m->g, m->G, m->kappa_f, m->gamma_1};
+  TrajDev pv{};
+  set_pulse(pv, pulse);
+  hipStream_t st = (hipStream_t)stream;
+  double2* base = reinterpret_cast<double2*>(d_rho);
+  double2* X1 = reinterpret_cast<double2*>(d_workspace);
+  double2* X2 = X1 + (size_t)N * N;
+  double2* acc = X2 + (size_t)N * N;
+  double2* Z = acc + (size_t)N * N;
+  const dim3 ga((N + lrk::kDenseWG - 1) / lrk::kDenseWG, N), gc((N + 31) / 32, (N + 31) / 32);
+  const int rec = 6 + m->d_q;
+  if (obs_stride > 0) hipLaunchKernelGGL(lrk::k_dense_obs, dim3(1), dim3(lrk::kDenseWG), 0, st, D, base, d_obs);
+  int64_t nrec = 1;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    const double t = t0 + (double)n * dt;
+    const double cs[4] = {0.0, 0.5, 0.5, 1.0};
+    const double2* in[4] = {base, X1, X2, X1};
+    double2* out[4] = {X1, X2, X1, nullptr};
+    for (int s = 0; s < 4; ++s) {
+      const double drv = lrk::drive_at(pv, t + cs[s] * dt);
+      hipLaunchKernelGGL(lrk::k_dense_apply, ga, dim3(lrk::kDenseWG), 0, st, D, drv, in[s], Z);
+      hipLaunchKernelGGL(lrk::k_dense_combine, gc, dim3(lrk::kDenseWG), 0, st, D, in[s], Z, base, acc, out[s], s,
+                         dt);
+    }
+    if (obs_stride > 0 && (n + 1) % obs_stride == 0)
+      hipLaunchKernelGGL(lrk::k_dense_obs, dim3(1), dim3(lrk::kDenseWG), 0, st, D, base, d_obs + (nrec++) * rec);
+  }
+  return hipGetLastError() == hipSuccess ? LR_OK : LR_ERR_HIP;
 }
 
 void lr_destroy(lr_ctx_t* c) {

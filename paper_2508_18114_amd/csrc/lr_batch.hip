@@ -2,15 +2,17 @@
 // layout and the launch sequence that integrates many independent
 // trajectories with the persistent on-chip kernel.
 //
-// Trajectories are packed, in order, into execution groups whose workgroups
-// are co-resident (one cooperative launch per chunk of steps); groups run one
-// after the other.  Within a group every trajectory has its own barrier
+// Trajectories are sorted by step count (longest first, stable) and packed,
+// in that order, into execution groups whose workgroups are co-resident (one
+// cooperative launch per chunk of steps); groups run one after the other, so
+// trajectories of similar length share a group and few workgroups idle.  Within a group every trajectory has its own barrier
 // flags, so trajectories of different shapes and step counts proceed
 // independently, and each result is bitwise that of the trajectory alone.
 
 struct lr_batch {
   int n = 0;
-  std::vector<lr_traj_t> tr;
+  std::vector<lr_traj_t> tr;   // in execution order (see lr_batch_init)
+  std::vector<int> pos;        // pos[i] = execution position of the caller's trajectory i
   std::vector<TrajDev> dev;
   std::vector<int> P, prt, rows;
   std::vector<size_t> lds, region, region_bytes;
@@ -87,7 +89,15 @@ int lr_batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n) {
   lr_batch* b = new (std::nothrow) lr_batch();
   if (!b) return LR_ERR_OOM;
   b->n = n;
-  b->tr.assign(trajs, trajs + n);
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return trajs[x].nsteps > trajs[y].nsteps; });
+  b->tr.resize(n);
+  b->pos.resize(n);
+  for (int k = 0; k < n; ++k) {
+    b->tr[k] = trajs[order[k]];
+    b->pos[order[k]] = k;
+  }
   b->dev.resize(n);
   b->P.resize(n);
   b->prt.resize(n);
@@ -300,13 +310,14 @@ int lr_batch_status(lr_batch_t* b, int32_t* codes, int64_t* failed_steps) {
   if (!b->ws) return LR_ERR_STATE;
   if (hipStreamSynchronize(b->stream) != hipSuccess) return LR_ERR_HIP;
   int first = LR_OK;
-  for (int t = 0; t < b->n; ++t) {
+  for (int i = 0; i < b->n; ++i) {
+    const TrajDev& v = b->dev[b->pos[i]];
     int32_t st = 0;
     int64_t fs = -1;
-    if (hipMemcpy(&st, b->dev[t].status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return LR_ERR_HIP;
-    if (hipMemcpy(&fs, b->dev[t].fail_step, sizeof(fs), hipMemcpyDeviceToHost) != hipSuccess) return LR_ERR_HIP;
-    if (codes) codes[t] = st;
-    if (failed_steps) failed_steps[t] = fs;
+    if (hipMemcpy(&st, v.status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return LR_ERR_HIP;
+    if (hipMemcpy(&fs, v.fail_step, sizeof(fs), hipMemcpyDeviceToHost) != hipSuccess) return LR_ERR_HIP;
+    if (codes) codes[i] = st;
+    if (failed_steps) failed_steps[i] = fs;
     if (first == LR_OK && st != LR_OK) first = st;
   }
   return first;

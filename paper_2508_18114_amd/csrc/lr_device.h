@@ -105,14 +105,14 @@ __device__ __forceinline__ double2 cjmac(double2 acc, double2 a, double2 b) {
 }
 
 // Cosine ramp r(x) of the flat-top window.
-__device__ __forceinline__ double ramp_up(double x, double t_r) {
+__host__ __device__ __forceinline__ double ramp_up(double x, double t_r) {
   if (x < 0.0) return 0.0;
   if (x >= t_r) return 1.0;
   return 0.5 * (1.0 - cos(M_PI * x / t_r));
 }
 
 // Drive coefficient d(t) multiplying (f + f^).
-__device__ __forceinline__ double drive_at(const TrajDev& T, double t) {
+__host__ __device__ __forceinline__ double drive_at(const TrajDev& T, double t) {
   if (T.pkind == 0) {
     return T.amp * ramp_up(t, T.t_ramp) * ramp_up(T.T - t, T.t_ramp) * cos(T.w_d * t);
   }

@@ -34,7 +34,7 @@ LR_MAX_M = 32
 # every symbol include/lr.h declares
 EXPORTS = ("lr_init", "lr_workspace_bytes", "lr_bind", "lr_rhs", "lr_integrate",
            "lr_observables", "lr_status", "lr_profile_enable", "lr_profile_read",
-           "lr_strerror", "lr_destroy",
+           "lr_readout_loss", "lr_dense_workspace_bytes", "lr_dense_integrate", "lr_strerror", "lr_destroy",
            "lr_batch_init", "lr_batch_workspace_bytes", "lr_batch_bind", "lr_batch_run",
            "lr_batch_status", "lr_batch_profile_enable", "lr_batch_profile_read", "lr_batch_destroy")
 
@@ -86,6 +86,10 @@ def _load():
         "lr_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64),
                                            ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
         "lr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "lr_readout_loss": (ctypes.c_int, [vp, vp, i64, i32, dbl, dbl, dbl, dbl, vp, vp]),
+        "lr_dense_workspace_bytes": (sz, [ctypes.POINTER(lr_model_t)]),
+        "lr_dense_integrate": (ctypes.c_int, [ctypes.POINTER(lr_model_t), ctypes.POINTER(lr_pulse_t), dbl, dbl, i64,
+                                              vp, i32, vp, vp, sz, vp]),
         "lr_batch_init": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lr_traj_t), i32]),
         "lr_batch_workspace_bytes": (sz, [vp]),
         "lr_batch_bind": (ctypes.c_int, [vp, vp, sz, vp]),
@@ -216,6 +220,50 @@ def lr_batch_profile_read(batch: int):
 
 def lr_batch_destroy(batch: int) -> None:
     _lib.lr_batch_destroy(batch)
+
+
+LOSS_KEYS = ("snr", "eps_sep", "eps_decay", "eps_a", "ionisation", "loss")
+
+
+def readout_loss(obs_g, obs_e, d_q, h, kappa_f, gamma_1, eta=0.6, stream=None):
+    """Figures of merit of a g/e pair on the device (lr_readout_loss).
+
+    obs_g, obs_e: device float64 tensors (nsamples, LR_OBS_LEN(d_q)).
+    Returns a dict of Python floats (synchronises the stream)."""
+    import torch
+    assert obs_g.shape == obs_e.shape and obs_g.dtype == torch.float64 and obs_g.is_cuda and obs_e.is_cuda
+    assert obs_g.shape[1] == 6 + d_q and obs_g.is_contiguous() and obs_e.is_contiguous()
+    out = torch.empty(6, dtype=torch.float64, device=obs_g.device)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = _lib.lr_readout_loss(obs_g.data_ptr(), obs_e.data_ptr(), obs_g.shape[0], d_q, h, kappa_f, gamma_1, eta,
+                              out.data_ptr(), st.cuda_stream)
+    if rc != LR_OK:
+        raise LrError(rc, "lr_readout_loss")
+    vals = out.cpu().tolist()
+    return dict(zip(LOSS_KEYS, vals))
+
+
+def dense_integrate(model, pulse, t0, dt, nsteps, rho, obs_stride=0, obs=None, workspace=None, stream=None):
+    """Dense full-Lindblad RK4 on the device (lr_dense_integrate).
+
+    rho: device complex128 tensor (N, N), row-major, Hermitian; updated in
+    place.  obs: device float64 tensor (nsteps // obs_stride + 1, 6 + d_q) when
+    obs_stride > 0.  workspace: optional device uint8 tensor to reuse."""
+    import torch
+    N = model.N
+    assert rho.shape == (N, N) and rho.dtype == torch.complex128 and rho.is_cuda and rho.is_contiguous()
+    ms = model_struct(model)
+    nbytes = _lib.lr_dense_workspace_bytes(ctypes.byref(ms))
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=rho.device)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    ps = pulse_struct(pulse)
+    rc = _lib.lr_dense_integrate(ctypes.byref(ms), ctypes.byref(ps), t0, dt, nsteps, rho.data_ptr(), obs_stride,
+                                 obs.data_ptr() if obs is not None else None, workspace.data_ptr(), nbytes,
+                                 st.cuda_stream)
+    if rc != LR_OK:
+        raise LrError(rc, "lr_dense_integrate")
+    return workspace
 
 
 # ---------------------------------------------------------------- helpers

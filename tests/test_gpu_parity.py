@@ -169,12 +169,40 @@ def _check_config(lr, name, trajs):
         _assert_obs(got, gd[key], f"{name} {tr.which}")
         obs[key] = got
     tr = trajs[0]
-    fm = loss.readout_loss(obs["obs_g"], obs["obs_e"], stride * tr.dt, tr.model.kappa_f, tr.model.gamma_1)
+    # figures of merit of the GPU series, computed on the device
+    import torch
+    fm = lr.readout_loss(torch.from_numpy(obs["obs_g"]).cuda(), torch.from_numpy(obs["obs_e"]).cuda(), tr.model.d_q,
+                         stride * tr.dt, tr.model.kappa_f, tr.model.gamma_1)
     snr_ref = float(gd["snr"])
     d = abs(fm["snr"] - snr_ref)
-    print(f"[parity] {name} SNR gpu {fm['snr']:.12e} oracle {snr_ref:.12e} eps_sep {fm['eps_sep']:.6e}")
+    print(f"[parity] {name} SNR gpu {fm['snr']:.12e} oracle {snr_ref:.12e} eps_sep {fm['eps_sep']:.6e} "
+          f"loss {fm['loss']:.9f} vs {float(gd['loss']):.9f}")
     assert d <= (1e-8 * snr_ref if snr_ref > 1e-3 else 1e-11)
+    # eps_sep = erfc(SNR / 2) / 2 has slope <= 1 / (2 sqrt(pi)) in SNR
+    assert abs(fm["eps_sep"] - float(gd["eps_sep"])) <= 0.3 * d + 1e-15
+    assert abs(fm["eps_decay"] - float(gd["eps_decay"])) <= 1e-15
     assert abs(fm["ionisation"] - float(gd["ionisation"])) <= 1e-10
+    assert abs(fm["loss"] - float(gd["loss"])) <= 1e-8
+
+
+def test_readout_loss_matches_oracle_on_same_series(lr):
+    """Device figures of merit (S3.A-B) on the cached oracle series equal the oracle's own, up to
+    summation order."""
+    import torch
+    for name, trajs in (("small", I.config_small()), ("paper_size", I.config_paper_size())):
+        gd = _golden(name)
+        tr = trajs[0]
+        h = int(gd["stride"]) * tr.dt
+        ref = loss.readout_loss(gd["obs_g"], gd["obs_e"], h, tr.model.kappa_f, tr.model.gamma_1)
+        got = lr.readout_loss(torch.from_numpy(gd["obs_g"]).cuda(), torch.from_numpy(gd["obs_e"]).cuda(),
+                              tr.model.d_q, h, tr.model.kappa_f, tr.model.gamma_1)
+        for k in lr.LOSS_KEYS:
+            print(f"[parity] loss {name} {k}: gpu {got[k]:.15e} oracle {ref[k]:.15e}")
+            assert abs(got[k] - ref[k]) <= 1e-12 * max(1.0, abs(ref[k])), k
+    # argument checks
+    o = torch.zeros((1, 6 + 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(lr.LrError):
+        lr.readout_loss(o, o, 4, 0.1, 0.1, 1e-5)
 
 
 def test_integrate_config_small(lr):
@@ -292,3 +320,52 @@ def test_batch_matches_oracle(lr):
         assert np.max(np.abs(got_B - Bo)) <= 1e-12
         if it["obs_stride"]:
             _assert_obs(it["obs"].cpu().numpy(), ref, f"batch dims {it['model'].d_q, it['model'].d_r}")
+
+
+# ------------------------------------------------------------ dense comparison solve
+
+def _dense_case(seed):
+    model = I.readout_model(3, 4, 3)
+    pulse = I.flattop_pulse(0.08, 2.0, t_ramp=0.5)
+    r = np.random.default_rng(seed)
+    N = model.N
+    # mixed, full-rank rho0 = V V^ / tr with the excited state dominant
+    V = 0.05 * (r.standard_normal((N, N)) + 1j * r.standard_normal((N, N)))
+    V[I.basis_index(model, 1, 0, 0), 0] += 1.0
+    rho0 = V @ V.conj().T
+    rho0 = 0.5 * (rho0 + rho0.conj().T)
+    return model, pulse, rho0 / np.trace(rho0).real
+
+
+def test_dense_lindblad_matches_oracle(lr):
+    """Dense full-Lindblad RK4 on the device vs the oracle's dense master equation (same stage times)."""
+    import torch
+    from oracle import dense
+    model, pulse, rho0 = _dense_case(11)
+    dt, nsteps, stride = 2e-3, 300, 100
+    rho = torch.from_numpy(rho0.copy()).cuda()
+    obs = torch.zeros((nsteps // stride + 1, 6 + model.d_q), dtype=torch.float64, device="cuda")
+    lr.dense_integrate(model, pulse, 0.0, dt, nsteps, rho, stride, obs)
+    torch.cuda.synchronize()
+    ref_rho, ref_obs = dense.integrate(model, pulse, 0.0, dt, nsteps, rho0, obs_stride=stride)
+    got = rho.cpu().numpy()
+    err = np.max(np.abs(got - ref_rho))
+    print(f"[parity] dense rho err {err:.3e}")
+    assert err <= 1e-12
+    assert np.array_equal(got, got.conj().T)  # exactly Hermitian
+    e_field, e_pop = _obs_errors(obs.cpu().numpy(), ref_obs)
+    print(f"[parity] dense obs: field err {e_field:.3e}, populations err {e_pop:.3e}")
+    assert e_field <= 1e-12 and e_pop <= 1e-12
+
+
+def test_dense_lindblad_edge_cases(lr):
+    import torch
+    model, pulse, rho0 = _dense_case(12)
+    rho = torch.from_numpy(rho0.copy()).cuda()
+    lr.dense_integrate(model, pulse, 0.0, 1e-3, 0, rho)  # zero steps: unchanged
+    torch.cuda.synchronize()
+    assert np.array_equal(rho.cpu().numpy(), rho0)
+    with pytest.raises(lr.LrError):
+        lr.dense_integrate(model, pulse, 0.0, -1e-3, 5, rho)
+    with pytest.raises(lr.LrError):
+        lr.dense_integrate(model, pulse, 0.0, 1e-3, 5, rho, obs_stride=2, obs=None)
