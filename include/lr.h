@@ -70,8 +70,17 @@ typedef struct {
   double  p[6];
 } lr_pulse_t;
 
-/* Arithmetic of the operator applications and Gram products.  The Cholesky
- * solve and the RK4 accumulation of B are FP64 in every mode. */
+/* Arithmetic of the operator applications (H_eff and L_k on B), the jump
+ * assembly and the Gram / cross products of lr_integrate and lr_batch_run:
+ *   LR_FP64    FP64 throughout;
+ *   LR_FP32    operands rounded to FP32, FP32 products and accumulation;
+ *   LR_BF16X3  operands rounded to FP32 and split into BF16 parts, each
+ *              product formed from the three leading part products with FP32
+ *              accumulation (evaluated on the vector ALU).
+ * The M x M solve, the reduction of the Gram partials across the state and
+ * the RK4 accumulation of B are FP64 in every mode.  lr_rhs and
+ * lr_observables always evaluate in FP64; the reduced modes need the
+ * persistent on-chip integrator (LR_ERR_ARG from lr_integrate otherwise). */
 enum { LR_FP64 = 0, LR_FP32 = 1, LR_BF16X3 = 2 };
 
 enum {
@@ -181,13 +190,16 @@ void lr_destroy(lr_ctx_t* ctx);
 typedef struct {
   lr_model_t model;
   int32_t M;
-  int32_t precision;        /* LR_FP64 */
+  int32_t precision;        /* LR_FP64, LR_FP32 or LR_BF16X3 */
   lr_pulse_t pulse;
   double t0, dt;
   int64_t nsteps;
-  lr_c64* d_B;              /* device, column-major N x M; in B(t0), out B(t0 + nsteps dt) */
+  lr_c64* d_B;              /* device, column-major N x M; in B(t_first), out B(t_first + nsteps dt) */
   int32_t obs_stride;       /* records as in lr_integrate (0: none) */
-  int32_t reserved;
+  int32_t step0;            /* index of the first step (>= 0): step n of this call runs from
+                               t0 + (step0 + n) dt, so a trajectory continued over several
+                               calls (t0 fixed, step0 advanced) sees bitwise the same stage
+                               times, hence the same result, as in one call */
   double* d_obs;            /* device, (nsteps / obs_stride + 1) x LR_OBS_LEN(d_q) */
 } lr_traj_t;
 

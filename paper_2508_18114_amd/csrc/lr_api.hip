@@ -109,7 +109,7 @@ int launch_persist(lr_ctx* c, int prologue, int64_t step0, int64_t nchunk) {
   const TrajDev* tr = dev_traj(c);
   const int2* tmap = reinterpret_cast<const int2*>(c->ws + c->off_ptilemap);
   void* args[] = {(void*)&tr, (void*)&tmap, (void*)&step0, (void*)&nchunk};
-  const void* fn = lrk::persist_kernel(c->prows, lrk::persist_ge(c->M), prologue != 0);
+  const void* fn = lrk::persist_kernel(c->prows, lrk::persist_ge(c->M), prologue != 0, c->prec);
   hipError_t e = hipLaunchCooperativeKernel(fn, dim3(c->P), dim3(lrk::kPW), args, (unsigned)c->pers_lds, c->stream);
   if (k >= 0) (void)hipEventRecord(c->ev_stage[2 * k + 1], c->stream);
   return e == hipSuccess ? LR_OK : LR_ERR_HIP;
@@ -167,7 +167,7 @@ int lr_init(lr_ctx_t** out, const lr_model_t* m, int32_t M, int32_t precision) {
   const long long N = (long long)m->d_q * m->d_r * m->d_f;
   if (N > (1LL << 26)) return LR_ERR_ARG;
   if (M < 1 || M > LR_MAX_M || M > N) return LR_ERR_ARG;
-  if (precision != LR_FP64) return LR_ERR_ARG;
+  if (precision != LR_FP64 && precision != LR_FP32 && precision != LR_BF16X3) return LR_ERR_ARG;
   const double vals[] = {m->w_q, m->alpha, m->w_r, m->w_f, m->g, m->G, m->kappa_f, m->gamma_1};
   for (double x : vals)
     if (!std::isfinite(x)) return LR_ERR_ARG;
@@ -264,6 +264,7 @@ int lr_bind(lr_ctx_t* c, void* d_ws, size_t bytes, void* stream) {
   b.P = c->P;
   b.rt = c->prt;
   b.npe = 3 * c->M * c->M;
+  b.prec = c->prec;
   if (c->P > 0) {
     b.SP = reinterpret_cast<double2*>(c->ws + c->off_SP);
     b.PART = reinterpret_cast<double2*>(c->ws + c->off_PART);
@@ -287,7 +288,7 @@ int lr_bind(lr_ctx_t* c, void* d_ws, size_t bytes, void* stream) {
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) return LR_ERR_HIP;
   if (c->P > 0) {
     for (int pro = 0; pro < 2; ++pro) {
-      const void* fn = lrk::persist_kernel(c->prows, lrk::persist_ge(c->M), pro != 0);
+      const void* fn = lrk::persist_kernel(c->prows, lrk::persist_ge(c->M), pro != 0, c->prec);
       if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->pers_lds) != hipSuccess)
         return LR_ERR_HIP;
     }
@@ -326,6 +327,8 @@ int lr_integrate(lr_ctx_t* c, const lr_pulse_t* pulse, double t0, double dt, int
   v.nsteps = nsteps;
   v.obs = obs_stride > 0 ? d_obs : nullptr;
   v.obs_stride = obs_stride;
+  // the reduced-precision modes exist on the persistent path only
+  if (c->prec != LR_FP64 && (c->P == 0 || std::getenv("LR_NO_PERSIST"))) return LR_ERR_ARG;
   if (c->P > 0 && !std::getenv("LR_NO_PERSIST")) {
     hipLaunchKernelGGL(lrk::k_set_traj, dim3(1), dim3(1), 0, c->stream, dev_traj(c), v);
     hipLaunchKernelGGL(lrk::k_reset, dim3(1), dim3(64), 0, c->stream, dev_traj(c), 1);

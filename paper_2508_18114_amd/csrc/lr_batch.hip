@@ -22,7 +22,7 @@ struct lr_batch {
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   struct Group {
-    int begin, end, wgs, rows, ge;
+    int begin, end, wgs, rows, ge, prec;
     size_t lds;
     int64_t max_steps, chunk;
   };
@@ -69,7 +69,7 @@ int check_model(const lr_model_t& m, int M, int precision) {
   const long long N = (long long)m.d_q * m.d_r * m.d_f;
   if (N > (1LL << 26)) return LR_ERR_ARG;
   if (M < 1 || M > LR_MAX_M || M > N) return LR_ERR_ARG;
-  if (precision != LR_FP64) return LR_ERR_ARG;
+  if (precision != LR_FP64 && precision != LR_FP32 && precision != LR_BF16X3) return LR_ERR_ARG;
   const double vals[] = {m.w_q, m.alpha, m.w_r, m.w_f, m.g, m.G, m.kappa_f, m.gamma_1};
   for (double x : vals)
     if (!std::isfinite(x)) return LR_ERR_ARG;
@@ -77,7 +77,9 @@ int check_model(const lr_model_t& m, int M, int precision) {
   return LR_OK;
 }
 
-const void* persist_fn(int rows, int ge, bool prologue = false) { return lrk::persist_kernel(rows, ge, prologue); }
+const void* persist_fn(int rows, int ge, int prec, bool prologue = false) {
+  return lrk::persist_kernel(rows, ge, prologue, prec);
+}
 
 }  // namespace
 
@@ -91,7 +93,11 @@ int lr_batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n) {
   b->n = n;
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return trajs[x].nsteps > trajs[y].nsteps; });
+  // kernel variants differ by precision mode: one mode per group
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (trajs[x].precision != trajs[y].precision) return trajs[x].precision < trajs[y].precision;
+    return trajs[x].nsteps > trajs[y].nsteps;
+  });
   b->tr.resize(n);
   b->pos.resize(n);
   for (int k = 0; k < n; ++k) {
@@ -116,7 +122,7 @@ int lr_batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n) {
     int e = check_model(x.model, x.M, x.precision);
     if (!e) e = check_pulse(&x.pulse);
     if (!e && (!x.d_B || !std::isfinite(x.t0) || !(x.dt > 0.0) || !std::isfinite(x.dt) || x.nsteps < 0 ||
-               x.obs_stride < 0 || (x.obs_stride > 0 && !x.d_obs)))
+               x.obs_stride < 0 || (x.obs_stride > 0 && !x.d_obs) || x.step0 < 0))
       e = LR_ERR_ARG;
     if (!e && !persist_config(x.model, x.M, b->prt[t], b->P[t], b->rows[t], b->lds[t])) e = LR_ERR_ARG;
     if (e) {
@@ -179,6 +185,7 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
     set_pulse(v, &x.pulse);
     v.t0 = x.t0;
     v.dt = x.dt;
+    v.step_base = x.step0;
     v.Bb = reinterpret_cast<double2*>(base + r);        r = align_up(r + nm, a);
     v.SP = reinterpret_cast<double2*>(base + r);        r = align_up(r + 2 * nm, a);
     v.PART = reinterpret_cast<double2*>(base + r);      r = align_up(r + 2 * P * npe, a);
@@ -194,6 +201,7 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
     v.P = (int)P;
     v.rt = b->prt[t];
     v.npe = 3 * x.M * x.M;
+    v.prec = x.precision;
     for (int w = 0; w < (int)P; ++w) tmap[(size_t)b->wg_offset[t] + w] = make_int2(t, w);
   }
   hipError_t e1 = hipMemcpyAsync(b->ws + b->off_trajs, b->dev.data(), sizeof(TrajDev) * (size_t)b->n,
@@ -209,27 +217,30 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess) return LR_ERR_HIP;
   size_t max_lds = 0;
   for (int t = 0; t < b->n; ++t) max_lds = std::max(max_lds, b->lds[t]);
-  for (int rows = 2; rows <= 3; ++rows)
-    for (int ge = 1; ge <= 2; ++ge)
-      for (int pro = 0; pro < 2; ++pro)
-        if (hipFuncSetAttribute(persist_fn(rows, ge, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)max_lds) != hipSuccess)
-          return LR_ERR_HIP;
-  auto capacity = [&](int rows, int ge, size_t lds) -> int {
+  for (int prec = 0; prec <= 2; ++prec)
+    for (int rows = 2; rows <= 3; ++rows)
+      for (int ge = 1; ge <= 2; ++ge)
+        for (int pro = 0; pro < 2; ++pro)
+          if (hipFuncSetAttribute(persist_fn(rows, ge, prec, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)max_lds) != hipSuccess)
+            return LR_ERR_HIP;
+  auto capacity = [&](int rows, int ge, int prec, size_t lds) -> int {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_fn(rows, ge), lrk::kPW, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_fn(rows, ge, prec), lrk::kPW, lds) !=
+        hipSuccess)
       return 0;
     return per_cu * ncu;
   };
   b->groups.clear();
   int t = 0;
   while (t < b->n) {
-    lr_batch::Group g{t, t, 0, 2, 1, 0, 0, 0};
+    lr_batch::Group g{t, t, 0, 2, 1, b->tr[t].precision, 0, 0, 0};
     while (t < b->n) {
+      if (b->tr[t].precision != g.prec) break;
       const int rows = std::max(g.rows, b->rows[t]);
       const int ge = std::max(g.ge, lrk::persist_ge(b->tr[t].M));
       const size_t lds = std::max(g.lds, b->lds[t]);
-      const int cap = capacity(rows, ge, lds);
+      const int cap = capacity(rows, ge, g.prec, lds);
       if (g.wgs + b->P[t] > cap) {
         if (g.end == g.begin) return LR_ERR_ARG;  // a single trajectory that cannot be co-resident
         break;
@@ -279,7 +290,7 @@ int lr_batch_run(lr_batch_t* b) {
         k = b->n_ev++;
         (void)hipEventRecord(b->ev[2 * k], b->stream);
       }
-      const hipError_t err = hipLaunchCooperativeKernel(persist_fn(g.rows, g.ge, prologue != 0), dim3(g.wgs),
+      const hipError_t err = hipLaunchCooperativeKernel(persist_fn(g.rows, g.ge, g.prec, prologue != 0), dim3(g.wgs),
                                                         dim3(lrk::kPW), args, (unsigned)g.lds, b->stream);
       if (k >= 0) (void)hipEventRecord(b->ev[2 * k + 1], b->stream);
       return err == hipSuccess ? LR_OK : LR_ERR_HIP;

@@ -25,10 +25,11 @@ struct TrajDev {
   int32_t d_q, d_r, d_f, M;
   int32_t N, L, ntiles, obs_stride;
   int64_t nsteps;
+  int64_t step_base;  // global index of step 0 of this call (stage times t0 + (step_base + n) dt)
   // model (rad/ns)
   double w_q, alpha, w_r, w_f, g, G, kappa, gamma;
   // drive
-  int32_t pkind, pad0;
+  int32_t pkind, prec;  // drive kind; arithmetic of the operator/Gram products (LR_FP64/FP32/BF16X3)
   double w_d, amp, t_ramp, T, p[6];
   // time grid
   double t0, dt;

@@ -63,6 +63,93 @@ __device__ __forceinline__ void st_g(g_double2* p, double2 v) {
   d[1] = v.y;
 }
 
+// Arithmetic of the operator applications, the jump assembly and the
+// Gram/cross partials by precision mode PREC (0 = FP64, 1 = FP32,
+// 2 = BF16x3).  In FP32 the operands are rounded to FP32 and products and
+// sums are FP32.  In BF16x3 each FP32 operand is split into BF16 parts
+// x = x_h + x_m + ..., and a product is formed from its three leading part
+// products x_h y_m + x_m y_h + x_h y_h (each exact in FP32) with FP32
+// accumulation -- the split-BF16 product of matrix engines, evaluated here on
+// the vector ALU.  The M x M solve, the cross-workgroup reduction of the
+// partials and the RK4 state and accumulation stay FP64 in every mode.
+// Reduced arithmetic needs the rank padding well above its rounding: with
+// padding columns of norm 1e-6 (G's smallest eigenvalues 1e-12 of its
+// largest) FP32 products drive the padded directions to O(1) errors, with the
+// paper's padding weight 1e-5 they stay at the 1e-6 level.
+// Arithmetic of the Gram G = B^B by mode: FP64 and FP32 as the mode; FP64
+// for BF16x3, whose ~16-bit products do not resolve G's smallest eigenvalues
+// (padding weight 1e-5 of the largest: a Schur complement turns
+// non-positive), while the cross products C_k, the operator applications and
+// the assembly take the split-BF16 arithmetic.
+#define LR_GRAM_PREC(p) ((p) == 2 ? 0 : (p))
+__device__ __forceinline__ float bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xFFFF0000u);
+}
+
+template <int PREC>
+struct Ar {  // FP64
+  typedef double R;
+  typedef double2 C;
+  static __device__ __forceinline__ R in(double v) { return v; }
+  static __device__ __forceinline__ C in(double2 v) { return v; }
+  static __device__ __forceinline__ double2 out(C v) { return v; }
+  static __device__ __forceinline__ R fma(R a, R b, R c) { return ::fma(a, b, c); }
+  static __device__ __forceinline__ R shfl_xor(R v, int m) { return __shfl_xor(v, m); }
+};
+template <>
+struct Ar<1> {  // FP32
+  typedef float R;
+  typedef float2 C;
+  static __device__ __forceinline__ R in(double v) { return (float)v; }
+  static __device__ __forceinline__ C in(double2 v) { return make_float2((float)v.x, (float)v.y); }
+  static __device__ __forceinline__ double2 out(C v) { return make_double2(v.x, v.y); }
+  static __device__ __forceinline__ R fma(R a, R b, R c) { return fmaf(a, b, c); }
+  static __device__ __forceinline__ R shfl_xor(R v, int m) { return __shfl_xor(v, m); }
+};
+template <>
+struct Ar<2> : Ar<1> {  // BF16x3
+  static __device__ __forceinline__ R fma(R a, R b, R c) {
+    const float ah = bf16_rne(a), am = bf16_rne(a - ah);
+    const float bh = bf16_rne(b), bm = bf16_rne(b - bh);
+    c = fmaf(am, bh, c);
+    c = fmaf(ah, bm, c);
+    return fmaf(ah, bh, c);
+  }
+};
+
+// complex forms in the arithmetic of A
+template <class A>
+__device__ __forceinline__ typename A::C amac(typename A::C acc, typename A::C a, typename A::C b) {
+  acc.x = A::fma(a.x, b.x, acc.x);
+  acc.x = A::fma(-a.y, b.y, acc.x);
+  acc.y = A::fma(a.x, b.y, acc.y);
+  acc.y = A::fma(a.y, b.x, acc.y);
+  return acc;
+}
+template <class A>
+__device__ __forceinline__ typename A::C ajmac(typename A::C acc, typename A::C a, typename A::C b) {
+  acc.x = A::fma(a.x, b.x, acc.x);
+  acc.x = A::fma(a.y, b.y, acc.x);
+  acc.y = A::fma(a.x, b.y, acc.y);
+  acc.y = A::fma(-a.y, b.x, acc.y);
+  return acc;
+}
+template <class A>
+__device__ __forceinline__ typename A::C afma(typename A::R s, typename A::C a, typename A::C acc) {
+  acc.x = A::fma(s, a.x, acc.x);
+  acc.y = A::fma(s, a.y, acc.y);
+  return acc;
+}
+template <class A>
+__device__ __forceinline__ typename A::C azero() {
+  typename A::C z;
+  z.x = 0;
+  z.y = 0;
+  return z;
+}
+
 __device__ __forceinline__ void flag_arrive(g_u32* flag, uint32_t value) {
   __syncthreads();
   if (threadIdx.x == 0) __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -105,8 +192,11 @@ __device__ __forceinline__ void publish_boundary(const double2* tile, g_double2*
 
 // v + (v of lane l ^ 32): the two halves of a wave; both lanes get the same
 // bits (the sum is commutative)
-__device__ __forceinline__ double2 add_wave_halves(double2 v) {
-  return make_double2(v.x + __shfl_xor(v.x, 32), v.y + __shfl_xor(v.y, 32));
+template <class A>
+__device__ __forceinline__ typename A::C add_wave_halves(typename A::C v) {
+  v.x += A::shfl_xor(v.x, 32);
+  v.y += A::shfl_xor(v.y, 32);
+  return v;
 }
 
 // Gram / cross partials of the tile (rows x M in LDS) -> dst[3 M^2]:
@@ -120,8 +210,12 @@ __device__ __forceinline__ double2 add_wave_halves(double2 v) {
 // are added across the wave.  Consecutive lanes of a half take consecutive
 // j, so the row reads of a half are bank-conflict free.  Every lane of the
 // block takes the same number of passes, so both partners are always present.
+template <int PREC, int GP>
 __device__ __forceinline__ void persist_partials(const TrajDev& T, const double2* tile, int R, const double* c1row,
                                                  const double* c2row, g_double2* dst) {
+  typedef Ar<PREC> A;
+  typedef typename A::C C;
+  typedef Ar<GP> G;  // arithmetic of the Gram G
   const int M = T.M, MM = M * M, d_f = T.d_f;
   const int nu = ((M + 1) >> 1) * M;   // (i pair, j) units
   const int Rh = (R + 1) >> 1;
@@ -133,34 +227,36 @@ __device__ __forceinline__ void persist_partials(const TrajDev& T, const double2
     const int ip = u / M, j = u - ip * M;
     const int i0 = 2 * ip, i1 = min(i0 + 1, M - 1);
     const int ra = h ? Rh : 0, rb = h ? R : Rh;
-    double2 g0 = make_double2(0.0, 0.0), g1 = g0, a0 = g0, a1 = g0, b0 = g0, b1 = g0;
+    typename G::C g0 = azero<G>(), g1 = g0;
+    C a0 = azero<A>(), a1 = a0, b0 = a0, b1 = a0;
     for (int r = ra; r < rb; ++r) {
       const double2* row = tile + r * M;
-      const double2 x0 = row[i0], x1 = row[i1], y = row[j];
-      const double2 yf = cscale(c1row[r], row[M + j]);
-      const double2 yq = cscale(c2row[r], row[d_f * M + j]);
-      g0 = cjmac(g0, x0, y);
-      g1 = cjmac(g1, x1, y);
-      a0 = cjmac(a0, x0, yf);
-      a1 = cjmac(a1, x1, yf);
-      b0 = cjmac(b0, x0, yq);
-      b1 = cjmac(b1, x1, yq);
+      const double2 xd0 = row[i0], xd1 = row[i1], yd = row[j];
+      g0 = ajmac<G>(g0, G::in(xd0), G::in(yd));
+      g1 = ajmac<G>(g1, G::in(xd1), G::in(yd));
+      const C x0 = A::in(xd0), x1 = A::in(xd1);
+      const C yf = A::in(cscale(c1row[r], row[M + j]));
+      const C yq = A::in(cscale(c2row[r], row[d_f * M + j]));
+      a0 = ajmac<A>(a0, x0, yf);
+      a1 = ajmac<A>(a1, x1, yf);
+      b0 = ajmac<A>(b0, x0, yq);
+      b1 = ajmac<A>(b1, x1, yq);
     }
-    g0 = add_wave_halves(g0);
-    g1 = add_wave_halves(g1);
-    a0 = add_wave_halves(a0);
-    a1 = add_wave_halves(a1);
-    b0 = add_wave_halves(b0);
-    b1 = add_wave_halves(b1);
+    g0 = add_wave_halves<G>(g0);
+    g1 = add_wave_halves<G>(g1);
+    a0 = add_wave_halves<A>(a0);
+    a1 = add_wave_halves<A>(a1);
+    b0 = add_wave_halves<A>(b0);
+    b1 = add_wave_halves<A>(b1);
     if (valid && h == 0) {
       const int o0 = i0 * M + j;
-      st_ag(dst + o0, g0);
-      st_ag(dst + MM + o0, a0);
-      st_ag(dst + 2 * MM + o0, b0);
+      st_ag(dst + o0, G::out(g0));
+      st_ag(dst + MM + o0, A::out(a0));
+      st_ag(dst + 2 * MM + o0, A::out(b0));
       if (i0 + 1 < M) {
-        st_ag(dst + o0 + M, g1);
-        st_ag(dst + MM + o0 + M, a1);
-        st_ag(dst + 2 * MM + o0 + M, b1);
+        st_ag(dst + o0 + M, G::out(g1));
+        st_ag(dst + MM + o0 + M, A::out(a1));
+        st_ag(dst + 2 * MM + o0 + M, A::out(b1));
       }
     }
   }
@@ -340,7 +436,7 @@ __device__ __forceinline__ double gram_fro2(const g_double2* red, int MM, double
 
 // The kernel body: the prologue (partials and reduction of the initial stage
 // input, no step) or a chunk of nchunk RK4 steps from step0.
-template <int ROWS, int GE>
+template <int ROWS, int GE, int PREC>
 __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, const int2* __restrict__ tilemap,
                                              int prologue, int64_t step0, int64_t nchunk) {
   extern __shared__ double2 lds[];
@@ -484,7 +580,7 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
     const int64_t g = 4 * step0;
     const int p = (int)(g & 1);
     __syncthreads();
-    persist_partials(T, tile, R, c1row, c2row, PARTg + ((size_t)p * P + w) * npe);
+    persist_partials<PREC, LR_GRAM_PREC(PREC)>(T, tile, R, c1row, c2row, PARTg + ((size_t)p * P + w) * npe);
     publish_boundary(tile, SPg + (size_t)p * NMn, row0, R, L, M);
     flag_arrive(myA, (uint32_t)(g + 1));
     bool ok = flag_wait(T, flagA, (uint32_t)(g + 1), &s_ok);
@@ -511,10 +607,11 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
   // of its input are in global memory
   load_halo((int)((4 * step0) & 1));
   const double dt = T.dt;
-  // time of stage s of step n: t_n + c_s dt with c = 0, 1/2, 1/2, 1
+  // time of stage s of step n: t_n + c_s dt with c = 0, 1/2, 1/2, 1 and
+  // t_n = t0 + (step_base + n) dt
   auto stage_time = [&](int64_t step, int s) {
     const double c = (s == 0) ? 0.0 : (s == 3 ? 1.0 : 0.5);
-    return T.t0 + (double)step * dt + c * dt;
+    return T.t0 + (double)(T.step_base + step) * dt + c * dt;
   };
   if (tid == 0) s_drv[0] = drive_at(T, stage_time(step0, 0));
   const int64_t nrun = max((int64_t)0, min(nchunk, T.nsteps - step0));  // trajectories of a batch end apart
@@ -553,26 +650,28 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
           const double sf0 = sqt[f], sf1 = sqt[min(f + 1, nq - 1)];
           const double sr0 = sqr[rk], sr1 = sqr[rk + 1];
           const bool rlo = r > 0, rhi = r + 1 < d_r;
-          double2 zz = cmul(make_double2(hr, hi), b);
+          typedef Ar<PREC> A;
+          typedef typename A::R Rr;
+          typename A::C zz = amac<A>(azero<A>(), A::in(make_double2(hr, hi)), A::in(b));
           if (q > 0) {
-            if (rlo) zz = cfma(T.g * sq0 * sr0, col[(rl - d_f - L) * M], zz);
-            if (rhi) zz = cfma(T.g * sq0 * sr1, col[(rl - d_f + L) * M], zz);
+            if (rlo) zz = afma<A>(A::in(T.g * sq0 * sr0), A::in(col[(rl - d_f - L) * M]), zz);
+            if (rhi) zz = afma<A>(A::in(T.g * sq0 * sr1), A::in(col[(rl - d_f + L) * M]), zz);
           }
           if (q + 1 < d_q) {
-            if (rlo) zz = cfma(T.g * sq1 * sr0, col[(rl + d_f - L) * M], zz);
-            if (rhi) zz = cfma(T.g * sq1 * sr1, col[(rl + d_f + L) * M], zz);
+            if (rlo) zz = afma<A>(A::in(T.g * sq1 * sr0), A::in(col[(rl + d_f - L) * M]), zz);
+            if (rhi) zz = afma<A>(A::in(T.g * sq1 * sr1), A::in(col[(rl + d_f + L) * M]), zz);
           }
           if (f > 0) {
-            if (rlo) zz = cfma(T.G * sf0 * sr0, col[(rl - L - 1) * M], zz);
-            if (rhi) zz = cfma(T.G * sf0 * sr1, col[(rl + L - 1) * M], zz);
-            zz = cfma(drv * sf0, col[(rl - 1) * M], zz);
+            if (rlo) zz = afma<A>(A::in(T.G * sf0 * sr0), A::in(col[(rl - L - 1) * M]), zz);
+            if (rhi) zz = afma<A>(A::in(T.G * sf0 * sr1), A::in(col[(rl + L - 1) * M]), zz);
+            zz = afma<A>((Rr)A::in(drv * sf0), A::in(col[(rl - 1) * M]), zz);
           }
           if (f + 1 < d_f) {
-            if (rlo) zz = cfma(T.G * sf1 * sr0, col[(rl - L + 1) * M], zz);
-            if (rhi) zz = cfma(T.G * sf1 * sr1, col[(rl + L + 1) * M], zz);
-            zz = cfma(drv * sf1, col[(rl + 1) * M], zz);
+            if (rlo) zz = afma<A>(A::in(T.G * sf1 * sr0), A::in(col[(rl - L + 1) * M]), zz);
+            if (rhi) zz = afma<A>(A::in(T.G * sf1 * sr1), A::in(col[(rl + L + 1) * M]), zz);
+            zz = afma<A>((Rr)A::in(drv * sf1), A::in(col[(rl + 1) * M]), zz);
           }
-          z[k] = zz;
+          z[k] = A::out(zz);
         }
       }
       // (2) W_k of this stage input
@@ -590,15 +689,17 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
       // coefficient is 0 where the jump leaves the mode); the W entries of
       // column j are loaded once for all rows of the thread.
       {
+        typedef Ar<PREC> A;
+        typedef typename A::C C;
         const double2* y1[ROWS];
         const double2* y2[ROWS];
-        double2 s1[ROWS], s2[ROWS];
+        C s1[ROWS], s2[ROWS];
 #pragma unroll
         for (int k = 0; k < ROWS; ++k) {
           const int rl = min(rg + k * NG, R - 1);  // rows past the tile read a valid row, unused
           y1[k] = tile + (rl + 1) * M;
           y2[k] = tile + (rl + d_f) * M;
-          s1[k] = make_double2(0.0, 0.0);
+          s1[k] = azero<A>();
           s2[k] = s1[k];
         }
         const double2* W1 = Wl + j;
@@ -606,19 +707,20 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
         int i = 0;
         if (ROWS == 2)
           for (; i + 2 <= M; i += 2) {
-            const double2 w1a = W1[i * M], w1b = W1[(i + 1) * M], w2a = W2[i * M], w2b = W2[(i + 1) * M];
+            const C w1a = A::in(W1[i * M]), w1b = A::in(W1[(i + 1) * M]), w2a = A::in(W2[i * M]),
+                    w2b = A::in(W2[(i + 1) * M]);
 #pragma unroll
             for (int k = 0; k < ROWS; ++k) {
-              s1[k] = cmac(cmac(s1[k], y1[k][i], w1a), y1[k][i + 1], w1b);
-              s2[k] = cmac(cmac(s2[k], y2[k][i], w2a), y2[k][i + 1], w2b);
+              s1[k] = amac<A>(amac<A>(s1[k], A::in(y1[k][i]), w1a), A::in(y1[k][i + 1]), w1b);
+              s2[k] = amac<A>(amac<A>(s2[k], A::in(y2[k][i]), w2a), A::in(y2[k][i + 1]), w2b);
             }
           }
         for (; i < M; ++i) {
-          const double2 w1a = W1[i * M], w2a = W2[i * M];
+          const C w1a = A::in(W1[i * M]), w2a = A::in(W2[i * M]);
 #pragma unroll
           for (int k = 0; k < ROWS; ++k) {
-            s1[k] = cmac(s1[k], y1[k][i], w1a);
-            s2[k] = cmac(s2[k], y2[k][i], w2a);
+            s1[k] = amac<A>(s1[k], A::in(y1[k][i]), w1a);
+            s2[k] = amac<A>(s2[k], A::in(y2[k][i]), w2a);
           }
         }
 #pragma unroll
@@ -626,7 +728,7 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
           const int rl = rg + k * NG;
           if (active && rl < R) {
             const double2 zz = z[k];
-            const double2 a = cfma(c2row[rl], s2[k], cscale(c1row[rl], s1[k]));
+            const double2 a = cfma(c2row[rl], A::out(s2[k]), cscale(c1row[rl], A::out(s1[k])));
             const double2 kk = make_double2(zz.y + 0.5 * a.x, -zz.x + 0.5 * a.y);
             double2 o;
             if (s == 0) {
@@ -656,7 +758,7 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
 
       // (4) partials and boundary layers of the next stage input
       const int pn = p ^ 1;
-      persist_partials(T, tile, R, c1row, c2row, PARTg + ((size_t)pn * P + w) * npe);
+      persist_partials<PREC, LR_GRAM_PREC(PREC)>(T, tile, R, c1row, c2row, PARTg + ((size_t)pn * P + w) * npe);
       publish_boundary(tile, SPg + (size_t)pn * NMn, row0, R, L, M);
 
       // (5) group barriers around the slice reduction; a wave that does not
@@ -693,27 +795,34 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
 
 // Chunk of RK4 steps (the integrator proper) and prologue, as separate
 // kernels so that timing tools see the step kernel alone.
-template <int ROWS, int GE>
+template <int ROWS, int GE, int PREC>
 __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ trajs,
                                                  const int2* __restrict__ tilemap, int64_t step0, int64_t nchunk) {
-  persist_body<ROWS, GE>(trajs, tilemap, 0, step0, nchunk);
+  persist_body<ROWS, GE, PREC>(trajs, tilemap, 0, step0, nchunk);
 }
-template <int ROWS, int GE>
+template <int ROWS, int GE, int PREC>
 __global__ __launch_bounds__(kPW) void k_persist_prologue(const TrajDev* __restrict__ trajs,
                                                           const int2* __restrict__ tilemap, int64_t step0,
                                                           int64_t /* nchunk: same signature as k_persist */) {
-  persist_body<ROWS, GE>(trajs, tilemap, 1, step0, 0);
+  persist_body<ROWS, GE, PREC>(trajs, tilemap, 1, step0, 0);
 }
 
-// Kernel variant for ROWS rows per thread and rank M.
+// Kernel variant for ROWS rows per thread, rank M and precision mode.
 inline int persist_ge(int M) { return M * M > kPW ? 2 : 1; }
-inline const void* persist_kernel(int rows, int ge, bool prologue) {
+template <int PREC>
+inline const void* persist_kernel_p(int rows, int ge, bool prologue) {
   if (prologue) {
-    if (rows <= 2) return ge <= 1 ? (const void*)k_persist_prologue<2, 1> : (const void*)k_persist_prologue<2, 2>;
-    return ge <= 1 ? (const void*)k_persist_prologue<3, 1> : (const void*)k_persist_prologue<3, 2>;
+    if (rows <= 2)
+      return ge <= 1 ? (const void*)k_persist_prologue<2, 1, PREC> : (const void*)k_persist_prologue<2, 2, PREC>;
+    return ge <= 1 ? (const void*)k_persist_prologue<3, 1, PREC> : (const void*)k_persist_prologue<3, 2, PREC>;
   }
-  if (rows <= 2) return ge <= 1 ? (const void*)k_persist<2, 1> : (const void*)k_persist<2, 2>;
-  return ge <= 1 ? (const void*)k_persist<3, 1> : (const void*)k_persist<3, 2>;
+  if (rows <= 2) return ge <= 1 ? (const void*)k_persist<2, 1, PREC> : (const void*)k_persist<2, 2, PREC>;
+  return ge <= 1 ? (const void*)k_persist<3, 1, PREC> : (const void*)k_persist<3, 2, PREC>;
+}
+inline const void* persist_kernel(int rows, int ge, bool prologue, int prec) {
+  if (prec == 1) return persist_kernel_p<1>(rows, ge, prologue);
+  if (prec == 2) return persist_kernel_p<2>(rows, ge, prologue);
+  return persist_kernel_p<0>(rows, ge, prologue);
 }
 
 // Zero the barrier flags and the abort flag of every trajectory of a batch.

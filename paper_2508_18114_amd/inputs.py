@@ -181,9 +181,11 @@ class Trajectory:
     dt: float
     nsteps: int
     precision: int = FP64
+    pad_scale: float = 1e-6  # norm of each padding column of B0
 
-    def B0(self, scale: float = 1e-6) -> np.ndarray:
-        return initial_state(self.model, self.M, self.which, self.seed, scale)
+    def B0(self, scale: float = None) -> np.ndarray:
+        return initial_state(self.model, self.M, self.which, self.seed,
+                             self.pad_scale if scale is None else scale)
 
 
 def config_small() -> List[Trajectory]:
@@ -201,6 +203,23 @@ def config_paper_size() -> List[Trajectory]:
     amp = float(draw_amplitudes_ghz(2, 1)[0])
     p = flattop_pulse(amp, 40.0)
     return [Trajectory(m, 20, p, w, seed=2, dt=5e-4, nsteps=80_000) for w in ("g", "e")]
+
+
+# the paper's padding weight p_j = 1e-5 (supplement S1.A, initial condition):
+# padding columns of norm sqrt(1e-5)
+PAPER_PAD_SCALE = 1e-5 ** 0.5
+
+
+def config_paper_size_paper_padding() -> List[Trajectory]:
+    """config_paper_size with the paper's padding weight p_j = 1e-5 instead of
+    the 1e-6 column scale (the reduced-precision modes need padding above their
+    rounding noise)."""
+    return [dataclasses.replace(t, pad_scale=PAPER_PAD_SCALE) for t in config_paper_size()]
+
+
+def config_small_paper_padding() -> List[Trajectory]:
+    """config_small with the paper's padding weight p_j = 1e-5."""
+    return [dataclasses.replace(t, pad_scale=PAPER_PAD_SCALE) for t in config_small()]
 
 
 def config_batched(n_pulses: int = 256, seed: int = 4, dt: float = 5e-4) -> List[Trajectory]:

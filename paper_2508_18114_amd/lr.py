@@ -65,7 +65,7 @@ class lr_traj_t(ctypes.Structure):
     _fields_ = [("model", lr_model_t), ("M", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("pulse", lr_pulse_t), ("t0", ctypes.c_double), ("dt", ctypes.c_double),
                 ("nsteps", ctypes.c_int64), ("d_B", ctypes.c_void_p), ("obs_stride", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("d_obs", ctypes.c_void_p)]
+                ("step0", ctypes.c_int32), ("d_obs", ctypes.c_void_p)]
 
 
 def _load():
@@ -335,9 +335,9 @@ class Context:
 
 
 def traj_struct(model, M, pulse, t0, dt, nsteps, B_dev, obs_stride=0, obs_dev=None,
-                precision=_inp.FP64) -> lr_traj_t:
+                precision=_inp.FP64, step0=0) -> lr_traj_t:
     return lr_traj_t(model_struct(model), M, precision, pulse_struct(pulse), t0, dt, nsteps,
-                     B_dev.data_ptr(), obs_stride, 0, obs_dev.data_ptr() if obs_dev is not None else 0)
+                     B_dev.data_ptr(), obs_stride, step0, obs_dev.data_ptr() if obs_dev is not None else 0)
 
 
 class Batch:
@@ -345,14 +345,18 @@ class Batch:
 
     items: sequence of dicts with keys model, M, pulse, dt, nsteps, B (device
     tensor (M, N) complex128), and optionally t0, obs_stride, obs (device
-    tensor).  The tensors must stay alive while the batch is used.
+    tensor), precision (FP64 / FP32 / BF16X3), step0 (index of the first step
+    when a trajectory is continued).  The tensors must stay alive while the
+    batch is used.
     """
 
     def __init__(self, items, stream=None):
         import torch
         self.items = list(items)
         ts = [traj_struct(it["model"], it["M"], it["pulse"], it.get("t0", 0.0), it["dt"], it["nsteps"],
-                          it["B"], it.get("obs_stride", 0), it.get("obs")) for it in self.items]
+                          it["B"], it.get("obs_stride", 0), it.get("obs"), it.get("precision", _inp.FP64),
+                          it.get("step0", 0))
+              for it in self.items]
         self.handle = lr_batch_init(ts)
         nbytes = lr_batch_workspace_bytes(self.handle)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")

@@ -1,0 +1,267 @@
+"""Serving loop for readout-loss evaluations: continuous batching of low-rank
+trajectories on one GPU.
+
+A request is one loss evaluation of a pulse candidate (supplement S3.B-C):
+the transmon starts in g and in e, both trajectories are integrated with the
+same drive, and the figures of merit of the pair (lr_readout_loss) are its
+result.  The server keeps every admitted trajectory's state B and its
+observation series resident on the device and advances all of them together
+in ticks: each tick is one lr_batch_run over the active trajectories, each
+moving ahead by up to `chunk` RK4 steps (`step0` continues the stage-time grid
+exactly, so a trajectory's result is bitwise the same whether it runs alone or
+in any mix, in one call or in many).  Between ticks, finished requests are
+retired and queued ones are admitted while their HBM footprint fits the
+budget and their workgroups fit the co-resident capacity.
+
+`EvolutionStrategy` is the gradient-free request source: a (mu, lambda)
+evolution strategy over the six Piecewise6 parameters that emits generations
+of candidates and moves its mean to the best of each finished generation.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import inputs as I
+from . import lr
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    model: I.ModelParams
+    M: int
+    pulse: I.PulseParams
+    dt: float
+    nsteps: int
+    precision: int = I.FP64
+    obs_stride: int = 200
+    pad_scale: float = I.PAPER_PAD_SCALE
+    seed: int = 0
+    arrival: float = 0.0          # seconds, relative to the start of the run
+
+
+@dataclasses.dataclass
+class _Traj:
+    req: Request
+    which: str
+    B: object                     # device tensor (M, N) complex128
+    obs: object                   # device tensor (records, 6 + d_q)
+    done: int = 0
+
+
+def trajectory_footprint(model: I.ModelParams, M: int, obs_records: int) -> int:
+    """Device bytes of one resident trajectory: state, observation series and
+    its share of a batch workspace (planned on the host, nothing allocated)."""
+    import torch
+    B = torch.empty((1,), dtype=torch.complex128)  # placeholder pointer, never dereferenced by planning
+    t = lr.traj_struct(model, M, I.flattop_pulse(0.05, 1.0), 0.0, 1e-3, 1, B, 0, None)
+    h = lr.lr_batch_init([t])
+    try:
+        ws = lr.lr_batch_workspace_bytes(h)
+    finally:
+        lr.lr_batch_destroy(h)
+    return ws + model.N * M * 16 + obs_records * (6 + model.d_q) * 8
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes: int, chunk: int = 2000, max_workgroups: Optional[int] = None,
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.budget = int(hbm_budget_bytes)
+        self.chunk = int(chunk)
+        props = torch.cuda.get_device_properties(0)
+        self.wg_cap = int(max_workgroups or props.multi_processor_count)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.queue: List[Request] = []
+        self.active: List[_Traj] = []
+        self.in_use = 0
+        self.wg_in_use = 0
+        self.results: Dict[int, dict] = {}
+        self.t_start = None
+        self.steps_done = 0
+        self.ticks = 0
+
+    # -------------------------------------------------------------- admission
+    def _need(self, r: Request):
+        nrec = r.nsteps // r.obs_stride + 1
+        fp = 2 * trajectory_footprint(r.model, r.M, nrec)
+        wgs = 2 * r.model.d_r  # one workgroup per resonator layer and trajectory
+        return fp, wgs
+
+    def submit(self, r: Request):
+        if r.nsteps % r.obs_stride:
+            raise ValueError("nsteps must be a multiple of obs_stride")
+        if self._need(r)[0] > self.budget:  # could never be admitted
+            self.results[r.rid] = {"arrival": r.arrival, "error": "footprint exceeds the HBM budget"}
+            return
+        self.queue.append(r)
+
+    def _admit(self, now: float):
+        torch = self.torch
+        keep = []
+        for r in self.queue:
+            fp, wgs = self._need(r)
+            fits = (r.arrival <= now and self.in_use + fp <= self.budget and
+                    (self.wg_in_use + wgs <= self.wg_cap or not self.active))
+            if not fits:
+                keep.append(r)
+                continue
+            nrec = r.nsteps // r.obs_stride + 1
+            for which in ("g", "e"):
+                B0 = I.initial_state(r.model, r.M, which, r.seed, r.pad_scale)
+                obs = torch.zeros((nrec, 6 + r.model.d_q), dtype=torch.float64, device="cuda")
+                self.active.append(_Traj(r, which, lr.to_device(B0), obs))
+            self.in_use += fp
+            self.wg_in_use += wgs
+            self.results[r.rid] = {"arrival": r.arrival, "admitted": now}
+        self.queue = keep
+
+    # -------------------------------------------------------------- one tick
+    def tick(self):
+        """Advance every active trajectory by up to `chunk` steps (one batch launch sequence)."""
+        torch = self.torch
+        items = []
+        for t in self.active:
+            r = t.req
+            n = min(self.chunk, r.nsteps - t.done)
+            if n <= 0:
+                continue
+            if n < r.nsteps - t.done:
+                n -= n % r.obs_stride  # keep record boundaries aligned
+                n = max(n, r.obs_stride)
+            items.append((t, dict(model=r.model, M=r.M, pulse=r.pulse, t0=0.0, dt=r.dt, nsteps=n, B=t.B,
+                                  obs_stride=r.obs_stride, obs=t.obs[t.done // r.obs_stride:],
+                                  precision=r.precision, step0=t.done)))
+        if not items:
+            return
+        b = lr.Batch([it for _, it in items], stream=self.stream)
+        b.run()
+        rc, codes, steps = b.status()
+        for (t, it), c in zip(items, codes):
+            if c != lr.LR_OK:
+                self.results[t.req.rid]["error"] = lr.lr_strerror(c)
+                t.done = t.req.nsteps
+            else:
+                t.done += it["nsteps"]
+                self.steps_done += it["nsteps"]
+        b.close()
+        self.ticks += 1
+
+    def _retire(self, now: float):
+        by_req: Dict[int, List[_Traj]] = {}
+        for t in self.active:
+            by_req.setdefault(t.req.rid, []).append(t)
+        still = []
+        for rid, ts in by_req.items():
+            r = ts[0].req
+            if all(t.done >= r.nsteps for t in ts):
+                res = self.results[rid]
+                if "error" not in res:
+                    tg = next(t for t in ts if t.which == "g")
+                    te = next(t for t in ts if t.which == "e")
+                    res["loss"] = lr.readout_loss(tg.obs, te.obs, r.model.d_q, r.obs_stride * r.dt,
+                                                  r.model.kappa_f, r.model.gamma_1, stream=self.stream)
+                    res["B_g"], res["B_e"] = tg.B, te.B
+                    res["obs_g"], res["obs_e"] = tg.obs, te.obs
+                res["done"] = now
+                res["latency"] = now - r.arrival
+                fp, wgs = self._need(r)
+                self.in_use -= fp
+                self.wg_in_use -= wgs
+            else:
+                still.extend(ts)
+        self.active = still
+
+    # -------------------------------------------------------------- run
+    def run(self, requests: List[Request], on_result=None):
+        """Serve requests with open-loop arrivals (Request.arrival, seconds from
+        now).  on_result(rid, result) is called as results complete and may
+        submit further requests.  Returns the statistics of the run."""
+        for r in requests:
+            self.submit(r)
+        t0 = time.perf_counter()
+        self.t_start = t0
+        reported = set()
+        while self.queue or self.active:
+            now = time.perf_counter() - t0
+            self._admit(now)
+            if not self.active:
+                nxt = min(r.arrival for r in self.queue)
+                time.sleep(max(0.0, min(nxt - now, 0.05)))
+                continue
+            self.tick()
+            self._retire(time.perf_counter() - t0)
+            if on_result is not None:
+                for rid, res in list(self.results.items()):
+                    if "done" in res and rid not in reported:
+                        reported.add(rid)
+                        on_result(rid, res)
+        wall = time.perf_counter() - t0
+        lat = np.array([res["latency"] for res in self.results.values() if "latency" in res])
+        return {"requests": len(lat), "wall_s": wall, "traj_steps": self.steps_done,
+                "traj_steps_per_s": self.steps_done / wall if wall > 0 else 0.0, "ticks": self.ticks,
+                "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else math.nan,
+                "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else math.nan,
+                "errors": sum(1 for res in self.results.values() if "error" in res)}
+
+
+class EvolutionStrategy:
+    """(mu, lambda) evolution strategy over the Piecewise6 parameters
+    (A_1, phi_1, Delta_1, A_2, phi_2, Delta_2) in rad/ns and rad."""
+
+    LO = np.array([I.ghz(0.02), 0.0, I.ghz(-0.02), I.ghz(0.02), 0.0, I.ghz(-0.02)])
+    HI = np.array([I.ghz(0.1), 2 * np.pi, I.ghz(0.02), I.ghz(0.1), 2 * np.pi, I.ghz(0.02)])
+
+    def __init__(self, seed: int, lam: int = 32, mu: int = 8, sigma: float = 0.15):
+        self.rng = I.rng(seed)
+        self.lam, self.mu, self.sigma = lam, mu, sigma
+        self.mean = 0.5 * (self.LO + self.HI)
+        self.generation = 0
+
+    def ask(self) -> List[np.ndarray]:
+        span = self.HI - self.LO
+        out = []
+        for _ in range(self.lam):
+            x = self.mean + self.sigma * span * self.rng.standard_normal(6)
+            out.append(np.clip(x, self.LO, self.HI))
+        return out
+
+    def tell(self, cands: List[np.ndarray], losses: List[float]):
+        order = np.argsort(np.asarray(losses))[: self.mu]
+        self.mean = np.mean([cands[i] for i in order], axis=0)
+        self.generation += 1
+
+
+def pulse_from(x: np.ndarray, T: float) -> I.PulseParams:
+    return I.PulseParams(kind=I.PULSE_PIECEWISE6, w_d=I.W_DRIVE, amp=0.0, t_ramp=I.T_RAMP, T=T,
+                         p=tuple(float(v) for v in x))
+
+
+def serving_requests(seed: int, n: int, rate_per_s: float, dt: float = 5e-4, step_cap: Optional[int] = None,
+                     obs_stride: int = 200, es_seed: int = 5) -> List[Request]:
+    """n requests of the serving workload: shapes from inputs.serving_request_shapes
+    (d_r in [13, 75], M in [4, 32], T in [10, 60] ns, FP32 / FP64), pulses from
+    the evolution strategy's first generations, open-loop Poisson arrivals at
+    rate_per_s.  step_cap (if given) bounds each request's step count."""
+    shapes = I.serving_request_shapes(seed, n, dt)
+    arr = I.poisson_arrivals(seed, n, rate_per_s)
+    es = EvolutionStrategy(es_seed)
+    cands: List[np.ndarray] = []
+    out = []
+    for k, sh in enumerate(shapes):
+        if not cands:
+            cands = es.ask()
+        nsteps = sh["nsteps"] if step_cap is None else min(sh["nsteps"], step_cap)
+        nsteps -= nsteps % obs_stride
+        nsteps = max(nsteps, obs_stride)
+        m = I.readout_model(8, sh["d_r"], 5)
+        out.append(Request(rid=k, model=m, M=sh["M"], pulse=pulse_from(cands.pop(), nsteps * dt), dt=dt,
+                           nsteps=nsteps, precision=sh["precision"], obs_stride=obs_stride,
+                           seed=seed * 1000 + k, arrival=float(arr[k])))
+    return out

@@ -7,6 +7,8 @@ Calls only the CPU oracle and the seeded input generators.  Usage:
 Outputs (numpy .npz, one per named workload):
     tests/golden/config_small.npz       dims (4,10,5),  M=4,  1e4 steps of 1e-3 ns
     tests/golden/config_paper_size.npz  dims (8,50,5),  M=20, 8e4 steps of 5e-4 ns
+    tests/golden/config_small_paper_padding.npz, config_paper_size_paper_padding.npz
+                                        the same with the paper's padding weight 1e-5
 each holding obs_g, obs_e (observable records every `stride` steps), the
 stride, dt, and the readout figures of merit from the g/e pair.
 """
@@ -26,12 +28,15 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 from oracle import loss, lowrank  # noqa: E402
 from paper_2508_18114_amd import inputs as I  # noqa: E402
 
-STRIDES = {"small": 100, "paper_size": 200}
+STRIDES = {"small": 100, "paper_size": 200, "small_paper_padding": 100, "paper_size_paper_padding": 200}
+CONFIGS = {"small": I.config_small, "paper_size": I.config_paper_size,
+           "small_paper_padding": I.config_small_paper_padding,
+           "paper_size_paper_padding": I.config_paper_size_paper_padding}
 
 
 def _run(args):
     name, idx = args
-    traj = (I.config_small() if name == "small" else I.config_paper_size())[idx]
+    traj = CONFIGS[name]()[idx]
     t0 = time.time()
     _, obs = lowrank.integrate(traj.model, traj.pulse, 0.0, traj.dt, traj.nsteps,
                                traj.B0(), obs_stride=STRIDES[name])
@@ -39,7 +44,7 @@ def _run(args):
 
 
 def make(name):
-    trajs = I.config_small() if name == "small" else I.config_paper_size()
+    trajs = CONFIGS[name]()
     with Pool(2) as pool:
         (obs_g, tg), (obs_e, te) = pool.map(_run, [(name, 0), (name, 1)])
     tr = trajs[0]
@@ -54,5 +59,5 @@ def make(name):
 
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "all"
-    for nm in (["small", "paper_size"] if which == "all" else [which]):
+    for nm in (list(CONFIGS) if which == "all" else [which]):
         make(nm)
