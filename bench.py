@@ -18,6 +18,7 @@ The JSON also carries
                    workload on the host cores.
 """
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -68,6 +69,7 @@ def cpu_baseline(nsteps):
 
 def comparisons(lr, I, torch, stream, plain_value):
     """Throughput of the other forms on the same GPU (bounded samples)."""
+    import numpy as np
     out = {}
     trajs = I.config_paper_size()
     m, M = trajs[0].model, trajs[0].M
@@ -131,6 +133,46 @@ def comparisons(lr, I, torch, stream, plain_value):
         "speedup_lowrank_vs_dense": (dms * 1e-3) * single,
         "workload": f"dense rho {N}x{N} FP64, same model/drive/dt, {dsteps} steps timed; full trajectory = "
                     f"{nfull} steps (extrapolated)"}
+    # reduced-precision modes (paper padding weight), g + e batch, same step count
+    steps = 2000
+    for name, prec in (("fp64", 0), ("fp32", 1), ("bf16x3", 2)):
+        tl = [dataclasses.replace(t, precision=prec) for t in I.config_paper_size_paper_padding()]
+        items = [dict(model=t.model, M=t.M, pulse=t.pulse, dt=t.dt, nsteps=steps, precision=prec,
+                      B=lr.to_device(t.B0())) for t in tl]
+        b = lr.Batch(items, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        if b.status()[0] != lr.LR_OK:
+            raise RuntimeError(f"precision {name} failed")
+        out.setdefault("precision_modes", {})[name] = {
+            "value": 2 * steps / el, "unit": "RK steps*trajectories/s",
+            "workload": f"g+e, N=2000, M=20, padding weight 1e-5, {steps} steps"}
+    # serving: requests of the serving workload (step count capped), saturation,
+    # the literal 50/s arrival rate, and 0.7 x the measured capacity
+    from paper_2508_18114_amd import serve
+    n_req, cap = 12, 4000
+    budget = 64 << 30
+
+    def serve_run(rate):
+        reqs = serve.serving_requests(5, n_req, rate, step_cap=cap)
+        srv = serve.Server(hbm_budget_bytes=budget, chunk=2000, stream=stream)
+        st = srv.run(reqs)
+        st["offered_rate_per_s"] = rate
+        return st, reqs
+
+    sat, reqs = serve_run(1e9)
+    mean_steps = float(np.mean([r.nsteps for r in reqs]))
+    capacity = sat["traj_steps_per_s"] / (2 * mean_steps)
+    lit, _ = serve_run(50.0)
+    sub, _ = serve_run(0.7 * capacity)
+    out["serving"] = {"saturation": sat, "literal_50_per_s": lit, "sub_saturation_0.7x": sub,
+                      "capacity_evals_per_s": capacity,
+                      "workload": f"{n_req} loss evaluations (g+e each) with the serving shapes (d_r 13-75, "
+                                  f"M 4-32, FP32/FP64), step count capped at {cap}, padding weight 1e-5, "
+                                  f"HBM budget {budget >> 30} GiB"}
     return out
 
 
