@@ -512,66 +512,78 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
   const int cs = (npe + P - 1) / P;
   const int e0 = w * cs, e1 = min(npe, e0 + cs), ne = max(0, e1 - e0);
 
-  // slice reduction of the partials of parity `par`: all loads in flight at
-  // once into LDS; then each entry is summed by a 16-lane group (lane l adds
-  // workgroups l, l + 16, ... in order, then a butterfly over the group), so
-  // the order depends on P only
-  auto reduce_slice = [&](int par) {
-    const g_double2* src = PARTg + (size_t)par * P * npe;
-    const int nit = ne * P;
-    for (int base_it = 0; base_it < nit; base_it += 8 * kPW) {
-      double2 v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int it = min(base_it + tid + u * kPW, nit - 1);
-        const int pp = it / ne, e = it - pp * ne;
-        v[u] = ld_ag(src + (size_t)pp * npe + e0 + e);
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int it = base_it + tid + u * kPW;
-        if (it < nit) RB[it] = v[u];
-      }
-    }
-    __syncthreads();
-    g_double2* dst = REDg + (size_t)par * npe + e0;
-    const int sub = tid & 15, grp = tid >> 4;
-    for (int eb = 0; eb < ne; eb += kPW / 16) {
-      const int e = eb + grp, ec = min(e, ne - 1);
-      double2 sum = make_double2(0.0, 0.0);
-      for (int pp = sub; pp < P; pp += 16) sum = cadd(sum, RB[pp * ne + ec]);
-#pragma unroll
-      for (int off = 8; off > 0; off >>= 1) {
-        sum.x += __shfl_xor(sum.x, off, 16);
-        sum.y += __shfl_xor(sum.y, off, 16);
-      }
-      if (sub == 0 && e < ne) st_ag(dst + e, sum);
-    }
-  };
-  auto load_halo = [&](int par) {
-    const g_double2* src = SPg + (size_t)par * NMn;
+  // Exchange after group barrier A for the stage input of parity `par`: the
+  // two halo layers (published boundary layers of the neighbours; zero past
+  // the ends) into SL, and the slice reduction of the partials.  Each slice
+  // entry is summed by a 16-lane group straight from global memory: lane l
+  // adds workgroups l, l + 16, ... in order, then a butterfly over the group,
+  // so the order depends on P only.  The halo loads and the first batch of
+  // partial loads are in flight together.
+  auto exchange = [&](int par, bool halo) {
+    const g_double2* hsrc = SPg + (size_t)par * NMn;
     const size_t lo_base = r0 > 0 ? (size_t)(row0 - L) * M : 0;
     const size_t hi_base = r1 < d_r ? (size_t)(row0 + R) * M : 0;
-    for (int base_idx = 0; base_idx < 2 * LM; base_idx += 4 * kPW) {
-      double2 v[4];
+    const g_double2* psrc = PARTg + (size_t)par * P * npe + e0;
+    g_double2* dst = REDg + (size_t)par * npe + e0;
+    const int nh = halo ? 2 * LM : 0;
+    const int sub = tid & 15, grp = tid >> 4;
+    constexpr int kPB = 8;  // partial loads per lane in flight
+    for (int b = 0; b * 4 * kPW < nh || b * (kPW / 16) < ne; ++b) {
+      const int hb = b * 4 * kPW, e = b * (kPW / 16) + grp;
+      const bool doh = hb < nh, dop = b * (kPW / 16) < ne;  // uniform
+      const int ec = min(e, ne - 1);
+      double2 hv[4], pv[kPB];
+      if (doh) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int idx = min(base_idx + tid + u * kPW, 2 * LM - 1);
-        const bool lo = idx < LM;
-        const int off = lo ? idx : idx - LM;
-        v[u] = ld_ag(src + (lo ? lo_base : hi_base) + off);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int idx = base_idx + tid + u * kPW;
-        if (idx < 2 * LM) {
+        for (int u = 0; u < 4; ++u) {
+          const int idx = min(hb + tid + u * kPW, nh - 1);
           const bool lo = idx < LM;
-          const int off = lo ? idx : idx - LM;
-          const bool have = lo ? r0 > 0 : r1 < d_r;
-          const double2 val = have ? v[u] : make_double2(0.0, 0.0);
-          if (lo) SL[off] = val;
-          else SL[(size_t)(R + L) * M + off] = val;
+          hv[u] = ld_ag(hsrc + (lo ? lo_base : hi_base) + (lo ? idx : idx - LM));
         }
+      }
+      double2 sum = make_double2(0.0, 0.0);
+      for (int pb = 0; dop && pb < P; pb += 16 * kPB) {
+#pragma unroll
+        for (int u = 0; u < kPB; ++u) pv[u] = ld_ag(psrc + (size_t)min(pb + sub + 16 * u, P - 1) * npe + ec);
+        if (doh && pb == 0) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int idx = hb + tid + u * kPW;
+            if (idx < nh) {
+              const bool lo = idx < LM;
+              const int off = lo ? idx : idx - LM;
+              const bool have = lo ? r0 > 0 : r1 < d_r;
+              const double2 val = have ? hv[u] : make_double2(0.0, 0.0);
+              if (lo) SL[off] = val;
+              else SL[(size_t)(R + L) * M + off] = val;
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kPB; ++u)
+          if (pb + sub + 16 * u < P) sum = cadd(sum, pv[u]);
+      }
+      if (doh && !dop) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int idx = hb + tid + u * kPW;
+          if (idx < nh) {
+            const bool lo = idx < LM;
+            const int off = lo ? idx : idx - LM;
+            const bool have = lo ? r0 > 0 : r1 < d_r;
+            const double2 val = have ? hv[u] : make_double2(0.0, 0.0);
+            if (lo) SL[off] = val;
+            else SL[(size_t)(R + L) * M + off] = val;
+          }
+        }
+      }
+      if (dop) {
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {
+          sum.x += __shfl_xor(sum.x, off, 16);
+          sum.y += __shfl_xor(sum.y, off, 16);
+        }
+        if (sub == 0 && e < ne) st_ag(dst + e, sum);
       }
     }
   };
@@ -585,7 +597,7 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
     flag_arrive(myA, (uint32_t)(g + 1));
     bool ok = flag_wait(T, flagA, (uint32_t)(g + 1), &s_ok);
     if (ok) {
-      reduce_slice(p);
+      exchange(p, false);
       flag_arrive(myB, (uint32_t)(g + 1));
       ok = flag_wait(T, flagB, (uint32_t)(g + 1), &s_ok);
     }
@@ -605,7 +617,20 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
 
   // chunk: the reduction of stage 4*step0 and the published boundary layers
   // of its input are in global memory
-  load_halo((int)((4 * step0) & 1));
+  {  // halo layers of the first stage input (published by the prologue or the previous chunk)
+    const int par = (int)((4 * step0) & 1);
+    const g_double2* hsrc = SPg + (size_t)par * NMn;
+    const size_t lo_base = r0 > 0 ? (size_t)(row0 - L) * M : 0;
+    const size_t hi_base = r1 < d_r ? (size_t)(row0 + R) * M : 0;
+    for (int idx = tid; idx < 2 * LM; idx += kPW) {
+      const bool lo = idx < LM;
+      const int off = lo ? idx : idx - LM;
+      const bool have = lo ? r0 > 0 : r1 < d_r;
+      const double2 val = have ? ld_ag(hsrc + (lo ? lo_base : hi_base) + off) : make_double2(0.0, 0.0);
+      if (lo) SL[off] = val;
+      else SL[(size_t)(R + L) * M + off] = val;
+    }
+  }
   const double dt = T.dt;
   // time of stage s of step n: t_n + c_s dt with c = 0, 1/2, 1/2, 1 and
   // t_n = t0 + (step_base + n) dt
@@ -758,8 +783,8 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
 
       // (4) partials and boundary layers of the next stage input
       const int pn = p ^ 1;
+      publish_boundary(tile, SPg + (size_t)pn * NMn, row0, R, L, M);  // stores drain during the partials
       persist_partials<PREC, LR_GRAM_PREC(PREC)>(T, tile, R, c1row, c2row, PARTg + ((size_t)pn * P + w) * npe);
-      publish_boundary(tile, SPg + (size_t)pn * NMn, row0, R, L, M);
 
       // (5) group barriers around the slice reduction; a wave that does not
       // poll computes the drive value of the next stage meanwhile
@@ -767,8 +792,7 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
       if (tid == 64) s_drv[(s + 1) & 1] = drive_at(T, s == 3 ? stage_time(step + 1, 0) : stage_time(step, s + 1));
       ok = flag_wait(T, flagA, (uint32_t)(g + 2), &s_ok);
       if (!ok) break;
-      load_halo(pn);
-      reduce_slice(pn);
+      exchange(pn, true);
       flag_arrive(myB, (uint32_t)(g + 2));
       ok = flag_wait(T, flagB, (uint32_t)(g + 2), &s_ok);
       if (!ok) break;
