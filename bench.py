@@ -176,6 +176,27 @@ def comparisons(lr, I, torch, stream, plain_value):
     return out
 
 
+def measured_traffic_per_step():
+    """HBM bytes per g+e RK4 step of k_persist from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel source changed
+    since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_persist_paper_size_traffic.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_b = re.search(r"^traffic_bytes_per_step: (\S+)$", txt, re.M)
+    m_h = re.search(r"^source_sha256: (\S+)$", txt, re.M)
+    if not (m_b and m_h):
+        return None
+    h = hashlib.sha256()
+    for f in ("paper_2508_18114_amd/csrc/lr_persistent.hip", "paper_2508_18114_amd/csrc/lr_device.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return float(m_b.group(1)) if h.hexdigest() == m_h.group(1) else None
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -226,6 +247,9 @@ def main():
     flops_per_step = 4 * m.N * M * (58 + 40 * M)
     flops_per_launch = flops_per_step * steps_per_launch * len(trajs)
     achieved = flops_per_launch / (launch_us * 1e-6) / 1e12
+    # measured HBM bytes per launch (rocprofv3 counters, calibrated by a copy)
+    tps = measured_traffic_per_step()
+    traffic = tps * steps_per_launch if tps is not None else None
 
     out = {
         "metric": "RK steps*trajectories/s at N=2000, M=20",
@@ -244,7 +268,7 @@ def main():
                                "trajectories g and e integrated together (one batch)",
                    "N": m.N, "M": M, "trajectories": len(trajs), "dt_ns": trajs[0].dt},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFS, "traffic": None,
+                     "frac": achieved / FP64_PEAK_TFS, "traffic": traffic,
                      "kernel": "k_persist", "kernel_mean_us": launch_us, "launches_timed": launches,
                      "steps_per_launch": steps_per_launch, "trajectories_per_launch": len(trajs),
                      "flops_per_launch": flops_per_launch},
