@@ -17,6 +17,8 @@ Modules
               the low-rank path is pinned against on tiny Hilbert spaces
   loss     -- readout figures of merit (supplement S3.A-B: SNR, separation
               and decay errors, ionisation penalty, loss)
+  validity -- spectrum p_1 >= ... >= p_M of the low-rank rho, the control
+              quantity p_M / p_1 and the purity (supplement S1.B)
 
 Every function is written in the notation of the paper, step by step, with
 numpy/scipy library primitives (matmul, Cholesky, triangular solve, erfc) as

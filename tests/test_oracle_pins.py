@@ -11,7 +11,7 @@ import pytest
 import scipy.integrate
 import scipy.linalg
 
-from oracle import dense, loss, lowrank, pulses
+from oracle import dense, loss, lowrank, pulses, validity
 from paper_2508_18114_amd import inputs as I
 
 
@@ -270,6 +270,44 @@ def test_observables_match_dense_trace_formulas():
     B = _rand_B(m.N, 3, 15)
     np.testing.assert_allclose(lowrank.observables(m, B), dense.observables(m, B @ B.conj().T),
                                rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------------ validity (S1.B)
+
+def test_spectrum_is_the_nonzero_spectrum_of_rho():
+    """p_j (eigenvalues of B^ B) are the M nonzero eigenvalues of the N x N rho = B B^."""
+    B = _rand_B(14, 4, 21)
+    p = validity.spectrum(B)
+    ev = np.sort(np.linalg.eigvalsh(B @ B.conj().T))[::-1]
+    np.testing.assert_allclose(p, ev[:4], rtol=1e-12, atol=1e-12 * p[0])
+    assert np.all(np.abs(ev[4:]) < 1e-12 * p[0])
+    np.testing.assert_allclose(validity.dense_top(B @ B.conj().T, 4), p, rtol=1e-12, atol=1e-12 * p[0])
+
+
+def test_spectrum_of_weighted_orthonormal_columns():
+    """Columns sqrt(p_j) psi_j with orthonormal psi_j (eq. "lowrank_diagonal") give back p_j;
+    the purity is sum p_j^2 and matches tr(rho^2) of the observation record."""
+    m = _model(3, 5, 2)
+    r = np.random.default_rng(22)
+    Q, _ = np.linalg.qr(r.standard_normal((m.N, 5)) + 1j * r.standard_normal((m.N, 5)))
+    p = np.array([0.7, 0.2, 0.05, 1e-5, 1e-9])
+    B = Q * np.sqrt(p)
+    got = validity.spectrum(B)
+    np.testing.assert_allclose(got, p, rtol=1e-12, atol=1e-15)
+    assert validity.control_ratio(got) == pytest.approx(1e-9 / 0.7, rel=1e-6)
+    assert validity.purity(got) == pytest.approx(float(np.sum(p ** 2)), rel=1e-13)
+    assert validity.purity(got) == pytest.approx(lowrank.observables(m, B)[5], rel=1e-12)
+
+
+def test_spectrum_unitary_invariance_and_trace():
+    """rho = B B^ does not change under B -> B U (U unitary), nor do the p_j; sum p_j = tr rho."""
+    B = _rand_B(20, 6, 23)
+    r = np.random.default_rng(24)
+    U, _ = np.linalg.qr(r.standard_normal((6, 6)) + 1j * r.standard_normal((6, 6)))
+    p = validity.spectrum(B)
+    np.testing.assert_allclose(validity.spectrum(B @ U), p, rtol=1e-12, atol=1e-12 * p[0])
+    assert float(np.sum(p)) == pytest.approx(float(np.vdot(B, B).real), rel=1e-13)
+    assert np.all(np.diff(p) <= 0)
 
 
 # ------------------------------------------------------------ pulses
