@@ -168,11 +168,82 @@ def comparisons(lr, I, torch, stream, plain_value):
     capacity = sat["traj_steps_per_s"] / (2 * mean_steps)
     lit, _ = serve_run(50.0)
     sub, _ = serve_run(0.7 * capacity)
+    out["validity_rank_study"] = validity_study(lr, I, torch)
     out["serving"] = {"saturation": sat, "literal_50_per_s": lit, "sub_saturation_0.7x": sub,
                       "capacity_evals_per_s": capacity,
                       "workload": f"{n_req} loss evaluations (g+e each) with the serving shapes (d_r 13-75, "
                                   f"M 4-32, FP32/FP64), step count capped at {cap}, padding weight 1e-5, "
                                   f"HBM budget {budget >> 30} GiB"}
+    return out
+
+
+def validity_study(lr, I, torch):
+    """Supplement S1.B on the small readout model (N=200, flat-top drive, 1e4
+    steps, padding weight 1e-5): the control quantity p_M/p_1 and the purity
+    tr rho^2 / (tr rho)^2 of the low-rank state against the full master
+    equation (dense GPU solve, its spectrum from numpy on the host), and the
+    SNR and assignment error eps_a of the g/e pair against the full ones, for
+    several ranks M.  (The padding adds (M-1) 1e-5 to tr rho, hence the
+    normalised purity.)"""
+    import numpy as np
+    base = I.config_small_paper_padding()
+    m, pulse, dt, nsteps = base[0].model, base[0].pulse, base[0].dt, base[0].nsteps
+    stride, nck = 100, 5
+    ck = nsteps // nck
+    cs = ck // stride
+    nrec = nsteps // stride + 1
+
+    def full(which):
+        n0 = I.basis_index(m, 0 if which == "g" else 1, 0, 0)
+        rho = torch.zeros((m.N, m.N), dtype=torch.complex128, device="cuda")
+        rho[n0, n0] = 1.0
+        obs = torch.zeros((nrec, 6 + m.d_q), dtype=torch.float64, device="cuda")
+        ws, ev = None, []
+        for k in range(nck):
+            ws = lr.dense_integrate(m, pulse, k * ck * dt, dt, ck, rho, stride, obs[k * cs:], workspace=ws)
+            ev.append(np.sort(np.linalg.eigvalsh(rho.cpu().numpy()))[::-1])
+        return obs, ev
+
+    def lowrank(which, M):
+        tr = I.Trajectory(m, M, pulse, which, seed=1, dt=dt, nsteps=nsteps, pad_scale=I.PAPER_PAD_SCALE)
+        ctx = lr.Context(m, M)
+        Bd = lr.to_device(tr.B0())
+        obs = torch.zeros((nrec, 6 + m.d_q), dtype=torch.float64, device="cuda")
+        sp = []
+        for k in range(nck):
+            ctx.integrate(pulse, k * ck * dt, dt, ck, Bd, stride, obs[k * cs:])
+            sp.append(ctx.spectrum(Bd).cpu().numpy())
+        rc, _ = ctx.status()
+        if rc != lr.LR_OK:
+            raise RuntimeError(f"validity study M={M}: {lr.lr_strerror(rc)}")
+        ctx.close()
+        return obs, sp
+
+    h = stride * dt
+    fg, evg = full("g")
+    fe, eve = full("e")
+    ref = lr.readout_loss(fg, fe, m.d_q, h, m.kappa_f, m.gamma_1)
+    def npur(w):
+        return float(np.sum(w ** 2) / np.sum(w) ** 2)
+
+    out = {"full_eps_a": ref["eps_a"], "full_snr": ref["snr"],
+           "checkpoints_ns": [round((k + 1) * ck * dt, 6) for k in range(nck)],
+           "full_purity_g": [npur(w) for w in evg],
+           "full_purity_e": [npur(w) for w in eve],
+           "ranks": {},
+           "workload": f"dims (4,10,5) N={m.N}, flat-top drive, dt={dt} ns, {nsteps} steps, g and e; "
+                       f"full = dense master equation on the GPU"}
+    for M in (2, 4, 8, 16, 32):
+        og, spg = lowrank("g", M)
+        oe, spe = lowrank("e", M)
+        f = lr.readout_loss(og, oe, m.d_q, h, m.kappa_f, m.gamma_1)
+        row = {"eps_a": f["eps_a"], "eps_a_rel_err": abs(f["eps_a"] - ref["eps_a"]) / ref["eps_a"],
+               "snr": f["snr"], "snr_rel_err": abs(f["snr"] - ref["snr"]) / ref["snr"]}
+        for which, sp, ev in (("g", spg, evg), ("e", spe, eve)):
+            row[f"pM_over_p1_{which}"] = [float(p[-1] / p[0]) for p in sp]
+            row[f"full_pM_over_p1_{which}"] = [float(w[M - 1] / w[0]) for w in ev]
+            row[f"purity_rel_dev_{which}"] = [npur(p) / npur(w) - 1.0 for p, w in zip(sp, ev)]
+        out["ranks"][str(M)] = row
     return out
 
 

@@ -129,6 +129,17 @@ int lr_integrate(lr_ctx_t* ctx, const lr_pulse_t* pulse, double t0, double dt, i
 #define LR_OBS_LEN(d_q) (6 + (d_q))
 int lr_observables(lr_ctx_t* ctx, const lr_c64* d_B, double* d_out);
 
+/* Spectrum of the low-rank density matrix (supplement S1.B, "Validity"):
+ * the eigenvalues p_1 >= ... >= p_M of G = B^B, which are the nonzero
+ * eigenvalues of rho = B B^ (the weights p_j of eq. "lowrank_diagonal").
+ * p_M / p_1 is the paper's control quantity of the approximation and
+ * sum_j p_j^2 = tr rho^2 its purity.  d_B: device, N x M in the layout of
+ * lr_integrate; d_eval: device, M doubles, written in descending order.
+ * FP64 throughout (Jacobi rotations of the real 2M x 2M form of G), one
+ * workgroup, asynchronous on the bound stream.  Each p_j is accurate to
+ * about 1e-15 ||G||_2 in absolute terms. */
+int lr_spectrum(lr_ctx_t* ctx, const lr_c64* d_B, double* d_eval);
+
 /* Synchronise the bound stream and return the first device-side error of the
  * last lr_integrate / lr_rhs / lr_observables (LR_OK if none); *failed_step
  * (may be NULL) receives the RK step index at which it occurred. */

@@ -14,6 +14,7 @@
 #include "lr_persistent.hip"
 #include "lr_loss.hip"
 #include "lr_dense.hip"
+#include "lr_spectrum.hip"
 
 using lrk::TrajDev;
 
@@ -283,6 +284,9 @@ int lr_bind(lr_ctx_t* c, void* d_ws, size_t bytes, void* stream) {
   hipError_t e4 = hipSuccess;
   if (c->P > 0)
     e4 = hipMemcpyAsync(c->ws + c->off_ptilemap, tm, sizeof(int2) * c->P, hipMemcpyHostToDevice, c->stream);
+  // a defined device status from the start (lr_status before any integration)
+  hipLaunchKernelGGL(lrk::k_set_traj, dim3(1), dim3(1), 0, c->stream, dev_traj(c), c->base);
+  hipLaunchKernelGGL(lrk::k_reset, dim3(1), dim3(64), 0, c->stream, dev_traj(c), 1);
   hipError_t e3 = hipStreamSynchronize(c->stream);
   delete[] tm;
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) return LR_ERR_HIP;
@@ -378,6 +382,14 @@ int lr_observables(lr_ctx_t* c, const lr_c64* d_B, double* d_out) {
   if (int e = prologue(c, v, d_B)) return e;
   launch_solve(c, 0, 0, lrk::MODE_GRAM);
   hipLaunchKernelGGL(lrk::k_obs, dim3(1), dim3(lrk::kWG), 0, c->stream, dev_traj(c), d_out);
+  return launch_ok();
+}
+
+int lr_spectrum(lr_ctx_t* c, const lr_c64* d_B, double* d_eval) {
+  if (!c || !d_B || !d_eval) return LR_ERR_ARG;
+  if (!c->ws) return LR_ERR_STATE;
+  hipLaunchKernelGGL(lrk::k_spectrum, dim3(1), dim3(lrk::kSpecWG), 0, c->stream,
+                     reinterpret_cast<const double2*>(d_B), c->N, c->M, d_eval);
   return launch_ok();
 }
 

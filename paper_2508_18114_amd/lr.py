@@ -33,7 +33,7 @@ LR_MAX_M = 32
 
 # every symbol include/lr.h declares
 EXPORTS = ("lr_init", "lr_workspace_bytes", "lr_bind", "lr_rhs", "lr_integrate",
-           "lr_observables", "lr_status", "lr_profile_enable", "lr_profile_read",
+           "lr_observables", "lr_spectrum", "lr_status", "lr_profile_enable", "lr_profile_read",
            "lr_readout_loss", "lr_dense_workspace_bytes", "lr_dense_integrate", "lr_strerror", "lr_destroy",
            "lr_batch_init", "lr_batch_workspace_bytes", "lr_batch_bind", "lr_batch_run",
            "lr_batch_status", "lr_batch_profile_enable", "lr_batch_profile_read", "lr_batch_destroy")
@@ -81,6 +81,7 @@ def _load():
         "lr_rhs": (ctypes.c_int, [vp, ctypes.POINTER(lr_pulse_t), dbl, vp, vp]),
         "lr_integrate": (ctypes.c_int, [vp, ctypes.POINTER(lr_pulse_t), dbl, dbl, i64, vp, i32, vp]),
         "lr_observables": (ctypes.c_int, [vp, vp, vp]),
+        "lr_spectrum": (ctypes.c_int, [vp, vp, vp]),
         "lr_status": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
         "lr_profile_enable": (ctypes.c_int, [vp, i32]),
         "lr_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64),
@@ -155,6 +156,10 @@ def lr_integrate(ctx: int, pulse: _inp.PulseParams, t0: float, dt: float, nsteps
 
 def lr_observables(ctx: int, d_B: int, d_out: int) -> int:
     return _lib.lr_observables(ctx, d_B, d_out)
+
+
+def lr_spectrum(ctx: int, d_B: int, d_eval: int) -> int:
+    return _lib.lr_spectrum(ctx, d_B, d_eval)
 
 
 def lr_status(ctx: int):
@@ -313,6 +318,16 @@ class Context:
 
     def observables(self, B_dev, out_dev):
         self._check(lr_observables(self.handle, B_dev.data_ptr(), out_dev.data_ptr()), "lr_observables")
+
+    def spectrum(self, B_dev, out_dev=None):
+        """Eigenvalues p_1 >= ... >= p_M of B^ B (device tensor of M doubles):
+        the weights of the low-rank density matrix; p_M / p_1 is the validity
+        control quantity and sum p_j^2 the purity (supplement S1.B)."""
+        import torch
+        if out_dev is None:
+            out_dev = torch.empty((self.M,), dtype=torch.float64, device=B_dev.device)
+        self._check(lr_spectrum(self.handle, B_dev.data_ptr(), out_dev.data_ptr()), "lr_spectrum")
+        return out_dev
 
     def status(self):
         return lr_status(self.handle)

@@ -514,3 +514,58 @@ def test_serving_rejects_request_above_budget(lr):
     s = serve.Server(hbm_budget_bytes=1024, chunk=800)
     st = s.run([r])
     assert st["requests"] == 0 and "error" in s.results[0]
+
+
+# ------------------------------------------------------------ validity spectrum (S1.B)
+
+def _gpu_spectrum(lr, model, M, B):
+    ctx = lr.Context(model, M)
+    p = ctx.spectrum(lr.to_device(B)).cpu().numpy()
+    rc, _ = ctx.status()
+    assert rc == lr.LR_OK, lr.lr_strerror(rc)
+    return p
+
+
+@pytest.mark.parametrize("M", [1, 4, 20, 32])
+def test_spectrum_matches_oracle(lr, M):
+    """lr_spectrum against the eigenvalues of B^ B: |d p_j| <= 1e-13 p_1 (both FP64; G is
+    formed in a different summation order and each eigensolver is backward stable), for a
+    well-conditioned factor and one padded like the initial state (columns 2..M at 1e-6)."""
+    from oracle import validity
+    m = I.readout_model(4, 10, 5)
+    for seed, scales in ((31, None), (32, [1.0] + [1e-6] * (M - 1))):
+        B = _rand_B(m.N, M, seed, scales)
+        got = _gpu_spectrum(lr, m, M, B)
+        ref = validity.spectrum(B)
+        err = float(np.max(np.abs(got - ref)))
+        print(f"[spectrum] M={M} seed={seed}: max |dp| / p_1 = {err / ref[0]:.2e}, "
+              f"p_M/p_1 {got[-1] / got[0]:.6e} (oracle {ref[-1] / ref[0]:.6e})")
+        assert err <= 1e-13 * ref[0]
+        assert np.all(np.diff(got) <= 0)
+
+
+def test_spectrum_of_integrated_paper_size_state(lr):
+    """The spectrum of a state the GPU integrated (N=2000, M=20, 400 steps) against the oracle
+    spectrum of the same factor, and sum p_j = tr rho, sum p_j^2 = tr rho^2 of lr_observables."""
+    import torch
+    from oracle import validity
+    tr = I.config_paper_size()[1]
+    B, _ = _gpu_integrate(lr, tr.model, tr.M, tr.pulse, tr.dt, 400, tr.B0(), 0)
+    got = _gpu_spectrum(lr, tr.model, tr.M, B)
+    ref = validity.spectrum(B)
+    assert float(np.max(np.abs(got - ref))) <= 1e-13 * ref[0]
+    ctx = lr.Context(tr.model, tr.M)
+    obs = torch.zeros((lr.obs_len(tr.model),), dtype=torch.float64, device="cuda")
+    ctx.observables(lr.to_device(B), obs)
+    o = obs.cpu().numpy()
+    assert float(np.sum(got)) == pytest.approx(o[4], rel=1e-12)
+    assert float(np.sum(got ** 2)) == pytest.approx(o[5], rel=1e-11)
+
+
+def test_spectrum_nonfinite_input_ends(lr):
+    """A non-finite factor ends the Jacobi loop at once; the output is not finite."""
+    m = I.readout_model(4, 10, 5)
+    B = _rand_B(m.N, 4, 33)
+    B[7, 2] = np.nan
+    got = _gpu_spectrum(lr, m, 4, B)
+    assert not np.all(np.isfinite(got))
