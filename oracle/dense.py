@@ -51,6 +51,32 @@ def hamiltonian(model, d_t):
     return H
 
 
+def hamiltonian_drive_frame(model, d_t, w_d, t):
+    """Dense H'(t) in the frame rotating at w_d: U H U^ - w_d (n_q + n_r + n_f)
+    with U = exp(i w_d t (n_q + n_r + n_f)), built from the phased ladder
+    operators b e^{-i w_d t}, a e^{-i w_d t}, f e^{-i w_d t} (all terms kept)."""
+    b, a, f = operators(model)
+    ph = np.exp(-1j * w_d * t)
+    bt, at, ft = b * ph, a * ph, f * ph
+    nq = b.conj().T @ b
+    Nn = nq.shape[0]
+    I = np.eye(Nn)
+    H = ((model.w_q - w_d) * nq + 0.5 * model.alpha * nq @ (nq - I)
+         + (model.w_r - w_d) * a.conj().T @ a + (model.w_f - w_d) * f.conj().T @ f)
+    H = H + model.g * (bt + bt.conj().T) @ (at + at.conj().T)
+    H = H + model.G * (at + at.conj().T) @ (ft + ft.conj().T)
+    H = H + d_t * (ft + ft.conj().T)
+    return H
+
+
+def frame_hamiltonian(model, pulse, t):
+    """H(t) of the pulse's frame (lab, or rotating at w_d)."""
+    d_t = pulses.drive(pulse, t) if pulse is not None else 0.0
+    if pulse is not None and getattr(pulse, "frame", 0) == 1:
+        return hamiltonian_drive_frame(model, d_t, pulse.w_d, t)
+    return hamiltonian(model, d_t)
+
+
 def jump_operators(model):
     b, _, f = operators(model)
     return [np.sqrt(model.kappa_f) * f, np.sqrt(model.gamma_1) * b]
@@ -58,8 +84,7 @@ def jump_operators(model):
 
 def lindbladian(model, pulse, t, rho):
     """Right-hand side of the master equation on a dense rho."""
-    d_t = pulses.drive(pulse, t) if pulse is not None else 0.0
-    H = hamiltonian(model, d_t)
+    H = frame_hamiltonian(model, pulse, t)
     out = -1j * (H @ rho - rho @ H)
     for L in jump_operators(model):
         LdL = L.conj().T @ L
@@ -70,8 +95,7 @@ def lindbladian(model, pulse, t, rho):
 def lowrank_rhs_pinv(model, pulse, t, B):
     """Literal low-rank right-hand side with dense matrices and numpy's pinv:
     -i H B + 1/2 sum_k [ L_k B (pinv(B) L_k B)^ - L_k^ L_k B ]."""
-    d_t = pulses.drive(pulse, t) if pulse is not None else 0.0
-    H = hamiltonian(model, d_t)
+    H = frame_hamiltonian(model, pulse, t)
     Bp = np.linalg.pinv(B)
     out = -1j * (H @ B)
     for L in jump_operators(model):

@@ -97,6 +97,35 @@ def apply_heff(model, d_t, B):
     return Z.reshape(B.shape)
 
 
+def apply_heff_drive_frame(model, d_t, w_d, t, B):
+    """Z = H'_eff(t) B in the frame rotating at the drive carrier w_d.
+
+    The state is B' = U B with U = exp(i w_d t (n_q + n_r + n_f)); every
+    ladder operator picks up a phase, c -> c e^{-i w_d t}, c^ -> c^ e^{i w_d t},
+    and the frame change subtracts w_d from each mode frequency:
+
+      H' = (w_q - w_d) n_q + alpha/2 n_q (n_q - 1) + (w_r - w_d) n_r + (w_f - w_d) n_f
+           + g  [ b^ a + b a^ + b^ a^ e^{2 i w_d t} + b a e^{-2 i w_d t} ]
+           + G  [ a^ f + a f^ + a^ f^ e^{2 i w_d t} + a f e^{-2 i w_d t} ]
+           + d(t) [ f^ e^{i w_d t} + f e^{-i w_d t} ]
+
+    with no term dropped (the paper's rotated Hamiltonian, supplement S2.E,
+    eq. "hamiltonian_rotated", keeps the counter-rotating terms).  The jump operators only gain a phase,
+    which leaves the dissipator unchanged, so H_eff = H' - i/2 (kappa_f n_f +
+    gamma_1 n_q) as in the lab frame."""
+    T = _as_tensor(model, B)
+    m2 = model.replace(w_q=model.w_q - w_d, w_r=model.w_r - w_d, w_f=model.w_f - w_d)
+    e1 = np.exp(1j * w_d * t)
+    e2 = np.exp(2j * w_d * t)
+    Z = diag_heff(m2)[..., None] * T
+    Z = Z + model.g * (raise_(lower(T, 1), 0) + lower(raise_(T, 1), 0)
+                       + e2 * raise_(raise_(T, 1), 0) + np.conj(e2) * lower(lower(T, 1), 0))
+    Z = Z + model.G * (raise_(lower(T, 2), 1) + lower(raise_(T, 2), 1)
+                       + e2 * raise_(raise_(T, 2), 1) + np.conj(e2) * lower(lower(T, 2), 1))
+    Z = Z + d_t * (e1 * raise_(T, 2) + np.conj(e1) * lower(T, 2))
+    return Z.reshape(B.shape)
+
+
 def apply_jumps(model, B):
     """[Y_1, Y_2] = [sqrt(kappa_f) f B, sqrt(gamma_1) b B]."""
     T = _as_tensor(model, B)
@@ -125,7 +154,10 @@ def gram_solve(G, C_list):
 def rhs(model, pulse, t, B):
     """dB/dt at time t (equation of motion of supplement S1.A)."""
     d_t = pulses.drive(pulse, t) if pulse is not None else 0.0
-    Z = apply_heff(model, d_t, B)
+    if pulse is not None and getattr(pulse, "frame", 0) == 1:
+        Z = apply_heff_drive_frame(model, d_t, pulse.w_d, t, B)
+    else:
+        Z = apply_heff(model, d_t, B)
     Y = apply_jumps(model, B)
     Bh = B.conj().T
     G = Bh @ B

@@ -36,6 +36,8 @@ TWO_PI = 2.0 * math.pi
 
 PULSE_FLATTOP = 0
 PULSE_PIECEWISE6 = 1
+FRAME_LAB = 0        # B and <a>, <f> in the lab frame
+FRAME_DRIVE = 1      # frame rotating at the drive carrier w_d (counter-rotating terms kept)
 
 FP64 = 0
 FP32 = 1
@@ -78,6 +80,7 @@ class PulseParams:
                             p = (A_1, phi_1, Delta_1, A_2, phi_2, Delta_2)
     w(t) is a flat-top window on [0, T] with cosine ramps of length t_ramp;
     w_1, w_2 split it at T/2 with a cosine cross-fade of length t_ramp.
+    frame FRAME_LAB or FRAME_DRIVE: the frame the state is integrated in.
     """
     kind: int
     w_d: float
@@ -85,6 +88,7 @@ class PulseParams:
     t_ramp: float
     T: float
     p: tuple = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0)
+    frame: int = FRAME_LAB
 
     def replace(self, **kw) -> "PulseParams":
         return dataclasses.replace(self, **kw)

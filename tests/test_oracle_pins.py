@@ -272,6 +272,56 @@ def test_observables_match_dense_trace_formulas():
                                rtol=1e-12, atol=1e-12)
 
 
+# ------------------------------------------------------------ drive frame (S2.E)
+
+def _frame_phase(m, w_d, t):
+    """Diagonal of U(t) = exp(i w_d t (n_q + n_r + n_f)) and the excitation number, basis order."""
+    q = np.arange(m.d_q)[:, None, None]
+    r = np.arange(m.d_r)[None, :, None]
+    f = np.arange(m.d_f)[None, None, :]
+    n = (q + r + f).reshape(-1).astype(np.float64)
+    return np.exp(1j * w_d * t * n), n
+
+
+ROT = PULSE.replace(frame=I.FRAME_DRIVE)
+
+
+def test_drive_frame_rhs_is_the_transformed_lab_rhs():
+    """d(U B)/dt = i w_d n (U B) + U dB/dt: the equation of motion in the rotating frame at
+    B' = U(t) B equals the transformed lab-frame one, at any t (exact identity)."""
+    m = _model(3, 4, 3)
+    B = _rand_B(m.N, 3, 41)
+    for t in (0.0, 1.37, 4.2):
+        u, n = _frame_phase(m, PULSE.w_d, t)
+        lhs = lowrank.rhs(m, ROT, t, u[:, None] * B)
+        ref = 1j * PULSE.w_d * (n * u)[:, None] * B + u[:, None] * lowrank.rhs(m, PULSE, t, B)
+        assert np.max(np.abs(lhs - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_drive_frame_master_equation_is_the_transformed_lab_one():
+    """Dense: d(U rho U^)/dt = i w_d [n, rho'] + U (d rho/dt) U^ with rho' = U rho U^."""
+    m = _model(2, 3, 3, kappa_f=0.7, gamma_1=0.3)
+    B = _rand_B(m.N, m.N, 42)
+    rho = B @ B.conj().T
+    t = 2.9
+    u, n = _frame_phase(m, PULSE.w_d, t)
+    U = np.diag(u)
+    rp = U @ rho @ U.conj().T
+    lhs = dense.lindbladian(m, ROT, t, rp)
+    ref = 1j * PULSE.w_d * (np.diag(n) @ rp - rp @ np.diag(n)) + U @ dense.lindbladian(m, PULSE, t, rho) @ U.conj().T
+    assert np.max(np.abs(lhs - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_drive_frame_full_rank_reproduces_lindbladian():
+    """At M = N in the rotating frame, B dB^ + dB B^ is the dense rotating-frame Lindbladian."""
+    m = _model(2, 3, 2, kappa_f=0.9, gamma_1=0.4)
+    B = _rand_B(m.N, m.N, 43)
+    dB = lowrank.rhs(m, ROT, 3.1, B)
+    lhs = B @ dB.conj().T + dB @ B.conj().T
+    ref = dense.lindbladian(m, ROT, 3.1, B @ B.conj().T)
+    assert np.max(np.abs(lhs - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
 # ------------------------------------------------------------ validity (S1.B)
 
 def test_spectrum_is_the_nonzero_spectrum_of_rho():
