@@ -63,9 +63,23 @@ typedef struct {
  * centred at T/2.  Every amplitude must satisfy |A| < 2 pi 0.4 rad/ns (the
  * drive bound of supplement S3.B-C), else LR_ERR_PULSE. */
 enum { LR_PULSE_FLATTOP = 0, LR_PULSE_PIECEWISE6 = 1 };
+/* frame: the frame the state B is integrated in (and reported in).
+ *   LR_FRAME_LAB    the lab frame.
+ *   LR_FRAME_DRIVE  the frame rotating at the carrier w_d (supplement S2.E,
+ *                   eq. "hamiltonian_rotated", with every counter-rotating
+ *                   term kept): B' = U B with U = exp(i w_d t (n_q + n_r + n_f)),
+ *                   H' = U H U^ - w_d (n_q + n_r + n_f), i.e. mode frequencies
+ *                   w - w_d, coupling pairs b^a^, a^f^ times e^{2 i w_d t}
+ *                   (b a, a f times the conjugate) and the drive d(t) on
+ *                   f^ e^{i w_d t} + f e^{-i w_d t}.  The dissipator is
+ *                   unchanged.  Observation records hold the rotating-frame
+ *                   <a>' = e^{i w_d t}<a> and <f>' = e^{i w_d t}<f>;
+ *                   populations, traces and the readout loss are frame-free.
+ * Any other value is LR_ERR_PULSE. */
+enum { LR_FRAME_LAB = 0, LR_FRAME_DRIVE = 1 };
 typedef struct {
   int32_t kind;
-  int32_t reserved;
+  int32_t frame;
   double  w_d, amp, t_ramp, T;
   double  p[6];
 } lr_pulse_t;

@@ -46,6 +46,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 int check_pulse(const lr_pulse_t* p) {
   if (!p) return LR_ERR_ARG;
   if (p->kind != LR_PULSE_FLATTOP && p->kind != LR_PULSE_PIECEWISE6) return LR_ERR_PULSE;
+  if (p->frame != LR_FRAME_LAB && p->frame != LR_FRAME_DRIVE) return LR_ERR_PULSE;
   if (!(std::isfinite(p->w_d) && std::isfinite(p->T) && std::isfinite(p->t_ramp)) || p->t_ramp < 0.0)
     return LR_ERR_PULSE;
   if (p->kind == LR_PULSE_FLATTOP) {
@@ -58,8 +59,16 @@ int check_pulse(const lr_pulse_t* p) {
   return LR_OK;
 }
 
+// Drive fields of a descriptor whose model fields are set; in the drive frame
+// the mode frequencies become w - w_d (the frame change of the diagonal).
 void set_pulse(TrajDev& v, const lr_pulse_t* p) {
   v.pkind = p->kind;
+  v.frame = p->frame;
+  if (p->frame == LR_FRAME_DRIVE) {
+    v.w_q -= p->w_d;
+    v.w_r -= p->w_d;
+    v.w_f -= p->w_d;
+  }
   v.w_d = p->w_d;
   v.amp = p->amp;
   v.t_ramp = p->t_ramp;
@@ -456,9 +465,14 @@ int lr_dense_integrate(const lr_model_t* m, const lr_pulse_t* pulse, double t0, 
     if (!std::isfinite(x)) return LR_ERR_ARG;
   if (m->kappa_f < 0.0 || m->gamma_1 < 0.0) return LR_ERR_ARG;
   const int N = (int)Nl;
-  lrk::DenseDev D{m->d_q, m->d_r, m->d_f, N, m->w_q, m->alpha, m->w_r, m->w_f, m->g, m->G, m->kappa_f, m->gamma_1};
   TrajDev pv{};
+  pv.w_q = m->w_q;
+  pv.w_r = m->w_r;
+  pv.w_f = m->w_f;
   set_pulse(pv, pulse);
+  const bool rot = pulse->frame == LR_FRAME_DRIVE;
+  lrk::DenseDev D{m->d_q, m->d_r, m->d_f, N, rot ? 1 : 0, pv.w_q, m->alpha, pv.w_r, pv.w_f, m->g, m->G, m->kappa_f,
+                  m->gamma_1};
   hipStream_t st = (hipStream_t)stream;
   double2* base = reinterpret_cast<double2*>(d_rho);
   double2* X1 = reinterpret_cast<double2*>(d_workspace);
@@ -475,8 +489,10 @@ int lr_dense_integrate(const lr_model_t* m, const lr_pulse_t* pulse, double t0, 
     const double2* in[4] = {base, X1, X2, X1};
     double2* out[4] = {X1, X2, X1, nullptr};
     for (int s = 0; s < 4; ++s) {
-      const double drv = lrk::drive_at(pv, t + cs[s] * dt);
-      hipLaunchKernelGGL(lrk::k_dense_apply, ga, dim3(lrk::kDenseWG), 0, st, D, drv, in[s], Z);
+      const double ts = t + cs[s] * dt;
+      const double drv = lrk::drive_at(pv, ts);
+      const double2 e1 = lrk::frame_phase(pv.w_d, ts), e2 = lrk::frame_phase(2.0 * pv.w_d, ts);
+      hipLaunchKernelGGL(lrk::k_dense_apply, ga, dim3(lrk::kDenseWG), 0, st, D, drv, e1, e2, in[s], Z);
       hipLaunchKernelGGL(lrk::k_dense_combine, gc, dim3(lrk::kDenseWG), 0, st, D, in[s], Z, base, acc, out[s], s,
                          dt);
     }

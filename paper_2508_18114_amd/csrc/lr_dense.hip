@@ -23,8 +23,17 @@ namespace lrk {
 
 struct DenseDev {
   int d_q, d_r, d_f, N;
+  int frame;  // 1: frame rotating at w_d (mode frequencies already w - w_d)
   double w_q, alpha, w_r, w_f, g, G, kappa, gamma;
 };
+
+// Phase of a tap to a neighbour with dn more excitations in the drive frame:
+// e^{-i w_d t dn}, from e1 = e^{i w_d t} and e2 = e^{2 i w_d t}.
+__device__ __forceinline__ double2 tap_phase(int dn, double2 e1, double2 e2) {
+  if (dn == 0) return make_double2(1.0, 0.0);
+  const double2 e = (dn == 2 || dn == -2) ? e2 : e1;
+  return dn < 0 ? e : make_double2(e.x, -e.y);
+}
 
 // mode indices of basis state n = (q d_r + r) d_f + f
 __device__ __forceinline__ void dense_modes(const DenseDev& D, int n, int& q, int& r, int& f) {
@@ -37,8 +46,10 @@ __device__ __forceinline__ void dense_modes(const DenseDev& D, int n, int& q, in
 constexpr int kDenseWG = 256;
 
 // Z[a][b] = -i (H_eff S)[a][b] for one row a and 256 columns per workgroup.
-__global__ __launch_bounds__(kDenseWG) void k_dense_apply(DenseDev D, double drv, const double2* __restrict__ S,
-                                                          double2* __restrict__ Z) {
+// In the drive frame (D.frame) each coupling and drive tap carries
+// tap_phase(dn) of the e1 = e^{i w_d t}, e2 = e^{2 i w_d t} of the stage.
+__global__ __launch_bounds__(kDenseWG) void k_dense_apply(DenseDev D, double drv, double2 e1, double2 e2,
+                                                          const double2* __restrict__ S, double2* __restrict__ Z) {
   const int a = blockIdx.y;
   const int b = blockIdx.x * kDenseWG + threadIdx.x;
   if (b >= D.N) return;
@@ -57,7 +68,9 @@ __global__ __launch_bounds__(kDenseWG) void k_dense_apply(DenseDev D, double drv
     for (int dr = -1; dr <= 1; dr += 2) {
       const int rr = r + dr;
       if (rr < 0 || rr >= D.d_r) continue;
-      z = cfma(D.g * cq * sqrt((double)max(r, rr)), col[(size_t)(a + dq * sq + dr * sr) * N], z);
+      const double c = D.g * cq * sqrt((double)max(r, rr));
+      const double2 nb = col[(size_t)(a + dq * sq + dr * sr) * N];
+      z = D.frame ? cadd(z, cmul(cscale(c, tap_phase(dq + dr, e1, e2)), nb)) : cfma(c, nb, z);
     }
   }
   // G (a + a^)(f + f^) and the drive (f + f^)
@@ -68,9 +81,12 @@ __global__ __launch_bounds__(kDenseWG) void k_dense_apply(DenseDev D, double drv
     for (int dr = -1; dr <= 1; dr += 2) {
       const int rr = r + dr;
       if (rr < 0 || rr >= D.d_r) continue;
-      z = cfma(D.G * cf * sqrt((double)max(r, rr)), col[(size_t)(a + dr * sr + df * sf) * N], z);
+      const double c = D.G * cf * sqrt((double)max(r, rr));
+      const double2 nb = col[(size_t)(a + dr * sr + df * sf) * N];
+      z = D.frame ? cadd(z, cmul(cscale(c, tap_phase(dr + df, e1, e2)), nb)) : cfma(c, nb, z);
     }
-    z = cfma(drv * cf, col[(size_t)(a + df * sf) * N], z);
+    const double2 nb = col[(size_t)(a + df * sf) * N];
+    z = D.frame ? cadd(z, cmul(cscale(drv * cf, tap_phase(df, e1, e2)), nb)) : cfma(drv * cf, nb, z);
   }
   Z[(size_t)a * N + b] = make_double2(z.y, -z.x);  // -i z
 }

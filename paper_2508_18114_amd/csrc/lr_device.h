@@ -30,6 +30,7 @@ struct TrajDev {
   double w_q, alpha, w_r, w_f, g, G, kappa, gamma;
   // drive
   int32_t pkind, prec;  // drive kind; arithmetic of the operator/Gram products (LR_FP64/FP32/BF16X3)
+  int32_t frame, pad2;  // 0 lab frame, 1 frame rotating at w_d (w_q, w_r, w_f then hold w - w_d)
   double w_d, amp, t_ramp, T, p[6];
   // time grid
   double t0, dt;
@@ -113,6 +114,11 @@ __host__ __device__ __forceinline__ double ramp_up(double x, double t_r) {
 }
 
 // Drive coefficient d(t) multiplying (f + f^).
+// e^{i w t} (the phase of a tap in the frame rotating at the drive carrier).
+__host__ __device__ __forceinline__ double2 frame_phase(double w, double t) {
+  return make_double2(cos(w * t), sin(w * t));
+}
+
 __host__ __device__ __forceinline__ double drive_at(const TrajDev& T, double t) {
   if (T.pkind == 0) {
     return T.amp * ramp_up(t, T.t_ramp) * ramp_up(T.T - t, T.t_ramp) * cos(T.w_d * t);

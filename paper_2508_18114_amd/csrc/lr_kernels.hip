@@ -143,6 +143,13 @@ __global__ __launch_bounds__(kWG) void k_stage(const TrajDev* __restrict__ trajs
   const double cs = (s == 0) ? 0.0 : (s == 3 ? 1.0 : 0.5);  // RK4 stage nodes 0, 1/2, 1/2, 1
   const double t = (mode == MODE_RHS) ? T.t0 : (T.t0 + (double)step * T.dt + cs * T.dt);
   const double drv = drive_at(T, t);
+  // drive frame: a tap to a neighbour with dn more excitations carries e^{-i w_d t dn}
+  const double2 e1 = frame_phase(T.w_d, t), e2 = frame_phase(2.0 * T.w_d, t);
+  auto tap = [&](double2 z, double c, int dn, double2 nb) {
+    if (!T.frame || dn == 0) return cfma(c, nb, z);
+    const double2 e = (dn == 2 || dn == -2) ? e2 : e1;
+    return cadd(z, cmul(cscale(c, dn < 0 ? e : make_double2(e.x, -e.y)), nb));
+  };
   const double dt = T.dt;
   const double sk = sqrt(T.kappa), sg = sqrt(T.gamma);
 
@@ -170,7 +177,7 @@ __global__ __launch_bounds__(kWG) void k_stage(const TrajDev* __restrict__ trajs
         const int rr = r + dr;
         if (rr < 0 || rr >= d_r) continue;
         const double c = T.g * cq * sqrt((double)max(r, rr));
-        z = cfma(c, col[(size_t)(rho + dq * d_f + dr * L) * M], z);
+        z = tap(z, c, dq + dr, col[(size_t)(rho + dq * d_f + dr * L) * M]);
       }
     }
     // G (a+a^)(f+f^): (r +- 1, f +- 1); drive d(t) (f+f^): f +- 1
@@ -184,9 +191,9 @@ __global__ __launch_bounds__(kWG) void k_stage(const TrajDev* __restrict__ trajs
         const int rr = r + dr;
         if (rr < 0 || rr >= d_r) continue;
         const double c = T.G * cf * sqrt((double)max(r, rr));
-        z = cfma(c, col[(size_t)(rho + dr * L + df) * M], z);
+        z = tap(z, c, dr + df, col[(size_t)(rho + dr * L + df) * M]);
       }
-      z = cfma(drv * cf, ldsT[e + df * M], z);
+      z = tap(z, drv * cf, df, ldsT[e + df * M]);
     }
     // jump assembly 1/2 sum_k (L_k B W_k)[rho, j]
     double2 a = make_double2(0.0, 0.0);

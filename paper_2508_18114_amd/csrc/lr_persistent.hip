@@ -23,6 +23,8 @@
 // cooperative, so all workgroups of a group are co-resident.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lr_device.h"
 
 namespace lrk {
@@ -445,6 +447,7 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
   __shared__ int s_bad;
   __shared__ double s_part[kPW / 64];
   __shared__ double s_drv[2];
+  __shared__ double2 s_ph[2][2];  // drive frame: e^{i w_d t}, e^{2 i w_d t} of the stage
 
   const int2 tm = tilemap[blockIdx.x];
   const TrajDev& T = trajs[tm.x];
@@ -638,7 +641,14 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
     const double c = (s == 0) ? 0.0 : (s == 3 ? 1.0 : 0.5);
     return T.t0 + (double)(T.step_base + step) * dt + c * dt;
   };
-  if (tid == 0) s_drv[0] = drive_at(T, stage_time(step0, 0));
+  if (tid == 0) {
+    const double t = stage_time(step0, 0);
+    s_drv[0] = drive_at(T, t);
+    if (T.frame) {
+      s_ph[0][0] = frame_phase(T.w_d, t);
+      s_ph[0][1] = frame_phase(2.0 * T.w_d, t);
+    }
+  }
   const int64_t nrun = max((int64_t)0, min(nchunk, T.nsteps - step0));  // trajectories of a batch end apart
   bool ok = true;
   bool failed = false;
@@ -656,49 +666,71 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
       SolveRegs<GE> SR;
       solve_load(REDg + (size_t)p * npe, M, SR);
       double2 z[ROWS];
-#pragma unroll
-      for (int k = 0; k < ROWS; ++k) {
-        const int rl = rg + k * NG;
-        z[k] = make_double2(0.0, 0.0);
-        if (active && rl < R) {
-          // opaque per stage: values derived from the row indices are formed
-          // here rather than held in registers across the whole chunk
-          int q = rq[k], f = rf[k], rk = rr[k];
-          asm volatile("" : "+v"(q), "+v"(f), "+v"(rk));
-          const int r = r0 + rk;
-          const double2* col = tile + j;  // row offsets relative to the tile (halo at -L, +R)
-          const double2 b = col[rl * M];
-          const double hr = T.w_q * q + 0.5 * T.alpha * q * (q - 1) + T.w_r * r + T.w_f * f;
-          const double hi = -0.5 * (T.kappa * f + T.gamma * q);
-          // sqrt(max(n, n +- 1)) of each mode: sqrt(n) downwards, sqrt(n + 1) upwards
-          const double sq0 = sqt[q], sq1 = sqt[min(q + 1, nq - 1)];
-          const double sf0 = sqt[f], sf1 = sqt[min(f + 1, nq - 1)];
-          const double sr0 = sqr[rk], sr1 = sqr[rk + 1];
-          const bool rlo = r > 0, rhi = r + 1 < d_r;
-          typedef Ar<PREC> A;
-          typedef typename A::R Rr;
-          typename A::C zz = amac<A>(azero<A>(), A::in(make_double2(hr, hi)), A::in(b));
-          if (q > 0) {
-            if (rlo) zz = afma<A>(A::in(T.g * sq0 * sr0), A::in(col[(rl - d_f - L) * M]), zz);
-            if (rhi) zz = afma<A>(A::in(T.g * sq0 * sr1), A::in(col[(rl - d_f + L) * M]), zz);
-          }
-          if (q + 1 < d_q) {
-            if (rlo) zz = afma<A>(A::in(T.g * sq1 * sr0), A::in(col[(rl + d_f - L) * M]), zz);
-            if (rhi) zz = afma<A>(A::in(T.g * sq1 * sr1), A::in(col[(rl + d_f + L) * M]), zz);
-          }
-          if (f > 0) {
-            if (rlo) zz = afma<A>(A::in(T.G * sf0 * sr0), A::in(col[(rl - L - 1) * M]), zz);
-            if (rhi) zz = afma<A>(A::in(T.G * sf0 * sr1), A::in(col[(rl + L - 1) * M]), zz);
-            zz = afma<A>((Rr)A::in(drv * sf0), A::in(col[(rl - 1) * M]), zz);
-          }
-          if (f + 1 < d_f) {
-            if (rlo) zz = afma<A>(A::in(T.G * sf1 * sr0), A::in(col[(rl - L + 1) * M]), zz);
-            if (rhi) zz = afma<A>(A::in(T.G * sf1 * sr1), A::in(col[(rl + L + 1) * M]), zz);
-            zz = afma<A>((Rr)A::in(drv * sf1), A::in(col[(rl + 1) * M]), zz);
-          }
-          z[k] = A::out(zz);
+      // Z rows of the thread, in the lab frame or the drive frame (one code
+      // path per frame, chosen once per stage).  In the drive frame a
+      // coupling or drive tap to a neighbour with dn more excitations carries
+      // e^{-i w_d t dn}: the raising pairs (dn = -2) e^{2 i w_d t}, the
+      // lowering pairs its conjugate, the drive taps d(t) e^{-+ i w_d t}, the
+      // mixed pairs nothing.
+      auto stencil = [&](auto rotc) {
+        constexpr bool kRot = decltype(rotc)::value;
+        double2 e1 = make_double2(1.0, 0.0), e2 = e1;
+        if constexpr (kRot) {
+          e1 = s_ph[s & 1][0];
+          e2 = s_ph[s & 1][1];
         }
-      }
+        const double2 e1c = make_double2(e1.x, -e1.y), e2c = make_double2(e2.x, -e2.y);
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k) {
+          const int rl = rg + k * NG;
+          z[k] = make_double2(0.0, 0.0);
+          if (active && rl < R) {
+            // opaque per stage: values derived from the row indices are formed
+            // here rather than held in registers across the whole chunk
+            int q = rq[k], f = rf[k], rk = rr[k];
+            asm volatile("" : "+v"(q), "+v"(f), "+v"(rk));
+            const int r = r0 + rk;
+            const double2* col = tile + j;  // row offsets relative to the tile (halo at -L, +R)
+            const double2 b = col[rl * M];
+            const double hr = T.w_q * q + 0.5 * T.alpha * q * (q - 1) + T.w_r * r + T.w_f * f;
+            const double hi = -0.5 * (T.kappa * f + T.gamma * q);
+            // sqrt(max(n, n +- 1)) of each mode: sqrt(n) downwards, sqrt(n + 1) upwards
+            const double sq0 = sqt[q], sq1 = sqt[min(q + 1, nq - 1)];
+            const double sf0 = sqt[f], sf1 = sqt[min(f + 1, nq - 1)];
+            const double sr0 = sqr[rk], sr1 = sqr[rk + 1];
+            const bool rlo = r > 0, rhi = r + 1 < d_r;
+            typedef Ar<PREC> A;
+            typedef typename A::R Rr;
+            typename A::C zz = amac<A>(azero<A>(), A::in(make_double2(hr, hi)), A::in(b));
+            auto tap = [&](double c, double2 ph, double2 nb) {  // real c in the lab frame
+              if constexpr (kRot) zz = amac<A>(zz, A::in(cscale(c, ph)), A::in(nb));
+              else zz = afma<A>((Rr)A::in(c), A::in(nb), zz);
+            };
+            auto tap0 = [&](double c, double2 nb) { zz = afma<A>((Rr)A::in(c), A::in(nb), zz); };
+            if (q > 0) {
+              if (rlo) tap(T.g * sq0 * sr0, e2, col[(rl - d_f - L) * M]);
+              if (rhi) tap0(T.g * sq0 * sr1, col[(rl - d_f + L) * M]);
+            }
+            if (q + 1 < d_q) {
+              if (rlo) tap0(T.g * sq1 * sr0, col[(rl + d_f - L) * M]);
+              if (rhi) tap(T.g * sq1 * sr1, e2c, col[(rl + d_f + L) * M]);
+            }
+            if (f > 0) {
+              if (rlo) tap(T.G * sf0 * sr0, e2, col[(rl - L - 1) * M]);
+              if (rhi) tap0(T.G * sf0 * sr1, col[(rl + L - 1) * M]);
+              tap(drv * sf0, e1, col[(rl - 1) * M]);
+            }
+            if (f + 1 < d_f) {
+              if (rlo) tap0(T.G * sf1 * sr0, col[(rl - L + 1) * M]);
+              if (rhi) tap(T.G * sf1 * sr1, e2c, col[(rl + L + 1) * M]);
+              tap(drv * sf1, e1c, col[(rl + 1) * M]);
+            }
+            z[k] = A::out(zz);
+          }
+        }
+      };
+      if (T.frame) stencil(std::true_type{});
+      else stencil(std::false_type{});
       // (2) W_k of this stage input
       {
         const int bad = solve_run<GE, ROWS == 2 ? 4 : 2>(SR, prow, pcol, RB, RB + 2 * MM, Wl, M, &s_nonfinite, &s_bad);
@@ -789,7 +821,14 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
       // (5) group barriers around the slice reduction; a wave that does not
       // poll computes the drive value of the next stage meanwhile
       flag_arrive(myA, (uint32_t)(g + 2));
-      if (tid == 64) s_drv[(s + 1) & 1] = drive_at(T, s == 3 ? stage_time(step + 1, 0) : stage_time(step, s + 1));
+      if (tid == 64) {
+        const double t = s == 3 ? stage_time(step + 1, 0) : stage_time(step, s + 1);
+        s_drv[(s + 1) & 1] = drive_at(T, t);
+        if (T.frame) {
+          s_ph[(s + 1) & 1][0] = frame_phase(T.w_d, t);
+          s_ph[(s + 1) & 1][1] = frame_phase(2.0 * T.w_d, t);
+        }
+      }
       ok = flag_wait(T, flagA, (uint32_t)(g + 2), &s_ok);
       if (!ok) break;
       exchange(pn, true);

@@ -55,7 +55,7 @@ class lr_model_t(ctypes.Structure):
 
 
 class lr_pulse_t(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("kind", ctypes.c_int32), ("frame", ctypes.c_int32),
                 ("w_d", ctypes.c_double), ("amp", ctypes.c_double),
                 ("t_ramp", ctypes.c_double), ("T", ctypes.c_double),
                 ("p", ctypes.c_double * 6)]
@@ -117,7 +117,7 @@ def model_struct(m: _inp.ModelParams) -> lr_model_t:
 
 
 def pulse_struct(p: _inp.PulseParams) -> lr_pulse_t:
-    return lr_pulse_t(p.kind, 0, p.w_d, p.amp, p.t_ramp, p.T, (ctypes.c_double * 6)(*p.p))
+    return lr_pulse_t(p.kind, p.frame, p.w_d, p.amp, p.t_ramp, p.T, (ctypes.c_double * 6)(*p.p))
 
 
 # ---------------------------------------------------------------- raw ABI

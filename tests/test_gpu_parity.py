@@ -569,3 +569,80 @@ def test_spectrum_nonfinite_input_ends(lr):
     B[7, 2] = np.nan
     got = _gpu_spectrum(lr, m, 4, B)
     assert not np.all(np.isfinite(got))
+
+
+# ------------------------------------------------------------ drive frame (S2.E)
+
+def test_rhs_drive_frame_matches_oracle(lr):
+    """lr_rhs in the frame rotating at w_d (counter-rotating terms kept) vs the oracle."""
+    m = I.readout_model(3, 5, 4).replace(kappa_f=0.7, gamma_1=0.3)
+    p = I.flattop_pulse(0.09, 6.0).replace(frame=I.FRAME_DRIVE)
+    B = _rand_B(m.N, 4, 51, scales=np.logspace(0, -3, 4))
+    for t in (0.0, 1.3, 3.7):
+        ref = lowrank.rhs(m, p, t, B)
+        got = _gpu_rhs(lr, m, 4, p, t, B)
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        print(f"[parity] rhs drive frame t={t}: rel err {err:.3e}")
+        assert err <= 1e-11
+
+
+@pytest.mark.parametrize("kind", ["flattop", "piecewise6"])
+def test_integrate_drive_frame_matches_oracle(lr, kind):
+    """Persistent RK4 in the drive frame vs the oracle: several tiles, ragged stride, a
+    rank-padded start; the records hold the rotating-frame <a>', <f>'."""
+    m = I.readout_model(3, 7, 4).replace(kappa_f=0.5, gamma_1=0.05)
+    p = (I.flattop_pulse(0.08, 0.5, t_ramp=0.1) if kind == "flattop"
+         else I.draw_piecewise6(I.rng(5), 0.6)).replace(frame=I.FRAME_DRIVE)
+    B0 = I.initial_state(m, 4, "e", seed=52, scale=1e-3)
+    dt, n, stride = 1e-3, 203, 7
+    Bo, ref = lowrank.integrate(m, p, 0.0, dt, n, B0, obs_stride=stride)
+    Bg, got = _gpu_integrate(lr, m, 4, p, dt, n, B0, stride)
+    _assert_obs(got, ref, f"drive frame {kind}")
+    assert np.max(np.abs(Bg - Bo)) <= 1e-10
+
+
+def test_batch_drive_frame_equals_single_bitwise(lr):
+    """A lab-frame and a drive-frame trajectory in one batch: each bitwise equal to its run alone."""
+    m = I.readout_model(3, 6, 4)
+    items = []
+    for frame in (I.FRAME_LAB, I.FRAME_DRIVE):
+        p = I.flattop_pulse(0.07, 0.4, t_ramp=0.1).replace(frame=frame)
+        B0 = I.initial_state(m, 3, "g", seed=53, scale=1e-3)
+        items.append(dict(model=m, M=3, pulse=p, dt=1e-3, nsteps=150, B=lr.to_device(B0), B0=B0,
+                          obs_stride=10, obs=lr.Context(m, 3).new_obs(150, 10)))
+    b = lr.Batch([{k: v for k, v in it.items() if k != "B0"} for it in items])
+    b.run()
+    rc, codes, _ = b.status()
+    assert rc == lr.LR_OK, codes
+    for it in items:
+        Bg, got = _gpu_integrate(lr, m, 3, it["pulse"], 1e-3, 150, it["B0"], 10)
+        assert np.array_equal(Bg, lr.from_device(it["B"]))
+        assert np.array_equal(got, it["obs"].cpu().numpy())
+
+
+def test_dense_lindblad_drive_frame_matches_oracle(lr):
+    """Dense full-Lindblad RK4 in the drive frame vs the oracle's dense master equation."""
+    import torch
+    from oracle import dense
+    model, pulse, rho0 = _dense_case(54)
+    pulse = pulse.replace(frame=I.FRAME_DRIVE)
+    dt, nsteps, stride = 2e-3, 300, 100
+    rho = torch.from_numpy(rho0.copy()).cuda()
+    obs = torch.zeros((nsteps // stride + 1, 6 + model.d_q), dtype=torch.float64, device="cuda")
+    lr.dense_integrate(model, pulse, 0.0, dt, nsteps, rho, stride, obs)
+    torch.cuda.synchronize()
+    ref_rho, ref_obs = dense.integrate(model, pulse, 0.0, dt, nsteps, rho0, obs_stride=stride)
+    err = np.max(np.abs(rho.cpu().numpy() - ref_rho))
+    print(f"[parity] dense drive frame rho err {err:.3e}")
+    assert err <= 1e-12
+    e_field, e_pop = _obs_errors(obs.cpu().numpy(), ref_obs)
+    assert e_field <= 1e-12 and e_pop <= 1e-12
+
+
+def test_drive_frame_rejects_unknown_frame(lr):
+    m = I.readout_model(2, 3, 2)
+    p = I.flattop_pulse(0.05, 1.0).replace(frame=7)
+    B = _rand_B(m.N, 2, 55)
+    ctx = lr.Context(m, 2)
+    with pytest.raises(lr.LrError):
+        ctx.integrate(p, 0.0, 1e-3, 5, lr.to_device(B))
