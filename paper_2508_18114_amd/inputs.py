@@ -36,6 +36,8 @@ TWO_PI = 2.0 * math.pi
 
 PULSE_FLATTOP = 0
 PULSE_PIECEWISE6 = 1
+PULSE_STEPWISE = 2   # smoothed stepwise complex envelope (supplement S2.C)
+PULSE_MAX_HEIGHTS = 63
 FRAME_LAB = 0        # B and <a>, <f> in the lab frame
 FRAME_DRIVE = 1      # frame rotating at the drive carrier w_d (counter-rotating terms kept)
 
@@ -80,6 +82,10 @@ class PulseParams:
                             p = (A_1, phi_1, Delta_1, A_2, phi_2, Delta_2)
     w(t) is a flat-top window on [0, T] with cosine ramps of length t_ramp;
     w_1, w_2 split it at T/2 with a cosine cross-fade of length t_ramp.
+    kind PULSE_STEPWISE:    d(t) = Re[ Omega(t) e^{-i w_d t} ],
+                            Omega(t) = sum_{j=1}^{n} (h_{j+1} - h_j) f(t, j T / n, sigma)
+                            with f the logistic function, h_1 = h_{n+1} = 0 and the
+                            n - 1 complex heights h_2 .. h_n given in `h`.
     frame FRAME_LAB or FRAME_DRIVE: the frame the state is integrated in.
     """
     kind: int
@@ -89,6 +95,8 @@ class PulseParams:
     T: float
     p: tuple = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0)
     frame: int = FRAME_LAB
+    sigma: float = 0.5       # logistic steepness of PULSE_STEPWISE (ns)
+    h: tuple = ()            # PULSE_STEPWISE heights h_2 .. h_n (complex, rad/ns)
 
     def replace(self, **kw) -> "PulseParams":
         return dataclasses.replace(self, **kw)
@@ -121,6 +129,12 @@ def flattop_pulse(amp_ghz: float, T: float, t_ramp: float = T_RAMP,
 # --------------------------------------------------------------------------
 # Seeded draws
 # --------------------------------------------------------------------------
+
+def stepwise_pulse(heights, T: float, sigma: float = 0.5, w_d: float = W_DRIVE) -> PulseParams:
+    """Smoothed stepwise pulse with complex heights h_2 .. h_n (rad/ns)."""
+    return PulseParams(kind=PULSE_STEPWISE, w_d=w_d, amp=0.0, t_ramp=0.0, T=T, sigma=sigma,
+                       h=tuple(complex(x) for x in heights))
+
 
 def rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))

@@ -272,6 +272,58 @@ def test_observables_match_dense_trace_formulas():
                                rtol=1e-12, atol=1e-12)
 
 
+# ------------------------------------------------------------ smoothed stepwise pulse (S2.C)
+
+STEP = I.stepwise_pulse([0.6 + 0.3j, 0.9 - 0.4j, 0.2j, -0.5 + 0.1j], 20.0, sigma=0.25)
+
+
+def test_stepwise_plateaus_and_edges():
+    """Mid-interval the envelope is the height of the interval, at a step centre the mean of
+    the two heights, and the drive is off before the first and after the last step (the
+    logistic tails are below exp(-T / (2 n sigma)) of the heights there)."""
+    hs = [0j] + list(STEP.h) + [0j]
+    n = len(hs) - 1
+    tail = 2 * sum(abs(x) for x in hs) * math.exp(-(STEP.T / n) / (2 * STEP.sigma))
+    for j in range(n):  # interval j between steps j and j + 1 (step 0 at t = 0)
+        om = pulses.stepwise_envelope(STEP, (j + 0.5) * STEP.T / n)
+        assert abs(om - hs[j]) <= tail
+    for j in range(1, n + 1):
+        om = pulses.stepwise_envelope(STEP, j * STEP.T / n)
+        assert abs(om - 0.5 * (hs[j - 1] + hs[j])) <= tail
+    assert abs(pulses.stepwise_envelope(STEP, STEP.T + 6.0)) <= tail
+
+
+def test_stepwise_area_matches_logistic_antiderivative():
+    """int_0^X Omega dt from adaptive quadrature equals the closed form of the logistic
+    antiderivative sigma log(1 + e^{(t - t_j) / sigma})."""
+    hs = [0j] + list(STEP.h) + [0j]
+    n = len(hs) - 1
+    X = STEP.T + 4.0
+    s = STEP.sigma
+    ref = 0j
+    for j in range(1, n + 1):
+        tj = j * STEP.T / n
+        ref += (hs[j] - hs[j - 1]) * s * (np.logaddexp(0.0, (X - tj) / s) - np.logaddexp(0.0, -tj / s))
+    pts = [j * STEP.T / n for j in range(1, n + 1)]
+    re = scipy.integrate.quad(lambda t: pulses.stepwise_envelope(STEP, t).real, 0.0, X, points=pts, limit=400,
+                              epsabs=1e-13, epsrel=1e-13)[0]
+    im = scipy.integrate.quad(lambda t: pulses.stepwise_envelope(STEP, t).imag, 0.0, X, points=pts, limit=400,
+                              epsabs=1e-13, epsrel=1e-13)[0]
+    assert abs(complex(re, im) - ref) <= 1e-10
+
+
+def test_stepwise_drive_is_the_envelope_on_the_carrier():
+    """d(t) = Re[Omega(t) e^{-i w_d t}]: a real envelope gives Re(Omega) cos(w_d t), an
+    imaginary one Im(Omega) sin(w_d t)."""
+    for t in (3.3, 7.9, 12.1):
+        re = STEP.replace(h=tuple(complex(x.real, 0.0) for x in STEP.h))
+        im = STEP.replace(h=tuple(complex(0.0, x.imag) for x in STEP.h))
+        assert pulses.drive(re, t) == pytest.approx(pulses.stepwise_envelope(re, t).real * math.cos(STEP.w_d * t),
+                                                    rel=1e-13, abs=1e-15)
+        assert pulses.drive(im, t) == pytest.approx(pulses.stepwise_envelope(im, t).imag * math.sin(STEP.w_d * t),
+                                                    rel=1e-13, abs=1e-15)
+
+
 # ------------------------------------------------------------ drive frame (S2.E)
 
 def _frame_phase(m, w_d, t):
