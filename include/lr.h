@@ -62,7 +62,15 @@ typedef struct {
  * w_1 = r(t)(1-c(t)), w_2 = r(T-t) c(t), c a cosine cross-fade of length t_ramp
  * centred at T/2.  Every amplitude must satisfy |A| < 2 pi 0.4 rad/ns (the
  * drive bound of supplement S3.B-C), else LR_ERR_PULSE. */
-enum { LR_PULSE_FLATTOP = 0, LR_PULSE_PIECEWISE6 = 1 };
+enum { LR_PULSE_FLATTOP = 0, LR_PULSE_PIECEWISE6 = 1, LR_PULSE_STEPWISE = 2 };
+/* LR_PULSE_STEPWISE (supplement S2.C, smoothed stepwise function): the complex
+ * envelope Omega(t) = sum_{j=1}^{n} (h_{j+1} - h_j) / (1 + e^{-(t - j T / n) / sigma})
+ * with n = nh + 1 logistic steps, h_1 = h_{n+1} = 0 (the drive is off before the
+ * first and after the last step) and the nh complex heights h_2 .. h_n in
+ * h[2 k], h[2 k + 1] (re, im), on the carrier: d(t) = Re[Omega(t) e^{-i w_d t}].
+ * Requires 1 <= nh <= LR_PULSE_MAX_H, sigma > 0, T > 0 and every |h_k| below the
+ * drive bound. */
+#define LR_PULSE_MAX_H 63
 /* frame: the frame the state B is integrated in (and reported in).
  *   LR_FRAME_LAB    the lab frame.
  *   LR_FRAME_DRIVE  the frame rotating at the carrier w_d (supplement S2.E,
@@ -82,6 +90,10 @@ typedef struct {
   int32_t frame;
   double  w_d, amp, t_ramp, T;
   double  p[6];
+  int32_t nh;                          /* LR_PULSE_STEPWISE: number of heights */
+  int32_t reserved;
+  double  sigma;                       /* LR_PULSE_STEPWISE: logistic steepness (ns) */
+  double  h[2 * LR_PULSE_MAX_H];       /* LR_PULSE_STEPWISE: heights h_2 .. h_n */
 } lr_pulse_t;
 
 /* Arithmetic of the operator applications (H_eff and L_k on B), the jump

@@ -40,17 +40,24 @@ struct lr_ctx {
 namespace {
 
 constexpr double kDriveBound = 2.0 * M_PI * 0.4;  // |amplitude| < 2 pi 400 MHz
+static_assert(lrk::kMaxPulseH == LR_PULSE_MAX_H, "stepwise heights of the device descriptor");
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 int check_pulse(const lr_pulse_t* p) {
   if (!p) return LR_ERR_ARG;
-  if (p->kind != LR_PULSE_FLATTOP && p->kind != LR_PULSE_PIECEWISE6) return LR_ERR_PULSE;
+  if (p->kind != LR_PULSE_FLATTOP && p->kind != LR_PULSE_PIECEWISE6 && p->kind != LR_PULSE_STEPWISE)
+    return LR_ERR_PULSE;
   if (p->frame != LR_FRAME_LAB && p->frame != LR_FRAME_DRIVE) return LR_ERR_PULSE;
   if (!(std::isfinite(p->w_d) && std::isfinite(p->T) && std::isfinite(p->t_ramp)) || p->t_ramp < 0.0)
     return LR_ERR_PULSE;
   if (p->kind == LR_PULSE_FLATTOP) {
     if (!(std::fabs(p->amp) < kDriveBound)) return LR_ERR_PULSE;
+  } else if (p->kind == LR_PULSE_STEPWISE) {
+    if (p->nh < 1 || p->nh > LR_PULSE_MAX_H || !(p->sigma > 0.0) || !std::isfinite(p->sigma) || !(p->T > 0.0))
+      return LR_ERR_PULSE;
+    for (int k = 0; k < p->nh; ++k)
+      if (!(std::hypot(p->h[2 * k], p->h[2 * k + 1]) < kDriveBound)) return LR_ERR_PULSE;
   } else {
     for (int i = 0; i < 6; ++i)
       if (!std::isfinite(p->p[i])) return LR_ERR_PULSE;
@@ -74,6 +81,9 @@ void set_pulse(TrajDev& v, const lr_pulse_t* p) {
   v.t_ramp = p->t_ramp;
   v.T = p->T;
   for (int i = 0; i < 6; ++i) v.p[i] = p->p[i];
+  v.nh = p->kind == LR_PULSE_STEPWISE ? p->nh : 0;
+  v.sigma = p->sigma;
+  for (int i = 0; i < 2 * LR_PULSE_MAX_H; ++i) v.h[i] = i < 2 * v.nh ? p->h[i] : 0.0;
 }
 
 TrajDev* dev_traj(const lr_ctx* c) { return reinterpret_cast<TrajDev*>(c->ws + c->off_traj); }

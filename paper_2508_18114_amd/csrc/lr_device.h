@@ -15,6 +15,7 @@ namespace lrk {
 
 constexpr int kWG = 256;          // threads per workgroup of the streaming kernels
 constexpr int kMaxM = 32;         // largest supported rank
+constexpr int kMaxPulseH = 63;    // heights of the smoothed stepwise envelope (n = nh + 1 <= 64 steps)
 constexpr int kMaxTileElems = 2048;  // rows*M of one tile (LDS budget: 32 KB of FP64 complex)
 constexpr int kMaxElemsPerThread = kMaxTileElems / kWG;
 
@@ -32,6 +33,8 @@ struct TrajDev {
   int32_t pkind, prec;  // drive kind; arithmetic of the operator/Gram products (LR_FP64/FP32/BF16X3)
   int32_t frame, pad2;  // 0 lab frame, 1 frame rotating at w_d (w_q, w_r, w_f then hold w - w_d)
   double w_d, amp, t_ramp, T, p[6];
+  int32_t nh, pad3;     // smoothed stepwise envelope: heights h_2 .. h_{nh+1}, logistic steepness
+  double sigma, h[2 * kMaxPulseH];
   // time grid
   double t0, dt;
   // device buffers, internal layout
@@ -119,7 +122,34 @@ __host__ __device__ __forceinline__ double2 frame_phase(double w, double t) {
   return make_double2(cos(w * t), sin(w * t));
 }
 
+// Term j (1 <= j <= n = nh + 1) of the smoothed stepwise envelope:
+// (h_{j+1} - h_j) f(t, j T / n, sigma), f the logistic function, h_1 = h_{n+1} = 0.
+__host__ __device__ __forceinline__ double2 stepwise_term(const TrajDev& T, int j, double t) {
+  const int n = T.nh + 1;
+  const double2 hp = j <= T.nh ? make_double2(T.h[2 * (j - 1)], T.h[2 * (j - 1) + 1]) : make_double2(0.0, 0.0);
+  const double2 hm = j >= 2 ? make_double2(T.h[2 * (j - 2)], T.h[2 * (j - 2) + 1]) : make_double2(0.0, 0.0);
+  const double f = 1.0 / (1.0 + exp(-(t - j * T.T / n) / T.sigma));
+  return make_double2((hp.x - hm.x) * f, (hp.y - hm.y) * f);
+}
+
+// Omega(t) of the smoothed stepwise envelope, steps summed in order (kept
+// out of line: it runs once per stage time, away from the kernels' hot loops).
+__host__ __device__ __attribute__((noinline)) inline double2 stepwise_envelope(const TrajDev& T, double t) {
+  double2 om = make_double2(0.0, 0.0);
+  for (int j = 1; j <= T.nh + 1; ++j) {
+    const double2 v = stepwise_term(T, j, t);
+    om.x += v.x;
+    om.y += v.y;
+  }
+  return om;
+}
+
+// Drive coefficient d(t) on (f + f^).
 __host__ __device__ __forceinline__ double drive_at(const TrajDev& T, double t) {
+  if (T.pkind == 2) {  // Re[Omega(t) e^{-i w_d t}]
+    const double2 om = stepwise_envelope(T, t);
+    return om.x * cos(T.w_d * t) + om.y * sin(T.w_d * t);
+  }
   if (T.pkind == 0) {
     return T.amp * ramp_up(t, T.t_ramp) * ramp_up(T.T - t, T.t_ramp) * cos(T.w_d * t);
   }

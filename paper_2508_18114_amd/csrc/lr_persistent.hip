@@ -30,6 +30,7 @@
 namespace lrk {
 
 constexpr int kPW = 512;  // threads per workgroup
+constexpr int kDriveWin = 32;  // steps per refill of the drive table (4 stages each, one thread per stage)
 // The kernel is instantiated for ROWS = 2 and 3 rows of one column per
 // thread (ceil(rows / (kPW / M)) <= ROWS); 2 keeps every value in registers.
 constexpr int kMaxRowsPerThread = 3;
@@ -446,8 +447,8 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
   __shared__ int s_nonfinite;
   __shared__ int s_bad;
   __shared__ double s_part[kPW / 64];
-  __shared__ double s_drv[2];
-  __shared__ double2 s_ph[2][2];  // drive frame: e^{i w_d t}, e^{2 i w_d t} of the stage
+  // per stage of kDriveWin steps: d(t) and, in the drive frame, e^{i w_d t}, e^{2 i w_d t}
+  __shared__ double s_dtab[4 * kDriveWin][5];
 
   const int2 tm = tilemap[blockIdx.x];
   const TrajDev& T = trajs[tm.x];
@@ -641,26 +642,36 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
     const double c = (s == 0) ? 0.0 : (s == 3 ? 1.0 : 0.5);
     return T.t0 + (double)(T.step_base + step) * dt + c * dt;
   };
-  if (tid == 0) {
-    const double t = stage_time(step0, 0);
-    s_drv[0] = drive_at(T, t);
-    if (T.frame) {
-      s_ph[0][0] = frame_phase(T.w_d, t);
-      s_ph[0][1] = frame_phase(2.0 * T.w_d, t);
+  // drive values of the stages of the next kDriveWin steps from step, one
+  // stage time per thread (any pulse kind costs the same per stage)
+  auto fill_drive = [&](int64_t step) {
+    __syncthreads();
+    if (tid < 4 * kDriveWin) {
+      const double t = stage_time(step + tid / 4, tid % 4);
+      s_dtab[tid][0] = drive_at(T, t);
+      if (T.frame) {
+        const double2 e1 = frame_phase(T.w_d, t), e2 = frame_phase(2.0 * T.w_d, t);
+        s_dtab[tid][1] = e1.x;
+        s_dtab[tid][2] = e1.y;
+        s_dtab[tid][3] = e2.x;
+        s_dtab[tid][4] = e2.y;
+      }
     }
-  }
+  };
   const int64_t nrun = max((int64_t)0, min(nchunk, T.nsteps - step0));  // trajectories of a batch end apart
   bool ok = true;
   bool failed = false;
   int64_t n = 0;
   for (; n < nrun && ok && !failed; ++n) {
     const int64_t step = step0 + n;
+    if (n % kDriveWin == 0) fill_drive(step);
     for (int s = 0; s < 4; ++s) {
       const int64_t g = 4 * step + s;
       const int p = (int)(g & 1);
+      const int ds = (int)(n % kDriveWin) * 4 + s;
       if (tid == 0) s_nonfinite = 0;
-      __syncthreads();  // stage input tile and halo, drive value in LDS
-      const double drv = s_drv[s & 1];
+      __syncthreads();  // stage input tile and halo, drive table in LDS
+      const double drv = s_dtab[ds][0];
 
       // (1) loads of the reduced G, C_k in flight while Z = H_eff(t) S is formed
       SolveRegs<GE> SR;
@@ -676,8 +687,8 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
         constexpr bool kRot = decltype(rotc)::value;
         double2 e1 = make_double2(1.0, 0.0), e2 = e1;
         if constexpr (kRot) {
-          e1 = s_ph[s & 1][0];
-          e2 = s_ph[s & 1][1];
+          e1 = make_double2(s_dtab[ds][1], s_dtab[ds][2]);
+          e2 = make_double2(s_dtab[ds][3], s_dtab[ds][4]);
         }
         const double2 e1c = make_double2(e1.x, -e1.y), e2c = make_double2(e2.x, -e2.y);
 #pragma unroll
@@ -818,17 +829,8 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
       publish_boundary(tile, SPg + (size_t)pn * NMn, row0, R, L, M);  // stores drain during the partials
       persist_partials<PREC, LR_GRAM_PREC(PREC)>(T, tile, R, c1row, c2row, PARTg + ((size_t)pn * P + w) * npe);
 
-      // (5) group barriers around the slice reduction; a wave that does not
-      // poll computes the drive value of the next stage meanwhile
+      // (5) group barriers around the slice reduction
       flag_arrive(myA, (uint32_t)(g + 2));
-      if (tid == 64) {
-        const double t = s == 3 ? stage_time(step + 1, 0) : stage_time(step, s + 1);
-        s_drv[(s + 1) & 1] = drive_at(T, t);
-        if (T.frame) {
-          s_ph[(s + 1) & 1][0] = frame_phase(T.w_d, t);
-          s_ph[(s + 1) & 1][1] = frame_phase(2.0 * T.w_d, t);
-        }
-      }
       ok = flag_wait(T, flagA, (uint32_t)(g + 2), &s_ok);
       if (!ok) break;
       exchange(pn, true);

@@ -58,7 +58,9 @@ class lr_pulse_t(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("frame", ctypes.c_int32),
                 ("w_d", ctypes.c_double), ("amp", ctypes.c_double),
                 ("t_ramp", ctypes.c_double), ("T", ctypes.c_double),
-                ("p", ctypes.c_double * 6)]
+                ("p", ctypes.c_double * 6),
+                ("nh", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sigma", ctypes.c_double), ("h", ctypes.c_double * (2 * _inp.PULSE_MAX_HEIGHTS))]
 
 
 class lr_traj_t(ctypes.Structure):
@@ -117,7 +119,13 @@ def model_struct(m: _inp.ModelParams) -> lr_model_t:
 
 
 def pulse_struct(p: _inp.PulseParams) -> lr_pulse_t:
-    return lr_pulse_t(p.kind, p.frame, p.w_d, p.amp, p.t_ramp, p.T, (ctypes.c_double * 6)(*p.p))
+    h = [0.0] * (2 * _inp.PULSE_MAX_HEIGHTS)
+    hs = list(p.h)[:_inp.PULSE_MAX_HEIGHTS]
+    for k, x in enumerate(hs):
+        h[2 * k], h[2 * k + 1] = complex(x).real, complex(x).imag
+    nh = len(p.h) if p.kind == _inp.PULSE_STEPWISE else 0  # too many heights: rejected by the library
+    return lr_pulse_t(p.kind, p.frame, p.w_d, p.amp, p.t_ramp, p.T, (ctypes.c_double * 6)(*p.p), nh, 0,
+                      p.sigma, (ctypes.c_double * (2 * _inp.PULSE_MAX_HEIGHTS))(*h))
 
 
 # ---------------------------------------------------------------- raw ABI

@@ -646,3 +646,46 @@ def test_drive_frame_rejects_unknown_frame(lr):
     ctx = lr.Context(m, 2)
     with pytest.raises(lr.LrError):
         ctx.integrate(p, 0.0, 1e-3, 5, lr.to_device(B))
+
+
+# ------------------------------------------------------------ smoothed stepwise pulse (S2.C)
+
+def _stepwise(n, seed, T=0.6, sigma=0.02):
+    r = np.random.default_rng(seed)
+    h = I.ghz(0.15) * (r.uniform(0.2, 1.0, n) * np.exp(1j * r.uniform(0, 2 * np.pi, n)))
+    return I.stepwise_pulse(h, T, sigma=sigma)
+
+
+def test_rhs_stepwise_pulse(lr):
+    m = I.readout_model(3, 6, 4)
+    p = _stepwise(9, 61)
+    B = _rand_B(m.N, 5, 62)
+    for t in (0.0, 0.07, 0.31, 0.6, 0.75):
+        ref = lowrank.rhs(m, p, t, B)
+        got = _gpu_rhs(lr, m, 5, p, t, B)
+        assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("nh,frame", [(1, 0), (20, 0), (63, 0), (20, 1)])
+def test_integrate_stepwise_pulse(lr, nh, frame):
+    """Persistent RK4 with the stepwise envelope (up to the 63-height maximum; each drive
+    table refill evaluates one stage time per thread) against the oracle, lab and drive frame."""
+    m = I.readout_model(3, 7, 4).replace(kappa_f=0.5, gamma_1=0.05)
+    p = _stepwise(nh, 63 + nh).replace(frame=frame)
+    B0 = I.initial_state(m, 4, "g", seed=64, scale=1e-3)
+    dt, n, stride = 1e-3, 203, 7
+    Bo, ref = lowrank.integrate(m, p, 0.0, dt, n, B0, obs_stride=stride)
+    Bg, got = _gpu_integrate(lr, m, 4, p, dt, n, B0, stride)
+    _assert_obs(got, ref, f"stepwise nh={nh} frame={frame}")
+    assert np.max(np.abs(Bg - Bo)) <= 1e-10
+
+
+def test_stepwise_pulse_rejections(lr):
+    m = I.readout_model(2, 3, 2)
+    B = lr.to_device(_rand_B(m.N, 2, 65))
+    ctx = lr.Context(m, 2)
+    bad = [I.stepwise_pulse([], 1.0), I.stepwise_pulse([0.1] * 64, 1.0), I.stepwise_pulse([0.1], 1.0, sigma=0.0),
+           I.stepwise_pulse([I.ghz(0.41)], 1.0), I.stepwise_pulse([0.1], 0.0)]
+    for p in bad:
+        with pytest.raises(lr.LrError):
+            ctx.integrate(p, 0.0, 1e-3, 3, B)
