@@ -16,6 +16,8 @@ budget and their workgroups fit the co-resident capacity.
 `EvolutionStrategy` is the gradient-free request source: a (mu, lambda)
 evolution strategy over the six Piecewise6 parameters that emits generations
 of candidates and moves its mean to the best of each finished generation.
+`SPSA` and `spsa_optimize` are the paper's own optimiser (supplement S3.C)
+over the smoothed stepwise pulse.
 """
 from __future__ import annotations
 
@@ -236,6 +238,109 @@ class EvolutionStrategy:
         order = np.argsort(np.asarray(losses))[: self.mu]
         self.mean = np.mean([cands[i] for i in order], axis=0)
         self.generation += 1
+
+
+def spsa_gradient(loss_plus: float, loss_minus: float, ck: float, delta: np.ndarray) -> np.ndarray:
+    """SPSA gradient estimate from the two losses at theta +- ck delta (delta_i = +-1)."""
+    return (loss_plus - loss_minus) / (2.0 * ck) / delta
+
+
+class SPSA:
+    """Simultaneous perturbation stochastic approximation (supplement S3.C): step k
+    draws a direction Delta with independent +-1 entries, the loss is evaluated at
+    theta + c_k Delta and theta - c_k Delta (two loss evaluations, each a g/e
+    pair), and theta moves by -a_k (L+ - L-) / (2 c_k) Delta^-1, with the usual
+    gain sequences a_k = a / (k + 1 + A)^alpha and c_k = c / (k + 1)^gamma.
+    `project` maps a parameter vector back into the admissible set."""
+
+    def __init__(self, theta0, seed: int, a: float, c: float, A: float = 10.0, alpha: float = 0.602,
+                 gamma: float = 0.101, project=None):
+        self.theta = np.asarray(theta0, dtype=np.float64).copy()
+        self.rng = I.rng(seed)
+        self.a, self.c, self.A, self.alpha, self.gamma = a, c, A, alpha, gamma
+        self.project = project if project is not None else (lambda x: x)
+        self.k = 0
+        self._delta = None
+
+    def gains(self):
+        return self.a / (self.k + 1 + self.A) ** self.alpha, self.c / (self.k + 1) ** self.gamma
+
+    def ask(self):
+        """The two parameter vectors of this step: theta + c_k Delta, theta - c_k Delta."""
+        _, ck = self.gains()
+        self._delta = self.rng.choice([-1.0, 1.0], size=self.theta.shape)
+        return self.project(self.theta + ck * self._delta), self.project(self.theta - ck * self._delta)
+
+    def tell(self, loss_plus: float, loss_minus: float):
+        ak, ck = self.gains()
+        ghat = spsa_gradient(loss_plus, loss_minus, ck, self._delta)
+        self.theta = self.project(self.theta - ak * ghat)
+        self.k += 1
+        return ghat
+
+
+def heights_from(theta: np.ndarray) -> np.ndarray:
+    """Complex heights from the real parameter vector (re, im interleaved)."""
+    return theta[0::2] + 1j * theta[1::2]
+
+
+def project_heights(theta: np.ndarray, bound: float = I.ghz(0.4) * (1.0 - 1e-9)) -> np.ndarray:
+    """Scale each complex height into the drive bound |h| < 2 pi 400 MHz."""
+    h = heights_from(theta)
+    a = np.abs(h)
+    h = np.where(a > bound, h * (bound / np.maximum(a, 1e-300)), h)
+    out = np.empty_like(theta)
+    out[0::2], out[1::2] = h.real, h.imag
+    return out
+
+
+def pulse_loss_batch(model: I.ModelParams, M: int, pulses, dt: float, nsteps: int, obs_stride: int,
+                     pad_scale: float = I.PAPER_PAD_SCALE, seed: int = 0, stream=None):
+    """Readout loss Lambda (and its figures of merit) of each pulse: the g and e
+    trajectories of every pulse integrated together in one batch, the loss of
+    each g/e pair formed on the device."""
+    import torch
+    items = []
+    nrec = nsteps // obs_stride + 1
+    for p in pulses:
+        for which in ("g", "e"):
+            B0 = I.initial_state(model, M, which, seed, pad_scale)
+            items.append(dict(model=model, M=M, pulse=p, dt=dt, nsteps=nsteps, B=lr.to_device(B0),
+                              obs_stride=obs_stride,
+                              obs=torch.zeros((nrec, 6 + model.d_q), dtype=torch.float64, device="cuda")))
+    b = lr.Batch(items, stream=stream)
+    b.run()
+    rc, codes, steps = b.status()
+    if rc != lr.LR_OK:
+        raise RuntimeError(f"loss batch failed: {lr.lr_strerror(rc)} (codes {codes})")
+    b.close()
+    out = []
+    for i in range(len(pulses)):
+        g, e = items[2 * i]["obs"], items[2 * i + 1]["obs"]
+        out.append(lr.readout_loss(g, e, model.d_q, obs_stride * dt, model.kappa_f, model.gamma_1, stream=stream))
+    return out
+
+
+def spsa_optimize(model: I.ModelParams, M: int, T: float, nh: int, iters: int, dt: float, obs_stride: int,
+                  seed: int = 1, a: float = 0.05, c: float = 0.05, sigma: float = 0.5,
+                  frame: int = I.FRAME_DRIVE, stream=None):
+    """The optimisation loop of supplement S3.C on the device: SPSA over the nh
+    complex heights of the smoothed stepwise pulse, started from the square shape
+    (all heights real, 2 pi 150 MHz), each step evaluating theta +- c_k Delta in
+    one batch of four trajectories.  Returns (theta, history) with the loss at
+    both probes of every step."""
+    theta0 = np.zeros(2 * nh)
+    theta0[0::2] = I.ghz(0.15)
+    opt = SPSA(theta0, seed, a=a, c=c, project=project_heights)
+    hist = []
+    for _ in range(iters):
+        tp, tm = opt.ask()
+        pulses = [I.stepwise_pulse(heights_from(x), T, sigma=sigma).replace(frame=frame) for x in (tp, tm)]
+        fp, fm = pulse_loss_batch(model, M, pulses, dt, int(round(T / dt)), obs_stride, stream=stream)
+        opt.tell(fp["loss"], fm["loss"])
+        hist.append({"k": opt.k, "loss_plus": fp["loss"], "loss_minus": fm["loss"],
+                     "eps_a_plus": fp["eps_a"], "eps_a_minus": fm["eps_a"]})
+    return opt.theta, hist
 
 
 def pulse_from(x: np.ndarray, T: float) -> I.PulseParams:
