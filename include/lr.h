@@ -246,6 +246,18 @@ typedef struct lr_batch lr_batch_t;
  * lr_integrate do), copies the descriptors and sizes the workspace.  The
  * device pointers inside the descriptors are used by lr_batch_run. */
 int lr_batch_init(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n);
+/* lr_batch_init with schedule flags.  0 is lr_batch_init.  LR_BATCH_PACKED:
+ * every LR_FP64 trajectory with d_q d_f M <= LR_PACKED_MAX_LM runs in a
+ * workgroup of its own (all of them in one launch per chunk of steps, as many
+ * per CU as fit), which fills the GPU with many trajectories at once instead
+ * of spreading each one over d_r workgroups; the other trajectories run as
+ * without the flag.  A packed trajectory's result does not depend on the
+ * batch either (fixed-order sums, one workgroup), but its rounding is not that
+ * of the spread schedule: the two agree to the FP64 tolerances of lr_integrate.
+ * Unknown flag bits: LR_ERR_ARG. */
+#define LR_BATCH_PACKED 1
+#define LR_PACKED_MAX_LM 2560
+int lr_batch_init_ex(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n, int32_t flags);
 size_t lr_batch_workspace_bytes(const lr_batch_t* batch);
 int lr_batch_bind(lr_batch_t* batch, void* d_workspace, size_t bytes, void* stream);
 /* Enqueue the integration of every trajectory of the batch on the bound

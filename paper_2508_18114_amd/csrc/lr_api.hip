@@ -15,6 +15,7 @@
 #include "lr_loss.hip"
 #include "lr_dense.hip"
 #include "lr_spectrum.hip"
+#include "lr_packed.hip"
 
 using lrk::TrajDev;
 
@@ -41,6 +42,7 @@ namespace {
 
 constexpr double kDriveBound = 2.0 * M_PI * 0.4;  // |amplitude| < 2 pi 400 MHz
 static_assert(lrk::kMaxPulseH == LR_PULSE_MAX_H, "stepwise heights of the device descriptor");
+static_assert(lrk::kTMaxLM == LR_PACKED_MAX_LM, "layer size of the packed kernel");
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

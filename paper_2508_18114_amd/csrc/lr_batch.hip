@@ -2,12 +2,19 @@
 // layout and the launch sequence that integrates many independent
 // trajectories with the persistent on-chip kernel.
 //
-// Trajectories are sorted by step count (longest first, stable) and packed,
-// in that order, into execution groups whose workgroups are co-resident (one
-// cooperative launch per chunk of steps); groups run one after the other, so
-// trajectories of similar length share a group and few workgroups idle.  Within a group every trajectory has its own barrier
-// flags, so trajectories of different shapes and step counts proceed
-// independently, and each result is bitwise that of the trajectory alone.
+// Spread schedule (the default): trajectories are sorted by step count
+// (longest first, stable) and packed, in that order, into execution groups
+// whose workgroups are co-resident (one cooperative launch per chunk of
+// steps); groups run one after the other, so trajectories of similar length
+// share a group and few workgroups idle.  Within a group every trajectory has
+// its own barrier flags, so trajectories of different shapes and step counts
+// proceed independently, and each result is bitwise that of the trajectory
+// alone.
+//
+// Packed schedule (LR_BATCH_PACKED): every FP64 trajectory whose layer fits
+// the packed kernel gets one workgroup of its own (lr_packed.hip); all of them
+// go into one ordinary launch per chunk, largest work first, and the hardware
+// fills each CU with as many as fit.  The others run in spread groups.
 
 struct lr_batch {
   int n = 0;
@@ -17,6 +24,7 @@ struct lr_batch {
   std::vector<int> P, prt, rows;
   std::vector<size_t> lds, region, region_bytes;
   std::vector<int> wg_offset;  // first tilemap entry of each trajectory
+  std::vector<char> packed;    // trajectory runs in the packed kernel
   size_t off_trajs = 0, off_tilemap = 0, total = 0;
   int total_wg = 0;
   char* ws = nullptr;
@@ -25,6 +33,7 @@ struct lr_batch {
     int begin, end, wgs, rows, ge, prec;
     size_t lds;
     int64_t max_steps, chunk;
+    int packed, kp;
   };
   std::vector<Group> groups;
   bool prof = false;
@@ -86,23 +95,42 @@ const void* persist_fn(int rows, int ge, int prec, bool prologue = false) {
 extern "C" {
 
 int lr_batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n) {
+  return lr_batch_init_ex(out, trajs, n, 0);
+}
+
+int lr_batch_init_ex(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flags) {
   if (!out || !trajs || n < 1) return LR_ERR_ARG;
+  if (flags & ~LR_BATCH_PACKED) return LR_ERR_ARG;
   *out = nullptr;
   lr_batch* b = new (std::nothrow) lr_batch();
   if (!b) return LR_ERR_OOM;
   b->n = n;
+  auto packs = [&](const lr_traj_t& x) {
+    const long long LM = (long long)x.model.d_q * x.model.d_f * x.M;
+    return (flags & LR_BATCH_PACKED) && x.precision == LR_FP64 && x.M >= 1 && x.M <= lrk::kMaxM && LM >= 1 &&
+           LM <= lrk::kTMaxLM;
+  };
+  auto work = [&](const lr_traj_t& x) {
+    return (double)x.nsteps * x.model.d_q * x.model.d_r * x.model.d_f * x.M;
+  };
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
-  // kernel variants differ by precision mode: one mode per group
+  // packed trajectories first, largest work first; then one precision mode
+  // per spread group (kernel variants differ by it), longest first
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const bool px = packs(trajs[x]), py = packs(trajs[y]);
+    if (px != py) return px;
+    if (px) return work(trajs[x]) > work(trajs[y]);
     if (trajs[x].precision != trajs[y].precision) return trajs[x].precision < trajs[y].precision;
     return trajs[x].nsteps > trajs[y].nsteps;
   });
   b->tr.resize(n);
   b->pos.resize(n);
+  b->packed.resize(n);
   for (int k = 0; k < n; ++k) {
     b->tr[k] = trajs[order[k]];
     b->pos[order[k]] = k;
+    b->packed[k] = packs(b->tr[k]);
   }
   b->dev.resize(n);
   b->P.resize(n);
@@ -124,7 +152,16 @@ int lr_batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n) {
     if (!e && (!x.d_B || !std::isfinite(x.t0) || !(x.dt > 0.0) || !std::isfinite(x.dt) || x.nsteps < 0 ||
                x.obs_stride < 0 || (x.obs_stride > 0 && !x.d_obs) || x.step0 < 0))
       e = LR_ERR_ARG;
-    if (!e && !persist_config(x.model, x.M, b->prt[t], b->P[t], b->rows[t], b->lds[t])) e = LR_ERR_ARG;
+    if (!e && b->packed[t]) {
+      b->prt[t] = 0;
+      b->P[t] = 1;
+      b->rows[t] = 0;
+      b->lds[t] = lrk::packed_lds_elems(x.model.d_q * x.model.d_f, x.M,
+                                        std::max(std::max(x.model.d_q, x.model.d_r), x.model.d_f)) *
+                  sizeof(double2);
+    } else if (!e && !persist_config(x.model, x.M, b->prt[t], b->P[t], b->rows[t], b->lds[t])) {
+      e = LR_ERR_ARG;
+    }
     if (e) {
       delete b;
       return e;
@@ -141,6 +178,15 @@ int lr_batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n) {
     const size_t nm = N * x.M * sizeof(double2), npe = 3 * (size_t)x.M * x.M * sizeof(double2);
     const size_t P = b->P[t];
     size_t r = 0;
+    if (b->packed[t]) {
+      for (int k = 0; k < 4; ++k) r = align_up(r + nm, a);  // Bb, S0, S1, acc
+      r = align_up(r + 2 * (size_t)x.M * x.M * sizeof(double2), a);  // W
+      r = align_up(r + 64, a);                             // step, fail_step, fro2, status, abort
+      b->region[t] = o;
+      b->region_bytes[t] = r;
+      o += r;
+      continue;
+    }
     r = align_up(r + nm, a);                               // Bb
     r = align_up(r + 2 * nm, a);                           // SP
     r = align_up(r + 2 * P * npe, a);                      // PART
@@ -186,12 +232,32 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
     v.t0 = x.t0;
     v.dt = x.dt;
     v.step_base = x.step0;
+    v.prec = x.precision;
+    if (b->packed[t]) {
+      v.Bb = reinterpret_cast<double2*>(base + r);      r = align_up(r + nm, a);
+      v.S0 = reinterpret_cast<double2*>(base + r);      r = align_up(r + nm, a);
+      v.S1 = reinterpret_cast<double2*>(base + r);      r = align_up(r + nm, a);
+      v.acc = reinterpret_cast<double2*>(base + r);     r = align_up(r + nm, a);
+      v.W = reinterpret_cast<double2*>(base + r);       r = align_up(r + 2 * (size_t)x.M * x.M * sizeof(double2), a);
+      if (r + 64 > b->region_bytes[t]) return LR_ERR_STATE;  // layout of lr_batch_init_ex
+      v.step = reinterpret_cast<int64_t*>(base + r);
+      v.fail_step = reinterpret_cast<int64_t*>(base + r + 8);
+      v.fro2 = reinterpret_cast<double*>(base + r + 16);
+      v.status = reinterpret_cast<int32_t*>(base + r + 24);
+      v.abort_flag = reinterpret_cast<uint32_t*>(base + r + 28);
+      v.obs = x.obs_stride > 0 ? x.d_obs : nullptr;
+      v.P = 0;
+      v.rt = 0;
+      tmap[(size_t)b->wg_offset[t]] = make_int2(t, 0);
+      continue;
+    }
     v.Bb = reinterpret_cast<double2*>(base + r);        r = align_up(r + nm, a);
     v.SP = reinterpret_cast<double2*>(base + r);        r = align_up(r + 2 * nm, a);
     v.PART = reinterpret_cast<double2*>(base + r);      r = align_up(r + 2 * P * npe, a);
     v.RED = reinterpret_cast<double2*>(base + r);       r = align_up(r + 2 * npe, a);
     v.flagA = reinterpret_cast<uint32_t*>(base + r);    r = align_up(r + P * lrk::kFlagStride * 4, a);
     v.flagB = reinterpret_cast<uint32_t*>(base + r);    r = align_up(r + P * lrk::kFlagStride * 4, a);
+    if (r + 64 > b->region_bytes[t]) return LR_ERR_STATE;  // layout of lr_batch_init_ex
     v.step = reinterpret_cast<int64_t*>(base + r);
     v.fail_step = reinterpret_cast<int64_t*>(base + r + 8);
     v.fro2 = reinterpret_cast<double*>(base + r + 16);
@@ -215,8 +281,17 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
   int dev_id = 0, ncu = 0;
   if (hipGetDevice(&dev_id) != hipSuccess) return LR_ERR_HIP;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess) return LR_ERR_HIP;
-  size_t max_lds = 0;
-  for (int t = 0; t < b->n; ++t) max_lds = std::max(max_lds, b->lds[t]);
+  size_t max_lds = 0, max_lds_packed = 0;
+  for (int t = 0; t < b->n; ++t) {
+    size_t& m = b->packed[t] ? max_lds_packed : max_lds;
+    m = std::max(m, b->lds[t]);
+  }
+  for (int kp : lrk::kPackedKP)
+    for (int pro = 0; pro < 2; ++pro)
+      if (max_lds_packed > 0 && hipFuncSetAttribute(lrk::packed_kernel(kp, pro != 0),
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                    (int)max_lds_packed) != hipSuccess)
+        return LR_ERR_HIP;
   for (int prec = 0; prec <= 2; ++prec)
     for (int rows = 2; rows <= 3; ++rows)
       for (int ge = 1; ge <= 2; ++ge)
@@ -233,8 +308,22 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
   };
   b->groups.clear();
   int t = 0;
+  if (t < b->n && b->packed[t]) {  // one launch per chunk holds every packed trajectory
+    lr_batch::Group g{t, t, 0, 0, 0, LR_FP64, 0, 0, 0, 1, 2};
+    while (t < b->n && b->packed[t]) {
+      g.kp = std::max(g.kp, lrk::packed_kp(b->tr[t].M));
+      g.lds = std::max(g.lds, b->lds[t]);
+      g.wgs += 1;
+      g.max_steps = std::max(g.max_steps, b->tr[t].nsteps);
+      const int64_t s = b->tr[t].obs_stride;
+      if (s > 0) g.chunk = g.chunk ? gcd64(g.chunk, s) : s;
+      g.end = ++t;
+    }
+    if (g.chunk == 0) g.chunk = 4096;
+    b->groups.push_back(g);
+  }
   while (t < b->n) {
-    lr_batch::Group g{t, t, 0, 2, 1, b->tr[t].precision, 0, 0, 0};
+    lr_batch::Group g{t, t, 0, 2, 1, b->tr[t].precision, 0, 0, 0, 0, 0};
     while (t < b->n) {
       if (b->tr[t].precision != g.prec) break;
       const int rows = std::max(g.rows, b->rows[t]);
@@ -290,8 +379,16 @@ int lr_batch_run(lr_batch_t* b) {
         k = b->n_ev++;
         (void)hipEventRecord(b->ev[2 * k], b->stream);
       }
-      const hipError_t err = hipLaunchCooperativeKernel(persist_fn(g.rows, g.ge, g.prec, prologue != 0), dim3(g.wgs),
-                                                        dim3(lrk::kPW), args, (unsigned)g.lds, b->stream);
+      hipError_t err;
+      if (g.packed) {
+        const TrajDev* ptr = trajs + g.begin;
+        void* pargs[] = {(void*)&ptr, (void*)&step0, (void*)&nchunk};
+        err = hipLaunchKernel(lrk::packed_kernel(g.kp, prologue != 0), dim3(g.wgs), dim3(lrk::kTW), pargs,
+                              g.lds, b->stream);
+      } else {
+        err = hipLaunchCooperativeKernel(persist_fn(g.rows, g.ge, g.prec, prologue != 0), dim3(g.wgs),
+                                         dim3(lrk::kPW), args, (unsigned)g.lds, b->stream);
+      }
       if (k >= 0) (void)hipEventRecord(b->ev[2 * k + 1], b->stream);
       return err == hipSuccess ? LR_OK : LR_ERR_HIP;
     };

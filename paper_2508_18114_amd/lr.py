@@ -30,12 +30,14 @@ LR_ERR_PULSE = -6
 LR_ERR_STATE = -7
 LR_ERR_TIMEOUT = -8
 LR_MAX_M = 32
+LR_BATCH_PACKED = 1       # lr_batch_init_ex flag: one workgroup per FP64 trajectory
+LR_PACKED_MAX_LM = 2560
 
 # every symbol include/lr.h declares
 EXPORTS = ("lr_init", "lr_workspace_bytes", "lr_bind", "lr_rhs", "lr_integrate",
            "lr_observables", "lr_spectrum", "lr_status", "lr_profile_enable", "lr_profile_read",
            "lr_readout_loss", "lr_dense_workspace_bytes", "lr_dense_integrate", "lr_strerror", "lr_destroy",
-           "lr_batch_init", "lr_batch_workspace_bytes", "lr_batch_bind", "lr_batch_run",
+           "lr_batch_init", "lr_batch_init_ex", "lr_batch_workspace_bytes", "lr_batch_bind", "lr_batch_run",
            "lr_batch_status", "lr_batch_profile_enable", "lr_batch_profile_read", "lr_batch_destroy")
 
 
@@ -94,6 +96,7 @@ def _load():
         "lr_dense_integrate": (ctypes.c_int, [ctypes.POINTER(lr_model_t), ctypes.POINTER(lr_pulse_t), dbl, dbl, i64,
                                               vp, i32, vp, vp, sz, vp]),
         "lr_batch_init": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lr_traj_t), i32]),
+        "lr_batch_init_ex": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lr_traj_t), i32, i32]),
         "lr_batch_workspace_bytes": (sz, [vp]),
         "lr_batch_bind": (ctypes.c_int, [vp, vp, sz, vp]),
         "lr_batch_run": (ctypes.c_int, [vp]),
@@ -191,11 +194,14 @@ def lr_destroy(ctx: int) -> None:
     _lib.lr_destroy(ctx)
 
 
-def lr_batch_init(trajs) -> int:
-    """trajs: sequence of lr_traj_t."""
+def lr_batch_init(trajs, flags: int = 0) -> int:
+    """trajs: sequence of lr_traj_t; flags: 0 or LR_BATCH_PACKED (lr_batch_init_ex)."""
     arr = (lr_traj_t * len(trajs))(*trajs)
     h = ctypes.c_void_p()
-    rc = _lib.lr_batch_init(ctypes.byref(h), arr, len(trajs))
+    if flags:
+        rc = _lib.lr_batch_init_ex(ctypes.byref(h), arr, len(trajs), flags)
+    else:
+        rc = _lib.lr_batch_init(ctypes.byref(h), arr, len(trajs))
     if rc != LR_OK:
         raise LrError(rc, "lr_batch_init")
     return h.value
@@ -370,17 +376,18 @@ class Batch:
     tensor (M, N) complex128), and optionally t0, obs_stride, obs (device
     tensor), precision (FP64 / FP32 / BF16X3), step0 (index of the first step
     when a trajectory is continued).  The tensors must stay alive while the
-    batch is used.
+    batch is used.  packed=True: the packed schedule (LR_BATCH_PACKED), one
+    workgroup per FP64 trajectory.
     """
 
-    def __init__(self, items, stream=None):
+    def __init__(self, items, stream=None, packed=False):
         import torch
         self.items = list(items)
         ts = [traj_struct(it["model"], it["M"], it["pulse"], it.get("t0", 0.0), it["dt"], it["nsteps"],
                           it["B"], it.get("obs_stride", 0), it.get("obs"), it.get("precision", _inp.FP64),
                           it.get("step0", 0))
               for it in self.items]
-        self.handle = lr_batch_init(ts)
+        self.handle = lr_batch_init(ts, LR_BATCH_PACKED if packed else 0)
         nbytes = lr_batch_workspace_bytes(self.handle)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         base = self.workspace.data_ptr()

@@ -721,3 +721,129 @@ def test_spsa_optimize_runs_on_device(lr):
     assert all(np.isfinite(h["loss_plus"]) and np.isfinite(h["loss_minus"]) for h in hist)
     assert np.all(np.abs(serve.heights_from(theta)) < I.ghz(0.4))
     assert np.any(serve.heights_from(theta) != I.ghz(0.15))  # (a 0.3 ns pulse moves the loss very little)
+
+
+# ------------------------------------------------------------ packed batch schedule (one workgroup per trajectory)
+
+def _run_packed(lr, items, packed=True):
+    b = lr.Batch(items, packed=packed)
+    b.run()
+    rc, codes, steps = b.status()
+    b.close()
+    return rc, codes, steps
+
+
+def test_packed_config_small_matches_oracle(lr):
+    """Configuration 1 (dims (4,10,5), M = 4, 1e4 RK4 steps, g and e) in the packed schedule against the
+    cached oracle run, with the figures of merit."""
+    import torch
+    trajs = I.config_small()
+    gd = _golden("small")
+    stride = int(gd["stride"])
+    items = [dict(model=t.model, M=t.M, pulse=t.pulse, dt=t.dt, nsteps=t.nsteps, B=lr.to_device(t.B0()),
+                  obs_stride=stride,
+                  obs=torch.zeros((t.nsteps // stride + 1, 6 + t.model.d_q), dtype=torch.float64, device="cuda"))
+             for t in trajs]
+    rc, codes, _ = _run_packed(lr, items)
+    assert rc == lr.LR_OK, codes
+    for it, key in zip(items, ("obs_g", "obs_e")):
+        _assert_obs(it["obs"].cpu().numpy(), gd[key], f"packed small {key}")
+    t = trajs[0]
+    fm = lr.readout_loss(items[0]["obs"], items[1]["obs"], t.model.d_q, stride * t.dt, t.model.kappa_f,
+                         t.model.gamma_1)
+    assert abs(fm["snr"] - float(gd["snr"])) <= 1e-8 * float(gd["snr"])
+    assert abs(fm["loss"] - float(gd["loss"])) <= 1e-8
+
+
+def test_packed_batch_matches_oracle(lr):
+    """Mixed shapes (M = 1 .. 20, different lengths and strides) and a drive-frame stepwise pulse, all in
+    one packed launch, against the oracle."""
+    items = _batch_items(lr, BATCH_SPECS)
+    m = I.readout_model(3, 7, 4).replace(kappa_f=0.5, gamma_1=0.05)
+    p = _stepwise(20, 83).replace(frame=1)
+    B0 = I.initial_state(m, 4, "e", seed=84, scale=1e-3)
+    import torch
+    items.append(dict(model=m, M=4, pulse=p, dt=1e-3, nsteps=203, B0=B0, B=lr.to_device(B0), obs_stride=7,
+                      obs=torch.zeros((203 // 7 + 1, 6 + 3), dtype=torch.float64, device="cuda")))
+    rc, codes, _ = _run_packed(lr, items)
+    assert rc == lr.LR_OK, codes
+    for it in items:
+        Bo, ref = lowrank.integrate(it["model"], it["pulse"], 0.0, it["dt"], it["nsteps"], it["B0"],
+                                    obs_stride=it["obs_stride"])
+        got_B = lr.from_device(it["B"])
+        err = np.max(np.abs(got_B - Bo))
+        print(f"[parity] packed dims {it['model'].d_q, it['model'].d_r, it['model'].d_f} M={it['M']}: |dB| {err:.3e}")
+        assert err <= 1e-10
+        if it["obs_stride"]:
+            _assert_obs(it["obs"].cpu().numpy(), ref, f"packed dims {it['model'].d_q, it['model'].d_r}")
+
+
+def test_packed_result_does_not_depend_on_the_batch(lr):
+    """A packed trajectory alone and among others: bitwise the same state and records."""
+    alone = _batch_items(lr, BATCH_SPECS[2:3])
+    assert _run_packed(lr, alone)[0] == lr.LR_OK
+    mix = _batch_items(lr, BATCH_SPECS)
+    assert _run_packed(lr, mix)[0] == lr.LR_OK
+    assert np.array_equal(lr.from_device(alone[0]["B"]), lr.from_device(mix[2]["B"]))
+    assert np.array_equal(alone[0]["obs"].cpu().numpy(), mix[2]["obs"].cpu().numpy())
+
+
+def test_packed_paper_size_agrees_with_spread(lr):
+    """Paper size (N = 2000, M = 20), 400 steps of g and e: the packed and the spread schedule agree to
+    the FP64 parity tolerances (different summation orders, same arithmetic)."""
+    import torch
+    trajs = I.config_paper_size()
+    out = {}
+    for packed in (False, True):
+        items = [dict(model=t.model, M=t.M, pulse=t.pulse, dt=t.dt, nsteps=400, B=lr.to_device(t.B0()),
+                      obs_stride=50, obs=torch.zeros((9, 6 + t.model.d_q), dtype=torch.float64, device="cuda"))
+                 for t in trajs]
+        rc, codes, _ = _run_packed(lr, items, packed=packed)
+        assert rc == lr.LR_OK, codes
+        out[packed] = [it["obs"].cpu().numpy() for it in items]
+    for a, b in zip(out[False], out[True]):
+        _assert_obs(b, a, "paper size packed vs spread")
+
+
+def test_packed_limits_and_fallback(lr):
+    """The largest packed layer (d_q d_f M = 2560) against the oracle; FP32 trajectories in a packed
+    batch run in the spread schedule, bitwise as in a batch without the flag."""
+    import torch
+    m = I.readout_model(8, 3, 10).replace(kappa_f=0.5, gamma_1=0.05)
+    assert m.d_q * m.d_f * 32 == lr.LR_PACKED_MAX_LM
+    p = I.flattop_pulse(0.05, 0.1, t_ramp=0.02)
+    B0 = I.initial_state(m, 32, "g", seed=91, scale=1e-2)
+    it = dict(model=m, M=32, pulse=p, dt=1e-3, nsteps=40, B=lr.to_device(B0), obs_stride=10,
+              obs=torch.zeros((5, 6 + 8), dtype=torch.float64, device="cuda"))
+    assert _run_packed(lr, [it])[0] == lr.LR_OK
+    Bo, ref = lowrank.integrate(m, p, 0.0, 1e-3, 40, B0, obs_stride=10)
+    _assert_obs(it["obs"].cpu().numpy(), ref, "packed largest layer")
+    # FP32 and BF16x3 fall back to the spread schedule
+    specs = [(m, 8, 1), (I.readout_model(4, 6, 5), 6, 2)]
+    res = {}
+    for packed in (False, True):
+        items = [dict(model=mm, M=M, pulse=p, dt=1e-3, nsteps=30, B=lr.to_device(I.initial_state(mm, M, "e", 92, scale=1e-2)),
+                      precision=prec) for mm, M, prec in specs]
+        assert _run_packed(lr, items, packed=packed)[0] == lr.LR_OK
+        res[packed] = [lr.from_device(x["B"]) for x in items]
+    for a, b in zip(res[False], res[True]):
+        assert np.array_equal(a, b)
+
+
+def test_packed_device_errors(lr):
+    """Rank-deficient and non-finite initial states stop their own trajectory at step 0 with the error
+    code; a healthy trajectory in the same packed launch is unaffected."""
+    m = I.readout_model(2, 3, 2)
+    p = I.flattop_pulse(0.05, 1.0)
+    B0 = _rand_B(m.N, 3, 10)
+    B0[:, 1] = 0.0
+    B1 = _rand_B(m.N, 3, 11)
+    B1[4, 2] = np.nan
+    B2 = _rand_B(m.N, 3, 12)
+    items = [dict(model=m, M=3, pulse=p, dt=1e-3, nsteps=5, B=lr.to_device(B)) for B in (B0, B1, B2)]
+    rc, codes, steps = _run_packed(lr, items)
+    assert list(codes) == [lr.LR_ERR_GRAM_NOT_PD, lr.LR_ERR_NONFINITE, lr.LR_OK]
+    assert list(steps[:2]) == [0, 0]
+    alone = [dict(model=m, M=3, pulse=p, dt=1e-3, nsteps=5, B=lr.to_device(B2))]
+    assert _run_packed(lr, alone)[0] == lr.LR_OK
+    assert np.array_equal(lr.from_device(alone[0]["B"]), lr.from_device(items[2]["B"]))
