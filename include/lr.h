@@ -247,8 +247,9 @@ typedef struct lr_batch lr_batch_t;
  * device pointers inside the descriptors are used by lr_batch_run. */
 int lr_batch_init(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n);
 /* lr_batch_init with schedule flags.  0 is lr_batch_init.  LR_BATCH_PACKED:
- * every LR_FP64 trajectory with d_q d_f M <= LR_PACKED_MAX_LM runs in a
- * workgroup of its own (all of them in one launch per chunk of steps, as many
+ * every LR_FP64 trajectory with d_q d_f M <= LR_PACKED_MAX_LM (and whose
+ * workgroup's LDS, about 16 (4 d_q d_f M + 2 M^2 + 2.5 d_q d_f) bytes, fits
+ * 159 KiB) runs in a workgroup of its own (all of them in one launch per chunk of steps, as many
  * per CU as fit), which fills the GPU with many trajectories at once instead
  * of spreading each one over d_r workgroups; the other trajectories run as
  * without the flag.  A packed trajectory's result does not depend on the
@@ -256,7 +257,7 @@ int lr_batch_init(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n);
  * of the spread schedule: the two agree to the FP64 tolerances of lr_integrate.
  * Unknown flag bits: LR_ERR_ARG. */
 #define LR_BATCH_PACKED 1
-#define LR_PACKED_MAX_LM 2560
+#define LR_PACKED_MAX_LM 1536
 int lr_batch_init_ex(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n, int32_t flags);
 size_t lr_batch_workspace_bytes(const lr_batch_t* batch);
 int lr_batch_bind(lr_batch_t* batch, void* d_workspace, size_t bytes, void* stream);

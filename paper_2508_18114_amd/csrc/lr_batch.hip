@@ -107,8 +107,11 @@ int lr_batch_init_ex(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_
   b->n = n;
   auto packs = [&](const lr_traj_t& x) {
     const long long LM = (long long)x.model.d_q * x.model.d_f * x.M;
-    return (flags & LR_BATCH_PACKED) && x.precision == LR_FP64 && x.M >= 1 && x.M <= lrk::kMaxM && LM >= 1 &&
-           LM <= lrk::kTMaxLM;
+    if (!((flags & LR_BATCH_PACKED) && x.precision == LR_FP64 && x.M >= 1 && x.M <= lrk::kMaxM && LM >= 1 &&
+          LM <= lrk::kTMaxLM && x.model.d_r >= 1 && x.model.d_r <= (1 << 20)))
+      return false;
+    const int dmax = std::max(std::max(x.model.d_q, x.model.d_r), x.model.d_f);
+    return lrk::packed_lds_elems(x.model.d_q * x.model.d_f, x.M, dmax) * sizeof(double2) <= lrk::kPackedLdsMax;
   };
   auto work = [&](const lr_traj_t& x) {
     return (double)x.nsteps * x.model.d_q * x.model.d_r * x.model.d_f * x.M;

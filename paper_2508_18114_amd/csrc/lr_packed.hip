@@ -10,12 +10,12 @@
 //
 // Per RK4 stage (the right-hand side of eq. "nosse", supplement S1.A):
 //   for each resonator layer r (L = d_q d_f rows x M columns):
-//     1. the layer of the stage input Y is in LDS (loaded while the previous
-//        layer's Gram terms were formed); each element takes the H_eff
-//        stencil (neighbour layers r +- 1 read from global memory), the jump
-//        assembly 1/2 sum_k (L_k Y)[rho, :] W_k[:, j] against the W_k in LDS,
-//        and the RK4 combination; the stage output goes to global memory and
-//        to a second LDS tile;
+//     1. layers r - 1, r, r + 1 of the stage input Y are in LDS (each loaded
+//        while the Gram terms of an earlier layer were formed); each element
+//        takes the H_eff stencil, the jump assembly 1/2 sum_k (L_k Y)[rho, :]
+//        W_k[:, j] against the W_k in LDS, and the RK4 combination with B_n
+//        and the accumulator (loaded during the assembly); the stage output
+//        goes to global memory and to a fourth LDS tile;
 //     2. every thread adds the layer's contribution to its own entries of
 //        [G | C_1 | C_2] = O^ [O | L_1 O | L_2 O] of the stage output O (the
 //        jumps stay in a layer), rows in order;
@@ -35,19 +35,23 @@
 namespace lrk {
 
 constexpr int kTW = 256;            // threads of a packed workgroup
-constexpr int kTMaxLM = 2560;       // rows x M of one layer
-constexpr int kTRowBlock = 4;       // layer rows per thread per assembly pass
+constexpr int kTMaxLM = 1536;       // rows x M of one layer
+constexpr size_t kPackedLdsMax = 159 * 1024;  // dynamic LDS of one workgroup (of 160 KiB per CU)
+constexpr int kTRowBlock = 2;       // layer rows per thread per assembly pass
 constexpr int kTPrefetch = 5;       // elements per thread of the next layer held in registers
 constexpr int kTDriveWin = 32;      // steps per drive table refill
 
-// LDS (in complex elements) of a packed workgroup: two layer tiles, or the
-// M x 3M elimination matrix; W_1, W_2; per-row tables (jump coefficients and
-// the diagonal of H_eff without its resonator term, 5 L doubles) and
-// sqrt(0 .. dmax), dmax = max(d_q, d_r, d_f).
+// LDS (in complex elements) of a packed workgroup: four layer tiles (three
+// layers of the stage input, one of the output), or the M x 3M elimination
+// matrix; W_1, W_2; the drive table (kTDriveWin steps x 4 stages x 5 doubles)
+// and the pivot row of the elimination (3M); per-row tables (jump
+// coefficients and the diagonal of H_eff without its resonator term, 5 L
+// doubles) and sqrt(0 .. dmax), dmax = max(d_q, d_r, d_f).
 __host__ __device__ inline size_t packed_lds_elems(int L, int M, int dmax) {
-  const size_t tiles = 2 * (size_t)L * M, aug = 3 * (size_t)M * M;
+  const size_t tiles = 4 * (size_t)L * M, aug = 3 * (size_t)M * M;
   // (+16: the Gram-term row blocks may read up to 15 elements past the output tile)
-  return (tiles > aug ? tiles : aug) + 2 * (size_t)M * M + (5 * (size_t)L + dmax + 2) / 2 + 16;
+  return (tiles > aug ? tiles : aug) + 2 * (size_t)M * M + 10 * kTDriveWin + 3 * (size_t)M +
+         (5 * (size_t)L + dmax + 2) / 2 + 16;
 }
 // Entries of [G | C_1 | C_2] per thread: thread t owns column t mod 3M and
 // the block of KPe consecutive rows from (t / 3M) KPe, KPe = ceil(M / NG),
@@ -79,15 +83,15 @@ __device__ __forceinline__ void gram_rows(double2 (&acc)[KP], const double2* Ot,
   }
 }
 
-// sq[k] = sqrt(k); hd[rl] = diagonal of H_eff at row rl without w_r r.
+// Element (rl, j) of layer r: z = H_eff Y (stencil and drive) from the layers
+// r - 1, r, r + 1 of the stage input in LDS (Yp, Yc, Yn).  sq[k] = sqrt(k);
+// hd[rl] = diagonal of H_eff at row rl without w_r r.
 template <bool ROT>
-__device__ __forceinline__ double2 packed_stencil(const TrajDev& T, const g_double2* __restrict__ in,
-                                                  const double2* Yt, const double* sq, const double2* hd, int r,
+__device__ __forceinline__ double2 packed_stencil(const TrajDev& T, const double2* Yp, const double2* Yc,
+                                                  const double2* Yn, const double* sq, const double2* hd, int r,
                                                   int rl, int q, int f, int j, double drv, double2 e1, double2 e2) {
-  const int M = T.M, L = T.L, d_f = T.d_f, d_q = T.d_q, d_r = T.d_r;
-  const size_t rho = (size_t)r * L + rl;
-  const g_double2* col = in + j;
-  const double2 b = Yt[rl * M + j];
+  const int M = T.M, d_f = T.d_f, d_q = T.d_q, d_r = T.d_r;
+  const double2 b = Yc[rl * M + j];
   auto tap = [&](double2 z, double c, int dn, double2 nb) {
     if (!ROT || dn == 0) return cfma(c, nb, z);
     const double2 e = (dn == 2 || dn == -2) ? e2 : e1;
@@ -101,25 +105,17 @@ __device__ __forceinline__ double2 packed_stencil(const TrajDev& T, const g_doub
     const int qq = q + dq;
     if (qq < 0 || qq >= d_q) continue;
     const double cq = T.g * sq[max(q, qq)];
-#pragma unroll
-    for (int dr = -1; dr <= 1; dr += 2) {
-      const int rr = r + dr;
-      if (rr < 0 || rr >= d_r) continue;
-      z = tap(z, cq * (dr < 0 ? sr_lo : sr_hi), dq + dr, ld_g(col + (rho + dq * d_f + dr * L) * M));
-    }
+    if (r > 0) z = tap(z, cq * sr_lo, dq - 1, Yp[(rl + dq * d_f) * M + j]);
+    if (r + 1 < d_r) z = tap(z, cq * sr_hi, dq + 1, Yn[(rl + dq * d_f) * M + j]);
   }
 #pragma unroll
   for (int df = -1; df <= 1; df += 2) {
     const int ff = f + df;
     if (ff < 0 || ff >= d_f) continue;
     const double cf = sq[max(f, ff)];
-#pragma unroll
-    for (int dr = -1; dr <= 1; dr += 2) {
-      const int rr = r + dr;
-      if (rr < 0 || rr >= d_r) continue;
-      z = tap(z, T.G * cf * (dr < 0 ? sr_lo : sr_hi), dr + df, ld_g(col + (rho + dr * L + df) * M));
-    }
-    z = tap(z, drv * cf, df, Yt[(rl + df) * M + j]);
+    if (r > 0) z = tap(z, T.G * cf * sr_lo, df - 1, Yp[(rl + df) * M + j]);
+    if (r + 1 < d_r) z = tap(z, T.G * cf * sr_hi, df + 1, Yn[(rl + df) * M + j]);
+    z = tap(z, drv * cf, df, Yc[(rl + df) * M + j]);
   }
   return z;
 }
@@ -130,8 +126,6 @@ __device__ __forceinline__ double2 packed_stencil(const TrajDev& T, const g_doub
 template <int KP, bool ROT>
 __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int64_t step0, int64_t nchunk) {
   extern __shared__ double2 lds[];
-  __shared__ double s_dtab[4 * kTDriveWin][5];
-  __shared__ double2 s_prow[3 * kMaxM];
   __shared__ double s_red[kTW / 64];
   __shared__ int s_flag;
   const int tid = threadIdx.x;
@@ -139,11 +133,15 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
   const int LM = L * M, C3 = 3 * M;
   const double dt = T.dt;
   const double sk = sqrt(T.kappa), sg = sqrt(T.gamma);
-  double2* Yt = lds;                                  // layer of the stage input
-  double2* Ot = lds + LM;                             // layer of the stage output
+  double2* Yp = lds;                                  // layers r - 1, r, r + 1 of the stage input
+  double2* Yc = lds + LM;
+  double2* Yn = lds + 2 * LM;
+  double2* Ot = lds + 3 * LM;                         // layer r of the stage output
   double2* Aug = lds;                                 // M x 3M elimination (after the layer loop)
-  double2* Wl = lds + (2 * LM > 3 * MM ? 2 * LM : 3 * MM);  // W_1, W_2 (M x M each, row i, column j)
-  double2* hd = Wl + 2 * MM;                                // [L] diagonal of H_eff without w_r r
+  double2* Wl = lds + (4 * LM > 3 * MM ? 4 * LM : 3 * MM);  // W_1, W_2 (M x M each, row i, column j)
+  double (*s_dtab)[5] = reinterpret_cast<double (*)[5]>(Wl + 2 * MM);  // [4 kTDriveWin][5] drive table
+  double2* s_prow = Wl + 2 * MM + 10 * kTDriveWin;          // [3M] pivot row
+  double2* hd = s_prow + 3 * M;                             // [L] diagonal of H_eff without w_r r
   double* coef = reinterpret_cast<double*>(hd + L);         // [3][L]: 1, filter jump, transmon jump
   double* sq = coef + 3 * L;                                // sqrt(0 .. dmax)
   g_double2* gBb = (g_double2*)T.Bb;
@@ -317,18 +315,33 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
 #pragma unroll
       for (int k = 0; k < KP; ++k) acc[k] = make_double2(0.0, 0.0);
       __syncthreads();  // Wl of this stage written; tiles free
-      for (int e = tid; e < LM; e += kTW) Yt[e] = ld_g(in + e);
+      Yp = lds;
+      Yc = lds + LM;
+      Yn = lds + 2 * LM;
+      for (int e = tid; e < LM; e += kTW) Yc[e] = ld_g(in + e);
+      if (d_r > 1)
+        for (int e = tid; e < LM; e += kTW) Yn[e] = ld_g(in + LM + e);
       __syncthreads();
       for (int r = 0; r < d_r; ++r) {
-        // 1. stage output of layer r
+        // 1. stage output of layer r, in blocks of kTRowBlock rows per thread
         if (eact) {
           for (int rb = eg; rb < L; rb += kTRowBlock * NGe) {
-            double2 a1[kTRowBlock], a2[kTRowBlock];
+            // B_n and the RK4 accumulator of the block are in flight during the jump assembly
+            double2 pb[kTRowBlock], pa[kTRowBlock];
+            if (s > 0) {
 #pragma unroll
-            for (int k = 0; k < kTRowBlock; ++k) a1[k] = a2[k] = make_double2(0.0, 0.0);
+              for (int k = 0; k < kTRowBlock; ++k) {
+                const int rl = min(rb + k * NGe, L - 1);
+                const size_t gi = ((size_t)r * L + rl) * M + ej;
+                pb[k] = ld_g(gBb + gi);
+                pa[k] = ld_g(gacc + gi);
+              }
+            }
+            double2 a1[kTRowBlock], a2[kTRowBlock];
             int s1[kTRowBlock], s2[kTRowBlock];  // source rows of the jumps, clamped into the tile
 #pragma unroll
             for (int k = 0; k < kTRowBlock; ++k) {
+              a1[k] = a2[k] = make_double2(0.0, 0.0);
               const int rl = min(rb + k * NGe, L - 1);
               s1[k] = min(rl + 1, L - 1) * M;
               s2[k] = min(rl + d_f, L - 1) * M;
@@ -337,47 +350,43 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
               const double2 w1 = Wl[i * M + ej], w2 = Wl[MM + i * M + ej];
 #pragma unroll
               for (int k = 0; k < kTRowBlock; ++k) {
-                a1[k] = cmac(a1[k], Yt[s1[k] + i], w1);
-                a2[k] = cmac(a2[k], Yt[s2[k] + i], w2);
+                a1[k] = cmac(a1[k], Yc[s1[k] + i], w1);
+                a2[k] = cmac(a2[k], Yc[s2[k] + i], w2);
               }
             }
 #pragma unroll
-            for (int k = 0; k < kTRowBlock; ++k) {  // the jump term parks in the output tile
+            for (int k = 0; k < kTRowBlock; ++k) {
               const int rl = rb + k * NGe;
-              if (rl < L) Ot[rl * M + ej] = cfma(coef[L + rl], a1[k], cscale(coef[2 * L + rl], a2[k]));
+              if (rl < L) {
+                const int q = rl / d_f, f = rl - q * d_f;
+                const double2 a = cfma(coef[L + rl], a1[k], cscale(coef[2 * L + rl], a2[k]));
+                const double2 z = packed_stencil<ROT>(T, Yp, Yc, Yn, sq, hd, r, rl, q, f, ej, drv, e1, e2);
+                const double2 kk = make_double2(z.y + 0.5 * a.x, -z.x + 0.5 * a.y);
+                const size_t gi = ((size_t)r * L + rl) * M + ej;
+                double2 o;
+                if (s == 0) {
+                  st_g(gacc + gi, kk);
+                  o = cfma(0.5 * dt, kk, Yc[rl * M + ej]);
+                } else if (s == 1) {
+                  st_g(gacc + gi, cfma(2.0, kk, pa[k]));
+                  o = cfma(0.5 * dt, kk, pb[k]);
+                } else if (s == 2) {
+                  st_g(gacc + gi, cfma(2.0, kk, pa[k]));
+                  o = cfma(dt, kk, pb[k]);
+                } else {
+                  o = cfma(dt / 6.0, cadd(pa[k], kk), pb[k]);
+                }
+                st_g(out + gi, o);
+                Ot[rl * M + ej] = o;
+              }
             }
-          }
-          // stencil and RK4 combination, two rows at a time
-#pragma unroll 2
-          for (int rl = eg; rl < L; rl += NGe) {
-            const int q = rl / d_f, f = rl - q * d_f;
-            const double2 a = Ot[rl * M + ej];
-            const double2 z = packed_stencil<ROT>(T, in, Yt, sq, hd, r, rl, q, f, ej, drv, e1, e2);
-            const double2 kk = make_double2(z.y + 0.5 * a.x, -z.x + 0.5 * a.y);
-            const size_t gi = ((size_t)r * L + rl) * M + ej;
-            const double2 base = (s == 0) ? Yt[rl * M + ej] : ld_g(gBb + gi);
-            double2 o;
-            if (s == 0) {
-              st_g(gacc + gi, kk);
-              o = cfma(0.5 * dt, kk, base);
-            } else if (s == 1) {
-              st_g(gacc + gi, cfma(2.0, kk, ld_g(gacc + gi)));
-              o = cfma(0.5 * dt, kk, base);
-            } else if (s == 2) {
-              st_g(gacc + gi, cfma(2.0, kk, ld_g(gacc + gi)));
-              o = cfma(dt, kk, base);
-            } else {
-              o = cfma(dt / 6.0, cadd(ld_g(gacc + gi), kk), base);
-            }
-            st_g(out + gi, o);
-            Ot[rl * M + ej] = o;
           }
         }
         __syncthreads();
-        // 2. the next layer of the stage input is in flight while the Gram
-        //    terms of this one are formed
-        if (r + 1 < d_r) {
-          const g_double2* nx = in + (size_t)(r + 1) * LM;
+        // 2. layer r + 2 of the stage input is in flight while the Gram terms
+        //    of layer r are formed; it replaces layer r - 1
+        if (r + 2 < d_r) {
+          const g_double2* nx = in + (size_t)(r + 2) * LM;
           double2 pf[kTPrefetch];
 #pragma unroll
           for (int u = 0; u < kTPrefetch; ++u) {
@@ -388,13 +397,17 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
 #pragma unroll
           for (int u = 0; u < kTPrefetch; ++u) {
             const int e = tid + u * kTW;
-            if (e < LM) Yt[e] = pf[u];
+            if (e < LM) Yp[e] = pf[u];
           }
-          for (int e = tid + kTPrefetch * kTW; e < LM; e += kTW) Yt[e] = ld_g(nx + e);
+          for (int e = tid + kTPrefetch * kTW; e < LM; e += kTW) Yp[e] = ld_g(nx + e);
         } else {
           add_terms(acc);
         }
         __syncthreads();
+        double2* t = Yp;
+        Yp = Yc;
+        Yc = Yn;
+        Yn = t;
       }
       double f2 = 0.0;
       const bool last = (s == 3) && (n + 1 == nrun);

@@ -31,7 +31,7 @@ LR_ERR_STATE = -7
 LR_ERR_TIMEOUT = -8
 LR_MAX_M = 32
 LR_BATCH_PACKED = 1       # lr_batch_init_ex flag: one workgroup per FP64 trajectory
-LR_PACKED_MAX_LM = 2560
+LR_PACKED_MAX_LM = 1536
 
 # every symbol include/lr.h declares
 EXPORTS = ("lr_init", "lr_workspace_bytes", "lr_bind", "lr_rhs", "lr_integrate",

@@ -806,10 +806,10 @@ def test_packed_paper_size_agrees_with_spread(lr):
 
 
 def test_packed_limits_and_fallback(lr):
-    """The largest packed layer (d_q d_f M = 2560) against the oracle; FP32 trajectories in a packed
+    """The largest packed layer (d_q d_f M = 1536) against the oracle; FP32 trajectories in a packed
     batch run in the spread schedule, bitwise as in a batch without the flag."""
     import torch
-    m = I.readout_model(8, 3, 10).replace(kappa_f=0.5, gamma_1=0.05)
+    m = I.readout_model(8, 3, 6).replace(kappa_f=0.5, gamma_1=0.05)
     assert m.d_q * m.d_f * 32 == lr.LR_PACKED_MAX_LM
     p = I.flattop_pulse(0.05, 0.1, t_ramp=0.02)
     B0 = I.initial_state(m, 32, "g", seed=91, scale=1e-2)
