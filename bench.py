@@ -74,10 +74,10 @@ def comparisons(lr, I, torch, stream, plain_value):
     trajs = I.config_paper_size()
     m, M = trajs[0].model, trajs[0].M
 
-    def run_batch(tr_list, nsteps_cap):
+    def run_batch(tr_list, nsteps_cap, packed=False):
         items = [dict(model=t.model, M=t.M, pulse=t.pulse, dt=t.dt, nsteps=min(t.nsteps, nsteps_cap),
                       B=lr.to_device(t.B0())) for t in tr_list]
-        b = lr.Batch(items, stream=stream)
+        b = lr.Batch(items, stream=stream, packed=packed)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         b.run()
@@ -107,13 +107,28 @@ def comparisons(lr, I, torch, stream, plain_value):
                                  "vs_plain_g_e": v / plain_value, "vs_plain_single": v / single,
                                  "workload": f"{2 * npulse} trajectories ({npulse} piecewise pulses x g/e), "
                                              f"N=2000, M=20, {steps} steps each, one batch ({el:.2f} s)"}
+    vp, elp = run_batch(I.batch_uniform(npulse), steps, packed=True)
+    out["batched_same_shape_packed"] = {"value": vp, "unit": "RK steps*trajectories/s", "vs_spread": vp / v,
+                                        "workload": f"as batched_same_shape, packed schedule ({elp:.2f} s)"}
+    # 512 trajectories of one shape (256 pulses x g/e, N=2000, M=20): spread vs packed schedule
+    n512 = I.batch_uniform(256)
+    v_s, el_s = run_batch(n512, 40)
+    v_p, el_p = run_batch(n512, 200, packed=True)
+    out["batched_512_same_shape"] = {
+        "spread": v_s, "packed": v_p, "packed_vs_spread": v_p / v_s, "packed_vs_plain_g_e": v_p / plain_value,
+        "unit": "RK steps*trajectories/s",
+        "workload": f"512 trajectories (256 piecewise pulses x g/e), N=2000, M=20; spread: first 40 steps "
+                    f"({el_s:.2f} s), packed: first 200 steps ({el_p:.2f} s)"}
     # batched mixed shapes: the 512 trajectories of the batched configuration, capped step count
     steps = 150
     c4 = I.config_batched()
     v, el = run_batch(c4, steps)
+    vp, elp = run_batch(c4, steps, packed=True)
     out["batched_mixed_c4_sample"] = {"value": v, "unit": "RK steps*trajectories/s",
+                                      "packed": vp, "packed_vs_spread": vp / v,
                                       "workload": f"{len(c4)} trajectories, N in {{1000,1520,2000,3000}}, "
-                                                  f"M in [8,32], first {steps} steps of each ({el:.2f} s)"}
+                                                  f"M in [8,32], first {steps} steps of each (spread "
+                                                  f"{el:.2f} s, packed {elp:.2f} s)"}
     # dense full-Lindblad RK4 at the same N, dt
     N = m.N
     rho = torch.zeros((N, N), dtype=torch.complex128, device="cuda")
@@ -156,9 +171,9 @@ def comparisons(lr, I, torch, stream, plain_value):
     n_req, cap = 12, 4000
     budget = 64 << 30
 
-    def serve_run(rate):
+    def serve_run(rate, packed=False):
         reqs = serve.serving_requests(5, n_req, rate, step_cap=cap)
-        srv = serve.Server(hbm_budget_bytes=budget, chunk=2000, stream=stream)
+        srv = serve.Server(hbm_budget_bytes=budget, chunk=2000, stream=stream, packed=packed)
         st = srv.run(reqs)
         st["offered_rate_per_s"] = rate
         return st, reqs

@@ -56,13 +56,14 @@ class _Traj:
     done: int = 0
 
 
-def trajectory_footprint(model: I.ModelParams, M: int, obs_records: int) -> int:
+def trajectory_footprint(model: I.ModelParams, M: int, obs_records: int, packed: bool = False,
+                         precision: int = I.FP64) -> int:
     """Device bytes of one resident trajectory: state, observation series and
     its share of a batch workspace (planned on the host, nothing allocated)."""
     import torch
     B = torch.empty((1,), dtype=torch.complex128)  # placeholder pointer, never dereferenced by planning
-    t = lr.traj_struct(model, M, I.flattop_pulse(0.05, 1.0), 0.0, 1e-3, 1, B, 0, None)
-    h = lr.lr_batch_init([t])
+    t = lr.traj_struct(model, M, I.flattop_pulse(0.05, 1.0), 0.0, 1e-3, 1, B, 0, None, precision)
+    h = lr.lr_batch_init([t], lr.LR_BATCH_PACKED if packed else 0)
     try:
         ws = lr.lr_batch_workspace_bytes(h)
     finally:
@@ -71,10 +72,15 @@ def trajectory_footprint(model: I.ModelParams, M: int, obs_records: int) -> int:
 
 
 class Server:
+    """packed=True runs the FP64 trajectories of every tick in the packed
+    schedule (one workgroup each, LR_BATCH_PACKED); they then count one
+    workgroup each against the workgroup cap instead of d_r."""
+
     def __init__(self, hbm_budget_bytes: int, chunk: int = 2000, max_workgroups: Optional[int] = None,
-                 stream=None):
+                 stream=None, packed: bool = False):
         import torch
         self.torch = torch
+        self.packed = bool(packed)
         self.budget = int(hbm_budget_bytes)
         self.chunk = int(chunk)
         props = torch.cuda.get_device_properties(0)
@@ -92,8 +98,9 @@ class Server:
     # -------------------------------------------------------------- admission
     def _need(self, r: Request):
         nrec = r.nsteps // r.obs_stride + 1
-        fp = 2 * trajectory_footprint(r.model, r.M, nrec)
-        wgs = 2 * r.model.d_r  # one workgroup per resonator layer and trajectory
+        packs = self.packed and r.precision == I.FP64
+        fp = 2 * trajectory_footprint(r.model, r.M, nrec, packs, r.precision)
+        wgs = 2 if packs else 2 * r.model.d_r  # one workgroup per trajectory, or per resonator layer
         return fp, wgs
 
     def submit(self, r: Request):
@@ -142,7 +149,7 @@ class Server:
                                   precision=r.precision, step0=t.done)))
         if not items:
             return
-        b = lr.Batch([it for _, it in items], stream=self.stream)
+        b = lr.Batch([it for _, it in items], stream=self.stream, packed=self.packed)
         b.run()
         rc, codes, steps = b.status()
         for (t, it), c in zip(items, codes):

@@ -493,6 +493,32 @@ def test_serving_result_alone_equals_mix(lr):
     print(f"[serving] alone {st1}, mix {st2}")
 
 
+def test_serving_packed_alone_equals_mix(lr):
+    """Packed serving: request 1 (FP64) alone and in the mix (the FP32 ones run in the spread schedule)
+    gives bitwise the same result, and agrees with the spread server to the FP64 tolerances."""
+    import copy
+    import torch
+    from paper_2508_18114_amd import serve
+    reqs = _serving_reqs()
+    assert reqs[1].precision == I.FP64
+    alone = serve.Server(hbm_budget_bytes=1 << 34, chunk=1000, packed=True)
+    st1 = alone.run([copy.deepcopy(reqs[1])])
+    assert st1["errors"] == 0
+    mixed = [copy.deepcopy(r) for r in reqs]
+    for k, r in enumerate(mixed):
+        r.arrival = 0.0 if k < 2 else 0.01 * k
+    mix = serve.Server(hbm_budget_bytes=1 << 34, chunk=600, packed=True)
+    st2 = mix.run(mixed)
+    assert st2["errors"] == 0 and st2["requests"] == len(reqs)
+    for key in ("B_g", "B_e", "obs_g", "obs_e"):
+        assert torch.equal(alone.results[1][key], mix.results[1][key]), key
+    spread = serve.Server(hbm_budget_bytes=1 << 34, chunk=1000)
+    assert spread.run([copy.deepcopy(reqs[1])])["errors"] == 0
+    for key in ("obs_g", "obs_e"):
+        _assert_obs(mix.results[1][key].cpu().numpy(), spread.results[1][key].cpu().numpy(), f"packed serving {key}")
+    print(f"[serving] packed alone {st1}, packed mix {st2}")
+
+
 def test_serving_admission_by_footprint(lr):
     """With an HBM budget that holds one request at a time, requests are served one after another and all
     complete; a budget below one request's footprint never admits it."""
