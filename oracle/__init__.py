@@ -19,6 +19,8 @@ Modules
               and decay errors, ionisation penalty, loss)
   validity -- spectrum p_1 >= ... >= p_M of the low-rank rho, the control
               quantity p_M / p_1 and the purity (supplement S1.B)
+  adaptive -- adaptive-step integration of the low-rank equation (the
+              Dormand-Prince 5(4) pair with an error-norm step controller)
 
 Every function is written in the notation of the paper, step by step, with
 numpy/scipy library primitives (matmul, Cholesky, triangular solve, erfc) as

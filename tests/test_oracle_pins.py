@@ -11,7 +11,7 @@ import pytest
 import scipy.integrate
 import scipy.linalg
 
-from oracle import dense, loss, lowrank, pulses, validity
+from oracle import adaptive, dense, loss, lowrank, pulses, validity
 from paper_2508_18114_amd import inputs as I
 
 
@@ -453,3 +453,83 @@ def test_loss_closed_forms():
     assert abs(r["eps_decay"] - tau * gam / 2) < 1e-18
     assert abs(r["ionisation"] - 3e-3) < 1e-15
     assert abs(r["loss"] - math.log10(r["eps_sep"] + r["eps_decay"] + 3e-3)) < 1e-14
+
+
+# ------------------------------------------------------------ adaptive Dormand-Prince 5(4) integration
+
+def _dp_order_terms(b):
+    """The 17 rooted-tree conditions up to order 5 for weights b with the tableau A, C."""
+    n = 7
+    Am = np.zeros((n, n))
+    for s in range(n):
+        Am[s, :s] = adaptive.A[s]
+    c = adaptive.C
+    Ac = Am @ c
+    Ac2 = Am @ c ** 2
+    Ac3 = Am @ c ** 3
+    AAc = Am @ Ac
+    return [
+        (b.sum(), 1.0), (b @ c, 1 / 2),
+        (b @ c ** 2, 1 / 3), (b @ Ac, 1 / 6),
+        (b @ c ** 3, 1 / 4), (b @ (c * Ac), 1 / 8), (b @ Ac2, 1 / 12), (b @ AAc, 1 / 24),
+        (b @ c ** 4, 1 / 5), (b @ (c ** 2 * Ac), 1 / 10), (b @ Ac ** 2, 1 / 20), (b @ (c * Ac2), 1 / 15),
+        (b @ Ac3, 1 / 20), (b @ (c * AAc), 1 / 30), (b @ (Am @ (c * Ac)), 1 / 40), (b @ (Am @ Ac2), 1 / 60),
+        (b @ (Am @ AAc), 1 / 120),
+    ]
+
+
+def test_dormand_prince_tableau_order_conditions():
+    """Rows sum to the nodes; the fifth-order weights meet all 17 conditions up to order 5; the
+    fourth-order weights meet the 8 up to order 4 and miss at least one of order 5 (so the error
+    estimate is of order 5); the last row is the fifth-order weights (first same as last)."""
+    for s in range(1, 7):
+        assert abs(sum(adaptive.A[s]) - adaptive.C[s]) <= 1e-15
+    for got, want in _dp_order_terms(adaptive.B5):
+        assert abs(got - want) <= 1e-14, (got, want)
+    t4 = _dp_order_terms(adaptive.B4)
+    for got, want in t4[:8]:
+        assert abs(got - want) <= 1e-14, (got, want)
+    assert max(abs(g - w) for g, w in t4[8:]) > 1e-6
+    assert np.array_equal(np.array(adaptive.A[6] + [0.0]), adaptive.B5)
+
+
+def test_adaptive_scalar_linear_ode_within_tolerance():
+    """y' = lam y with complex lam: the adaptive result at several output times matches exp(lam t) to a
+    small multiple of the tolerance, and a tighter tolerance takes more steps and errs less."""
+    lam = -0.7 + 9.0j
+    fun = lambda t, y: lam * y  # noqa: E731
+    t_out = [0.25, 0.5, 1.0, 2.0]
+    errs, steps = [], []
+    for rtol in (1e-6, 1e-9):
+        ys, acc, rej = adaptive.integrate_ode(fun, 0.0, np.array([1.0 + 0.5j]), t_out, 0.1, rtol, 1e-14)
+        e = max(abs(y[0] - (1.0 + 0.5j) * np.exp(lam * t)) / abs((1.0 + 0.5j) * np.exp(lam * t))
+                for y, t in zip(ys, t_out))
+        assert e <= 200 * rtol, (rtol, e)
+        errs.append(e)
+        steps.append(acc)
+    assert errs[1] < errs[0] and steps[1] > steps[0]
+
+
+def test_adaptive_step_size_follows_the_controller():
+    """On y' = -y from y = 1, the first trial step of 1.0 is rejected at rtol 1e-8 and later steps grow
+    by at most the factor 5; the output time is hit exactly."""
+    fun = lambda t, y: -y  # noqa: E731
+    ys, acc, rej = adaptive.integrate_ode(fun, 0.0, np.array([1.0 + 0j]), [3.0], 1.0, 1e-8, 1e-12)
+    assert rej >= 1 and acc >= 3
+    assert abs(ys[0][0] - math.exp(-3.0)) <= 1e-6
+
+
+def test_adaptive_lowrank_matches_fine_fixed_step_rk4():
+    """The adaptive low-rank integration (drive frame, stepwise pulse) against classic RK4 with a step
+    far below the adaptive error: observables agree to the tolerance scale."""
+    m = I.readout_model(3, 5, 3).replace(kappa_f=0.5, gamma_1=0.05)
+    h = I.ghz(0.15) * np.array([0.5, 1.0 + 0.3j, 0.8])
+    p = I.stepwise_pulse(h, 2.0, sigma=0.1).replace(frame=I.FRAME_DRIVE)
+    B0 = I.initial_state(m, 3, "e", seed=5, scale=1e-2)
+    Ba, oa, acc, rej = adaptive.integrate(m, p, 0.0, 0.05, 40, B0, rtol=1e-10, atol=1e-12, obs_stride=8)
+    Br, orf = lowrank.integrate(m, p, 0.0, 5e-4, 4000, B0, obs_stride=800)
+    assert oa.shape == orf.shape
+    scale = max(1.0, np.max(np.abs(orf[:, 0:4])))
+    assert np.max(np.abs(oa[:, 0:4] - orf[:, 0:4])) <= 1e-7 * scale
+    assert np.max(np.abs(oa[:, 4:] - orf[:, 4:])) <= 1e-7
+    assert acc < 4000  # fewer steps than the fixed-step reference
