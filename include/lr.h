@@ -118,7 +118,8 @@ enum {
   LR_ERR_NONFINITE = -5,    /* non-finite B or Gram (device, via lr_status)       */
   LR_ERR_PULSE = -6,        /* drive amplitude above the bound, or bad kind       */
   LR_ERR_STATE = -7,        /* call order (e.g. no workspace bound)               */
-  LR_ERR_TIMEOUT = -8       /* a bounded device-side wait expired (via lr_status) */
+  LR_ERR_TIMEOUT = -8,      /* a bounded device-side wait expired (via lr_status) */
+  LR_ERR_STEP = -9          /* adaptive step size underflow or step budget spent (via status) */
 };
 
 typedef struct lr_ctx lr_ctx_t;
@@ -259,6 +260,22 @@ int lr_batch_init(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n);
 #define LR_BATCH_PACKED 1
 #define LR_PACKED_MAX_LM 1536
 int lr_batch_init_ex(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n, int32_t flags);
+/* Adaptive-step batch (main text, "Computational performance": the paper's
+ * solver has an adaptive time step): every trajectory takes Dormand-Prince
+ * 5(4) steps of its own size in the packed schedule, with the error norm
+ * sqrt(mean_i |e_i|^2 / (atol + rtol max(|y_i|, |ynew_i|))^2) over the N M
+ * entries of B and the step controller min(5, max(0.2, 0.9 err^(-1/5))).
+ * For an adaptive trajectory, dt is the output grid and the first trial
+ * step: it is integrated from t0 + step0 dt to t0 + (step0 + nsteps) dt and
+ * recorded every obs_stride grid points (steps land on those times).  Every
+ * trajectory must qualify for LR_BATCH_PACKED (LR_FP64, layer size), and
+ * rtol, atol > 0; else LR_ERR_ARG.  A step size below 1e-14 max(1, |t|), or
+ * more than 2^22 attempts within one output interval, stops the trajectory
+ * with LR_ERR_STEP. */
+int lr_batch_init_adaptive(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n, double rtol, double atol);
+/* Accepted and rejected step counts of an adaptive batch after lr_batch_run
+ * (arrays of n, caller order; synchronises).  LR_ERR_STATE for other batches. */
+int lr_batch_adaptive_stats(lr_batch_t* batch, int64_t* accepted, int64_t* rejected);
 size_t lr_batch_workspace_bytes(const lr_batch_t* batch);
 int lr_batch_bind(lr_batch_t* batch, void* d_workspace, size_t bytes, void* stream);
 /* Enqueue the integration of every trajectory of the batch on the bound

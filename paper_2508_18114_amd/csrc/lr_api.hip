@@ -16,6 +16,7 @@
 #include "lr_dense.hip"
 #include "lr_spectrum.hip"
 #include "lr_packed.hip"
+#include "lr_adaptive.hip"
 
 using lrk::TrajDev;
 
@@ -178,6 +179,7 @@ const char* lr_strerror(int code) {
     case LR_ERR_PULSE: return "invalid pulse (unknown kind or amplitude above 2*pi*0.4 rad/ns)";
     case LR_ERR_STATE: return "invalid call order (no workspace bound)";
     case LR_ERR_TIMEOUT: return "device-side wait expired";
+    case LR_ERR_STEP: return "adaptive step size underflow or step budget spent";
     default: return "unknown error";
   }
 }

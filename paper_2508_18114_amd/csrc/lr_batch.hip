@@ -25,6 +25,10 @@ struct lr_batch {
   std::vector<size_t> lds, region, region_bytes;
   std::vector<int> wg_offset;  // first tilemap entry of each trajectory
   std::vector<char> packed;    // trajectory runs in the packed kernel
+  bool adaptive = false;       // packed trajectories take adaptive Dormand-Prince steps
+  double rtol = 0.0, atol = 0.0;
+  size_t off_ad = 0;           // AdaptDev descriptors (adaptive batches)
+  std::vector<lrk::AdaptDev> ad;
   size_t off_trajs = 0, off_tilemap = 0, total = 0;
   int total_wg = 0;
   char* ws = nullptr;
@@ -90,6 +94,9 @@ const void* persist_fn(int rows, int ge, int prec, bool prologue = false) {
   return lrk::persist_kernel(rows, ge, prologue, prec);
 }
 
+int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flags, bool adaptive, double rtol,
+               double atol);
+
 }  // namespace
 
 extern "C" {
@@ -99,12 +106,42 @@ int lr_batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n) {
 }
 
 int lr_batch_init_ex(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flags) {
+  return batch_init(out, trajs, n, flags, false, 0.0, 0.0);
+}
+
+int lr_batch_init_adaptive(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, double rtol, double atol) {
+  if (!(rtol > 0.0) || !(atol > 0.0) || !std::isfinite(rtol) || !std::isfinite(atol)) return LR_ERR_ARG;
+  return batch_init(out, trajs, n, LR_BATCH_PACKED, true, rtol, atol);
+}
+
+int lr_batch_adaptive_stats(lr_batch_t* b, int64_t* accepted, int64_t* rejected) {
+  if (!b) return LR_ERR_ARG;
+  if (!b->adaptive) return LR_ERR_STATE;
+  if (!b->ws) return LR_ERR_STATE;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return LR_ERR_HIP;
+  for (int i = 0; i < b->n; ++i) {
+    int64_t c[2] = {0, 0};
+    if (hipMemcpy(c, b->ad[b->pos[i]].cnt, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess) return LR_ERR_HIP;
+    if (accepted) accepted[i] = c[0];
+    if (rejected) rejected[i] = c[1];
+  }
+  return LR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flags, bool adaptive, double rtol,
+               double atol) {
   if (!out || !trajs || n < 1) return LR_ERR_ARG;
   if (flags & ~LR_BATCH_PACKED) return LR_ERR_ARG;
   *out = nullptr;
   lr_batch* b = new (std::nothrow) lr_batch();
   if (!b) return LR_ERR_OOM;
   b->n = n;
+  b->adaptive = adaptive;
+  b->rtol = rtol;
+  b->atol = atol;
   auto packs = [&](const lr_traj_t& x) {
     const long long LM = (long long)x.model.d_q * x.model.d_f * x.M;
     if (!((flags & LR_BATCH_PACKED) && x.precision == LR_FP64 && x.M >= 1 && x.M <= lrk::kMaxM && LM >= 1 &&
@@ -143,10 +180,18 @@ int lr_batch_init_ex(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_
   b->region.resize(n);
   b->region_bytes.resize(n);
   b->wg_offset.resize(n);
+  if (adaptive)  // every trajectory must take the packed kernel
+    for (int k = 0; k < n; ++k)
+      if (!b->packed[k]) {
+        delete b;
+        return LR_ERR_ARG;
+      }
   const size_t a = 256;
   size_t o = 0;
   b->off_trajs = o;
   o = align_up(o + sizeof(TrajDev) * (size_t)n, a);
+  b->off_ad = o;
+  if (adaptive) o = align_up(o + sizeof(lrk::AdaptDev) * (size_t)n, a);
   int wg = 0;
   for (int t = 0; t < n; ++t) {
     const lr_traj_t& x = b->tr[t];
@@ -184,6 +229,10 @@ int lr_batch_init_ex(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_
     if (b->packed[t]) {
       for (int k = 0; k < 4; ++k) r = align_up(r + nm, a);  // Bb, S0, S1, acc
       r = align_up(r + 2 * (size_t)x.M * x.M * sizeof(double2), a);  // W
+      if (adaptive) {
+        r = align_up(r + 7 * nm, a);                       // k_1 .. k_7
+        r = align_up(r + 64, a);                           // t, h, counters
+      }
       r = align_up(r + 64, a);                             // step, fail_step, fro2, status, abort
       b->region[t] = o;
       b->region_bytes[t] = r;
@@ -205,6 +254,9 @@ int lr_batch_init_ex(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_
   *out = b;
   return LR_OK;
 }
+}  // namespace
+
+extern "C" {
 
 size_t lr_batch_workspace_bytes(const lr_batch_t* b) { return b ? b->total : 0; }
 
@@ -214,6 +266,7 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
   if (bytes < b->total) return LR_ERR_OOM;
   b->ws = static_cast<char*>(d_ws);
   b->stream = static_cast<hipStream_t>(stream);
+  b->ad.assign(b->adaptive ? b->n : 0, lrk::AdaptDev{});
   const size_t a = 256;
   std::vector<int2> tmap((size_t)b->total_wg);
   for (int t = 0; t < b->n; ++t) {
@@ -242,6 +295,15 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
       v.S1 = reinterpret_cast<double2*>(base + r);      r = align_up(r + nm, a);
       v.acc = reinterpret_cast<double2*>(base + r);     r = align_up(r + nm, a);
       v.W = reinterpret_cast<double2*>(base + r);       r = align_up(r + 2 * (size_t)x.M * x.M * sizeof(double2), a);
+      if (b->adaptive) {
+        lrk::AdaptDev& d = b->ad[t];
+        d.rtol = b->rtol;
+        d.atol = b->atol;
+        d.K = reinterpret_cast<double2*>(base + r);     r = align_up(r + 7 * nm, a);
+        d.st = reinterpret_cast<double*>(base + r);
+        d.cnt = reinterpret_cast<int64_t*>(base + r + 16);
+        r = align_up(r + 64, a);
+      }
       if (r + 64 > b->region_bytes[t]) return LR_ERR_STATE;  // layout of lr_batch_init_ex
       v.step = reinterpret_cast<int64_t*>(base + r);
       v.fail_step = reinterpret_cast<int64_t*>(base + r + 8);
@@ -277,8 +339,12 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
                                  hipMemcpyHostToDevice, b->stream);
   hipError_t e2 = hipMemcpyAsync(b->ws + b->off_tilemap, tmap.data(), sizeof(int2) * tmap.size(),
                                  hipMemcpyHostToDevice, b->stream);
+  hipError_t e4 = hipSuccess;
+  if (b->adaptive)
+    e4 = hipMemcpyAsync(b->ws + b->off_ad, b->ad.data(), sizeof(lrk::AdaptDev) * b->ad.size(), hipMemcpyHostToDevice,
+                        b->stream);
   hipError_t e3 = hipStreamSynchronize(b->stream);
-  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return LR_ERR_HIP;
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) return LR_ERR_HIP;
 
   // execution groups of co-resident workgroups
   int dev_id = 0, ncu = 0;
@@ -291,9 +357,11 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
   }
   for (int kp : lrk::kPackedKP)
     for (int pro = 0; pro < 2; ++pro)
-      if (max_lds_packed > 0 && hipFuncSetAttribute(lrk::packed_kernel(kp, pro != 0),
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                    (int)max_lds_packed) != hipSuccess)
+      if (max_lds_packed > 0 &&
+          (hipFuncSetAttribute(lrk::packed_kernel(kp, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)max_lds_packed) != hipSuccess ||
+           hipFuncSetAttribute(lrk::dp5_kernel(kp, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)max_lds_packed) != hipSuccess))
         return LR_ERR_HIP;
   for (int prec = 0; prec <= 2; ++prec)
     for (int rows = 2; rows <= 3; ++rows)
@@ -359,6 +427,9 @@ int lr_batch_run(lr_batch_t* b) {
   const int2* tmap = reinterpret_cast<const int2*>(b->ws + b->off_tilemap);
   hipLaunchKernelGGL(lrk::k_reset, dim3((b->n + 63) / 64), dim3(64), 0, b->stream, trajs, b->n);
   hipLaunchKernelGGL(lrk::k_reset_persist, dim3(b->n), dim3(256), 0, b->stream, trajs, b->n);
+  const lrk::AdaptDev* ads = reinterpret_cast<const lrk::AdaptDev*>(b->ws + b->off_ad);
+  if (b->adaptive)
+    hipLaunchKernelGGL(lrk::k_dp5_reset, dim3((b->n + 63) / 64), dim3(64), 0, b->stream, trajs, ads, b->n);
   for (int t = 0; t < b->n; ++t) {
     const TrajDev& v = b->dev[t];
     long long e = (long long)v.N * v.M;
@@ -385,9 +456,16 @@ int lr_batch_run(lr_batch_t* b) {
       hipError_t err;
       if (g.packed) {
         const TrajDev* ptr = trajs + g.begin;
-        void* pargs[] = {(void*)&ptr, (void*)&step0, (void*)&nchunk};
-        err = hipLaunchKernel(lrk::packed_kernel(g.kp, prologue != 0), dim3(g.wgs), dim3(lrk::kTW), pargs,
-                              g.lds, b->stream);
+        if (b->adaptive) {
+          const lrk::AdaptDev* aptr = ads + g.begin;
+          void* pargs[] = {(void*)&ptr, (void*)&aptr, (void*)&step0, (void*)&nchunk};
+          err = hipLaunchKernel(lrk::dp5_kernel(g.kp, prologue != 0), dim3(g.wgs), dim3(lrk::kTW), pargs, g.lds,
+                                b->stream);
+        } else {
+          void* pargs[] = {(void*)&ptr, (void*)&step0, (void*)&nchunk};
+          err = hipLaunchKernel(lrk::packed_kernel(g.kp, prologue != 0), dim3(g.wgs), dim3(lrk::kTW), pargs,
+                                g.lds, b->stream);
+        }
       } else {
         err = hipLaunchCooperativeKernel(persist_fn(g.rows, g.ge, g.prec, prologue != 0), dim3(g.wgs),
                                          dim3(lrk::kPW), args, (unsigned)g.lds, b->stream);

@@ -83,6 +83,109 @@ __device__ __forceinline__ void gram_rows(double2 (&acc)[KP], const double2* Ot,
   }
 }
 
+// Mapping of a packed workgroup's threads onto [G | C_1 | C_2] (M x 3M): thread
+// t owns column pc = t mod 3M of [O | L_1 O | L_2 O] (pkind 0, 1, 2 = G, filter,
+// transmon; pcc its column within) and rows pi0 .. pi0 + KPe - 1.
+struct PackedMap {
+  int M, C3, L, d_f, KPe, pc, pi0, pkind, pcc;
+  bool pact;
+};
+
+// Gram terms of the layer tile Ot, added to the thread's entries (the block
+// size KPe is uniform: one branch picks the unrolled loop).
+template <int KP>
+__device__ __forceinline__ void packed_terms(double2 (&acc)[KP], const PackedMap& P, const double2* Ot,
+                                             const double* coef) {
+  if (!P.pact) return;
+  const int L = P.L, M = P.M, KPe = P.KPe, pcc = P.pcc, pi0 = P.pi0;
+  const int shift = P.pkind == 0 ? 0 : (P.pkind == 1 ? 1 : P.d_f);
+  const double* cr = coef + P.pkind * L;
+  if (KPe <= 2 || KP == 2) {
+    gram_rows<2>(acc, Ot, cr, L, M, shift, pcc, pi0);
+  } else if (KPe <= 3 || KP == 3) {
+    if constexpr (KP >= 3) gram_rows<3>(acc, Ot, cr, L, M, shift, pcc, pi0);
+  } else if (KPe <= 5 || KP == 5) {
+    if constexpr (KP >= 5) gram_rows<5>(acc, Ot, cr, L, M, shift, pcc, pi0);
+  } else if (KPe <= 8 || KP == 8) {
+    if constexpr (KP >= 8) gram_rows<8>(acc, Ot, cr, L, M, shift, pcc, pi0);
+  } else if (KPe <= 12 || KP == 12) {
+    if constexpr (KP >= 12) gram_rows<12>(acc, Ot, cr, L, M, shift, pcc, pi0);
+  } else {
+    if constexpr (KP >= 16) gram_rows<16>(acc, Ot, cr, L, M, shift, pcc, pi0);
+  }
+}
+
+// [G | C_1 | C_2] (the threads' entries) -> W_1, W_2 in Wl, through the M x 3M
+// elimination in Aug; returns 0, or -4 (pivot <= 0) / -5 (non-finite).
+template <int KP>
+__device__ __forceinline__ int packed_solve(double2 (&acc)[KP], const PackedMap& P, double2* Aug, double2* Wl,
+                                            double2* s_prow, double* s_red, int* s_flag, bool want_fro2,
+                                            double* fro2) {
+  const int tid = threadIdx.x, M = P.M, MM = M * M, C3 = P.C3, KPe = P.KPe, pi0 = P.pi0, pc = P.pc;
+  const bool pact = P.pact;
+  const int pkind = P.pkind;
+  __syncthreads();  // the tiles are free
+  int bad = 0;
+  double f2 = 0.0;
+  if (pact) {
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int i = pi0 + k;
+      if (k < KPe && i < M) {
+        Aug[i * C3 + pc] = acc[k];
+        if (!isfinite(acc[k].x) || !isfinite(acc[k].y)) bad = 1;
+        if (pkind == 0) f2 += acc[k].x * acc[k].x + acc[k].y * acc[k].y;
+      }
+    }
+  }
+  if (tid == 0) *s_flag = 0;
+  __syncthreads();
+  if (bad) *s_flag = 1;
+  if (want_fro2) {
+    for (int off = 32; off > 0; off >>= 1) f2 += __shfl_xor(f2, off);
+    if ((tid & 63) == 0) s_red[tid >> 6] = f2;
+  }
+  __syncthreads();
+  if (want_fro2) {
+    double tot = 0.0;
+    for (int w = 0; w < kTW / 64; ++w) tot += s_red[w];
+    *fro2 = tot;
+  }
+  if (*s_flag) return -5;
+  // pivot p: the scaled pivot row goes to s_prow, then every entry right of
+  // the pivot column takes x - Aug[i][p] prow[c] (the pivot row: prow[c]);
+  // the pivot column is only read
+  const int tot = M * C3;
+  for (int p = 0; p < M; ++p) {
+    const double piv = Aug[p * C3 + p].x;
+    if (!(piv > 0.0)) return -4;
+    const double rp = pivot_rcp(piv);
+    for (int c = p + 1 + tid; c < C3; c += kTW) s_prow[c] = cscale(rp, Aug[p * C3 + c]);
+    __syncthreads();
+    for (int e = tid; e < tot; e += kTW) {
+      const int i = e / C3, c = e - i * C3;
+      if (c > p) {
+        const double2 pr = s_prow[c];
+        if (i == p) {
+          Aug[e] = pr;
+        } else {
+          const double2 l = Aug[i * C3 + p];
+          Aug[e] = cadd(Aug[e], cmul(make_double2(-l.x, -l.y), pr));
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // W_k[i][j] = conj(X_k[j][i]), X_k = columns M (k + 1) .. of the eliminated matrix
+  for (int e = tid; e < 2 * MM; e += kTW) {
+    const int k = e / MM, o = e - k * MM, i = o / M, j = o - i * M;
+    const double2 x = Aug[j * C3 + M * (k + 1) + i];
+    Wl[e] = make_double2(x.x, -x.y);
+  }
+  __syncthreads();
+  return 0;
+}
+
 // Element (rl, j) of layer r: z = H_eff Y (stencil and drive) from the layers
 // r - 1, r, r + 1 of the stage input in LDS (Yp, Yc, Yn).  sq[k] = sqrt(k);
 // hd[rl] = diagonal of H_eff at row rl without w_r r.
@@ -193,89 +296,10 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
     __syncthreads();
   };
 
-  // Gram terms of the layer tile Ot, added to the thread's entries
-  // (the block size KPe is uniform: one branch picks the unrolled loop)
-  auto add_terms = [&](double2 (&acc)[KP]) {
-    if (!pact) return;
-    const int shift = pkind == 0 ? 0 : (pkind == 1 ? 1 : d_f);
-    const double* cr = coef + pkind * L;
-    if (KPe <= 2 || KP == 2) {
-      gram_rows<2>(acc, Ot, cr, L, M, shift, pcc, pi0);
-    } else if (KPe <= 3 || KP == 3) {
-      if constexpr (KP >= 3) gram_rows<3>(acc, Ot, cr, L, M, shift, pcc, pi0);
-    } else if (KPe <= 5 || KP == 5) {
-      if constexpr (KP >= 5) gram_rows<5>(acc, Ot, cr, L, M, shift, pcc, pi0);
-    } else if (KPe <= 8 || KP == 8) {
-      if constexpr (KP >= 8) gram_rows<8>(acc, Ot, cr, L, M, shift, pcc, pi0);
-    } else if (KPe <= 12 || KP == 12) {
-      if constexpr (KP >= 12) gram_rows<12>(acc, Ot, cr, L, M, shift, pcc, pi0);
-    } else {
-      if constexpr (KP >= 16) gram_rows<16>(acc, Ot, cr, L, M, shift, pcc, pi0);
-    }
-  };
-
-  // [G | C_1 | C_2] -> W_1, W_2 in Wl; returns 0, or -4 (pivot <= 0) / -5 (non-finite)
+  const PackedMap PM{M, C3, L, d_f, KPe, pc, pi0, pkind, pcc, pact};
+  auto add_terms = [&](double2 (&acc)[KP]) { packed_terms<KP>(acc, PM, Ot, coef); };
   auto solve = [&](double2 (&acc)[KP], bool want_fro2, double* fro2) -> int {
-    __syncthreads();  // the tiles are free
-    int bad = 0;
-    double f2 = 0.0;
-    if (pact) {
-#pragma unroll
-      for (int k = 0; k < KP; ++k) {
-        const int i = pi0 + k;
-        if (k < KPe && i < M) {
-          Aug[i * C3 + pc] = acc[k];
-          if (!isfinite(acc[k].x) || !isfinite(acc[k].y)) bad = 1;
-          if (pkind == 0) f2 += acc[k].x * acc[k].x + acc[k].y * acc[k].y;
-        }
-      }
-    }
-    if (tid == 0) s_flag = 0;
-    __syncthreads();
-    if (bad) s_flag = 1;
-    if (want_fro2) {
-      for (int off = 32; off > 0; off >>= 1) f2 += __shfl_xor(f2, off);
-      if ((tid & 63) == 0) s_red[tid >> 6] = f2;
-    }
-    __syncthreads();
-    if (want_fro2) {
-      double tot = 0.0;
-      for (int w = 0; w < kTW / 64; ++w) tot += s_red[w];
-      *fro2 = tot;
-    }
-    if (s_flag) return -5;
-    // pivot p: the scaled pivot row goes to s_prow, then every entry right of
-    // the pivot column takes x - Aug[i][p] prow[c] (the pivot row: prow[c]);
-    // the pivot column is only read
-    const int tot = M * C3;
-    for (int p = 0; p < M; ++p) {
-      const double piv = Aug[p * C3 + p].x;
-      if (!(piv > 0.0)) return -4;
-      const double rp = pivot_rcp(piv);
-      for (int c = p + 1 + tid; c < C3; c += kTW) s_prow[c] = cscale(rp, Aug[p * C3 + c]);
-      __syncthreads();
-      for (int e = tid; e < tot; e += kTW) {
-        const int i = e / C3, c = e - i * C3;
-        if (c > p) {
-          const double2 pr = s_prow[c];
-          if (i == p) {
-            Aug[e] = pr;
-          } else {
-            const double2 l = Aug[i * C3 + p];
-            Aug[e] = cadd(Aug[e], cmul(make_double2(-l.x, -l.y), pr));
-          }
-        }
-      }
-      __syncthreads();
-    }
-    // W_k[i][j] = conj(X_k[j][i]), X_k = columns M (k + 1) .. of the eliminated matrix
-    for (int e = tid; e < 2 * MM; e += kTW) {
-      const int k = e / MM, o = e - k * MM, i = o / M, j = o - i * M;
-      const double2 x = Aug[j * C3 + M * (k + 1) + i];
-      Wl[e] = make_double2(x.x, -x.y);
-    }
-    __syncthreads();
-    return 0;
+    return packed_solve<KP>(acc, PM, Aug, Wl, s_prow, s_red, &s_flag, want_fro2, fro2);
   };
 
   double2 acc[KP];

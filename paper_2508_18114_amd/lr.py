@@ -29,6 +29,7 @@ LR_ERR_NONFINITE = -5
 LR_ERR_PULSE = -6
 LR_ERR_STATE = -7
 LR_ERR_TIMEOUT = -8
+LR_ERR_STEP = -9
 LR_MAX_M = 32
 LR_BATCH_PACKED = 1       # lr_batch_init_ex flag: one workgroup per FP64 trajectory
 LR_PACKED_MAX_LM = 1536
@@ -37,7 +38,8 @@ LR_PACKED_MAX_LM = 1536
 EXPORTS = ("lr_init", "lr_workspace_bytes", "lr_bind", "lr_rhs", "lr_integrate",
            "lr_observables", "lr_spectrum", "lr_status", "lr_profile_enable", "lr_profile_read",
            "lr_readout_loss", "lr_dense_workspace_bytes", "lr_dense_integrate", "lr_strerror", "lr_destroy",
-           "lr_batch_init", "lr_batch_init_ex", "lr_batch_workspace_bytes", "lr_batch_bind", "lr_batch_run",
+           "lr_batch_init", "lr_batch_init_ex", "lr_batch_init_adaptive", "lr_batch_adaptive_stats",
+           "lr_batch_workspace_bytes", "lr_batch_bind", "lr_batch_run",
            "lr_batch_status", "lr_batch_profile_enable", "lr_batch_profile_read", "lr_batch_destroy")
 
 
@@ -97,6 +99,8 @@ def _load():
                                               vp, i32, vp, vp, sz, vp]),
         "lr_batch_init": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lr_traj_t), i32]),
         "lr_batch_init_ex": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lr_traj_t), i32, i32]),
+        "lr_batch_init_adaptive": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lr_traj_t), i32, dbl, dbl]),
+        "lr_batch_adaptive_stats": (ctypes.c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "lr_batch_workspace_bytes": (sz, [vp]),
         "lr_batch_bind": (ctypes.c_int, [vp, vp, sz, vp]),
         "lr_batch_run": (ctypes.c_int, [vp]),
@@ -194,11 +198,14 @@ def lr_destroy(ctx: int) -> None:
     _lib.lr_destroy(ctx)
 
 
-def lr_batch_init(trajs, flags: int = 0) -> int:
-    """trajs: sequence of lr_traj_t; flags: 0 or LR_BATCH_PACKED (lr_batch_init_ex)."""
+def lr_batch_init(trajs, flags: int = 0, adaptive=None) -> int:
+    """trajs: sequence of lr_traj_t; flags: 0 or LR_BATCH_PACKED (lr_batch_init_ex);
+    adaptive: (rtol, atol) for lr_batch_init_adaptive."""
     arr = (lr_traj_t * len(trajs))(*trajs)
     h = ctypes.c_void_p()
-    if flags:
+    if adaptive is not None:
+        rc = _lib.lr_batch_init_adaptive(ctypes.byref(h), arr, len(trajs), float(adaptive[0]), float(adaptive[1]))
+    elif flags:
         rc = _lib.lr_batch_init_ex(ctypes.byref(h), arr, len(trajs), flags)
     else:
         rc = _lib.lr_batch_init(ctypes.byref(h), arr, len(trajs))
@@ -377,17 +384,18 @@ class Batch:
     tensor), precision (FP64 / FP32 / BF16X3), step0 (index of the first step
     when a trajectory is continued).  The tensors must stay alive while the
     batch is used.  packed=True: the packed schedule (LR_BATCH_PACKED), one
-    workgroup per FP64 trajectory.
+    workgroup per FP64 trajectory.  adaptive=(rtol, atol): adaptive
+    Dormand-Prince steps (lr_batch_init_adaptive); dt is then the output grid.
     """
 
-    def __init__(self, items, stream=None, packed=False):
+    def __init__(self, items, stream=None, packed=False, adaptive=None):
         import torch
         self.items = list(items)
         ts = [traj_struct(it["model"], it["M"], it["pulse"], it.get("t0", 0.0), it["dt"], it["nsteps"],
                           it["B"], it.get("obs_stride", 0), it.get("obs"), it.get("precision", _inp.FP64),
                           it.get("step0", 0))
               for it in self.items]
-        self.handle = lr_batch_init(ts, LR_BATCH_PACKED if packed else 0)
+        self.handle = lr_batch_init(ts, LR_BATCH_PACKED if packed else 0, adaptive)
         nbytes = lr_batch_workspace_bytes(self.handle)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         base = self.workspace.data_ptr()
@@ -404,6 +412,16 @@ class Batch:
 
     def status(self):
         return lr_batch_status(self.handle, len(self.items))
+
+    def adaptive_stats(self):
+        """(accepted, rejected) step counts per trajectory of an adaptive batch."""
+        n = len(self.items)
+        acc = (ctypes.c_int64 * n)()
+        rej = (ctypes.c_int64 * n)()
+        rc = _lib.lr_batch_adaptive_stats(self.handle, acc, rej)
+        if rc != LR_OK:
+            raise LrError(rc, "lr_batch_adaptive_stats")
+        return list(acc), list(rej)
 
     def profile(self, on=True):
         rc = lr_batch_profile_enable(self.handle, on)

@@ -873,3 +873,96 @@ def test_packed_device_errors(lr):
     alone = [dict(model=m, M=3, pulse=p, dt=1e-3, nsteps=5, B=lr.to_device(B2))]
     assert _run_packed(lr, alone)[0] == lr.LR_OK
     assert np.array_equal(lr.from_device(alone[0]["B"]), lr.from_device(items[2]["B"]))
+
+
+# ------------------------------------------------------------ adaptive Dormand-Prince steps (packed schedule)
+
+def _adaptive_case(lr, frame, seed=5):
+    import torch
+    m = I.readout_model(3, 5, 3).replace(kappa_f=0.5, gamma_1=0.05)
+    h = I.ghz(0.15) * np.array([0.5, 1.0 + 0.3j, 0.8])
+    p = I.stepwise_pulse(h, 2.0, sigma=0.1).replace(frame=frame)
+    B0 = I.initial_state(m, 3, "e", seed=seed, scale=1e-2)
+    it = dict(model=m, M=3, pulse=p, dt=0.05, nsteps=40, B0=B0, B=lr.to_device(B0), obs_stride=8,
+              obs=torch.zeros((6, 6 + 3), dtype=torch.float64, device="cuda"))
+    return it
+
+
+def test_adaptive_matches_oracle(lr):
+    """Dormand-Prince 5(4) with per-trajectory steps, drive and lab frame, against the oracle's adaptive
+    integration at the same tolerances: observables to the tolerance scale, step counts nearly equal."""
+    from oracle import adaptive
+    rtol, atol = 1e-9, 1e-12
+    for frame in (I.FRAME_DRIVE, I.FRAME_LAB):
+        it = _adaptive_case(lr, frame)
+        b = lr.Batch([it], adaptive=(rtol, atol))
+        b.run()
+        rc, codes, _ = b.status()
+        assert rc == lr.LR_OK, codes
+        acc, rej = b.adaptive_stats()
+        Bo, ref, acc_o, rej_o = adaptive.integrate(it["model"], it["pulse"], 0.0, 0.05, 40, it["B0"], rtol, atol,
+                                                   obs_stride=8)
+        got = it["obs"].cpu().numpy()
+        scale = max(1.0, np.max(np.abs(ref[:, 0:4])))
+        ef = np.max(np.abs(got[:, 0:4] - ref[:, 0:4])) / scale
+        ep = np.max(np.abs(got[:, 4:] - ref[:, 4:]))
+        print(f"[parity] adaptive frame={frame}: steps gpu {acc[0]}+{rej[0]} rejected, oracle {acc_o}+{rej_o}; "
+              f"field err {ef:.3e}, populations err {ep:.3e}")
+        assert ef <= 1e-7 and ep <= 1e-7
+        assert abs(acc[0] - acc_o) <= 3 and abs(rej[0] - rej_o) <= 3
+        b.close()
+
+
+def test_adaptive_result_does_not_depend_on_the_batch(lr):
+    alone = [_adaptive_case(lr, I.FRAME_DRIVE)]
+    b = lr.Batch(alone, adaptive=(1e-8, 1e-11))
+    b.run()
+    assert b.status()[0] == lr.LR_OK
+    mix = [_adaptive_case(lr, I.FRAME_LAB, seed=6), _adaptive_case(lr, I.FRAME_DRIVE), _adaptive_case(lr, I.FRAME_DRIVE, 7)]
+    bm = lr.Batch(mix, adaptive=(1e-8, 1e-11))
+    bm.run()
+    assert bm.status()[0] == lr.LR_OK
+    assert np.array_equal(lr.from_device(alone[0]["B"]), lr.from_device(mix[1]["B"]))
+    assert np.array_equal(alone[0]["obs"].cpu().numpy(), mix[1]["obs"].cpu().numpy())
+    assert b.adaptive_stats()[0][0] == bm.adaptive_stats()[0][1]
+
+
+def test_adaptive_paper_size_drive_frame(lr):
+    """Paper size (N = 2000, M = 20), 2 ns of g and e in the drive frame, adaptive at rtol 1e-8, against
+    fixed-step RK4 at dt = 2.5e-4 ns in the drive frame (spread schedule): records agree to 1e-6."""
+    import torch
+    trajs = I.config_paper_size()
+    out = {}
+    for mode in ("fixed", "adaptive"):
+        dt = 2.5e-4 if mode == "fixed" else 0.1
+        n = int(round(2.0 / dt))
+        stride = int(round(0.5 / dt))
+        items = [dict(model=t.model, M=t.M, pulse=t.pulse.replace(frame=I.FRAME_DRIVE), dt=dt, nsteps=n,
+                      B=lr.to_device(t.B0()), obs_stride=stride,
+                      obs=torch.zeros((n // stride + 1, 6 + t.model.d_q), dtype=torch.float64, device="cuda"))
+                 for t in trajs]
+        b = lr.Batch(items, adaptive=(1e-8, 1e-10) if mode == "adaptive" else None)
+        b.run()
+        rc, codes, _ = b.status()
+        assert rc == lr.LR_OK, codes
+        out[mode] = [it["obs"].cpu().numpy() for it in items]
+        if mode == "adaptive":
+            acc, rej = b.adaptive_stats()
+            print(f"[adaptive] paper size 2 ns drive frame: accepted {acc}, rejected {rej} (fixed: 8000 steps)")
+    for a, f in zip(out["adaptive"], out["fixed"]):
+        scale = max(1.0, np.max(np.abs(f[:, 0:4])))
+        assert np.max(np.abs(a[:, 0:4] - f[:, 0:4])) <= 1e-6 * scale
+        assert np.max(np.abs(a[:, 4:] - f[:, 4:])) <= 1e-6
+
+
+def test_adaptive_rejections(lr):
+    it = _adaptive_case(lr, I.FRAME_DRIVE)
+    for tol in ((0.0, 1e-12), (1e-8, -1.0), (float("nan"), 1e-12)):
+        with pytest.raises(lr.LrError):
+            lr.Batch([it], adaptive=tol)
+    fp32 = dict(it, precision=1)
+    with pytest.raises(lr.LrError):
+        lr.Batch([fp32], adaptive=(1e-8, 1e-12))
+    b = lr.Batch([_adaptive_case(lr, I.FRAME_DRIVE)], packed=True)
+    with pytest.raises(lr.LrError):
+        b.adaptive_stats()
