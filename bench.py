@@ -318,6 +318,32 @@ def drive_frame_study(lr, I, torch):
     out["largest_dt_ns_at_1e-6"] = best
     if "lab" in best and "drive" in best:
         out["physical_time_speedup_drive_vs_lab"] = best["drive"] / best["lab"]
+    # adaptive Dormand-Prince 5(4) steps in the drive frame over the first 2 ns (one packed
+    # workgroup), against the same reference records
+    ad = {}
+    for rtol in (1e-6, 1e-8):
+        nrec = 4
+        obs = torch.zeros((nrec + 1, 6 + m.d_q), dtype=torch.float64, device="cuda")
+        it = dict(model=m, M=M, pulse=rot, dt=0.5, nsteps=nrec, B=lr.to_device(B0), obs_stride=1, obs=obs)
+        b = lr.Batch([it], adaptive=(rtol, 1e-2 * rtol))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run()
+        rc = b.status()[0]
+        el = time.perf_counter() - t0
+        acc, rej = b.adaptive_stats()
+        o = obs.cpu().numpy()
+        f = o[:, 2] + 1j * o[:, 3]
+        ok = rc == lr.LR_OK
+        ad[f"rtol{rtol:g}"] = {
+            "status": lr.lr_strerror(rc), "accepted": acc[0], "rejected": rej[0],
+            "rhs_evaluations": 6 * (acc[0] + rej[0]) + 1,
+            "field_err_rel": float(np.max(np.abs(f - fref[:nrec + 1])) / scale) if ok else None,
+            "population_err": float(np.max(np.abs(o[:, 6:] - pref[:nrec + 1]))) if ok else None,
+            "wall_s": el,
+            "fixed_rk4_rhs_evaluations_same_span": {k: 4 * int(round(2.0 / v)) for k, v in best.items()}}
+        b.close()
+    out["adaptive_drive_frame_2ns"] = ad
     return out
 
 
