@@ -39,7 +39,33 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the batched / single / dense comparisons")
     ap.add_argument("--cpu-steps", type=int, default=2000, help="oracle steps per trajectory in the CPU sample")
+    ap.add_argument("--packed-sample", type=int, default=0, metavar="STEPS",
+                    help="only run the packed schedule on 512 trajectories (N=2000, M=20) for STEPS steps "
+                         "(a workload for kernel profiles) and print its rate")
     return ap.parse_args()
+
+
+def packed_sample(lr, I, torch, steps):
+    """512 trajectories (256 piecewise pulses x g/e, N=2000, M=20) in the packed schedule, kernel time
+    from HIP events on the batch stream."""
+    tl = I.batch_uniform(256)
+    items = [dict(model=t.model, M=t.M, pulse=t.pulse, dt=t.dt, nsteps=steps, B=lr.to_device(t.B0())) for t in tl]
+    b = lr.Batch(items, packed=True)
+    b.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    if b.status()[0] != lr.LR_OK:
+        raise RuntimeError("packed sample failed")
+    ms, launches = b.profile_read()
+    m, M = tl[0].model, tl[0].M
+    fl = 4 * m.N * M * (58 + 40 * M) * steps * len(items)
+    print(json.dumps({"workload": f"packed schedule, {len(items)} trajectories, N={m.N}, M={M}, {steps} steps",
+                      "value": len(items) * steps / el, "unit": "RK steps*trajectories/s",
+                      "kernel": "k_packed", "kernel_ms": ms, "launches": launches,
+                      "achieved_tflops": fl / (ms * 1e-3) / 1e12, "peak": 78.6}), flush=True)
 
 
 def _oracle_worker(args):
@@ -114,8 +140,13 @@ def comparisons(lr, I, torch, stream, plain_value):
     n512 = I.batch_uniform(256)
     v_s, el_s = run_batch(n512, 40)
     v_p, el_p = run_batch(n512, 200, packed=True)
+    # algorithmic FP64 flops per RK step and trajectory (same count as the main line's roofline)
+    fl = 4 * m.N * M * (58 + 40 * M)
     out["batched_512_same_shape"] = {
         "spread": v_s, "packed": v_p, "packed_vs_spread": v_p / v_s, "packed_vs_plain_g_e": v_p / plain_value,
+        "packed_roofline": {"bound": "alu", "achieved": v_p * fl / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                            "frac": v_p * fl / 1e12 / 78.6,
+                            "note": "whole-batch wall time (launch overhead and the prologue included)"},
         "unit": "RK steps*trajectories/s",
         "workload": f"512 trajectories (256 piecewise pulses x g/e), N=2000, M=20; spread: first 40 steps "
                     f"({el_s:.2f} s), packed: first 200 steps ({el_p:.2f} s)"}
@@ -380,6 +411,9 @@ def main():
     from paper_2508_18114_amd import lr
 
     torch.cuda.set_device(0)
+    if a.packed_sample > 0:
+        packed_sample(lr, I, torch, a.packed_sample)
+        return
     trajs = I.config_paper_size()
     m, M = trajs[0].model, trajs[0].M
     stream = torch.cuda.current_stream()
