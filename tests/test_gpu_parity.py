@@ -966,3 +966,28 @@ def test_adaptive_rejections(lr):
     b = lr.Batch([_adaptive_case(lr, I.FRAME_DRIVE)], packed=True)
     with pytest.raises(lr.LrError):
         b.adaptive_stats()
+
+
+@pytest.mark.parametrize("d_r,M", [(1, 1), (2, 3), (3, 8)])
+def test_packed_and_adaptive_few_layers(lr, d_r, M):
+    """Packed RK4 and adaptive steps with one to three resonator layers (the three-layer window at its
+    edges) and rank 1, against the oracle."""
+    import torch
+    from oracle import adaptive
+    m = I.readout_model(3, d_r, 4).replace(kappa_f=0.5, gamma_1=0.05)
+    p = _stepwise(6, 90 + d_r, T=0.3).replace(frame=1)
+    B0 = I.initial_state(m, M, "e", seed=91 + d_r, scale=1e-2)
+    it = dict(model=m, M=M, pulse=p, dt=2e-3, nsteps=150, B=lr.to_device(B0), obs_stride=30,
+              obs=torch.zeros((6, 6 + 3), dtype=torch.float64, device="cuda"))
+    assert _run_packed(lr, [it])[0] == lr.LR_OK
+    _, ref = lowrank.integrate(m, p, 0.0, 2e-3, 150, B0, obs_stride=30)
+    _assert_obs(it["obs"].cpu().numpy(), ref, f"packed d_r={d_r} M={M}")
+    ia = dict(model=m, M=M, pulse=p, dt=0.05, nsteps=6, B=lr.to_device(B0), obs_stride=2,
+              obs=torch.zeros((4, 6 + 3), dtype=torch.float64, device="cuda"))
+    b = lr.Batch([ia], adaptive=(1e-9, 1e-12))
+    b.run()
+    assert b.status()[0] == lr.LR_OK
+    acc, rej = b.adaptive_stats()
+    _, refa, acc_o, rej_o = adaptive.integrate(m, p, 0.0, 0.05, 6, B0, 1e-9, 1e-12, obs_stride=2)
+    _assert_obs(ia["obs"].cpu().numpy(), refa, f"adaptive d_r={d_r} M={M}")
+    assert abs(acc[0] - acc_o) <= 3 and abs(rej[0] - rej_o) <= 3
