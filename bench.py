@@ -150,6 +150,31 @@ def comparisons(lr, I, torch, stream, plain_value):
         "unit": "RK steps*trajectories/s",
         "workload": f"512 trajectories (256 piecewise pulses x g/e), N=2000, M=20; spread: first 40 steps "
                     f"({el_s:.2f} s), packed: first 200 steps ({el_p:.2f} s)"}
+    # HIP graph replay of a packed batch with many short chunks (records every 10 steps)
+    gl = I.batch_uniform(64)
+    gsteps, gstride = 400, 10
+    gitems = [dict(model=t.model, M=t.M, pulse=t.pulse, dt=t.dt, nsteps=gsteps, B=lr.to_device(t.B0()),
+                   obs_stride=gstride, obs=torch.zeros((gsteps // gstride + 1, 6 + t.model.d_q),
+                                                       dtype=torch.float64, device="cuda")) for t in gl]
+    gb = lr.Batch(gitems, stream=torch.cuda.Stream(), packed=True)  # a capturable stream
+    gt = {}
+    for mode in ("eager", "graph"):
+        if mode == "graph":
+            gb.graph(True)
+            gb.run()  # capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            gb.run()
+        torch.cuda.synchronize()
+        gt[mode] = (time.perf_counter() - t0) / 3
+        if gb.status()[0] != lr.LR_OK:
+            raise RuntimeError("graph comparison failed")
+    gb.close()
+    out["graph_replay_packed"] = {"eager_s": gt["eager"], "graph_s": gt["graph"],
+                                  "speedup": gt["eager"] / gt["graph"],
+                                  "workload": f"{len(gitems)} packed trajectories, N=2000, M=20, {gsteps} steps, "
+                                              f"records every {gstride} steps ({gsteps // gstride} chunks)"}
     # batched mixed shapes: the 512 trajectories of the batched configuration, capped step count
     steps = 150
     c4 = I.config_batched()

@@ -282,6 +282,17 @@ int lr_batch_bind(lr_batch_t* batch, void* d_workspace, size_t bytes, void* stre
  * stream.  Trajectories are packed into co-resident groups and run
  * concurrently, group after group. */
 int lr_batch_run(lr_batch_t* batch);
+/* Graph mode for batches whose trajectories all run in the packed schedule
+ * (LR_BATCH_PACKED or adaptive): while on, the first lr_batch_run captures its
+ * whole launch sequence on the bound stream into a HIP graph and every call
+ * replays it.  A replay integrates the same problems again from the current
+ * contents of every d_B (descriptors, step counts and records as at
+ * lr_batch_init); kernel timing (lr_batch_profile_*) is not recorded while on.
+ * on = 0 drops the graph.  LR_ERR_STATE before lr_batch_bind, when the batch
+ * is bound to the null stream (which cannot be captured), or when a
+ * trajectory runs in the spread schedule (its cooperative launches are not
+ * captured). */
+int lr_batch_graph(lr_batch_t* batch, int32_t on);
 /* Synchronise; per-trajectory status codes and failing step indices
  * (arrays of n, may be NULL).  Returns the first non-OK code or LR_OK. */
 int lr_batch_status(lr_batch_t* batch, int32_t* codes, int64_t* failed_steps);

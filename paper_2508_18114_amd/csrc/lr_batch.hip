@@ -25,6 +25,9 @@ struct lr_batch {
   std::vector<size_t> lds, region, region_bytes;
   std::vector<int> wg_offset;  // first tilemap entry of each trajectory
   std::vector<char> packed;    // trajectory runs in the packed kernel
+  bool graph_on = false;       // lr_batch_run captures its launch sequence once and replays it
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
   bool adaptive = false;       // packed trajectories take adaptive Dormand-Prince steps
   double rtol = 0.0, atol = 0.0;
   size_t off_ad = 0;           // AdaptDev descriptors (adaptive batches)
@@ -420,9 +423,55 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
   return LR_OK;
 }
 
+namespace {
+void drop_graph(lr_batch* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+}
+int enqueue(lr_batch* b);
+}  // namespace
+
+int lr_batch_graph(lr_batch_t* b, int32_t on) {
+  if (!b) return LR_ERR_ARG;
+  if (!b->ws) return LR_ERR_STATE;
+  drop_graph(b);
+  b->graph_on = false;
+  if (!on) return LR_OK;
+  if (!b->stream) return LR_ERR_STATE;  // the null stream cannot be captured
+  for (int t = 0; t < b->n; ++t)
+    if (!b->packed[t]) return LR_ERR_STATE;  // cooperative launches are not captured
+  b->graph_on = true;
+  return LR_OK;
+}
+
 int lr_batch_run(lr_batch_t* b) {
   if (!b) return LR_ERR_ARG;
   if (!b->ws) return LR_ERR_STATE;
+  if (!b->graph_on) return enqueue(b);
+  if (!b->gexec) {
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return LR_ERR_HIP;
+    const int e = enqueue(b);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->stream, &g);
+    if (e != LR_OK || ec != hipSuccess) {
+      if (ec == hipSuccess && g) (void)hipGraphDestroy(g);
+      return e != LR_OK ? e : LR_ERR_HIP;
+    }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+      drop_graph(b);
+      return LR_ERR_HIP;
+    }
+  }
+  return hipGraphLaunch(b->gexec, b->stream) == hipSuccess ? LR_OK : LR_ERR_HIP;
+}
+
+}  // extern "C"
+
+namespace {
+int enqueue(lr_batch* b) {
   TrajDev* trajs = reinterpret_cast<TrajDev*>(b->ws + b->off_trajs);
   const int2* tmap = reinterpret_cast<const int2*>(b->ws + b->off_tilemap);
   hipLaunchKernelGGL(lrk::k_reset, dim3((b->n + 63) / 64), dim3(64), 0, b->stream, trajs, b->n);
@@ -444,7 +493,7 @@ int lr_batch_run(lr_batch_t* b) {
     auto launch = [&](int prologue, int64_t step0, int64_t nchunk) -> int {
       void* args[] = {(void*)&gtr, (void*)&gmap, (void*)&step0, (void*)&nchunk};
       int64_t k = -1;
-      if (b->prof && !prologue && b->n_ev < LR_PROFILE_MAX) {
+      if (b->prof && !b->graph_on && !prologue && b->n_ev < LR_PROFILE_MAX) {
         while ((int64_t)b->ev.size() < 2 * (b->n_ev + 1)) {
           hipEvent_t e;
           if (hipEventCreate(&e) != hipSuccess) return LR_ERR_HIP;
@@ -493,6 +542,9 @@ int lr_batch_run(lr_batch_t* b) {
   }
   return hipGetLastError() == hipSuccess ? LR_OK : LR_ERR_HIP;
 }
+}  // namespace
+
+extern "C" {
 
 int lr_batch_status(lr_batch_t* b, int32_t* codes, int64_t* failed_steps) {
   if (!b) return LR_ERR_ARG;
@@ -535,6 +587,7 @@ int lr_batch_profile_read(lr_batch_t* b, double* ms, int64_t* launches) {
 
 void lr_batch_destroy(lr_batch_t* b) {
   if (!b) return;
+  drop_graph(b);
   for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
   delete b;
 }

@@ -39,7 +39,7 @@ EXPORTS = ("lr_init", "lr_workspace_bytes", "lr_bind", "lr_rhs", "lr_integrate",
            "lr_observables", "lr_spectrum", "lr_status", "lr_profile_enable", "lr_profile_read",
            "lr_readout_loss", "lr_dense_workspace_bytes", "lr_dense_integrate", "lr_strerror", "lr_destroy",
            "lr_batch_init", "lr_batch_init_ex", "lr_batch_init_adaptive", "lr_batch_adaptive_stats",
-           "lr_batch_workspace_bytes", "lr_batch_bind", "lr_batch_run",
+           "lr_batch_workspace_bytes", "lr_batch_graph", "lr_batch_bind", "lr_batch_run",
            "lr_batch_status", "lr_batch_profile_enable", "lr_batch_profile_read", "lr_batch_destroy")
 
 
@@ -101,6 +101,7 @@ def _load():
         "lr_batch_init_ex": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lr_traj_t), i32, i32]),
         "lr_batch_init_adaptive": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lr_traj_t), i32, dbl, dbl]),
         "lr_batch_adaptive_stats": (ctypes.c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "lr_batch_graph": (ctypes.c_int, [vp, i32]),
         "lr_batch_workspace_bytes": (sz, [vp]),
         "lr_batch_bind": (ctypes.c_int, [vp, vp, sz, vp]),
         "lr_batch_run": (ctypes.c_int, [vp]),
@@ -412,6 +413,12 @@ class Batch:
 
     def status(self):
         return lr_batch_status(self.handle, len(self.items))
+
+    def graph(self, on=True):
+        """Capture the launch sequence once and replay it on every run (packed batches)."""
+        rc = _lib.lr_batch_graph(self.handle, 1 if on else 0)
+        if rc != LR_OK:
+            raise LrError(rc, "lr_batch_graph")
 
     def adaptive_stats(self):
         """(accepted, rejected) step counts per trajectory of an adaptive batch."""

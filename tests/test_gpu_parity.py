@@ -991,3 +991,50 @@ def test_packed_and_adaptive_few_layers(lr, d_r, M):
     _, refa, acc_o, rej_o = adaptive.integrate(m, p, 0.0, 0.05, 6, B0, 1e-9, 1e-12, obs_stride=2)
     _assert_obs(ia["obs"].cpu().numpy(), refa, f"adaptive d_r={d_r} M={M}")
     assert abs(acc[0] - acc_o) <= 3 and abs(rej[0] - rej_o) <= 3
+
+
+# ------------------------------------------------------------ HIP graph capture of a packed batch
+
+def test_graph_replays_equal_eager_run(lr):
+    """A packed batch (several chunks and records) captured once and replayed three times, with eager
+    work (state resets, another batch) between the replays: every replay bitwise equals the eager run;
+    the same for an adaptive batch."""
+    import torch
+    for adaptive in (None, (1e-8, 1e-11)):
+        items = _batch_items(lr, BATCH_SPECS[:3]) if adaptive is None else \
+            [_adaptive_case(lr, I.FRAME_DRIVE), _adaptive_case(lr, I.FRAME_LAB, seed=8)]
+        st = torch.cuda.Stream()  # a capturable stream (not the null stream)
+        b = lr.Batch(items, stream=st, packed=True, adaptive=adaptive)
+        b.run()
+        assert b.status()[0] == lr.LR_OK
+        ref = [(it["B"].clone(), it["obs"].clone() if it.get("obs") is not None else None) for it in items]
+        b.graph(True)
+        for rep in range(3):
+            for it in items:
+                it["B"].copy_(lr.to_device(it["B0"]))
+                if it.get("obs") is not None:
+                    it["obs"].zero_()
+            other = _batch_items(lr, BATCH_SPECS[3:4])  # eager work between replays
+            ob = lr.Batch(other)
+            ob.run()
+            assert ob.status()[0] == lr.LR_OK
+            torch.cuda.synchronize()
+            b.run()
+            assert b.status()[0] == lr.LR_OK
+            for it, (Br, Or) in zip(items, ref):
+                assert torch.equal(it["B"], Br), (adaptive, rep)
+                if Or is not None:
+                    assert torch.equal(it["obs"], Or), (adaptive, rep)
+        b.graph(False)
+        b.close()
+
+
+def test_graph_needs_packed_batch_on_a_stream(lr):
+    import torch
+    items = _batch_items(lr, BATCH_SPECS[:1])
+    b = lr.Batch(items, stream=torch.cuda.Stream())
+    with pytest.raises(lr.LrError):
+        b.graph(True)
+    b2 = lr.Batch(_batch_items(lr, BATCH_SPECS[:1]), packed=True)  # the null stream
+    with pytest.raises(lr.LrError):
+        b2.graph(True)
