@@ -180,6 +180,14 @@ def comparisons(lr, I, torch, stream, plain_value):
     c4 = I.config_batched()
     v, el = run_batch(c4, steps)
     vp, elp = run_batch(c4, steps, packed=True)
+    from paper_2508_18114_amd import autotune
+    titems = [dict(model=t.model, M=t.M, pulse=t.pulse, dt=t.dt, nsteps=min(t.nsteps, steps),
+                   B=lr.to_device(t.B0())) for t in c4]
+    tch = autotune.tune(titems, steps=10, stream=stream)
+    out["autotune_c4"] = {"choice": f'{tch["schedule"]} (tile height {tch["layers"]})' if tch["schedule"] == "spread"
+                          else "packed", "rates_10_steps": tch["rates"],
+                          "workload": "the 512 trajectories of the batched configuration, 10 steps per candidate"}
+    del titems
     out["batched_mixed_c4_sample"] = {"value": v, "unit": "RK steps*trajectories/s",
                                       "packed": vp, "packed_vs_spread": vp / v,
                                       "workload": f"{len(c4)} trajectories, N in {{1000,1520,2000,3000}}, "

@@ -259,6 +259,11 @@ int lr_batch_init(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n);
  * Unknown flag bits: LR_ERR_ARG. */
 #define LR_BATCH_PACKED 1
 #define LR_PACKED_MAX_LM 1536
+/* Tile height of the spread schedule: resonator layers per workgroup
+ * (1..255; 0 or absent: one).  A height whose tile does not fit the kernel's
+ * register rows or LDS is lowered to the largest that fits.  Combined with the
+ * other flags by |; the autotuner of the Python package searches it. */
+#define LR_BATCH_SPREAD_LAYERS(k) ((int32_t)((k) & 0xff) << 8)
 int lr_batch_init_ex(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n, int32_t flags);
 /* Adaptive-step batch (main text, "Computational performance": the paper's
  * solver has an adaptive time step): every trajectory takes Dormand-Prince

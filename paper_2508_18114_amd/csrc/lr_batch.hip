@@ -60,11 +60,12 @@ int64_t gcd64(int64_t a, int64_t b) {
 }
 
 // Persistent configuration of one shape: layers per workgroup, register rows.
-bool persist_config(const lr_model_t& m, int M, int& prt, int& P, int& rows, size_t& lds) {
+bool persist_config(const lr_model_t& m, int M, int layers, int& prt, int& P, int& rows, size_t& lds) {
   const int L = m.d_q * m.d_f;
   const int NG = lrk::kPW / M;
   prt = 1;
   if (const char* e = std::getenv("LR_PERSIST_LAYERS")) prt = std::atoi(e);
+  if (layers > 0) prt = layers;
   if (prt < 1) prt = 1;
   if (prt > m.d_r) prt = m.d_r;
   while (prt > 1 && ((prt * L + NG - 1) / NG > lrk::kMaxRowsPerThread ||
@@ -137,7 +138,7 @@ namespace {
 int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flags, bool adaptive, double rtol,
                double atol) {
   if (!out || !trajs || n < 1) return LR_ERR_ARG;
-  if (flags & ~LR_BATCH_PACKED) return LR_ERR_ARG;
+  if (flags & ~(LR_BATCH_PACKED | LR_BATCH_SPREAD_LAYERS(0xff))) return LR_ERR_ARG;
   *out = nullptr;
   lr_batch* b = new (std::nothrow) lr_batch();
   if (!b) return LR_ERR_OOM;
@@ -210,7 +211,7 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
       b->lds[t] = lrk::packed_lds_elems(x.model.d_q * x.model.d_f, x.M,
                                         std::max(std::max(x.model.d_q, x.model.d_r), x.model.d_f)) *
                   sizeof(double2);
-    } else if (!e && !persist_config(x.model, x.M, b->prt[t], b->P[t], b->rows[t], b->lds[t])) {
+    } else if (!e && !persist_config(x.model, x.M, (flags >> 8) & 0xff, b->prt[t], b->P[t], b->rows[t], b->lds[t])) {
       e = LR_ERR_ARG;
     }
     if (e) {

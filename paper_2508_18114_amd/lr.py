@@ -34,6 +34,11 @@ LR_MAX_M = 32
 LR_BATCH_PACKED = 1       # lr_batch_init_ex flag: one workgroup per FP64 trajectory
 LR_PACKED_MAX_LM = 1536
 
+
+def LR_BATCH_SPREAD_LAYERS(k: int) -> int:
+    """lr_batch_init_ex flag: resonator layers per workgroup of the spread schedule."""
+    return (int(k) & 0xFF) << 8
+
 # every symbol include/lr.h declares
 EXPORTS = ("lr_init", "lr_workspace_bytes", "lr_bind", "lr_rhs", "lr_integrate",
            "lr_observables", "lr_spectrum", "lr_status", "lr_profile_enable", "lr_profile_read",
@@ -389,14 +394,14 @@ class Batch:
     Dormand-Prince steps (lr_batch_init_adaptive); dt is then the output grid.
     """
 
-    def __init__(self, items, stream=None, packed=False, adaptive=None):
+    def __init__(self, items, stream=None, packed=False, adaptive=None, flags=0):
         import torch
         self.items = list(items)
         ts = [traj_struct(it["model"], it["M"], it["pulse"], it.get("t0", 0.0), it["dt"], it["nsteps"],
                           it["B"], it.get("obs_stride", 0), it.get("obs"), it.get("precision", _inp.FP64),
                           it.get("step0", 0))
               for it in self.items]
-        self.handle = lr_batch_init(ts, LR_BATCH_PACKED if packed else 0, adaptive)
+        self.handle = lr_batch_init(ts, (LR_BATCH_PACKED if packed else 0) | int(flags), adaptive)
         nbytes = lr_batch_workspace_bytes(self.handle)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         base = self.workspace.data_ptr()

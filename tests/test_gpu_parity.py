@@ -1038,3 +1038,37 @@ def test_graph_needs_packed_batch_on_a_stream(lr):
     b2 = lr.Batch(_batch_items(lr, BATCH_SPECS[:1]), packed=True)  # the null stream
     with pytest.raises(lr.LrError):
         b2.graph(True)
+
+
+def test_spread_tile_height_and_autotuner(lr, tmp_path):
+    """Tile heights 1..3 of the spread schedule agree to the FP64 tolerances (other summation orders);
+    the autotuner picks a configuration that runs, its tuned batch equals bitwise a batch built with the
+    picked flags, and the choice is cached on disk."""
+    from paper_2508_18114_amd import autotune
+    specs = [((4, 10, 5), 4, "g", 120, 10, 1), ((3, 7, 4), 6, "e", 120, 10, 2)]
+    res = {}
+    for k in (1, 2, 3):
+        items = _batch_items(lr, specs)
+        b = lr.Batch(items, flags=lr.LR_BATCH_SPREAD_LAYERS(k))
+        b.run()
+        assert b.status()[0] == lr.LR_OK
+        res[k] = [it["obs"].cpu().numpy() for it in items]
+    for k in (2, 3):
+        for a, r in zip(res[k], res[1]):
+            _assert_obs(a, r, f"spread tile height {k} vs 1")
+    items = _batch_items(lr, specs)
+    path = str(tmp_path / "tune.json")
+    choice = autotune.tune(items, steps=10, cache_path=path)
+    print(f"[autotune] {choice}")
+    assert choice["schedule"] in ("spread", "packed") and max(v for v in choice["rates"].values() if v) > 0
+    tb = autotune.tuned_batch(items, cache_path=path)
+    tb.run()
+    assert tb.status()[0] == lr.LR_OK
+    ref = _batch_items(lr, specs)
+    rb = lr.Batch(ref, flags=choice["flags"])
+    rb.run()
+    assert rb.status()[0] == lr.LR_OK
+    for a, r in zip(items, ref):
+        assert np.array_equal(lr.from_device(a["B"]), lr.from_device(r["B"]))
+    import json
+    assert autotune.signature(items) in json.load(open(path))

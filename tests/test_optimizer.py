@@ -78,3 +78,17 @@ def test_project_heights_holds_the_drive_bound():
     assert out[0] == h[0] and out[3] == 0.0          # inside: unchanged
     np.testing.assert_allclose(np.angle(out[1:3]), np.angle(h[1:3]))  # outside: radial scaling
     np.testing.assert_allclose(np.abs(out[1:3]), bound, rtol=1e-8)
+
+
+def test_autotune_signature_and_candidates():
+    """Host logic of the schedule autotuner: the signature is the multiset of shapes, and every candidate
+    maps to the library's flags."""
+    from paper_2508_18114_amd import autotune, lr
+    m1, m2 = I.readout_model(8, 50, 5), I.readout_model(8, 25, 5)
+    items = [dict(model=m1, M=20), dict(model=m2, M=8, precision=1), dict(model=m1, M=20)]
+    assert autotune.signature(items) == "8x25x5:M8:p1*1;8x50x5:M20:p0*2"
+    assert autotune.signature(list(reversed(items))) == autotune.signature(items)
+    cands = autotune.candidates(3)
+    assert [c["schedule"] for c in cands] == ["spread"] * 3 + ["packed"]
+    assert autotune.flags_of(cands[1]) == lr.LR_BATCH_SPREAD_LAYERS(2) == 2 << 8
+    assert autotune.flags_of(cands[-1]) == lr.LR_BATCH_PACKED
