@@ -16,6 +16,11 @@ import os
 
 import numpy as np
 
+# torch first: the library then binds to the HIP runtime torch already loaded
+# (the one that owns the device memory and streams passed in), whatever
+# module imports this one first
+import torch  # noqa: F401
+
 from . import inputs as _inp
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblr.so")
