@@ -21,6 +21,9 @@ Modules
               quantity p_M / p_1 and the purity (supplement S1.B)
   adaptive -- adaptive-step integration of the low-rank equation (the
               Dormand-Prince 5(4) pair with an error-norm step controller)
+  papermodel -- the paper's mode basis: charge-basis transmon levels and charge
+              operator (supplement S2.A), resonator-filter normal modes and
+              their coupling coefficients (supplement S2.D)
 
 Every function is written in the notation of the paper, step by step, with
 numpy/scipy library primitives (matmul, Cholesky, triangular solve, erfc) as

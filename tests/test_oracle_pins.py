@@ -11,7 +11,7 @@ import pytest
 import scipy.integrate
 import scipy.linalg
 
-from oracle import adaptive, dense, loss, lowrank, pulses, validity
+from oracle import adaptive, dense, loss, lowrank, papermodel, pulses, validity
 from paper_2508_18114_amd import inputs as I
 
 
@@ -533,3 +533,72 @@ def test_adaptive_lowrank_matches_fine_fixed_step_rk4():
     assert np.max(np.abs(oa[:, 0:4] - orf[:, 0:4])) <= 1e-7 * scale
     assert np.max(np.abs(oa[:, 4:] - orf[:, 4:])) <= 1e-7
     assert acc < 4000  # fewer steps than the fixed-step reference
+
+
+# ------------------------------------------------------------ the paper's mode basis (S2.A, S2.D)
+
+def test_transmon_levels_are_mathieu_characteristic_values():
+    """The charge-basis diagonalisation of 4 E_c n^2 - E_j cos(phi) at zero offset charge gives
+    E_m = E_c x (a_0, b_2, a_2, b_4, a_4, b_6)(E_j / 2 E_c), Mathieu characteristic values (an independent
+    library routine); the paper's E_c / 2pi = 315 MHz, E_j / E_c = 51 give omega_01 / 2pi = 6.03 GHz
+    (the paper: 6 GHz)."""
+    import scipy.special as sp
+    for ej in (20.0, 51.0, 80.0):
+        w, _ = papermodel.transmon_levels(1.0, ej, 6)
+        q = ej / 2.0
+        ref = [sp.mathieu_a(0, q), sp.mathieu_b(2, q), sp.mathieu_a(2, q), sp.mathieu_b(4, q), sp.mathieu_a(4, q),
+               sp.mathieu_b(6, q)]
+        np.testing.assert_allclose(w, ref, rtol=0, atol=1e-10 * ej)
+    Ec = I.ghz(0.315)
+    w, nt = papermodel.transmon_levels(Ec, 51 * Ec, 6)
+    assert abs((w[1] - w[0]) / (2 * np.pi) - 6.0) < 0.06
+
+
+def test_transmon_charge_operator_structure():
+    """n_t in the eigenbasis is real symmetric with zero diagonal (S2.E) and, at zero offset charge,
+    couples only levels of opposite parity; its nearest-neighbour elements grow like sqrt(j + 1)
+    times the ground-state charge fluctuation (harmonic limit, E_j / E_c large)."""
+    w, nt = papermodel.transmon_levels(1.0, 400.0, 5)
+    assert np.allclose(nt, nt.T, atol=1e-12)
+    assert np.max(np.abs(np.diag(nt))) < 1e-12
+    for j in range(5):
+        for k in range(5):
+            if (j + k) % 2 == 0:
+                assert abs(nt[j, k]) < 1e-10
+    n01 = abs(nt[0, 1])
+    for j in range(1, 4):
+        assert abs(abs(nt[j, j + 1]) / n01 - math.sqrt(j + 1)) < 0.05 * math.sqrt(j + 1)
+
+
+def _fock_rf(w_r, w_f, J, n):
+    a = np.diag(np.sqrt(np.arange(1, n)), 1)
+    ia = np.eye(n)
+    A, F = np.kron(a, ia), np.kron(ia, a)
+    X = lambda o: o.conj().T - o  # noqa: E731
+    H = w_r * A.conj().T @ A + w_f * F.conj().T @ F - J * X(A) @ X(F)
+    return H, A, F, X
+
+
+def test_normal_modes_match_brute_force_fock_diagonalisation():
+    """The normal-mode frequencies are the first excitation energies of H_rf diagonalised in a truncated
+    Fock basis, and |<0|(a^ - a)|1_l>| = |mu_l|, |<0|(f^ - f)|1_u>| = |nu_u| etc.; the eigenvectors of
+    Omega carry bosonic norms -1, -1, +1, +1 and S Sigma_c S^ = Sigma_a (eq. "symplecticmatrices")."""
+    tp = 2 * np.pi
+    w_r, w_f, J = tp * 7.2, tp * 7.21, tp * 0.03
+    wl, wu, U, S = papermodel.normal_modes(w_r, w_f, J)
+    Om = papermodel.omega_matrix(w_r, w_f, J)
+    assert np.max(np.abs(Om @ U - U @ np.diag([-wu, -wl, wl, wu]))) < 1e-10 * wu
+    np.testing.assert_allclose(papermodel.bosonic_norms(U), [-1, -1, 1, 1], atol=1e-12)
+    Sa = np.block([[np.zeros((2, 2)), np.eye(2)], [-np.eye(2), np.zeros((2, 2))]])
+    sx = np.array([[0.0, 1.0], [1.0, 0.0]])
+    Sc = np.block([[np.zeros((2, 2)), -sx], [sx, np.zeros((2, 2))]])
+    assert np.max(np.abs(S @ Sc @ S.conj().T - Sa)) < 1e-12
+    H, A, F, X = _fock_rf(w_r, w_f, J, 12)
+    e, V = np.linalg.eigh(H)
+    assert abs((e[1] - e[0]) - wl) < 1e-8 * wl and abs((e[2] - e[0]) - wu) < 1e-8 * wu
+    mu_u, mu_l, nu_u, nu_l = papermodel.couplings(S)
+    g0, l1, u1 = V[:, 0], V[:, 1], V[:, 2]
+    assert abs(abs(g0 @ X(A) @ l1) - abs(mu_l)) < 1e-8
+    assert abs(abs(g0 @ X(A) @ u1) - abs(mu_u)) < 1e-8
+    assert abs(abs(g0 @ X(F) @ l1) - abs(nu_l)) < 1e-8
+    assert abs(abs(g0 @ X(F) @ u1) - abs(nu_u)) < 1e-8
