@@ -38,8 +38,17 @@ def operators(model):
 
 
 def hamiltonian(model, d_t):
-    """Dense H(t) for the drive coefficient d_t."""
+    """Dense H(t) for the drive coefficient d_t (kind 1: the paper's
+    Hamiltonian with the transmon in its eigenbasis, see lowrank.apply_heff)."""
     b, a, f = operators(model)
+    if getattr(model, "kind", 0) == 1:
+        Ht = _embed(model, np.diag(np.asarray(model.E_t, dtype=np.float64)).astype(np.complex128), 0)
+        Nt = _embed(model, np.asarray(model.n_t, dtype=np.float64).reshape(model.d_q, model.d_q).astype(np.complex128), 0)
+        Xa = a.conj().T - a
+        Xf = f.conj().T - f
+        H = Ht + model.w_r * a.conj().T @ a + model.w_f * f.conj().T @ f
+        H = H + 1j * model.g * Nt @ Xa - model.G * Xa @ Xf + d_t * 1j * Xf
+        return H
     nq = b.conj().T @ b
     Nn = nq.shape[0]
     I = np.eye(Nn)
@@ -55,6 +64,8 @@ def hamiltonian_drive_frame(model, d_t, w_d, t):
     """Dense H'(t) in the frame rotating at w_d: U H U^ - w_d (n_q + n_r + n_f)
     with U = exp(i w_d t (n_q + n_r + n_f)), built from the phased ladder
     operators b e^{-i w_d t}, a e^{-i w_d t}, f e^{-i w_d t} (all terms kept)."""
+    if getattr(model, "kind", 0) == 1:
+        raise NotImplementedError("the drive frame is built for the Duffing model only")
     b, a, f = operators(model)
     ph = np.exp(-1j * w_d * t)
     bt, at, ft = b * ph, a * ph, f * ph

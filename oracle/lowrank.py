@@ -77,20 +77,40 @@ def quadrature(T, axis):
     return lower(T, axis) + raise_(T, axis)
 
 
+def iquadrature(T, axis):
+    """i (b^ - b) along `axis` (Hermitian)."""
+    return 1j * (raise_(T, axis) - lower(T, axis))
+
+
 def diag_heff(model):
-    """Diagonal of H_eff on the (d_q, d_r, d_f) grid (complex)."""
+    """Diagonal of H_eff on the (d_q, d_r, d_f) grid (complex).  Transmon
+    levels: Duffing w_q q + alpha/2 q (q - 1), or the given eigenvalues E_t."""
     q = np.arange(model.d_q, dtype=np.float64)[:, None, None]
     r = np.arange(model.d_r, dtype=np.float64)[None, :, None]
     f = np.arange(model.d_f, dtype=np.float64)[None, None, :]
-    h = (model.w_q * q + 0.5 * model.alpha * q * (q - 1.0)
-         + model.w_r * r + model.w_f * f)
+    if getattr(model, "kind", 0) == 1:
+        hq = np.asarray(model.E_t, dtype=np.float64)[:, None, None]
+    else:
+        hq = model.w_q * q + 0.5 * model.alpha * q * (q - 1.0)
+    h = hq + model.w_r * r + model.w_f * f
     return h - 0.5j * (model.kappa_f * f + model.gamma_1 * q)
 
 
 def apply_heff(model, d_t, B):
-    """Z = H_eff(t) B, with d_t the drive coefficient d(t)."""
+    """Z = H_eff(t) B, with d_t the drive coefficient d(t).
+
+    kind 1 (the paper's Hamiltonian, eq. "hamiltonianpurcell", transmon in its
+    eigenbasis, bare resonator and filter): i g n_t (a^ - a) - J (a^ - a)(f^ - f)
+    + d(t) i (f^ - f), J held in model.G; the drive quadrature i (f^ - f) takes
+    d(t) in place of the paper's Omega_d(t) sin(w_d t)."""
     T = _as_tensor(model, B)
     Z = diag_heff(model)[..., None] * T
+    if getattr(model, "kind", 0) == 1:
+        nt = np.asarray(model.n_t, dtype=np.float64).reshape(model.d_q, model.d_q)
+        Z = Z + model.g * np.einsum("qp,prfj->qrfj", nt, iquadrature(T, 1))
+        Z = Z - model.G * (raise_(raise_(T, 2) - lower(T, 2), 1) - lower(raise_(T, 2) - lower(T, 2), 1))
+        Z = Z + d_t * iquadrature(T, 2)
+        return Z.reshape(B.shape)
     Z = Z + model.g * quadrature(quadrature(T, 0), 1)
     Z = Z + model.G * quadrature(quadrature(T, 1), 2)
     Z = Z + d_t * quadrature(T, 2)
@@ -113,6 +133,8 @@ def apply_heff_drive_frame(model, d_t, w_d, t, B):
     eq. "hamiltonian_rotated", keeps the counter-rotating terms).  The jump operators only gain a phase,
     which leaves the dissipator unchanged, so H_eff = H' - i/2 (kappa_f n_f +
     gamma_1 n_q) as in the lab frame."""
+    if getattr(model, "kind", 0) == 1:
+        raise NotImplementedError("the drive frame is built for the Duffing model only")
     T = _as_tensor(model, B)
     m2 = model.replace(w_q=model.w_q - w_d, w_r=model.w_r - w_d, w_f=model.w_f - w_d)
     e1 = np.exp(1j * w_d * t)

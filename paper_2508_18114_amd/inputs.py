@@ -37,6 +37,8 @@ TWO_PI = 2.0 * math.pi
 PULSE_FLATTOP = 0
 PULSE_PIECEWISE6 = 1
 PULSE_STEPWISE = 2   # smoothed stepwise complex envelope (supplement S2.C)
+MODEL_DUFFING, MODEL_TRANSMON = 0, 1
+MAX_DQ = 16
 PULSE_MAX_HEIGHTS = 63
 FRAME_LAB = 0        # B and <a>, <f> in the lab frame
 FRAME_DRIVE = 1      # frame rotating at the drive carrier w_d (counter-rotating terms kept)
@@ -53,6 +55,14 @@ def ghz(x: float) -> float:
 
 @dataclasses.dataclass
 class ModelParams:
+    """kind MODEL_DUFFING: the benchmark's Duffing transmon and couplings
+    g (b+b^)(a+a^), G (a+a^)(f+f^), drive d(t) (f+f^).
+    kind MODEL_TRANSMON: the paper's Hamiltonian in the bare resonator/filter
+    basis with the transmon in its eigenbasis: levels E_t (d_q values, rad/ns),
+    charge operator n_t (d_q x d_q, row-major, real symmetric); couplings
+    i g n_t (a^ - a) and -G (a^ - a)(f^ - f) (G plays J), drive d(t) i (f^ - f);
+    w_q and alpha unused.  Jumps in both: sqrt(kappa_f) f, sqrt(gamma_1) b with
+    b the ladder sum_q sqrt(q) |q-1><q|."""
     d_q: int
     d_r: int
     d_f: int
@@ -64,6 +74,9 @@ class ModelParams:
     G: float
     kappa_f: float
     gamma_1: float
+    kind: int = 0
+    E_t: tuple = ()
+    n_t: tuple = ()
 
     @property
     def N(self) -> int:

@@ -602,3 +602,63 @@ def test_normal_modes_match_brute_force_fock_diagonalisation():
     assert abs(abs(g0 @ X(A) @ u1) - abs(mu_u)) < 1e-8
     assert abs(abs(g0 @ X(F) @ l1) - abs(nu_l)) < 1e-8
     assert abs(abs(g0 @ X(F) @ u1) - abs(nu_u)) < 1e-8
+
+
+# ------------------------------------------------------------ the paper's Hamiltonian in the bare basis (kind 1)
+
+def _transmon_model(dq, dr, df, kappa_f=0.6, gamma_1=0.2, g=0.9, J=0.35):
+    Ec = I.ghz(0.315)
+    w, nt = papermodel.transmon_levels(Ec, 51 * Ec, dq)
+    return I.readout_model(dq, dr, df).replace(kind=I.MODEL_TRANSMON, E_t=tuple(w - w[0]),
+                                                n_t=tuple(nt.ravel()), g=g, G=J, kappa_f=kappa_f,
+                                                gamma_1=gamma_1)
+
+
+def test_transmon_model_hamiltonian_matrix_elements():
+    """Dense H of the paper's Hamiltonian (eq. "hamiltonianpurcell", bare resonator/filter, transmon
+    eigenbasis) is Hermitian and has the closed-form elements <q', r+1, f|H|q, r, f> = i g n_t[q'][q]
+    sqrt(r + 1), <q, r+1, f+1|H|q, r, f> = -J sqrt(r+1) sqrt(f+1), <q, r+1, f-1|H|q, r, f> = J sqrt(r+1)
+    sqrt(f), <q, r, f+1|H|q, r, f> = i d sqrt(f+1) and diagonal E_q + w_r r + w_f f."""
+    m = _transmon_model(4, 3, 3)
+    d = 0.37
+    H = dense.hamiltonian(m, d)
+    assert np.max(np.abs(H - H.conj().T)) < 1e-12
+    nt = np.asarray(m.n_t).reshape(4, 4)
+    idx = lambda q, r, f: I.basis_index(m, q, r, f)  # noqa: E731
+    for (q, r, f) in [(0, 0, 0), (1, 1, 2), (3, 0, 1), (2, 1, 1)]:
+        assert abs(H[idx(q, r, f), idx(q, r, f)] - (m.E_t[q] + m.w_r * r + m.w_f * f)) < 1e-12
+        for qq in range(4):
+            if qq != q and r + 1 < 3:
+                assert abs(H[idx(qq, r + 1, f), idx(q, r, f)] - 1j * m.g * nt[qq, q] * math.sqrt(r + 1)) < 1e-12
+        if r + 1 < 3 and f + 1 < 3:
+            assert abs(H[idx(q, r + 1, f + 1), idx(q, r, f)] + m.G * math.sqrt(r + 1) * math.sqrt(f + 1)) < 1e-12
+        if r + 1 < 3 and f >= 1:
+            assert abs(H[idx(q, r + 1, f - 1), idx(q, r, f)] - m.G * math.sqrt(r + 1) * math.sqrt(f)) < 1e-12
+        if f + 1 < 3:
+            assert abs(H[idx(q, r, f + 1), idx(q, r, f)] - 1j * d * math.sqrt(f + 1)) < 1e-12
+
+
+def test_transmon_model_rhs_equals_literal_pinv_formula_and_full_rank_lindbladian():
+    m = _transmon_model(3, 3, 2)
+    B = _rand_B(m.N, 3, 21)
+    for t in (0.3, 1.7):
+        a = lowrank.rhs(m, PULSE, t, B)
+        b = dense.lowrank_rhs_pinv(m, PULSE, t, B)
+        assert np.max(np.abs(a - b)) <= 1e-11 * np.max(np.abs(b))
+    Bf = _rand_B(m.N, m.N, 22)
+    dB = lowrank.rhs(m, PULSE, 2.2, Bf)
+    lhs = Bf @ dB.conj().T + dB @ Bf.conj().T
+    ref = dense.lindbladian(m, PULSE, 2.2, Bf @ Bf.conj().T)
+    assert np.max(np.abs(lhs - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_transmon_model_decoupled_phases():
+    """With g = J = 0, no drive and no dissipation every basis state only picks up the phase
+    exp(-i (E_q + w_r r + w_f f) t)."""
+    m = _transmon_model(3, 2, 2, kappa_f=0.0, gamma_1=0.0, g=0.0, J=0.0)
+    p = I.flattop_pulse(0.0, 1.0)
+    B0 = _rand_B(m.N, 2, 23)
+    B, _ = lowrank.integrate(m, p, 0.0, 1e-4, 4000, B0)
+    E = np.array([m.E_t[q] + m.w_r * r + m.w_f * f for q in range(3) for r in range(2) for f in range(2)])
+    exact = np.exp(-1j * E * 0.4)[:, None] * B0
+    assert np.max(np.abs(B - exact)) < 1e-7  # RK4 truncation at |E| dt <= 0.013
