@@ -45,13 +45,30 @@ extern "C" {
 
 typedef struct { double re, im; } lr_c64;
 
-/* Model parameters (rad/ns).  d_q >= 2 (g and e must exist), d_r, d_f >= 1. */
+/* Model parameters (rad/ns).  d_q >= 2 (g and e must exist), d_r, d_f >= 1.
+ * kind LR_MODEL_DUFFING (0): the Duffing transmon w_q n + alpha/2 n (n - 1)
+ *   and the couplings g (b+b^)(a+a^), G (a+a^)(f+f^); drive d(t) (f + f^).
+ * kind LR_MODEL_TRANSMON (1): the paper's Hamiltonian (main text, eq.
+ *   "hamiltonianpurcell") in the bare resonator/filter basis with the
+ *   transmon in its eigenbasis (supplement S2.A): levels E_t[0..d_q-1], charge
+ *   operator n_t (d_q x d_q, row-major, real symmetric), couplings
+ *   i g n_t (a^ - a) and -G (a^ - a)(f^ - f) (G is the paper's J), drive
+ *   d(t) i (f^ - f); w_q and alpha unused; d_q <= LR_MAX_DQ.  This kind runs in
+ *   the packed batch schedule only, in the lab frame, with fixed RK4 steps
+ *   (LR_ERR_ARG elsewhere).
+ * Both kinds: L_1 = sqrt(kappa_f) f, L_2 = sqrt(gamma_1) b, b the ladder
+ * sum_n sqrt(n) |n-1><n| of the transmon levels. */
+#define LR_MODEL_DUFFING 0
+#define LR_MODEL_TRANSMON 1
+#define LR_MAX_DQ 8
 typedef struct {
   int32_t d_q, d_r, d_f;
-  int32_t reserved;
+  int32_t kind;                   /* LR_MODEL_DUFFING or LR_MODEL_TRANSMON                */
   double  w_q, alpha, w_r, w_f;   /* Duffing transmon w_q n + alpha/2 n(n-1); bare modes */
-  double  g, G;                   /* g (b+b^)(a+a^),  G (a+a^)(f+f^)                    */
+  double  g, G;                   /* g (b+b^)(a+a^),  G (a+a^)(f+f^)  (kind 0)           */
   double  kappa_f, gamma_1;       /* L_1 = sqrt(kappa_f) f,  L_2 = sqrt(gamma_1) b      */
+  double  E_t[LR_MAX_DQ];         /* kind 1: transmon levels                            */
+  double  n_t[LR_MAX_DQ * LR_MAX_DQ];  /* kind 1: charge operator, row-major d_q x d_q   */
 } lr_model_t;
 
 /* Drive coefficient d(t) multiplying (f + f^).

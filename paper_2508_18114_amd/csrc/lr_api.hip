@@ -44,6 +44,7 @@ namespace {
 constexpr double kDriveBound = 2.0 * M_PI * 0.4;  // |amplitude| < 2 pi 400 MHz
 static_assert(lrk::kMaxPulseH == LR_PULSE_MAX_H, "stepwise heights of the device descriptor");
 static_assert(lrk::kTMaxLM == LR_PACKED_MAX_LM, "layer size of the packed kernel");
+static_assert(lrk::kMaxDq == LR_MAX_DQ, "transmon levels of the eigenbasis model");
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -187,6 +188,7 @@ const char* lr_strerror(int code) {
 int lr_init(lr_ctx_t** out, const lr_model_t* m, int32_t M, int32_t precision) {
   if (!out || !m) return LR_ERR_ARG;
   *out = nullptr;
+  if (m->kind != LR_MODEL_DUFFING) return LR_ERR_ARG;  // the eigenbasis model runs in packed batches only
   if (m->d_q < 2 || m->d_r < 1 || m->d_f < 1) return LR_ERR_ARG;
   const long long N = (long long)m->d_q * m->d_r * m->d_f;
   if (N > (1LL << 26)) return LR_ERR_ARG;
@@ -468,6 +470,7 @@ int lr_dense_integrate(const lr_model_t* m, const lr_pulse_t* pulse, double t0, 
                        lr_c64* d_rho, int32_t obs_stride, double* d_obs, void* d_workspace, size_t bytes,
                        void* stream) {
   if (!m || !d_rho || !d_workspace || m->d_q < 1 || m->d_r < 1 || m->d_f < 1) return LR_ERR_ARG;
+  if (m->kind != LR_MODEL_DUFFING) return LR_ERR_ARG;
   const long long Nl = (long long)m->d_q * m->d_r * m->d_f;
   if (Nl > 16384) return LR_ERR_ARG;
   if (bytes < lr_dense_workspace_bytes(m)) return LR_ERR_ARG;

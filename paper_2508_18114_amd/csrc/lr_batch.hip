@@ -83,6 +83,20 @@ bool persist_config(const lr_model_t& m, int M, int layers, int& prt, int& P, in
 
 int check_model(const lr_model_t& m, int M, int precision) {
   if (m.d_q < 2 || m.d_r < 1 || m.d_f < 1) return LR_ERR_ARG;
+  if (m.kind != LR_MODEL_DUFFING && m.kind != LR_MODEL_TRANSMON) return LR_ERR_ARG;
+  if (m.kind == LR_MODEL_TRANSMON) {
+    if (m.d_q > LR_MAX_DQ) return LR_ERR_ARG;
+    double big = 0.0;
+    for (int i = 0; i < m.d_q * m.d_q; ++i) {
+      if (!std::isfinite(m.n_t[i])) return LR_ERR_ARG;
+      big = std::max(big, std::fabs(m.n_t[i]));
+    }
+    for (int i = 0; i < m.d_q; ++i) {
+      if (!std::isfinite(m.E_t[i])) return LR_ERR_ARG;
+      for (int j = 0; j < i; ++j)
+        if (std::fabs(m.n_t[i * m.d_q + j] - m.n_t[j * m.d_q + i]) > 1e-12 * big) return LR_ERR_ARG;
+    }
+  }
   const long long N = (long long)m.d_q * m.d_r * m.d_f;
   if (N > (1LL << 26)) return LR_ERR_ARG;
   if (M < 1 || M > LR_MAX_M || M > N) return LR_ERR_ARG;
@@ -184,12 +198,17 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
   b->region.resize(n);
   b->region_bytes.resize(n);
   b->wg_offset.resize(n);
-  if (adaptive)  // every trajectory must take the packed kernel
+  if (adaptive)  // every trajectory must take the packed kernel (Duffing model)
     for (int k = 0; k < n; ++k)
-      if (!b->packed[k]) {
+      if (!b->packed[k] || b->tr[k].model.kind != LR_MODEL_DUFFING) {
         delete b;
         return LR_ERR_ARG;
       }
+  for (int k = 0; k < n; ++k)  // the eigenbasis model runs packed, in the lab frame
+    if (b->tr[k].model.kind == LR_MODEL_TRANSMON && (!b->packed[k] || b->tr[k].pulse.frame != LR_FRAME_LAB)) {
+      delete b;
+      return LR_ERR_ARG;
+    }
   const size_t a = 256;
   size_t o = 0;
   b->off_trajs = o;
@@ -288,6 +307,11 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
     v.nsteps = x.nsteps;
     v.w_q = m.w_q; v.alpha = m.alpha; v.w_r = m.w_r; v.w_f = m.w_f;
     v.g = m.g; v.G = m.G; v.kappa = m.kappa_f; v.gamma = m.gamma_1;
+    v.mkind = m.kind;
+    if (m.kind == LR_MODEL_TRANSMON) {
+      for (int i = 0; i < m.d_q; ++i) v.Et[i] = m.E_t[i];
+      for (int i = 0; i < m.d_q * m.d_q; ++i) v.ntq[i] = m.n_t[i];
+    }
     set_pulse(v, &x.pulse);
     v.t0 = x.t0;
     v.dt = x.dt;

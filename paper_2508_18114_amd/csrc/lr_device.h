@@ -16,6 +16,7 @@ namespace lrk {
 constexpr int kWG = 256;          // threads per workgroup of the streaming kernels
 constexpr int kMaxM = 32;         // largest supported rank
 constexpr int kMaxPulseH = 63;    // heights of the smoothed stepwise envelope (n = nh + 1 <= 64 steps)
+constexpr int kMaxDq = 8;         // transmon levels of the eigenbasis model (keeps TrajDev a small kernel argument)
 constexpr int kMaxTileElems = 2048;  // rows*M of one tile (LDS budget: 32 KB of FP64 complex)
 constexpr int kMaxElemsPerThread = kMaxTileElems / kWG;
 
@@ -31,7 +32,7 @@ struct TrajDev {
   double w_q, alpha, w_r, w_f, g, G, kappa, gamma;
   // drive
   int32_t pkind, prec;  // drive kind; arithmetic of the operator/Gram products (LR_FP64/FP32/BF16X3)
-  int32_t frame, pad2;  // 0 lab frame, 1 frame rotating at w_d (w_q, w_r, w_f then hold w - w_d)
+  int32_t frame, mkind; // 0 lab frame, 1 frame rotating at w_d (w_q, w_r, w_f then hold w - w_d); model kind
   double w_d, amp, t_ramp, T, p[6];
   int32_t nh, pad3;     // smoothed stepwise envelope: heights h_2 .. h_{nh+1}, logistic steepness
   double sigma, h[2 * kMaxPulseH];
@@ -58,6 +59,9 @@ struct TrajDev {
   uint32_t* flagA;      // [P * kFlagStride] "partials of stage g published" = g + 1
   uint32_t* flagB;      // [P * kFlagStride] "reduction of stage g done"     = g + 1
   uint32_t* abort_flag; // set when a bounded wait expires
+  // model kind 1 (transmon eigenbasis): levels and charge operator (row-major d_q x d_q)
+  double Et[kMaxDq];
+  double ntq[kMaxDq * kMaxDq];
 };
 
 constexpr int kFlagStride = 32;    // one 128-byte line per flag

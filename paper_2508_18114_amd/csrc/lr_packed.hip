@@ -223,13 +223,52 @@ __device__ __forceinline__ double2 packed_stencil(const TrajDev& T, const double
   return z;
 }
 
+// Element (rl, j) of layer r for the transmon-eigenbasis model (lab frame):
+// z = H Y with H = diag(E_q + w_r r + w_f f) - i/2 (jumps) + i g n_t (a^ - a)
+// - J (a^ - a)(f^ - f) + d(t) i (f^ - f), J held in T.G.  (a^ Y)[r] = sqrt(r)
+// Y[r-1], (a Y)[r] = sqrt(r+1) Y[r+1]; n_t couples the transmon levels densely
+// (row q of nt, from LDS).
+__device__ __forceinline__ double2 packed_stencil_tm(const TrajDev& T, const double2* Yp, const double2* Yc,
+                                                     const double2* Yn, const double* sq, const double2* hd,
+                                                     const double* nt, int r, int rl, int q, int f, int j,
+                                                     double drv) {
+  const int M = T.M, d_f = T.d_f, d_q = T.d_q, d_r = T.d_r;
+  const double2 h = hd[rl];
+  double2 z = cmul(make_double2(h.x + T.w_r * r, h.y), Yc[rl * M + j]);
+  const double sr_lo = sq[r], sr_hi = sq[min(r + 1, d_r)];
+  // i g n_t (a^ - a)
+  double2 s = make_double2(0.0, 0.0);
+  for (int p = 0; p < d_q; ++p) {
+    const double c = nt[q * d_q + p];
+    if (c == 0.0) continue;
+    const int row = p * d_f + f;
+    if (r > 0) s = cfma(c * sr_lo, Yp[row * M + j], s);
+    if (r + 1 < d_r) s = cfma(-c * sr_hi, Yn[row * M + j], s);
+  }
+  z = make_double2(z.x - T.g * s.y, z.y + T.g * s.x);
+  // -J (a^ - a)(f^ - f), and d(t) i (f^ - f)
+  double2 u = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int df = -1; df <= 1; df += 2) {
+    const int ff = f + df;
+    if (ff < 0 || ff >= d_f) continue;
+    const double cf = (df < 0 ? 1.0 : -1.0) * sq[max(f, ff)];
+    if (r > 0) u = cfma(cf * sr_lo, Yp[(rl + df) * M + j], u);
+    if (r + 1 < d_r) u = cfma(-cf * sr_hi, Yn[(rl + df) * M + j], u);
+    v = cfma(cf, Yc[(rl + df) * M + j], v);
+  }
+  z = cfma(-T.G, u, z);
+  return make_double2(z.x - drv * v.y, z.y + drv * v.x);
+}
+
 // The kernel body: prologue (Gram terms and W of the initial state, no step)
 // or a chunk of nchunk RK4 steps from step0.  KP = entries of [G|C_1|C_2] per
 // thread (packed_kp).
-template <int KP, bool ROT>
+template <int KP, bool ROT, int MK = 0>
 __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int64_t step0, int64_t nchunk) {
   extern __shared__ double2 lds[];
   __shared__ double s_red[kTW / 64];
+  __shared__ double s_nt[kMaxDq * kMaxDq];
   __shared__ int s_flag;
   const int tid = threadIdx.x;
   const int M = T.M, MM = M * M, L = T.L, d_f = T.d_f, d_q = T.d_q, d_r = T.d_r;
@@ -252,9 +291,12 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
   g_double2* gW = (g_double2*)T.W;
 
   if (tid == 0) s_flag = *T.status;
+  if constexpr (MK == 1)
+    for (int i = tid; i < d_q * d_q; i += kTW) s_nt[i] = T.ntq[i];
   for (int rl = tid; rl < L; rl += kTW) {
     const int q = rl / d_f, f = rl - q * d_f;
-    hd[rl] = make_double2(T.w_q * q + 0.5 * T.alpha * q * (q - 1) + T.w_f * f, -0.5 * (T.kappa * f + T.gamma * q));
+    const double eq = MK == 1 ? T.Et[q] : T.w_q * q + 0.5 * T.alpha * q * (q - 1);
+    hd[rl] = make_double2(eq + T.w_f * f, -0.5 * (T.kappa * f + T.gamma * q));
     coef[rl] = 1.0;
     coef[L + rl] = (f + 1 < d_f) ? sk * sqrt((double)(f + 1)) : 0.0;
     coef[2 * L + rl] = (q + 1 < d_q) ? sg * sqrt((double)(q + 1)) : 0.0;
@@ -384,7 +426,11 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
               if (rl < L) {
                 const int q = rl / d_f, f = rl - q * d_f;
                 const double2 a = cfma(coef[L + rl], a1[k], cscale(coef[2 * L + rl], a2[k]));
-                const double2 z = packed_stencil<ROT>(T, Yp, Yc, Yn, sq, hd, r, rl, q, f, ej, drv, e1, e2);
+                double2 z;
+                if constexpr (MK == 1)
+                  z = packed_stencil_tm(T, Yp, Yc, Yn, sq, hd, s_nt, r, rl, q, f, ej, drv);
+                else
+                  z = packed_stencil<ROT>(T, Yp, Yc, Yn, sq, hd, r, rl, q, f, ej, drv, e1, e2);
                 const double2 kk = make_double2(z.y + 0.5 * a.x, -z.x + 0.5 * a.y);
                 const size_t gi = ((size_t)r * L + rl) * M + ej;
                 double2 o;
@@ -455,7 +501,9 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
 template <int KP>
 __global__ __launch_bounds__(kTW) void k_packed(const TrajDev* __restrict__ trajs, int64_t step0, int64_t nchunk) {
   const TrajDev& T = trajs[blockIdx.x];
-  if (T.frame)
+  if (T.mkind == 1)
+    packed_body<KP, false, 1>(T, 0, step0, nchunk);
+  else if (T.frame)
     packed_body<KP, true>(T, 0, step0, nchunk);
   else
     packed_body<KP, false>(T, 0, step0, nchunk);

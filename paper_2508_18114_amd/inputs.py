@@ -38,7 +38,7 @@ PULSE_FLATTOP = 0
 PULSE_PIECEWISE6 = 1
 PULSE_STEPWISE = 2   # smoothed stepwise complex envelope (supplement S2.C)
 MODEL_DUFFING, MODEL_TRANSMON = 0, 1
-MAX_DQ = 16
+MAX_DQ = 8
 PULSE_MAX_HEIGHTS = 63
 FRAME_LAB = 0        # B and <a>, <f> in the lab frame
 FRAME_DRIVE = 1      # frame rotating at the drive carrier w_d (counter-rotating terms kept)

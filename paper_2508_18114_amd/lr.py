@@ -61,11 +61,13 @@ class LrError(RuntimeError):
 
 class lr_model_t(ctypes.Structure):
     _fields_ = [("d_q", ctypes.c_int32), ("d_r", ctypes.c_int32), ("d_f", ctypes.c_int32),
-                ("reserved", ctypes.c_int32),
+                ("kind", ctypes.c_int32),
                 ("w_q", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("w_r", ctypes.c_double), ("w_f", ctypes.c_double),
                 ("g", ctypes.c_double), ("G", ctypes.c_double),
-                ("kappa_f", ctypes.c_double), ("gamma_1", ctypes.c_double)]
+                ("kappa_f", ctypes.c_double), ("gamma_1", ctypes.c_double),
+                ("E_t", ctypes.c_double * _inp.MAX_DQ),
+                ("n_t", ctypes.c_double * (_inp.MAX_DQ * _inp.MAX_DQ))]
 
 
 class lr_pulse_t(ctypes.Structure):
@@ -132,8 +134,16 @@ _lib = _load()
 
 
 def model_struct(m: _inp.ModelParams) -> lr_model_t:
-    return lr_model_t(m.d_q, m.d_r, m.d_f, 0, m.w_q, m.alpha, m.w_r, m.w_f,
-                      m.g, m.G, m.kappa_f, m.gamma_1)
+    s = lr_model_t(m.d_q, m.d_r, m.d_f, int(getattr(m, "kind", 0)), m.w_q, m.alpha, m.w_r, m.w_f,
+                   m.g, m.G, m.kappa_f, m.gamma_1)
+    if s.kind == _inp.MODEL_TRANSMON:
+        if m.d_q > _inp.MAX_DQ or len(m.E_t) != m.d_q or len(m.n_t) != m.d_q * m.d_q:
+            raise ValueError("transmon model: E_t needs d_q values and n_t d_q * d_q (d_q <= MAX_DQ)")
+        for k, x in enumerate(m.E_t):
+            s.E_t[k] = float(x)
+        for k, x in enumerate(m.n_t):
+            s.n_t[k] = float(x)
+    return s
 
 
 def pulse_struct(p: _inp.PulseParams) -> lr_pulse_t:

@@ -1072,3 +1072,53 @@ def test_spread_tile_height_and_autotuner(lr, tmp_path):
         assert np.array_equal(lr.from_device(a["B"]), lr.from_device(r["B"]))
     import json
     assert autotune.signature(items) in json.load(open(path))
+
+
+# ------------------------------------------------------------ the paper's Hamiltonian, transmon eigenbasis (kind 1)
+
+def _tm_items(lr, model, M, pulse, dt, nsteps, stride, which="e", seed=101, scale=1e-2):
+    import torch
+    B0 = I.initial_state(model, M, which, seed=seed, scale=scale)
+    return dict(model=model, M=M, pulse=pulse, dt=dt, nsteps=nsteps, B0=B0, B=lr.to_device(B0), obs_stride=stride,
+                obs=torch.zeros((nsteps // stride + 1, 6 + model.d_q), dtype=torch.float64, device="cuda"))
+
+
+def test_transmon_model_packed_matches_oracle(lr):
+    """The paper's Hamiltonian (transmon eigenbasis tables, dense n_t coupling, -J (a^ - a)(f^ - f),
+    drive on i (f^ - f)) in the packed kernel against the oracle: a small model with strong dissipation,
+    and the paper's parameters at N_t = 6 with a stepwise drive."""
+    from paper_2508_18114_amd import transmon
+    small = transmon.paper_model(4, 6, 4).replace(kappa_f=0.5, gamma_1=0.05, g=0.9, G=0.4)
+    paper = transmon.paper_model(6, 12, 5)
+    cases = [(small, 4, _stepwise(8, 102, T=0.3).replace(w_d=transmon.PAPER_W_DRIVE), 1e-3, 240, 40),
+             (paper, 8, I.stepwise_pulse(I.ghz(0.15) * np.array([1.0, 1.0j, 0.7]), 0.5, sigma=0.05,
+                                         w_d=transmon.PAPER_W_DRIVE), 5e-4, 600, 100)]
+    items = [_tm_items(lr, m, M, p, dt, n, s) for (m, M, p, dt, n, s) in cases]
+    rc, codes, _ = _run_packed(lr, items)
+    assert rc == lr.LR_OK, codes
+    for it in items:
+        Bo, ref = lowrank.integrate(it["model"], it["pulse"], 0.0, it["dt"], it["nsteps"], it["B0"],
+                                    obs_stride=it["obs_stride"])
+        _assert_obs(it["obs"].cpu().numpy(), ref, f"transmon model dims {it['model'].d_q, it['model'].d_r, it['model'].d_f}")
+        assert np.max(np.abs(lr.from_device(it["B"]) - Bo)) <= 1e-10
+
+
+def test_transmon_model_rejections(lr):
+    """Kind 1 runs packed in the lab frame with fixed steps only: a Context, a spread batch, the drive
+    frame, adaptive steps and a non-symmetric n_t are refused; d_q above the table size too."""
+    from paper_2508_18114_amd import transmon
+    m = transmon.paper_model(4, 3, 3)
+    p = I.flattop_pulse(0.05, 0.2)
+    with pytest.raises(lr.LrError):
+        lr.Context(m, 2)
+    for kw in (dict(), dict(packed=True, adaptive=(1e-8, 1e-10))):
+        with pytest.raises(lr.LrError):
+            lr.Batch([_tm_items(lr, m, 2, p, 1e-3, 10, 5)], **kw)
+    with pytest.raises(lr.LrError):
+        lr.Batch([_tm_items(lr, m, 2, p.replace(frame=1), 1e-3, 10, 5)], packed=True)
+    nt = list(m.n_t)
+    nt[1] += 0.5
+    with pytest.raises(lr.LrError):
+        lr.Batch([_tm_items(lr, m.replace(n_t=tuple(nt)), 2, p, 1e-3, 10, 5)], packed=True)
+    with pytest.raises(ValueError):
+        lr.model_struct(transmon.paper_model(9, 2, 2))

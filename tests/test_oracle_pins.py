@@ -662,3 +662,16 @@ def test_transmon_model_decoupled_phases():
     E = np.array([m.E_t[q] + m.w_r * r + m.w_f * f for q in range(3) for r in range(2) for f in range(2)])
     exact = np.exp(-1j * E * 0.4)[:, None] * B0
     assert np.max(np.abs(B - exact)) < 1e-7  # RK4 truncation at |E| dt <= 0.013
+
+
+def test_package_transmon_tables_match_the_oracle():
+    """The package's eigenbasis tables (model input for the device) equal the oracle's pinned
+    construction: levels, and the charge operator up to the sign convention shared by both."""
+    from paper_2508_18114_amd import transmon
+    Ec = I.ghz(0.315)
+    lv, nt = transmon.eigenbasis(Ec, 51 * Ec, 6)
+    w, nto = papermodel.transmon_levels(Ec, 51 * Ec, 6)
+    np.testing.assert_allclose(lv, w - w[0], atol=1e-9)
+    np.testing.assert_allclose(nt, nto, atol=1e-10)
+    m = transmon.paper_model(6, 4, 3)
+    assert m.kind == I.MODEL_TRANSMON and len(m.n_t) == 36 and m.E_t[0] == 0.0
