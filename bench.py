@@ -175,6 +175,32 @@ def comparisons(lr, I, torch, stream, plain_value):
                                   "speedup": gt["eager"] / gt["graph"],
                                   "workload": f"{len(gitems)} packed trajectories, N=2000, M=20, {gsteps} steps, "
                                               f"records every {gstride} steps ({gsteps // gstride} chunks)"}
+    # the paper's Hamiltonian (transmon eigenbasis, N_t = 6 levels; bare resonator 60 x filter 10,
+    # N = 3600), 256 seeded stepwise pulses x g/e in the packed schedule
+    from paper_2508_18114_amd import transmon
+    pm = transmon.paper_model(6, 60, 10)
+    rng = np.random.default_rng(11)
+    pitems = []
+    for k in range(256):
+        hts = I.ghz(0.15) * rng.uniform(0.3, 1.0, 4) * np.exp(1j * rng.uniform(0, 2 * np.pi, 4))
+        pp = I.stepwise_pulse(hts, 40.0, w_d=transmon.PAPER_W_DRIVE)
+        for which in ("g", "e"):
+            pitems.append(dict(model=pm, M=20, pulse=pp, dt=5e-4, nsteps=100,
+                               B=lr.to_device(I.initial_state(pm, 20, which, 12 + k, I.PAPER_PAD_SCALE))))
+    pb = lr.Batch(pitems, stream=stream, packed=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pb.run()
+    torch.cuda.synchronize()
+    pel = time.perf_counter() - t0
+    if pb.status()[0] != lr.LR_OK:
+        raise RuntimeError("paper model batch failed")
+    pb.close()
+    del pitems
+    out["paper_model_packed"] = {"value": 512 * 100 / pel, "unit": "RK steps*trajectories/s",
+                                 "workload": "the paper's Hamiltonian (transmon eigenbasis N_t=6, resonator 60, "
+                                             "filter 10: N=3600), M=20, 256 stepwise pulses x g/e, 100 steps "
+                                             f"each, packed schedule ({pel:.2f} s)"}
     # batched mixed shapes: the 512 trajectories of the batched configuration, capped step count
     steps = 150
     c4 = I.config_batched()
