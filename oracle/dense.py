@@ -64,8 +64,11 @@ def hamiltonian_drive_frame(model, d_t, w_d, t):
     """Dense H'(t) in the frame rotating at w_d: U H U^ - w_d (n_q + n_r + n_f)
     with U = exp(i w_d t (n_q + n_r + n_f)), built from the phased ladder
     operators b e^{-i w_d t}, a e^{-i w_d t}, f e^{-i w_d t} (all terms kept)."""
-    if getattr(model, "kind", 0) == 1:
-        raise NotImplementedError("the drive frame is built for the Duffing model only")
+    if getattr(model, "kind", 0) == 1:  # U H U^ - w_d n, n = q + n_r + n_f, from the lab-frame matrix
+        n = np.array([q + r + f for q in range(model.d_q) for r in range(model.d_r) for f in range(model.d_f)],
+                     dtype=np.float64)
+        u = np.exp(1j * w_d * t * n)
+        return (u[:, None] * hamiltonian(model, d_t) * np.conj(u)[None, :]) - w_d * np.diag(n)
     b, a, f = operators(model)
     ph = np.exp(-1j * w_d * t)
     bt, at, ft = b * ph, a * ph, f * ph

@@ -134,7 +134,7 @@ def apply_heff_drive_frame(model, d_t, w_d, t, B):
     which leaves the dissipator unchanged, so H_eff = H' - i/2 (kappa_f n_f +
     gamma_1 n_q) as in the lab frame."""
     if getattr(model, "kind", 0) == 1:
-        raise NotImplementedError("the drive frame is built for the Duffing model only")
+        return _apply_heff_drive_frame_transmon(model, d_t, w_d, t, B)
     T = _as_tensor(model, B)
     m2 = model.replace(w_q=model.w_q - w_d, w_r=model.w_r - w_d, w_f=model.w_f - w_d)
     e1 = np.exp(1j * w_d * t)
@@ -145,6 +145,32 @@ def apply_heff_drive_frame(model, d_t, w_d, t, B):
     Z = Z + model.G * (raise_(lower(T, 2), 1) + lower(raise_(T, 2), 1)
                        + e2 * raise_(raise_(T, 2), 1) + np.conj(e2) * lower(lower(T, 2), 1))
     Z = Z + d_t * (e1 * raise_(T, 2) + np.conj(e1) * lower(T, 2))
+    return Z.reshape(B.shape)
+
+
+def _apply_heff_drive_frame_transmon(model, d_t, w_d, t, B):
+    """Kind 1 in the frame U = exp(i w_d t (q + n_r + n_f)), q the transmon
+    level index: every term X that changes the excitation count by D becomes
+    e^{i w_d t D} X, and the diagonal loses w_d (q + r + f).  The levels are
+    E_q - w_d q; i g n_t[q'][q] a^ gains e^{i w_d t (q' - q + 1)} and the a part
+    e^{i w_d t (q' - q - 1)}; -J (a^ - a)(f^ - f) has D = 2 (a^ f^), 0, 0, -2
+    (a f); the drive i (f^ - f) has D = +1, -1.  Nothing is dropped."""
+    T = _as_tensor(model, B)
+    dq = model.d_q
+    m2 = model.replace(E_t=tuple(np.asarray(model.E_t) - w_d * np.arange(dq)), w_r=model.w_r - w_d,
+                       w_f=model.w_f - w_d)
+    Z = diag_heff(m2)[..., None] * T
+    nt = np.asarray(model.n_t, dtype=np.float64).reshape(dq, dq)
+    qd = np.arange(dq)[:, None] - np.arange(dq)[None, :]          # q' - q (row q', column q)
+    up = nt * np.exp(1j * w_d * t * (qd + 1))
+    dn = nt * np.exp(1j * w_d * t * (qd - 1))
+    Z = Z + 1j * model.g * (np.einsum("qp,prfj->qrfj", up, raise_(T, 1))
+                            - np.einsum("qp,prfj->qrfj", dn, lower(T, 1)))
+    e1 = np.exp(1j * w_d * t)
+    e2 = e1 * e1
+    Z = Z - model.G * (e2 * raise_(raise_(T, 2), 1) - raise_(lower(T, 2), 1)
+                       - lower(raise_(T, 2), 1) + np.conj(e2) * lower(lower(T, 2), 1))
+    Z = Z + d_t * 1j * (e1 * raise_(T, 2) - np.conj(e1) * lower(T, 2))
     return Z.reshape(B.shape)
 
 

@@ -675,3 +675,22 @@ def test_package_transmon_tables_match_the_oracle():
     np.testing.assert_allclose(nt, nto, atol=1e-10)
     m = transmon.paper_model(6, 4, 3)
     assert m.kind == I.MODEL_TRANSMON and len(m.n_t) == 36 and m.E_t[0] == 0.0
+
+
+def test_transmon_model_drive_frame_is_the_transformed_lab_rhs():
+    """Kind 1, frame U = exp(i w_d t (q + n_r + n_f)): the low-rank equation of motion at B' = U B equals
+    i w_d n B' + U dB/dt (exact, any t), and at full rank it reproduces the dense rotating-frame
+    Lindbladian (built by rotating the lab matrix numerically)."""
+    m = _transmon_model(3, 3, 3)
+    B = _rand_B(m.N, 3, 61)
+    for t in (0.0, 1.37, 4.2):
+        u, n = _frame_phase(m, PULSE.w_d, t)
+        lhs = lowrank.rhs(m, ROT, t, u[:, None] * B)
+        ref = 1j * PULSE.w_d * (n * u)[:, None] * B + u[:, None] * lowrank.rhs(m, PULSE, t, B)
+        assert np.max(np.abs(lhs - ref)) <= 1e-11 * np.max(np.abs(ref))
+    mf = _transmon_model(2, 3, 2)
+    Bf = _rand_B(mf.N, mf.N, 62)
+    dB = lowrank.rhs(mf, ROT, 3.1, Bf)
+    lhs = Bf @ dB.conj().T + dB @ Bf.conj().T
+    ref = dense.lindbladian(mf, ROT, 3.1, Bf @ Bf.conj().T)
+    assert np.max(np.abs(lhs - ref)) <= 1e-10 * np.max(np.abs(ref))
