@@ -204,8 +204,8 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
         delete b;
         return LR_ERR_ARG;
       }
-  for (int k = 0; k < n; ++k)  // the eigenbasis model runs packed, in the lab frame
-    if (b->tr[k].model.kind == LR_MODEL_TRANSMON && (!b->packed[k] || b->tr[k].pulse.frame != LR_FRAME_LAB)) {
+  for (int k = 0; k < n; ++k)  // the eigenbasis model runs packed
+    if (b->tr[k].model.kind == LR_MODEL_TRANSMON && !b->packed[k]) {
       delete b;
       return LR_ERR_ARG;
     }

@@ -223,27 +223,37 @@ __device__ __forceinline__ double2 packed_stencil(const TrajDev& T, const double
   return z;
 }
 
-// Element (rl, j) of layer r for the transmon-eigenbasis model (lab frame):
+// Element (rl, j) of layer r for the transmon-eigenbasis model:
 // z = H Y with H = diag(E_q + w_r r + w_f f) - i/2 (jumps) + i g n_t (a^ - a)
 // - J (a^ - a)(f^ - f) + d(t) i (f^ - f), J held in T.G.  (a^ Y)[r] = sqrt(r)
 // Y[r-1], (a Y)[r] = sqrt(r+1) Y[r+1]; n_t couples the transmon levels densely
-// (row q of nt, from LDS).
+// (row q of nt, from LDS).  ROT: the frame rotating at w_d (levels and mode
+// frequencies already reduced by w_d in hd and T); a tap from a neighbour with
+// dn more excitations (level index + n_r + n_f) carries e^{-i w_d t dn}, read
+// as the conjugate of ph[dn + ph0] = e^{i w_d t dn}.
+template <bool ROT>
 __device__ __forceinline__ double2 packed_stencil_tm(const TrajDev& T, const double2* Yp, const double2* Yc,
                                                      const double2* Yn, const double* sq, const double2* hd,
-                                                     const double* nt, int r, int rl, int q, int f, int j,
-                                                     double drv) {
+                                                     const double* nt, const double2* ph, int ph0, int r, int rl,
+                                                     int q, int f, int j, double drv) {
   const int M = T.M, d_f = T.d_f, d_q = T.d_q, d_r = T.d_r;
   const double2 h = hd[rl];
   double2 z = cmul(make_double2(h.x + T.w_r * r, h.y), Yc[rl * M + j]);
   const double sr_lo = sq[r], sr_hi = sq[min(r + 1, d_r)];
+  // c nb, phased by e^{-i w_d t dn} in the rotating frame
+  auto tap = [&](double2 acc, double c, int dn, double2 nb) {
+    if (!ROT || dn == 0) return cfma(c, nb, acc);
+    const double2 e = ph[dn + ph0];
+    return cadd(acc, cmul(make_double2(c * e.x, -c * e.y), nb));
+  };
   // i g n_t (a^ - a)
   double2 s = make_double2(0.0, 0.0);
   for (int p = 0; p < d_q; ++p) {
     const double c = nt[q * d_q + p];
     if (c == 0.0) continue;
     const int row = p * d_f + f;
-    if (r > 0) s = cfma(c * sr_lo, Yp[row * M + j], s);
-    if (r + 1 < d_r) s = cfma(-c * sr_hi, Yn[row * M + j], s);
+    if (r > 0) s = tap(s, c * sr_lo, p - q - 1, Yp[row * M + j]);
+    if (r + 1 < d_r) s = tap(s, -c * sr_hi, p - q + 1, Yn[row * M + j]);
   }
   z = make_double2(z.x - T.g * s.y, z.y + T.g * s.x);
   // -J (a^ - a)(f^ - f), and d(t) i (f^ - f)
@@ -253,9 +263,9 @@ __device__ __forceinline__ double2 packed_stencil_tm(const TrajDev& T, const dou
     const int ff = f + df;
     if (ff < 0 || ff >= d_f) continue;
     const double cf = (df < 0 ? 1.0 : -1.0) * sq[max(f, ff)];
-    if (r > 0) u = cfma(cf * sr_lo, Yp[(rl + df) * M + j], u);
-    if (r + 1 < d_r) u = cfma(-cf * sr_hi, Yn[(rl + df) * M + j], u);
-    v = cfma(cf, Yc[(rl + df) * M + j], v);
+    if (r > 0) u = tap(u, cf * sr_lo, df - 1, Yp[(rl + df) * M + j]);
+    if (r + 1 < d_r) u = tap(u, -cf * sr_hi, df + 1, Yn[(rl + df) * M + j]);
+    v = tap(v, cf, df, Yc[(rl + df) * M + j]);
   }
   z = cfma(-T.G, u, z);
   return make_double2(z.x - drv * v.y, z.y + drv * v.x);
@@ -269,6 +279,7 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
   extern __shared__ double2 lds[];
   __shared__ double s_red[kTW / 64];
   __shared__ double s_nt[kMaxDq * kMaxDq];
+  __shared__ double2 s_ph[2 * kMaxDq + 3];  // e^{i w_d t m}, m = -(d_q + 1) .. d_q + 1, of the stage (kind 1, rotating frame)
   __shared__ int s_flag;
   const int tid = threadIdx.x;
   const int M = T.M, MM = M * M, L = T.L, d_f = T.d_f, d_q = T.d_q, d_r = T.d_r;
@@ -295,7 +306,7 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
     for (int i = tid; i < d_q * d_q; i += kTW) s_nt[i] = T.ntq[i];
   for (int rl = tid; rl < L; rl += kTW) {
     const int q = rl / d_f, f = rl - q * d_f;
-    const double eq = MK == 1 ? T.Et[q] : T.w_q * q + 0.5 * T.alpha * q * (q - 1);
+    const double eq = MK == 1 ? T.Et[q] - (ROT ? T.w_d * q : 0.0) : T.w_q * q + 0.5 * T.alpha * q * (q - 1);
     hd[rl] = make_double2(eq + T.w_f * f, -0.5 * (T.kappa * f + T.gamma * q));
     coef[rl] = 1.0;
     coef[L + rl] = (f + 1 < d_f) ? sk * sqrt((double)(f + 1)) : 0.0;
@@ -380,6 +391,8 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
       const double2 e1 = make_double2(s_dtab[ds][1], s_dtab[ds][2]), e2 = make_double2(s_dtab[ds][3], s_dtab[ds][4]);
 #pragma unroll
       for (int k = 0; k < KP; ++k) acc[k] = make_double2(0.0, 0.0);
+      if constexpr (MK == 1 && ROT)
+        if (tid < 2 * d_q + 3) s_ph[tid] = frame_phase((tid - d_q - 1) * T.w_d, stage_time(step, s));
       __syncthreads();  // Wl of this stage written; tiles free
       Yp = lds;
       Yc = lds + LM;
@@ -428,7 +441,7 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
                 const double2 a = cfma(coef[L + rl], a1[k], cscale(coef[2 * L + rl], a2[k]));
                 double2 z;
                 if constexpr (MK == 1)
-                  z = packed_stencil_tm(T, Yp, Yc, Yn, sq, hd, s_nt, r, rl, q, f, ej, drv);
+                  z = packed_stencil_tm<ROT>(T, Yp, Yc, Yn, sq, hd, s_nt, s_ph, d_q + 1, r, rl, q, f, ej, drv);
                 else
                   z = packed_stencil<ROT>(T, Yp, Yc, Yn, sq, hd, r, rl, q, f, ej, drv, e1, e2);
                 const double2 kk = make_double2(z.y + 0.5 * a.x, -z.x + 0.5 * a.y);
@@ -501,9 +514,12 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
 template <int KP>
 __global__ __launch_bounds__(kTW) void k_packed(const TrajDev* __restrict__ trajs, int64_t step0, int64_t nchunk) {
   const TrajDev& T = trajs[blockIdx.x];
-  if (T.mkind == 1)
-    packed_body<KP, false, 1>(T, 0, step0, nchunk);
-  else if (T.frame)
+  if (T.mkind == 1) {
+    if (T.frame)
+      packed_body<KP, true, 1>(T, 0, step0, nchunk);
+    else
+      packed_body<KP, false, 1>(T, 0, step0, nchunk);
+  } else if (T.frame)
     packed_body<KP, true>(T, 0, step0, nchunk);
   else
     packed_body<KP, false>(T, 0, step0, nchunk);

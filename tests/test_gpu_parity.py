@@ -1092,20 +1092,25 @@ def test_transmon_model_packed_matches_oracle(lr):
     paper = transmon.paper_model(6, 12, 5)
     cases = [(small, 4, _stepwise(8, 102, T=0.3).replace(w_d=transmon.PAPER_W_DRIVE), 1e-3, 240, 40),
              (paper, 8, I.stepwise_pulse(I.ghz(0.15) * np.array([1.0, 1.0j, 0.7]), 0.5, sigma=0.05,
-                                         w_d=transmon.PAPER_W_DRIVE), 5e-4, 600, 100)]
+                                         w_d=transmon.PAPER_W_DRIVE), 5e-4, 600, 100),
+             # the frame rotating at the drive carrier, every term kept
+             (small, 4, _stepwise(8, 103, T=0.3).replace(w_d=transmon.PAPER_W_DRIVE, frame=1), 1e-3, 240, 40),
+             (paper, 8, I.stepwise_pulse(I.ghz(0.15) * np.array([1.0, 1.0j, 0.7]), 0.5, sigma=0.05,
+                                         w_d=transmon.PAPER_W_DRIVE).replace(frame=1), 5e-4, 600, 100)]
     items = [_tm_items(lr, m, M, p, dt, n, s) for (m, M, p, dt, n, s) in cases]
     rc, codes, _ = _run_packed(lr, items)
     assert rc == lr.LR_OK, codes
     for it in items:
         Bo, ref = lowrank.integrate(it["model"], it["pulse"], 0.0, it["dt"], it["nsteps"], it["B0"],
                                     obs_stride=it["obs_stride"])
-        _assert_obs(it["obs"].cpu().numpy(), ref, f"transmon model dims {it['model'].d_q, it['model'].d_r, it['model'].d_f}")
+        _assert_obs(it["obs"].cpu().numpy(), ref,
+                    f"transmon model dims {it['model'].d_q, it['model'].d_r, it['model'].d_f} frame {it['pulse'].frame}")
         assert np.max(np.abs(lr.from_device(it["B"]) - Bo)) <= 1e-10
 
 
 def test_transmon_model_rejections(lr):
-    """Kind 1 runs packed in the lab frame with fixed steps only: a Context, a spread batch, the drive
-    frame, adaptive steps and a non-symmetric n_t are refused; d_q above the table size too."""
+    """Kind 1 runs packed with fixed steps only: a Context, a spread batch, adaptive steps and a
+    non-symmetric n_t are refused; d_q above the table size too."""
     from paper_2508_18114_amd import transmon
     m = transmon.paper_model(4, 3, 3)
     p = I.flattop_pulse(0.05, 0.2)
@@ -1114,8 +1119,6 @@ def test_transmon_model_rejections(lr):
     for kw in (dict(), dict(packed=True, adaptive=(1e-8, 1e-10))):
         with pytest.raises(lr.LrError):
             lr.Batch([_tm_items(lr, m, 2, p, 1e-3, 10, 5)], **kw)
-    with pytest.raises(lr.LrError):
-        lr.Batch([_tm_items(lr, m, 2, p.replace(frame=1), 1e-3, 10, 5)], packed=True)
     nt = list(m.n_t)
     nt[1] += 0.5
     with pytest.raises(lr.LrError):
