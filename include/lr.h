@@ -56,7 +56,8 @@ typedef struct { double re, im; } lr_c64;
  *   d(t) i (f^ - f); w_q and alpha unused; d_q <= LR_MAX_DQ.  In the drive
  *   frame the rotation counts the transmon level index as its excitation
  *   number (levels E_q - w_d q), every term kept.  This kind runs in the
- *   packed batch schedule only, with fixed RK4 steps (LR_ERR_ARG elsewhere).
+ *   packed batch schedule only (fixed RK4 or adaptive steps; LR_ERR_ARG
+ *   elsewhere).
  * Both kinds: L_1 = sqrt(kappa_f) f, L_2 = sqrt(gamma_1) b, b the ladder
  * sum_n sqrt(n) |n-1><n| of the transmon levels. */
 #define LR_MODEL_DUFFING 0

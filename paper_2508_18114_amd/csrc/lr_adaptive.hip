@@ -61,12 +61,14 @@ __global__ void k_dp5_reset(const TrajDev* __restrict__ trajs, const AdaptDev* _
   }
 }
 
-template <int KP, bool ROT>
+template <int KP, bool ROT, int MK = 0>
 __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, int prologue, int64_t step0,
                                          int64_t nchunk) {
   extern __shared__ double2 lds[];
   __shared__ double s_red[kTW / 64];
   __shared__ int s_flag;
+  __shared__ double s_nt[kMaxDq * kMaxDq];
+  __shared__ double2 s_ph[2 * kMaxDq + 3];
   const int tid = threadIdx.x;
   const int M = T.M, MM = M * M, L = T.L, d_f = T.d_f, d_q = T.d_q, d_r = T.d_r;
   const int LM = L * M, C3 = 3 * M;
@@ -85,12 +87,15 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
   if (tid == 0) s_flag = *T.status;
   for (int rl = tid; rl < L; rl += kTW) {
     const int q = rl / d_f, f = rl - q * d_f;
-    hd[rl] = make_double2(T.w_q * q + 0.5 * T.alpha * q * (q - 1) + T.w_f * f, -0.5 * (T.kappa * f + T.gamma * q));
+    const double eq = MK == 1 ? T.Et[q] - (ROT ? T.w_d * q : 0.0) : T.w_q * q + 0.5 * T.alpha * q * (q - 1);
+    hd[rl] = make_double2(eq + T.w_f * f, -0.5 * (T.kappa * f + T.gamma * q));
     coef[rl] = 1.0;
     coef[L + rl] = (f + 1 < d_f) ? sk * sqrt((double)(f + 1)) : 0.0;
     coef[2 * L + rl] = (q + 1 < d_q) ? sg * sqrt((double)(q + 1)) : 0.0;
   }
   for (int k = tid; k <= max(max(d_q, d_r), d_f); k += kTW) sq[k] = sqrt((double)k);
+  if constexpr (MK == 1)
+    for (int i = tid; i < d_q * d_q; i += kTW) s_nt[i] = T.ntq[i];
   __syncthreads();
   if (s_flag != 0) return;
   if (!prologue && step0 >= T.nsteps) return;
@@ -164,6 +169,8 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
       s_drv[3] = p2.x;
       s_drv[4] = p2.y;
     }
+    if constexpr (MK == 1 && ROT)
+      if (tid < 2 * d_q + 3) s_ph[tid] = frame_phase((tid - d_q - 1) * T.w_d, ts);
     double2* Yp = lds;
     double2* Yc = lds + LM;
     double2* Yn = lds + 2 * LM;
@@ -202,7 +209,11 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
             if (rl < L) {
               const int q = rl / d_f, f = rl - q * d_f;
               const double2 a = cfma(coef[L + rl], a1[k], cscale(coef[2 * L + rl], a2[k]));
-              const double2 z = packed_stencil<ROT>(T, Yp, Yc, Yn, sq, hd, r, rl, q, f, ej, drv, e1, e2);
+              double2 z;
+              if constexpr (MK == 1)
+                z = packed_stencil_tm<ROT>(T, Yp, Yc, Yn, sq, hd, s_nt, s_ph, d_q + 1, r, rl, q, f, ej, drv);
+              else
+                z = packed_stencil<ROT>(T, Yp, Yc, Yn, sq, hd, r, rl, q, f, ej, drv, e1, e2);
               const double2 kk = make_double2(z.y + 0.5 * a.x, -z.x + 0.5 * a.y);
               const size_t gi = ((size_t)r * L + rl) * M + ej;
               st_g(kout + gi, kk);
@@ -332,10 +343,16 @@ template <int KP>
 __global__ __launch_bounds__(kTW) void k_dp5(const TrajDev* __restrict__ trajs, const AdaptDev* __restrict__ ads,
                                              int64_t step0, int64_t nchunk) {
   const TrajDev& T = trajs[blockIdx.x];
-  if (T.frame)
+  if (T.mkind == 1) {
+    if (T.frame)
+      dp5_body<KP, true, 1>(T, ads[blockIdx.x], 0, step0, nchunk);
+    else
+      dp5_body<KP, false, 1>(T, ads[blockIdx.x], 0, step0, nchunk);
+  } else if (T.frame) {
     dp5_body<KP, true>(T, ads[blockIdx.x], 0, step0, nchunk);
-  else
+  } else {
     dp5_body<KP, false>(T, ads[blockIdx.x], 0, step0, nchunk);
+  }
 }
 template <int KP>
 __global__ __launch_bounds__(kTW) void k_dp5_prologue(const TrajDev* __restrict__ trajs,

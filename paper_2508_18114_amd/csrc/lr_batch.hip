@@ -198,9 +198,9 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
   b->region.resize(n);
   b->region_bytes.resize(n);
   b->wg_offset.resize(n);
-  if (adaptive)  // every trajectory must take the packed kernel (Duffing model)
+  if (adaptive)  // every trajectory must take the packed kernel
     for (int k = 0; k < n; ++k)
-      if (!b->packed[k] || b->tr[k].model.kind != LR_MODEL_DUFFING) {
+      if (!b->packed[k]) {
         delete b;
         return LR_ERR_ARG;
       }

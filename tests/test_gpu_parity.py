@@ -1109,19 +1109,38 @@ def test_transmon_model_packed_matches_oracle(lr):
 
 
 def test_transmon_model_rejections(lr):
-    """Kind 1 runs packed with fixed steps only: a Context, a spread batch, adaptive steps and a
-    non-symmetric n_t are refused; d_q above the table size too."""
+    """Kind 1 runs packed only: a Context, a spread batch and a non-symmetric n_t are refused; d_q
+    above the table size too."""
     from paper_2508_18114_amd import transmon
     m = transmon.paper_model(4, 3, 3)
     p = I.flattop_pulse(0.05, 0.2)
     with pytest.raises(lr.LrError):
         lr.Context(m, 2)
-    for kw in (dict(), dict(packed=True, adaptive=(1e-8, 1e-10))):
-        with pytest.raises(lr.LrError):
-            lr.Batch([_tm_items(lr, m, 2, p, 1e-3, 10, 5)], **kw)
+    with pytest.raises(lr.LrError):
+        lr.Batch([_tm_items(lr, m, 2, p, 1e-3, 10, 5)])
     nt = list(m.n_t)
     nt[1] += 0.5
     with pytest.raises(lr.LrError):
         lr.Batch([_tm_items(lr, m.replace(n_t=tuple(nt)), 2, p, 1e-3, 10, 5)], packed=True)
     with pytest.raises(ValueError):
         lr.model_struct(transmon.paper_model(9, 2, 2))
+
+
+def test_transmon_model_adaptive_matches_oracle(lr):
+    """The paper's set-up: its Hamiltonian (transmon eigenbasis) in the drive frame, adaptive
+    Dormand-Prince steps, against the oracle's adaptive integration (same step counts, records)."""
+    from oracle import adaptive
+    from paper_2508_18114_amd import transmon
+    m = transmon.paper_model(4, 8, 4).replace(kappa_f=0.3, gamma_1=0.02)
+    p = I.stepwise_pulse(I.ghz(0.15) * np.array([1.0j, 0.8j]), 1.0, sigma=0.1,
+                         w_d=transmon.PAPER_W_DRIVE).replace(frame=1)
+    it = _tm_items(lr, m, 4, p, 0.1, 10, 2)
+    b = lr.Batch([it], adaptive=(1e-9, 1e-12))
+    b.run()
+    rc, codes, _ = b.status()
+    assert rc == lr.LR_OK, codes
+    acc, rej = b.adaptive_stats()
+    _, ref, acc_o, rej_o = adaptive.integrate(m, p, 0.0, 0.1, 10, it["B0"], 1e-9, 1e-12, obs_stride=2)
+    print(f"[parity] transmon model adaptive drive frame: steps gpu {acc[0]}+{rej[0]}, oracle {acc_o}+{rej_o}")
+    _assert_obs(it["obs"].cpu().numpy(), ref, "transmon model adaptive")
+    assert abs(acc[0] - acc_o) <= 3 and abs(rej[0] - rej_o) <= 3
