@@ -302,10 +302,15 @@ def project_heights(theta: np.ndarray, bound: float = I.ghz(0.4) * (1.0 - 1e-9))
 
 
 def pulse_loss_batch(model: I.ModelParams, M: int, pulses, dt: float, nsteps: int, obs_stride: int,
-                     pad_scale: float = I.PAPER_PAD_SCALE, seed: int = 0, stream=None):
+                     pad_scale: float = I.PAPER_PAD_SCALE, seed: int = 0, stream=None, packed=None,
+                     adaptive=None):
     """Readout loss Lambda (and its figures of merit) of each pulse: the g and e
     trajectories of every pulse integrated together in one batch, the loss of
-    each g/e pair formed on the device."""
+    each g/e pair formed on the device.  packed: the packed schedule (default:
+    on for the transmon-eigenbasis model, which runs only there); adaptive:
+    (rtol, atol) for adaptive steps, dt then being the output grid."""
+    if packed is None:
+        packed = getattr(model, "kind", 0) == I.MODEL_TRANSMON
     import torch
     items = []
     nrec = nsteps // obs_stride + 1
@@ -315,7 +320,7 @@ def pulse_loss_batch(model: I.ModelParams, M: int, pulses, dt: float, nsteps: in
             items.append(dict(model=model, M=M, pulse=p, dt=dt, nsteps=nsteps, B=lr.to_device(B0),
                               obs_stride=obs_stride,
                               obs=torch.zeros((nrec, 6 + model.d_q), dtype=torch.float64, device="cuda")))
-    b = lr.Batch(items, stream=stream)
+    b = lr.Batch(items, stream=stream, packed=packed, adaptive=adaptive)
     b.run()
     rc, codes, steps = b.status()
     if rc != lr.LR_OK:
@@ -330,7 +335,7 @@ def pulse_loss_batch(model: I.ModelParams, M: int, pulses, dt: float, nsteps: in
 
 def spsa_optimize(model: I.ModelParams, M: int, T: float, nh: int, iters: int, dt: float, obs_stride: int,
                   seed: int = 1, a: float = 0.05, c: float = 0.05, sigma: float = 0.5,
-                  frame: int = I.FRAME_DRIVE, stream=None):
+                  frame: int = I.FRAME_DRIVE, stream=None, w_d: float = I.W_DRIVE, adaptive=None):
     """The optimisation loop of supplement S3.C on the device: SPSA over the nh
     complex heights of the smoothed stepwise pulse, started from the square shape
     (all heights real, 2 pi 150 MHz), each step evaluating theta +- c_k Delta in
@@ -342,8 +347,9 @@ def spsa_optimize(model: I.ModelParams, M: int, T: float, nh: int, iters: int, d
     hist = []
     for _ in range(iters):
         tp, tm = opt.ask()
-        pulses = [I.stepwise_pulse(heights_from(x), T, sigma=sigma).replace(frame=frame) for x in (tp, tm)]
-        fp, fm = pulse_loss_batch(model, M, pulses, dt, int(round(T / dt)), obs_stride, stream=stream)
+        pulses = [I.stepwise_pulse(heights_from(x), T, sigma=sigma, w_d=w_d).replace(frame=frame) for x in (tp, tm)]
+        fp, fm = pulse_loss_batch(model, M, pulses, dt, int(round(T / dt)), obs_stride, stream=stream,
+                                  adaptive=adaptive)
         opt.tell(fp["loss"], fm["loss"])
         hist.append({"k": opt.k, "loss_plus": fp["loss"], "loss_minus": fm["loss"],
                      "eps_a_plus": fp["eps_a"], "eps_a_minus": fm["eps_a"]})

@@ -1144,3 +1144,14 @@ def test_transmon_model_adaptive_matches_oracle(lr):
     print(f"[parity] transmon model adaptive drive frame: steps gpu {acc[0]}+{rej[0]}, oracle {acc_o}+{rej_o}")
     _assert_obs(it["obs"].cpu().numpy(), ref, "transmon model adaptive")
     assert abs(acc[0] - acc_o) <= 3 and abs(rej[0] - rej_o) <= 3
+
+
+def test_spsa_on_the_paper_model_with_adaptive_steps(lr):
+    """Two SPSA steps over the paper's Hamiltonian (transmon eigenbasis, drive frame, adaptive steps):
+    finite losses, heights inside the bound."""
+    from paper_2508_18114_amd import serve, transmon
+    m = transmon.paper_model(4, 6, 4).replace(kappa_f=0.3, gamma_1=0.02)
+    theta, hist = serve.spsa_optimize(m, 4, T=0.4, nh=3, iters=2, dt=0.1, obs_stride=1, seed=5,
+                                      w_d=transmon.PAPER_W_DRIVE, adaptive=(1e-8, 1e-11))
+    assert len(hist) == 2 and all(np.isfinite(h["loss_plus"]) and np.isfinite(h["loss_minus"]) for h in hist)
+    assert np.all(np.abs(serve.heights_from(theta)) < I.ghz(0.4))
