@@ -431,7 +431,7 @@ def test_reduced_precision_errors(lr, precision):
 
 
 def test_reduced_precision_needs_padding_above_rounding(lr):
-    """With the 1e-6 padding of the benchmark configuration, FP32 products leave G indefinite within a
+    """With the 1e-6 padding of the paper-size workload, FP32 products leave G indefinite within a
     few thousand steps: the integrator stops with GRAM_NOT_PD and its step (no silent garbage)."""
     import torch
     trajs = I.config_paper_size()
