@@ -1155,3 +1155,27 @@ def test_spsa_on_the_paper_model_with_adaptive_steps(lr):
                                       w_d=transmon.PAPER_W_DRIVE, adaptive=(1e-8, 1e-11))
     assert len(hist) == 2 and all(np.isfinite(h["loss_plus"]) and np.isfinite(h["loss_minus"]) for h in hist)
     assert np.all(np.abs(serve.heights_from(theta)) < I.ghz(0.4))
+
+
+@pytest.mark.parametrize("d_r,M,frame", [(1, 1, 0), (2, 3, 1), (3, 8, 1)])
+def test_transmon_model_few_layers(lr, d_r, M, frame):
+    """The eigenbasis model with one to three resonator layers and rank 1, both frames, fixed and
+    adaptive steps, against the oracle."""
+    from oracle import adaptive
+    from paper_2508_18114_amd import transmon
+    m = transmon.paper_model(3, d_r, 4).replace(kappa_f=0.4, gamma_1=0.05)
+    p = I.stepwise_pulse(I.ghz(0.15) * np.array([1.0j, 0.5]), 0.3, sigma=0.03,
+                         w_d=transmon.PAPER_W_DRIVE).replace(frame=frame)
+    it = _tm_items(lr, m, M, p, 2e-4 if frame == 0 else 1e-3, 300 if frame == 0 else 300, 60,
+                   seed=110 + d_r)
+    assert _run_packed(lr, [it])[0] == lr.LR_OK
+    _, ref = lowrank.integrate(m, p, 0.0, it["dt"], it["nsteps"], it["B0"], obs_stride=60)
+    _assert_obs(it["obs"].cpu().numpy(), ref, f"transmon d_r={d_r} M={M} frame={frame}")
+    ia = _tm_items(lr, m, M, p, 0.05, 4, 2, seed=110 + d_r)
+    b = lr.Batch([ia], adaptive=(1e-9, 1e-12))
+    b.run()
+    assert b.status()[0] == lr.LR_OK
+    acc, rej = b.adaptive_stats()
+    _, refa, acc_o, rej_o = adaptive.integrate(m, p, 0.0, 0.05, 4, ia["B0"], 1e-9, 1e-12, obs_stride=2)
+    _assert_obs(ia["obs"].cpu().numpy(), refa, f"transmon adaptive d_r={d_r} M={M} frame={frame}")
+    assert abs(acc[0] - acc_o) <= 3 and abs(rej[0] - rej_o) <= 3
