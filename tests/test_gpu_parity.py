@@ -322,6 +322,29 @@ def test_batch_matches_oracle(lr):
             _assert_obs(it["obs"].cpu().numpy(), ref, f"batch dims {it['model'].d_q, it['model'].d_r}")
 
 
+@pytest.mark.parametrize("dims,M", [((8, 75, 5), 32), ((8, 38, 5), 24), ((8, 9, 6), 22)])
+def test_spread_largest_shapes_match_oracle(lr, dims, M):
+    """The spread schedule at the largest shape of the batched workload (N = 3000, M = 32: three
+    register rows, two solve entries per thread) and at the other two variants (M = 24: two rows, two
+    entries; 48-row layers at M = 22: three rows, one entry), integrated against the oracle."""
+    m = I.readout_model(*dims).replace(kappa_f=0.5, gamma_1=0.02)
+    nsteps, stride, dt = 40, 10, 5e-4
+    p = I.draw_piecewise6(I.rng(17), nsteps * dt)
+    B0 = I.initial_state(m, M, "e", seed=17, scale=1e-3)
+    import torch
+    it = dict(model=m, M=M, pulse=p, dt=dt, nsteps=nsteps, B=lr.to_device(B0), obs_stride=stride,
+              obs=torch.zeros((nsteps // stride + 1, 6 + dims[0]), dtype=torch.float64, device="cuda"))
+    print(f"[parity] spread dims={dims} M={M}", flush=True)
+    b = lr.Batch([it])
+    b.run()
+    assert b.status()[0] == lr.LR_OK
+    Bo, ref = lowrank.integrate(m, p, 0.0, dt, nsteps, B0, obs_stride=stride)
+    err = np.max(np.abs(lr.from_device(it["B"]) - Bo))
+    print(f"[parity] spread dims={dims} M={M}: max |dB| {err:.3e} (tol 1e-12)")
+    assert err <= 1e-12
+    _assert_obs(it["obs"].cpu().numpy(), ref, f"spread dims {dims} M={M}")
+
+
 # ------------------------------------------------------------ dense comparison solve
 
 def _dense_case(seed):
