@@ -142,11 +142,17 @@ def comparisons(lr, I, torch, stream, plain_value):
     v_p, el_p = run_batch(n512, 200, packed=True)
     # algorithmic FP64 flops per RK step and trajectory (same count as the main line's roofline)
     fl = 4 * m.N * M * (58 + 40 * M)
+    by = 17 * 16 * m.N * M
     out["batched_512_same_shape"] = {
         "spread": v_s, "packed": v_p, "packed_vs_spread": v_p / v_s, "packed_vs_plain_g_e": v_p / plain_value,
         "packed_roofline": {"bound": "alu", "achieved": v_p * fl / 1e12, "peak": 78.6, "unit": "TFLOP/s",
                             "frac": v_p * fl / 1e12 / 78.6,
                             "note": "whole-batch wall time (launch overhead and the prologue included)"},
+        # the HBM side of the same run: 17 passes of 16 N M bytes per trajectory-step
+        # (stage input 4, B_n and accumulator reads 6, stage output 4, accumulator writes 3)
+        "packed_hbm": {"bound": "hbm", "achieved": v_p * by / 1e9, "peak": 8000.0, "unit": "GB/s",
+                       "frac": v_p * by / 1e9 / 8000.0, "algorithmic_bytes_per_traj_step": by,
+                       "traffic_per_traj_step": measured_packed_traffic_per_traj_step()},
         "unit": "RK steps*trajectories/s",
         "workload": f"512 trajectories (256 piecewise pulses x g/e), N=2000, M=20; spread: first 40 steps "
                     f"({el_s:.2f} s), packed: first 200 steps ({el_p:.2f} s)"}
@@ -437,25 +443,37 @@ def drive_frame_study(lr, I, torch):
     return out
 
 
-def measured_traffic_per_step():
-    """HBM bytes per g+e RK4 step of k_persist from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel source changed
-    since the counters were taken."""
+def _profiled_traffic(summary, key, sources):
+    """HBM bytes `key` from a committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary
+    under profiles/, or None when the kernel sources changed since the counters
+    were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "k_persist_paper_size_traffic.md")
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
-    m_b = re.search(r"^traffic_bytes_per_step: (\S+)$", txt, re.M)
+    m_b = re.search(r"^" + key + r": (\S+)$", txt, re.M)
     m_h = re.search(r"^source_sha256: (\S+)$", txt, re.M)
     if not (m_b and m_h):
         return None
     h = hashlib.sha256()
-    for f in ("paper_2508_18114_amd/csrc/lr_persistent.hip", "paper_2508_18114_amd/csrc/lr_device.h"):
-        with open(os.path.join(ROOT, f), "rb") as fh:
+    for f in sources:
+        with open(os.path.join(ROOT, "paper_2508_18114_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return float(m_b.group(1)) if h.hexdigest() == m_h.group(1) else None
+
+
+def measured_traffic_per_step():
+    """HBM bytes per g+e RK4 step of k_persist (measured), or None."""
+    return _profiled_traffic("k_persist_paper_size_traffic.md", "traffic_bytes_per_step",
+                             ("lr_persistent.hip", "lr_device.h"))
+
+
+def measured_packed_traffic_per_traj_step():
+    """HBM bytes per trajectory-step of k_packed on 512 trajectories (measured), or None."""
+    return _profiled_traffic("k_packed_512_same_shape_traffic.md", "traffic_bytes_per_traj_step",
+                             ("lr_packed.hip", "lr_device.h"))
 
 
 def main():
