@@ -23,6 +23,14 @@ so that  dB/dt = -i H_eff B + 1/2 sum_k Y_k X_k^  with
 
 G^-1 C_k is evaluated through the Cholesky factor G = R R^ and two triangular
 solves; a non-positive pivot raises GramNotPD.
+
+Summation order.  The row sums of the Gram and cross products (G, C_k) and of
+the observables are mathematically fixed but their rounding depends on the
+order in which the N rows are added.  `sum_order` selects it: "matmul" (the
+library product, the reference order), "reversed" (the rows taken in reverse
+basis order) or "blocked" (sums over consecutive blocks of `_BLOCK` rows,
+then the block sums in order).  Runs that differ only in this order measure
+the oracle's own rounding floor at a given workload.
 """
 from __future__ import annotations
 
@@ -182,6 +190,43 @@ def apply_jumps(model, B):
     return [Y1.reshape(B.shape), Y2.reshape(B.shape)]
 
 
+# ---------------------------------------------------------------- row sums
+
+SUM_ORDERS = ("matmul", "reversed", "blocked")
+_BLOCK = 40
+
+
+def inner(X, Y, sum_order="matmul"):
+    """X^ Y = sum over rows n of conj(X[n, :])^T Y[n, :], rows added in the
+    given order (see the module header)."""
+    if sum_order == "matmul":
+        return X.conj().T @ Y
+    if sum_order == "reversed":
+        return X[::-1].conj().T @ Y[::-1]
+    if sum_order == "blocked":
+        acc = np.zeros((X.shape[1], Y.shape[1]), dtype=np.complex128)
+        for b in range(0, X.shape[0], _BLOCK):
+            acc = acc + X[b:b + _BLOCK].conj().T @ Y[b:b + _BLOCK]
+        return acc
+    raise ValueError(f"unknown sum_order {sum_order!r}")
+
+
+def total(x, sum_order="matmul"):
+    """Sum of all entries of x (flattened in C order), in the given order."""
+    if sum_order == "matmul":
+        return np.sum(x)
+    v = np.ravel(x)
+    if sum_order == "reversed":
+        return np.sum(v[::-1])
+    if sum_order == "blocked":
+        blk = _BLOCK * 64
+        acc = 0.0
+        for b in range(0, v.size, blk):
+            acc = acc + np.sum(v[b:b + blk])
+        return acc
+    raise ValueError(f"unknown sum_order {sum_order!r}")
+
+
 # ---------------------------------------------------------------- RHS
 
 def gram_solve(G, C_list):
@@ -199,7 +244,7 @@ def gram_solve(G, C_list):
     return out
 
 
-def rhs(model, pulse, t, B):
+def rhs(model, pulse, t, B, sum_order="matmul"):
     """dB/dt at time t (equation of motion of supplement S1.A)."""
     d_t = pulses.drive(pulse, t) if pulse is not None else 0.0
     if pulse is not None and getattr(pulse, "frame", 0) == 1:
@@ -207,9 +252,8 @@ def rhs(model, pulse, t, B):
     else:
         Z = apply_heff(model, d_t, B)
     Y = apply_jumps(model, B)
-    Bh = B.conj().T
-    G = Bh @ B
-    C = [Bh @ Yk for Yk in Y]
+    G = inner(B, B, sum_order)
+    C = [inner(B, Yk, sum_order) for Yk in Y]
     X = gram_solve(G, C)
     dB = -1j * Z
     for Yk, Xk in zip(Y, X):
@@ -222,19 +266,22 @@ def rhs(model, pulse, t, B):
 OBS_HEADER = ("re_a", "im_a", "re_f", "im_f", "tr_rho", "tr_rho2")
 
 
-def observables(model, B):
+def observables(model, B, sum_order="matmul"):
     """[Re<a>, Im<a>, Re<f>, Im<f>, tr rho, tr rho^2, P_q(0..d_q-1)].
 
     <O> = tr(O rho) = sum_j b_j^ O b_j (unnormalised); tr rho^2 = ||B^ B||_F^2
     (since tr (B B^)^2 = tr (B^ B)^2); P_q(k) = tr(|k><k|_q rho).
     """
     T = _as_tensor(model, B)
-    a = np.sum(T.conj() * lower(T, 1))
-    f = np.sum(T.conj() * lower(T, 2))
-    tr = np.sum(np.abs(T) ** 2)
-    G = B.conj().T @ B
+    a = total(T.conj() * lower(T, 1), sum_order)
+    f = total(T.conj() * lower(T, 2), sum_order)
+    tr = total(np.abs(T) ** 2, sum_order)
+    G = inner(B, B, sum_order)
     tr2 = np.sum(np.abs(G) ** 2)
-    Pq = np.sum(np.abs(T) ** 2, axis=(1, 2, 3))
+    if sum_order == "matmul":
+        Pq = np.sum(np.abs(T) ** 2, axis=(1, 2, 3))
+    else:
+        Pq = np.array([total(np.abs(T[q]) ** 2, sum_order) for q in range(model.d_q)])
     return np.concatenate([[a.real, a.imag, f.real, f.imag, tr, tr2], Pq])
 
 
@@ -248,7 +295,7 @@ def rk4_step(fun, t, dt, B):
     return B + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
 
 
-def integrate(model, pulse, t0, dt, nsteps, B0, obs_stride=0):
+def integrate(model, pulse, t0, dt, nsteps, B0, obs_stride=0, sum_order="matmul"):
     """Classic fixed-step RK4 from B(t0) = B0 over nsteps steps of dt.
 
     Step n runs from t_n = t0 + n dt.  Observables are recorded at step 0 and
@@ -256,13 +303,13 @@ def integrate(model, pulse, t0, dt, nsteps, B0, obs_stride=0):
     of shape (nsteps // obs_stride + 1, 6 + d_q) (empty if obs_stride == 0).
     """
     B = np.array(B0, dtype=np.complex128, copy=True)
-    fun = lambda t, X: rhs(model, pulse, t, X)  # noqa: E731
+    fun = lambda t, X: rhs(model, pulse, t, X, sum_order)  # noqa: E731
     rec = []
     if obs_stride > 0:
-        rec.append(observables(model, B))
+        rec.append(observables(model, B, sum_order))
     for n in range(nsteps):
         B = rk4_step(fun, t0 + n * dt, dt, B)
         if obs_stride > 0 and (n + 1) % obs_stride == 0:
-            rec.append(observables(model, B))
+            rec.append(observables(model, B, sum_order))
     obs = np.array(rec) if rec else np.zeros((0, 6 + model.d_q))
     return B, obs

@@ -1,0 +1,98 @@
+"""Measure the oracle's own rounding floor on the cached workloads.
+
+Reruns the CPU oracle with the Gram / cross-product and observable row sums
+taken in other orders ("reversed", "blocked"; see oracle.lowrank) and compares
+each run with the cached reference-order run (tests/golden/config_<name>.npz).
+Two FP64 runs that differ only in summation order are equally valid, so the
+largest difference is the floor below which no implementation can be judged;
+the GPU parity tolerances are 100 times this floor (capped by the bounds of
+the FP64 parity contract).  Calls only the oracle and the seeded inputs.
+
+    OMP_NUM_THREADS=1 python tests/golden/oracle_floor.py [small|paper_size|all]
+
+Writes tests/golden/oracle_floor.json: per workload and order, the largest
+differences of
+  field     max |d <a>|, |d <f>| / max(1, max |<a>|, |<f>|)
+  pop       max |d P_q(k)|
+  trace     max |d tr rho|, |d tr rho^2|
+  snr_rel   |d SNR| / SNR
+and their maxima over the orders ("floor").
+"""
+import json
+import os
+import sys
+import time
+from multiprocessing import Pool
+
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
+
+import numpy as np  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import loss, lowrank  # noqa: E402
+from paper_2508_18114_amd import inputs as I  # noqa: E402
+
+CONFIGS = {"small": I.config_small, "paper_size": I.config_paper_size}
+ORDERS = ("reversed", "blocked")
+OUT = os.path.join(HERE, "oracle_floor.json")
+
+
+def _run(args):
+    name, idx, order, stride = args
+    tr = CONFIGS[name]()[idx]
+    t0 = time.time()
+    _, obs = lowrank.integrate(tr.model, tr.pulse, 0.0, tr.dt, tr.nsteps, tr.B0(), obs_stride=stride,
+                               sum_order=order)
+    return (name, idx, order), obs, time.time() - t0
+
+
+def differences(ref, got):
+    fa = max(1.0, float(np.max(np.abs(ref[:, 0:4]))))
+    return {"field": float(np.max(np.abs(got[:, 0:4] - ref[:, 0:4]))) / fa,
+            "pop": float(np.max(np.abs(got[:, 6:] - ref[:, 6:]))),
+            "trace": float(np.max(np.abs(got[:, 4:6] - ref[:, 4:6])))}
+
+
+def measure(names):
+    jobs = []
+    for name in names:
+        gd = np.load(os.path.join(HERE, f"config_{name}.npz"))
+        for order in ORDERS:
+            for idx in (0, 1):
+                jobs.append((name, idx, order, int(gd["stride"])))
+    with Pool(min(len(jobs), 8)) as pool:
+        res = pool.map(_run, jobs)
+    runs = {k: (obs, sec) for k, obs, sec in res}
+    out = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    for name in names:
+        gd = np.load(os.path.join(HERE, f"config_{name}.npz"))
+        tr = CONFIGS[name]()[0]
+        h = int(gd["stride"]) * tr.dt
+        entry = {"orders": {}}
+        for order in ORDERS:
+            og, sg = runs[(name, 0, order)]
+            oe, se = runs[(name, 1, order)]
+            dg, de = differences(gd["obs_g"], og), differences(gd["obs_e"], oe)
+            fm = loss.readout_loss(og, oe, h, tr.model.kappa_f, tr.model.gamma_1)
+            d = {k: max(dg[k], de[k]) for k in dg}
+            d.update({k + "_g": v for k, v in dg.items()})
+            d.update({k + "_e": v for k, v in de.items()})
+            d["snr_rel"] = abs(fm["snr"] - float(gd["snr"])) / float(gd["snr"])
+            d["seconds"] = [sg, se]
+            entry["orders"][order] = d
+        entry["floor"] = {k: max(entry["orders"][o][k] for o in ORDERS) for k in ("field", "pop", "trace",
+                                                                                   "snr_rel")}
+        entry["workload"] = f"config_{name}: {tr.model.d_q, tr.model.d_r, tr.model.d_f} M={tr.M}, " \
+                            f"{tr.nsteps} RK4 steps of {tr.dt} ns, g and e"
+        out[name] = entry
+        print(name, json.dumps(entry["floor"]), flush=True)
+    with open(OUT, "w") as fh:
+        json.dump(out, fh, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    which = sys.argv[1] if len(sys.argv) > 1 else "all"
+    measure(list(CONFIGS) if which == "all" else [which])
