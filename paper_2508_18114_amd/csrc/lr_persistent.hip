@@ -6,8 +6,9 @@
 // input in LDS -- stays on chip for a whole chunk of steps.  Per RK4 stage:
 //
 //   1. solve G X_k = C_k for the reduced G = S^S, C_k = S^ L_k S of the stage
-//      input (FP64 elimination of the augmented [G | C_1 C_2] in registers,
-//      one pivot per barrier); W_k = X_k^
+//      input (FP64 Gauss-Jordan elimination of the augmented [G | C_1 C_2],
+//      held in the registers of four waves that each eliminate G and a quarter
+//      of the right-hand sides on their own, no barrier per pivot); W_k = X_k^
 //   2. k_s = -i H_eff(t_s) S + 1/2 sum_k (L_k S) W_k for the own rows (banded
 //      stencil with one halo layer up and down, jump assembly), RK4 stage
 //      update in registers
@@ -37,10 +38,10 @@ constexpr int kMaxRowsPerThread = 3;
 constexpr size_t kPersistLdsMax = 159 * 1024;  // dynamic LDS (160 KB less the static part)
 
 // Dynamic LDS bytes of k_persist for rt layers of L rows at rank M and P
-// workgroups: stage input with halos, W, slice-reduction buffer, pivot
-// row/column (double buffered), per-row jump coefficients, square-root table.
-__host__ __device__ inline size_t persist_lds_bytes(int rt, int L, int M, int P) {
-  return (size_t)((rt + 2) * L * M + 2 * M * M + 3 * M * M + P + 8 * M) * 16 + (size_t)(2 * rt * L + L + rt + 1) * 8;
+// workgroups: stage input with halos, W, the solver waves' exchange areas
+// (4 x 256 complex), per-row jump coefficients, square-root table.
+__host__ __device__ inline size_t persist_lds_bytes(int rt, int L, int M, int /* P */) {
+  return (size_t)((rt + 2) * L * M + 2 * M * M + 4 * 256) * 16 + (size_t)(2 * rt * L + L + rt + 1) * 8;
 }
 
 // agent-coherent 16-byte store / load (two 64-bit atomic accesses)
@@ -162,13 +163,15 @@ __device__ __forceinline__ void flag_arrive(g_u32* flag, uint32_t value) {
 // if the wait expired or the group was aborted.
 __device__ __forceinline__ bool flag_wait(const TrajDev& T, const g_u32* flags, uint32_t target, int* s_ok) {
   g_u32* abort_flag = (g_u32*)T.abort_flag;
+  const uint32_t limit = T.spin_limit ? T.spin_limit : kSpinLimit;
+  target += T.wait_bias;
   if (threadIdx.x < 64) {
     bool ok = true;
     for (int w = threadIdx.x; w < T.P && ok; w += 64) {
       uint32_t n = 0;
       while (__hip_atomic_load(flags + (size_t)w * kFlagStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
              target) {
-        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++n > kSpinLimit) {
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++n > limit) {
           __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ok = false;
           break;
@@ -274,151 +277,238 @@ __device__ __forceinline__ double pivot_rcp(double p) {
   return r;
 }
 
-// W_k = X_k^ with X_k = G^-1 C_k (G Hermitian positive definite), in two
-// parallel phases:
-//   1. in-place Gauss-Jordan inversion of G without pivoting: M pivot steps,
-//      each taking every entry off the pivot row and column to
-//      x - G[i][k] G[k][j] / p, the pivot row to x / p, the pivot column to
-//      -x / p and the pivot to 1 / p (one barrier per pivot; every thread
-//      owns at most GE entries).  Its pivots are those of the Cholesky
-//      factorisation G = L D L^ (D_k > 0 iff G is positive definite); a
-//      non-positive pivot is reported like a failed Cholesky.  The pivot is
-//      taken as the real part of the diagonal entry and its inverse stored
-//      exactly real (G is Hermitian; any imaginary part is rounding).
-//   2. W_k[i][j] = sum_l conj(C_k[l][i]) (G^-1)[l][j]  (= (G^-1 C_k)^ since
-//      G^-1 is Hermitian), every entry independent.
-// G entries live in registers (thread t owns flat entries t + u kPW); C_k and
-// G^-1 go through LDS.  solve_load issues the loads of the reduced G, C_k so
-// that their latency overlaps other work; solve_run finishes.
+// W_k = X_k^ with X_k = G^-1 C_k (G Hermitian positive definite): Gauss-Jordan
+// elimination of the augmented M x 3M matrix [G | C_1 | C_2] without
+// pivoting, down to [I | X_1 | X_2].  Pivot k takes every row i != k to
+// row_i - A[i][k] row_k / p and row k to row_k / p, p = Re A[k][k]: these are
+// the pivots of G = L D L^ (all positive iff G is positive definite, so a
+// non-positive one is reported like a failed Cholesky), the imaginary part of
+// the diagonal entry being rounding (G is Hermitian).  The right-hand sides
+// are eliminated directly: no inverse of G is formed (an explicit inverse
+// followed by a product carries cond(G) times more rounding into X_k, and G
+// is ill-conditioned through the rank padding).
+//
+// The elimination runs inside single waves, with no workgroup barrier per
+// pivot: each of the first kSolveWaves waves of the workgroup holds all of G
+// and its own share of the 2M right-hand-side columns, and eliminates that
+// M x (M + share) matrix on its own (the G columns are eliminated identically
+// in every wave).  Within a wave, H consecutive lanes own one column and lane
+// h of a column holds the RPL consecutive rows h RPL .. h RPL + RPL - 1 in
+// registers.  Per pivot the
+// multiplier column (column k) and the pivot row entries are handed between
+// lanes through a small per-wave LDS area (written by their owners during the
+// previous pivot; a wave's LDS accesses are performed in order).
+constexpr int kSolveWaves = 4;
+constexpr int kWsLds = 4 * 64;  // LDS (complex entries) per solver wave: multiplier column and pivot row, two each
+constexpr int kWsRows = 10;     // register rows of a solver lane (ranks M <= 20)
 
-// GE = entries of G and of C_1, C_2 per thread: 1 for M^2 <= 512, 2 for
-// M^2 <= 1024.
-template <int GE>
-struct SolveRegs {
-  double2 g[GE];
-  double2 c[2 * GE];
+// Lane map of a solver wave for rank M.
+struct WsMap {
+  int H, RPL;      // lanes per column, rows per lane
+  int slot, h;     // column slot of the lane (G columns 0..M-1, then the wave's right-hand sides) and row block
+  int cbase;       // first right-hand-side column (0 .. 2M-1 over [C_1 | C_2]) of the wave
+  bool act;        // the lane owns a column
 };
-
-template <int GE>
-__device__ __forceinline__ void solve_load(const g_double2* red, int M, SolveRegs<GE>& S) {
-  const int MM = M * M;
-#pragma unroll
-  for (int u = 0; u < GE; ++u) S.g[u] = ld_ag(red + min((int)threadIdx.x + u * kPW, MM - 1));
-#pragma unroll
-  for (int u = 0; u < 2 * GE; ++u) S.c[u] = ld_ag(red + MM + min((int)threadIdx.x + u * kPW, 2 * MM - 1));
+__host__ __device__ inline int ws_cols_per_wave(int M) { return (2 * M + kSolveWaves - 1) / kSolveWaves; }
+// H = ceil(M / kWsRows) lanes per column, each with kWsRows register rows; the
+// register solver takes ranks whose columns of all lanes fit a wave
+__host__ __device__ inline int ws_lanes_per_col(int M) { return (M + kWsRows - 1) / kWsRows; }
+__host__ __device__ inline bool ws_fits(int M) { return ws_lanes_per_col(M) * (M + ws_cols_per_wave(M)) <= 64; }
+__device__ __forceinline__ WsMap ws_map(int M) {
+  WsMap m;
+  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int ncw = ws_cols_per_wave(M);
+  m.H = ws_lanes_per_col(M);
+  m.RPL = kWsRows;
+  m.slot = lane / m.H;
+  m.h = lane - m.slot * m.H;
+  m.cbase = w * ncw;
+  const int nc = max(0, min(2 * M, m.cbase + ncw) - m.cbase);
+  m.act = w < kSolveWaves && m.slot < M + nc;
+  return m;
+}
+// Offset in the reduced [G | C_1 | C_2] (each M x M row-major) of row 0 of the
+// lane's column (rows are M apart).
+__device__ __forceinline__ int ws_col_offset(const WsMap& m, int M) {
+  if (m.slot < M) return m.slot;
+  const int cc = m.cbase + m.slot - M;
+  return cc < M ? M * M + cc : 2 * M * M + (cc - M);
 }
 
-// Cs (2 M^2) and Gi (M^2) are LDS scratch; prow and pcol hold 2 x M entries.  nonfinite_flag is an LDS word that the caller zeroed before
-// a barrier that precedes this call; bad_flag is LDS scratch.  Writes W_k to
-// Wl.  Returns -1, the first non-positive pivot, or -2 for a non-finite
-// input.  LB = l values per batch of loads in the W product (register
-// budget).
-template <int GE, int LB>
-__device__ __forceinline__ int solve_run(SolveRegs<GE>& S, double2* prow, double2* pcol, double2* Cs, double2* Gi,
-                                         double2* Wl, int M, int* nonfinite_flag, int* bad_flag) {
-  const int MM = M * M;
-  const int tid = threadIdx.x;
-  int bad_local = 0;
+// RC = register rows per lane (>= ws_rows_per_lane(M)).
+template <int RC>
+struct WsRegs {
+  double2 a[RC];
+};
+
+// Loads of the lane's column of the reduced [G | C_1 | C_2] (issued early so
+// that their latency overlaps other work).
+template <int RC>
+__device__ __forceinline__ void wsolve_load(const g_double2* red, int M, const WsMap& m, WsRegs<RC>& R) {
+  const int off = ws_col_offset(m, M);
 #pragma unroll
-  for (int u = 0; u < GE; ++u)
-    if (tid + u * kPW < MM && (!isfinite(S.g[u].x) || !isfinite(S.g[u].y))) bad_local = 1;
+  for (int idx = 0; idx < RC; ++idx) {
+    const int r = m.h * RC + idx;
+    R.a[idx] = make_double2(0.0, 0.0);
+    if (m.act && r < M) R.a[idx] = ld_ag(red + off + (size_t)r * M);
+  }
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Elimination by one solver wave (every lane of the wave calls it).  scratch:
+// the wave's kWsLds LDS entries.  Writes W_k[i][j] = conj(X_k[j][i]) of the
+// wave's right-hand-side columns to Wl (W_1 then W_2, M x M row-major each).
+// s_nonfinite (LDS) is set on a non-finite input; *badk receives the first
+// non-positive pivot or -1.  The caller synchronises the workgroup before
+// reading Wl or the flags.  A lane holds RC rows (rows past M are zero and
+// stay zero); the pivots run in blocks of RC, so that within a block the
+// register of the pivot row is known at compile time.
+template <int RC>
+__device__ __forceinline__ void wsolve_run(WsRegs<RC>& R, const WsMap& m, double2* scratch, double2* Wl, int M,
+                                           int* s_nonfinite, int* badk) {
+  double2* mcol = scratch;        // [2][64] multiplier column of the pivot, by row
+  double2* prow = scratch + 128;  // [2][64] pivot row, by column slot
+  const int h = m.h, slot = m.slot;
+  bool bad = false;
 #pragma unroll
-  for (int u = 0; u < 2 * GE; ++u) {
-    const int o = tid + u * kPW;
-    if (o < 2 * MM) {
-      if (!isfinite(S.c[u].x) || !isfinite(S.c[u].y)) bad_local = 1;
-      Cs[o] = S.c[u];
+  for (int idx = 0; idx < RC; ++idx) bad = bad || !isfinite(R.a[idx].x) || !isfinite(R.a[idx].y);
+  *badk = -1;
+  if (__any(bad)) {  // uniform
+    if (bad) *s_nonfinite = 1;
+    return;
+  }
+  double2* myrows = mcol + h * RC;  // this lane's rows in a multiplier column
+  // pivot 0: column 0 and row 0 (row block 0, register 0)
+  if (slot == 0) {
+#pragma unroll
+    for (int idx = 0; idx < RC; ++idx) myrows[idx] = R.a[idx];
+  }
+  if (h == 0) prow[slot] = R.a[0];
+  bool stop = false;
+  for (int kb = 0, hk = 0; kb < M && !stop; kb += RC, ++hk) {  // row block hk: pivots kb .. kb + RC - 1
+#pragma unroll
+    for (int j = 0; j < RC; ++j) {  // j, hence the register of the pivot row, is a constant per copy
+      const int k = kb + j;
+      if (k < M && !stop) {  // uniform
+        const int par = k & 1;
+        wave_lds_sync();
+        const double2* mrow = myrows + par * 64;
+        double2 mi[RC];
+#pragma unroll
+        for (int idx = 0; idx < RC; ++idx) mi[idx] = mrow[idx];  // A[row][k] of the lane's rows
+        const double piv = mcol[par * 64 + k].x;
+        const double2 pr = prow[par * 64 + slot];
+        const double rinv = pivot_rcp(piv > 0.0 ? piv : 1.0);  // (the reads above complete together)
+        if (!(piv > 0.0)) {  // uniform: every lane read the same pivot
+          *badk = k;
+          stop = true;
+        } else {
+          const double2 pc = make_double2(pr.x * rinv, pr.y * rinv);  // row k of the result, this column
+#pragma unroll
+          for (int idx = 0; idx < RC; ++idx) {
+            double2 v = R.a[idx];
+            v.x = fma(-mi[idx].x, pc.x, v.x);
+            v.x = fma(mi[idx].y, pc.y, v.x);
+            v.y = fma(-mi[idx].x, pc.y, v.y);
+            v.y = fma(-mi[idx].y, pc.x, v.y);
+            R.a[idx] = v;
+          }
+          if (h == hk) R.a[j] = pc;  // the pivot row itself
+          // pivot row and multiplier column of the next pivot k + 1 (row block hn, register (j + 1) % RC)
+          const int hn = j + 1 < RC ? hk : hk + 1;
+          if (h == hn) prow[(par ^ 1) * 64 + slot] = R.a[(j + 1) % RC];
+          if (slot == k + 1) {
+            double2* mnext = myrows + (par ^ 1) * 64;
+#pragma unroll
+            for (int idx = 0; idx < RC; ++idx) mnext[idx] = R.a[idx];
+          }
+        }
+      }
     }
   }
-  if (bad_local) *nonfinite_flag = 1;  // seen after the first pivot barrier
-
-  int gi[GE], gj[GE];
-  bool own[GE];
+  if (stop) return;
+  // right-hand-side lanes hold X_k[:, i]: W_k[i][j] = conj(X_k[j][i])
+  if (m.act && slot >= M) {
+    const int cc = m.cbase + slot - M, kk = cc < M ? 0 : 1, i = cc - kk * M;
+    double2* dst = Wl + (size_t)kk * M * M + (size_t)i * M;
 #pragma unroll
-  for (int u = 0; u < GE; ++u) {
-    const int o = tid + u * kPW;
-    own[u] = o < MM;
-    const int oc = min(o, MM - 1);
-    gi[u] = oc / M;
-    gj[u] = oc - gi[u] * M;
+    for (int idx = 0; idx < RC; ++idx) {
+      const int j = h * RC + idx;
+      if (j < M) dst[j] = make_double2(R.a[idx].x, -R.a[idx].y);
+    }
   }
-  int bad = -1;
+}
+
+// The same elimination for ranks whose columns do not fit a solver wave's
+// registers (M >= 21 with 10 register rows per lane): the M x 3M matrix sits in
+// LDS and the whole workgroup takes each pivot, one barrier per pivot.  The
+// pivot rows are left unscaled -- pivot k takes row i != k to
+// row_i - (A[i][k] / p) row_k, which reads row k and column k but writes
+// neither -- so that a pivot needs no second barrier; the result rows are
+// divided by their pivots at the end (X_k = D^-1 [eliminated C_k], D the
+// pivots).  Aug: 3 M^2 complex entries of LDS.  Returns like wsolve_run
+// through the same flags (every thread calls it; the flags are valid after
+// the caller's barrier).
+__device__ __forceinline__ void lsolve_run(const g_double2* red, double2* Aug, double2* Wl, int M,
+                                           int* s_nonfinite, int* s_bad) {
+  const int MM = M * M, C3 = 3 * M, tot = M * C3, tid = threadIdx.x;
+  bool bad = false;
+  for (int e = tid; e < tot; e += kPW) {  // Aug[i][c] = [G | C_1 | C_2][i][c]
+    const int i = e / C3, c = e - i * C3, blk = c / M;
+    const double2 v = ld_ag(red + (size_t)blk * MM + i * M + (c - blk * M));
+    bad = bad || !isfinite(v.x) || !isfinite(v.y);
+    Aug[e] = v;
+  }
+  if (bad) *s_nonfinite = 1;
+  if (tid == 0) *s_bad = -1;
+  __syncthreads();
+  if (*s_nonfinite) return;
   for (int k = 0; k < M; ++k) {
-    double2* pr = prow + (k & 1) * M;  // row k of the current matrix
-    double2* pc = pcol + (k & 1) * M;  // column k
-#pragma unroll
-    for (int u = 0; u < GE; ++u) {
-      if (own[u]) {
-        if (gi[u] == k) pr[gj[u]] = S.g[u];
-        if (gj[u] == k) pc[gi[u]] = S.g[u];
+    const double piv = Aug[k * C3 + k].x;
+    if (!(piv > 0.0)) {  // uniform
+      if (tid == 0) *s_bad = k;
+      return;
+    }
+    const double rp = pivot_rcp(piv);
+    for (int e = tid; e < tot; e += kPW) {
+      const int i = e / C3, c = e - i * C3;
+      if (c > k && i != k) {
+        const double2 a = Aug[i * C3 + k], b = Aug[k * C3 + c];
+        const double2 l = make_double2(a.x * rp, a.y * rp);
+        double2 v = Aug[e];
+        v.x = fma(-l.x, b.x, v.x);
+        v.x = fma(l.y, b.y, v.x);
+        v.y = fma(-l.x, b.y, v.y);
+        v.y = fma(-l.y, b.x, v.y);
+        Aug[e] = v;
       }
     }
     __syncthreads();
-    // pivot, pivot column and pivot row entries read together
-    const double piv = pr[k].x;
-    double2 a[GE], b[GE];
+  }
+  // X_k[j][i] = Aug[j][M (k + 1) + i] / p_j;  W_k[i][j] = conj(X_k[j][i]) (Wl aliases Aug: read, then write)
+  constexpr int kWPer = (2 * kMaxM * kMaxM + kPW - 1) / kPW;
+  double2 w[kWPer];
 #pragma unroll
-    for (int u = 0; u < GE; ++u) {
-      a[u] = pc[gi[u]];
-      b[u] = pr[gj[u]];
-    }
-    const bool pos = piv > 0.0;  // uniform: every thread read the same pivot
-    if (!pos && bad < 0) bad = k;
-    const double inv = pivot_rcp(pos ? piv : 1.0);
-#pragma unroll
-    for (int u = 0; u < GE; ++u) {
-      const bool ri = gi[u] == k, cj = gj[u] == k;
-      const double2 x = S.g[u];
-      const double2 t = cmul(a[u], b[u]);
-      double2 v = make_double2(fma(-inv, t.x, x.x), fma(-inv, t.y, x.y));
-      const double sc = cj ? -inv : inv;
-      v = (ri || cj) ? make_double2(sc * x.x, sc * x.y) : v;
-      v = (ri && cj) ? make_double2(inv, 0.0) : v;
-      S.g[u] = v;
+  for (int u = 0; u < kWPer; ++u) {
+    const int e = tid + u * kPW;
+    if (e < 2 * MM) {
+      const int kk = e / MM, o = e - kk * MM, i = o / M, j = o - i * M;
+      const double r = pivot_rcp(Aug[j * C3 + j].x);
+      const double2 x = Aug[j * C3 + M * (kk + 1) + i];
+      w[u] = make_double2(x.x * r, -x.y * r);
     }
   }
-#pragma unroll
-  for (int u = 0; u < GE; ++u)
-    if (own[u]) Gi[tid + u * kPW] = S.g[u];
-  if (tid == 0) *bad_flag = bad;
   __syncthreads();
-  if (*nonfinite_flag) return -2;
-  if (*bad_flag >= 0) return *bad_flag;
-  // W_k[i][j] = sum_l conj(C_k[l][i]) Gi[l][j]; the entry (i, j) of both
-  // jumps per thread, LB l per batch of loads, two accumulators each
-  for (int o = tid; o < MM; o += kPW) {
-    const int i = o / M, j = o - i * M;
-    const double2* C1 = Cs + i;
-    const double2* C2 = Cs + MM + i;
-    const double2* Gc = Gi + j;
-    double2 w1a = make_double2(0.0, 0.0), w1b = w1a, w2a = w1a, w2b = w1a;
-    int l = 0;
-    for (; l + LB <= M; l += LB) {
-      double2 g[LB], c1[LB], c2[LB];
 #pragma unroll
-      for (int v = 0; v < LB; ++v) {
-        g[v] = Gc[(l + v) * M];
-        c1[v] = C1[(l + v) * M];
-        c2[v] = C2[(l + v) * M];
-      }
-#pragma unroll
-      for (int v = 0; v < LB; v += 2) {
-        w1a = cjmac(w1a, c1[v], g[v]);
-        w2a = cjmac(w2a, c2[v], g[v]);
-        w1b = cjmac(w1b, c1[v + 1], g[v + 1]);
-        w2b = cjmac(w2b, c2[v + 1], g[v + 1]);
-      }
-    }
-    for (; l < M; ++l) {
-      const double2 g = Gc[l * M];
-      w1a = cjmac(w1a, C1[l * M], g);
-      w2a = cjmac(w2a, C2[l * M], g);
-    }
-    Wl[o] = cadd(w1a, w1b);
-    Wl[MM + o] = cadd(w2a, w2b);
+  for (int u = 0; u < kWPer; ++u) {
+    const int e = tid + u * kPW;
+    if (e < 2 * MM) Wl[e] = w[u];
   }
-  __syncthreads();
-  return -1;
 }
 
 // Sum of |G_ij|^2 over the reduced Gram (block reduction, fixed order).
@@ -467,10 +557,8 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
   double2* SL = lds;                              // (rt + 2) L M: [halo | tile | halo]
   double2* tile = SL + LM;
   double2* Wl = SL + (size_t)(rt + 2) * LM;       // 2 M^2
-  double2* RB = Wl + 2 * MM;                      // 3 M^2 + P: slice reduction; C_k, G^-1 in the solve
-  double2* prow = RB + 3 * MM + P;                // 2 x M
-  double2* pcol = prow + 4 * M;                   // 2 x M
-  double* c1row = reinterpret_cast<double*>(pcol + 4 * M);
+  double2* WS = Wl + 2 * MM;                      // kSolveWaves x kWsLds: solver waves' exchange areas
+  double* c1row = reinterpret_cast<double*>(WS + kSolveWaves * kWsLds);
   double* c2row = c1row + rt * L;
   double* sqt = c2row + rt * L;                   // sqrt(n), n < nq; then sqrt(r0 + k), k <= rt
   const int nq = max(d_q, d_f);
@@ -485,6 +573,8 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
     c2row[rl] = q + 1 < d_q ? sqrt(T.gamma * (double)(q + 1)) : 0.0;
   }
   for (int n = tid; n < nq + rt + 1; n += kPW) sqt[n] = sqrt((double)(n < nq ? n : r0 + (n - nq)));
+
+  const WsMap wsm = ws_map(M);  // solver-wave lane map
 
   // element mapping: column j, rows rg, rg + NG, ...
   const int NG = kPW / M;
@@ -673,9 +763,11 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
       __syncthreads();  // stage input tile and halo, drive table in LDS
       const double drv = s_dtab[ds][0];
 
-      // (1) loads of the reduced G, C_k in flight while Z = H_eff(t) S is formed
-      SolveRegs<GE> SR;
-      solve_load(REDg + (size_t)p * npe, M, SR);
+      // (1) loads of the reduced G, C_k (solver waves of the register solver) in flight while
+      // Z = H_eff(t) S is formed (with three register rows they are issued after it: registers)
+      constexpr bool kWaveSolve = GE == 1, kEarlyLoad = kWaveSolve && ROWS == 2;
+      WsRegs<kWsRows> SR;
+      if constexpr (kEarlyLoad) wsolve_load(REDg + (size_t)p * npe, M, wsm, SR);
       double2 z[ROWS];
       // Z rows of the thread, in the lab frame or the drive frame (one code
       // path per frame, chosen once per stage).  In the drive frame a
@@ -742,9 +834,21 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
       };
       if (T.frame) stencil(std::true_type{});
       else stencil(std::false_type{});
-      // (2) W_k of this stage input
+      // (2) W_k of this stage input (register solver: solver waves, the others wait at the
+      // barrier; LDS solver: the whole workgroup)
       {
-        const int bad = solve_run<GE, ROWS == 2 ? 4 : 2>(SR, prow, pcol, RB, RB + 2 * MM, Wl, M, &s_nonfinite, &s_bad);
+        if constexpr (kWaveSolve) {
+          if (tid < kSolveWaves * 64) {
+            int badk;
+            if constexpr (!kEarlyLoad) wsolve_load(REDg + (size_t)p * npe, M, wsm, SR);
+            wsolve_run<kWsRows>(SR, wsm, WS + (tid >> 6) * kWsLds, Wl, M, &s_nonfinite, &badk);
+            if (tid == 0) s_bad = badk;
+          }
+        } else {
+          lsolve_run(REDg + (size_t)p * npe, Wl, Wl, M, &s_nonfinite, &s_bad);
+        }
+        __syncthreads();
+        const int bad = s_nonfinite ? -2 : s_bad;
         if (bad != -1) {
           if (tid == 0) report(T, bad == -2 ? -5 /* LR_ERR_NONFINITE */ : -4 /* LR_ERR_GRAM_NOT_PD */, step);
           failed = true;
@@ -860,6 +964,7 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
 
 // Chunk of RK4 steps (the integrator proper) and prologue, as separate
 // kernels so that timing tools see the step kernel alone.
+// GE selects the solver: in the registers of the solver waves (1) or in LDS (2).
 template <int ROWS, int GE, int PREC>
 __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ trajs,
                                                  const int2* __restrict__ tilemap, int64_t step0, int64_t nchunk) {
@@ -872,8 +977,10 @@ __global__ __launch_bounds__(kPW) void k_persist_prologue(const TrajDev* __restr
   persist_body<ROWS, GE, PREC>(trajs, tilemap, 1, step0, 0);
 }
 
-// Kernel variant for ROWS rows per thread, rank M and precision mode.
-inline int persist_ge(int M) { return M * M > kPW ? 2 : 1; }
+// Kernel variant for ROWS rows per thread, rank M and precision mode: the
+// register solver (GE = 1) when the lanes of a solver wave's columns fit the
+// wave, else the LDS solver (GE = 2).
+inline int persist_ge(int M) { return ws_fits(M) ? 1 : 2; }
 template <int PREC>
 inline const void* persist_kernel_p(int rows, int ge, bool prologue) {
   if (prologue) {
