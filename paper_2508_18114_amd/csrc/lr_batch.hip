@@ -596,6 +596,19 @@ int lr_batch_profile_enable(lr_batch_t* b, int32_t on) {
   return LR_OK;
 }
 
+int lr_batch_wait_limits(lr_batch_t* b, uint32_t spins, int32_t never) {
+  if (!b) return LR_ERR_ARG;
+  if (!b->ws) return LR_ERR_STATE;
+  for (TrajDev& v : b->dev) {
+    v.spin_limit = spins;
+    v.wait_bias = never ? 1u : 0u;
+  }
+  const hipError_t e = hipMemcpyAsync(b->ws + b->off_trajs, b->dev.data(), sizeof(TrajDev) * (size_t)b->n,
+                                      hipMemcpyHostToDevice, b->stream);
+  if (e != hipSuccess) return LR_ERR_HIP;
+  return hipStreamSynchronize(b->stream) == hipSuccess ? LR_OK : LR_ERR_HIP;
+}
+
 int lr_batch_profile_read(lr_batch_t* b, double* ms, int64_t* launches) {
   if (!b) return LR_ERR_ARG;
   if (b->stream && hipStreamSynchronize(b->stream) != hipSuccess) return LR_ERR_HIP;

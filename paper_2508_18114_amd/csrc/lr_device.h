@@ -62,6 +62,9 @@ struct TrajDev {
   // model kind 1 (transmon eigenbasis): levels and charge operator (row-major d_q x d_q)
   double Et[kMaxDq];
   double ntq[kMaxDq * kMaxDq];
+  // bounded waits of the group barriers: polls before a wait expires (0: kSpinLimit), and an offset
+  // added to every barrier target (nonzero only to make every wait expire, for failure-handling tests)
+  uint32_t spin_limit, wait_bias;
 };
 
 constexpr int kFlagStride = 32;    // one 128-byte line per flag
