@@ -42,7 +42,26 @@ def parse():
     ap.add_argument("--packed-sample", type=int, default=0, metavar="STEPS",
                     help="only run the packed schedule on 512 trajectories (N=2000, M=20) for STEPS steps "
                          "(a workload for kernel profiles) and print its rate")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device three times (the reference that HBM byte "
+                         "counters are calibrated against) and print the rate")
     return ap.parse_args()
+
+
+def copy_calibration(torch, mib):
+    """A plain device copy of a known size: FETCH_SIZE / WRITE_SIZE read for it give the factors that turn
+    the counters into bytes moved."""
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        t0 = time.perf_counter()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(json.dumps({"copy_mib": mib, "ms": el * 1e3, "gb_per_s_read_plus_write": 2 * mib * (1 << 20) / el / 1e9}),
+              flush=True)
 
 
 def packed_sample(lr, I, torch, steps):
@@ -60,6 +79,7 @@ def packed_sample(lr, I, torch, steps):
     if b.status()[0] != lr.LR_OK:
         raise RuntimeError("packed sample failed")
     ms, launches = b.profile_read()
+    b.close()
     m, M = tl[0].model, tl[0].M
     fl = 4 * m.N * M * (58 + 40 * M) * steps * len(items)
     print(json.dumps({"workload": f"packed schedule, {len(items)} trajectories, N={m.N}, M={M}, {steps} steps",
@@ -110,6 +130,7 @@ def comparisons(lr, I, torch, stream, plain_value):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         rc, codes, _ = b.status()
+        b.close()
         if rc != lr.LR_OK:
             raise RuntimeError(f"batch failed: {lr.lr_strerror(rc)}")
         return sum(it["nsteps"] for it in items) / el, el
@@ -124,6 +145,7 @@ def comparisons(lr, I, torch, stream, plain_value):
     ctx.integrate(trajs[0].pulse, 0.0, trajs[0].dt, steps, B)
     torch.cuda.synchronize()
     single = steps / (time.perf_counter() - t0)
+    ctx.close()
     out["plain_single"] = {"value": single, "unit": "RK steps*trajectories/s",
                            "workload": f"one trajectory (g), N={m.N}, M={M}, {steps} steps"}
     # batched, same shape: 16 piecewise pulses x {g, e} at N=2000, M=20
@@ -258,6 +280,7 @@ def comparisons(lr, I, torch, stream, plain_value):
         el = time.perf_counter() - t0
         if b.status()[0] != lr.LR_OK:
             raise RuntimeError(f"precision {name} failed")
+        b.close()
         out.setdefault("precision_modes", {})[name] = {
             "value": 2 * steps / el, "unit": "RK steps*trajectories/s",
             "workload": f"g+e, N=2000, M=20, padding weight 1e-5, {steps} steps"}
@@ -488,6 +511,9 @@ def main():
     from paper_2508_18114_amd import lr
 
     torch.cuda.set_device(0)
+    if a.copy_calibration > 0:
+        copy_calibration(torch, a.copy_calibration)
+        return
     if a.packed_sample > 0:
         packed_sample(lr, I, torch, a.packed_sample)
         return
@@ -509,6 +535,7 @@ def main():
     wb, _ = make_batch(a.warmup)
     wb.run()
     check(wb)
+    wb.close()
     # timed region: K RK4 steps of both trajectories in one batch (inputs
     # resident in HBM); the persistent kernel's launches are bracketed by HIP
     # events on the batch stream
@@ -522,6 +549,7 @@ def main():
     check(tb)
     value = len(trajs) * a.steps / elapsed
     kernel_ms, launches = tb.profile_read()
+    tb.close()
     launch_us = 1e3 * kernel_ms / max(launches, 1)
     steps_per_launch = a.steps / max(launches, 1)
     # algorithmic FP64 work of one trajectory-step: 4 stages x N x M elements x

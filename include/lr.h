@@ -17,8 +17,11 @@
  *
  * integrated by classic fixed-step RK4.  Each right-hand side evaluation
  * applies H_eff = H - i/2 sum_k L_k^ L_k and L_k mode-wise, forms the Gram
- * G = B^ B and C_k = B^ L_k B, solves G X_k = C_k by Cholesky in FP64 and
- * assembles dB/dt = -i H_eff B + 1/2 sum_k (L_k B) X_k^.
+ * G = B^ B and C_k = B^ L_k B, solves G X_k = C_k in FP64 and assembles
+ * dB/dt = -i H_eff B + 1/2 sum_k (L_k B) X_k^.  The integrators solve by
+ * Gauss-Jordan elimination of the augmented [G | C_1 C_2] without pivoting
+ * (its pivots are those of G = L D L^, positive iff G is positive definite);
+ * the multi-kernel path behind lr_rhs factors G by Cholesky.
  *
  * Units: rad/ns and ns.  Basis index n = (i_q d_r + i_r) d_f + i_f.
  *
@@ -133,7 +136,7 @@ enum {
   LR_ERR_ARG = -1,          /* invalid argument (dims, M, sizes, null pointers)   */
   LR_ERR_OOM = -2,          /* workspace smaller than lr_workspace_bytes          */
   LR_ERR_HIP = -3,          /* a HIP runtime call failed                          */
-  LR_ERR_GRAM_NOT_PD = -4,  /* Cholesky pivot of B^B <= 0 (device, via lr_status) */
+  LR_ERR_GRAM_NOT_PD = -4,  /* a pivot of B^B (LDL^ / Cholesky) <= 0 (device, via lr_status) */
   LR_ERR_NONFINITE = -5,    /* non-finite B or Gram (device, via lr_status)       */
   LR_ERR_PULSE = -6,        /* drive amplitude above the bound, or bad kind       */
   LR_ERR_STATE = -7,        /* call order (e.g. no workspace bound)               */
@@ -200,6 +203,15 @@ int lr_status(lr_ctx_t* ctx, int64_t* failed_step);
  * stream and returns the summed kernel times (ms) and launch counts. */
 #define LR_PROFILE_MAX 4096
 int lr_profile_enable(lr_ctx_t* ctx, int32_t on);
+/* Bounded waits of the on-chip integrator's group barriers (failure
+ * handling).  Every wait of a workgroup for the others polls at most `spins`
+ * times (0: the default, 2^20 polls, far above any healthy wait) before it
+ * gives up, ends its trajectory's whole workgroup group and reports
+ * LR_ERR_TIMEOUT through lr_status; the context stays usable.  never != 0
+ * makes every barrier wait for a value that no workgroup writes, so that each
+ * wait expires after `spins` polls: a deterministic way for tests to drive the
+ * timeout path from the host.  Applies to later lr_integrate calls. */
+int lr_wait_limits(lr_ctx_t* ctx, uint32_t spins, int32_t never);
 int lr_profile_read(lr_ctx_t* ctx, double* stage_ms, int64_t* stage_launches, double* solve_ms,
                     int64_t* solve_launches);
 
@@ -233,6 +245,21 @@ size_t lr_dense_workspace_bytes(const lr_model_t* m);
 int lr_dense_integrate(const lr_model_t* m, const lr_pulse_t* pulse, double t0, double dt, int64_t nsteps,
                        lr_c64* d_rho, int32_t obs_stride, double* d_obs, void* d_workspace, size_t bytes,
                        void* stream);
+
+/* Operator application on its own (supplement S1.A: the H_eff B term of the
+ * right-hand side of eq. "nosse"): Z = H_eff(t) B, with H_eff = H(t) -
+ * i/2 (kappa_f n_f + gamma_1 n_q) the model's non-Hermitian Hamiltonian
+ * (kind LR_MODEL_DUFFING) in the lab frame or, with pulse->frame =
+ * LR_FRAME_DRIVE, in the frame rotating at the carrier as lr_integrate takes
+ * it.  d_B, d_Z: device, column-major N x ncols interleaved complex FP64
+ * (column j at d_B + N j); columns are independent, so the factors of many
+ * trajectories of one model at one time may lie side by side (ncols = K M).
+ * B and Z must not overlap.  The integrators fuse this operation into their
+ * stage kernels; this streaming pass reads B once and writes Z once.
+ * Enqueued on `stream` (NULL: the null stream).  LR_ERR_ARG for invalid
+ * arguments, N > 8192 or another model kind; LR_ERR_PULSE for a bad pulse. */
+int lr_apply_heff(const lr_model_t* model, const lr_pulse_t* pulse, double t, const lr_c64* d_B, int64_t ncols,
+                  lr_c64* d_Z, void* stream);
 
 const char* lr_strerror(int code);
 void lr_destroy(lr_ctx_t* ctx);
@@ -326,6 +353,11 @@ int lr_batch_status(lr_batch_t* batch, int32_t* codes, int64_t* failed_steps);
  * again resets the count).  lr_batch_profile_read synchronises the stream and
  * returns the summed kernel time (ms) and the launch count. */
 int lr_batch_profile_enable(lr_batch_t* batch, int32_t on);
+/* lr_wait_limits for every spread-schedule trajectory of a bound batch
+ * (enqueued on the bound stream; applies to later lr_batch_run calls; the
+ * packed and adaptive kernels have no group barriers).  LR_ERR_STATE before
+ * lr_batch_bind. */
+int lr_batch_wait_limits(lr_batch_t* batch, uint32_t spins, int32_t never);
 int lr_batch_profile_read(lr_batch_t* batch, double* ms, int64_t* launches);
 void lr_batch_destroy(lr_batch_t* batch);
 

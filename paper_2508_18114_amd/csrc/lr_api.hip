@@ -17,6 +17,7 @@
 #include "lr_spectrum.hip"
 #include "lr_packed.hip"
 #include "lr_adaptive.hip"
+#include "lr_apply.hip"
 
 using lrk::TrajDev;
 
@@ -175,7 +176,7 @@ const char* lr_strerror(int code) {
     case LR_ERR_ARG: return "invalid argument";
     case LR_ERR_OOM: return "workspace too small";
     case LR_ERR_HIP: return "HIP runtime error";
-    case LR_ERR_GRAM_NOT_PD: return "Gram matrix B^B not positive definite (Cholesky pivot <= 0)";
+    case LR_ERR_GRAM_NOT_PD: return "Gram matrix B^B not positive definite (elimination pivot <= 0)";
     case LR_ERR_NONFINITE: return "non-finite state";
     case LR_ERR_PULSE: return "invalid pulse (unknown kind or amplitude above 2*pi*0.4 rad/ns)";
     case LR_ERR_STATE: return "invalid call order (no workspace bound)";
@@ -437,6 +438,13 @@ int lr_profile_enable(lr_ctx_t* c, int32_t on) {
   return LR_OK;
 }
 
+int lr_wait_limits(lr_ctx_t* c, uint32_t spins, int32_t never) {
+  if (!c) return LR_ERR_ARG;
+  c->base.spin_limit = spins;
+  c->base.wait_bias = never ? 1u : 0u;
+  return LR_OK;
+}
+
 int lr_profile_read(lr_ctx_t* c, double* stage_ms, int64_t* stage_launches, double* solve_ms,
                     int64_t* solve_launches) {
   if (!c) return LR_ERR_ARG;
@@ -517,6 +525,54 @@ int lr_dense_integrate(const lr_model_t* m, const lr_pulse_t* pulse, double t0, 
       hipLaunchKernelGGL(lrk::k_dense_obs, dim3(1), dim3(lrk::kDenseWG), 0, st, D, base, d_obs + (nrec++) * rec);
   }
   return hipGetLastError() == hipSuccess ? LR_OK : LR_ERR_HIP;
+}
+
+int lr_apply_heff(const lr_model_t* m, const lr_pulse_t* pulse, double t, const lr_c64* d_B, int64_t ncols,
+                  lr_c64* d_Z, void* stream) {
+  if (!m || !d_B || !d_Z || ncols < 0 || !std::isfinite(t)) return LR_ERR_ARG;
+  if (m->kind != LR_MODEL_DUFFING || m->d_q < 1 || m->d_r < 1 || m->d_f < 1) return LR_ERR_ARG;
+  const long long Nl = (long long)m->d_q * m->d_r * m->d_f;
+  if (Nl > lrk::kApMaxN) return LR_ERR_ARG;
+  const double vals[] = {m->w_q, m->alpha, m->w_r, m->w_f, m->g, m->G, m->kappa_f, m->gamma_1};
+  for (double x : vals)
+    if (!std::isfinite(x)) return LR_ERR_ARG;
+  if (m->kappa_f < 0.0 || m->gamma_1 < 0.0) return LR_ERR_ARG;
+  if (int e = check_pulse(pulse)) return e;
+  if (reinterpret_cast<const char*>(d_B) < reinterpret_cast<const char*>(d_Z) + Nl * ncols * 16 &&
+      reinterpret_cast<const char*>(d_Z) < reinterpret_cast<const char*>(d_B) + Nl * ncols * 16)
+    return LR_ERR_ARG;  // B and Z overlap
+  if (ncols == 0) return LR_OK;
+  TrajDev pv{};
+  pv.w_q = m->w_q;
+  pv.w_r = m->w_r;
+  pv.w_f = m->w_f;
+  set_pulse(pv, pulse);
+  const bool rot = pulse->frame == LR_FRAME_DRIVE;
+  lrk::ApplyDev D{m->d_q, m->d_r, m->d_f, (int)Nl, pv.w_q, m->alpha, pv.w_r, pv.w_f, m->g, m->G, m->kappa_f,
+                  m->gamma_1, lrk::drive_at(pv, t), lrk::frame_phase(pulse->w_d, t),
+                  lrk::frame_phase(2.0 * pulse->w_d, t)};
+  const int dmax = std::max(std::max(m->d_q, m->d_r), m->d_f);
+  const size_t lds = lrk::apply_lds_bytes((int)Nl, dmax);
+  const void* fn = rot ? (const void*)lrk::k_apply_heff<true> : (const void*)lrk::k_apply_heff<false>;
+  if (lds > 64 * 1024 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return LR_ERR_HIP;
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return LR_ERR_HIP;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, lrk::kApWG, lds) != hipSuccess || per_cu < 1)
+    return LR_ERR_HIP;
+  const long long grid = std::min<long long>(ncols, (long long)per_cu * ncu * 8);
+  const double2* Bp = reinterpret_cast<const double2*>(d_B);
+  double2* Zp = reinterpret_cast<double2*>(d_Z);
+  if (rot)
+    hipLaunchKernelGGL(lrk::k_apply_heff<true>, dim3((unsigned)grid), dim3(lrk::kApWG), lds, (hipStream_t)stream, D,
+                       Bp, Zp, (int64_t)ncols);
+  else
+    hipLaunchKernelGGL(lrk::k_apply_heff<false>, dim3((unsigned)grid), dim3(lrk::kApWG), lds, (hipStream_t)stream, D,
+                       Bp, Zp, (int64_t)ncols);
+  return launch_ok();
 }
 
 void lr_destroy(lr_ctx_t* c) {

@@ -50,7 +50,8 @@ EXPORTS = ("lr_init", "lr_workspace_bytes", "lr_bind", "lr_rhs", "lr_integrate",
            "lr_readout_loss", "lr_dense_workspace_bytes", "lr_dense_integrate", "lr_strerror", "lr_destroy",
            "lr_batch_init", "lr_batch_init_ex", "lr_batch_init_adaptive", "lr_batch_adaptive_stats",
            "lr_batch_workspace_bytes", "lr_batch_graph", "lr_batch_bind", "lr_batch_run",
-           "lr_batch_status", "lr_batch_profile_enable", "lr_batch_profile_read", "lr_batch_destroy")
+           "lr_batch_status", "lr_batch_profile_enable", "lr_batch_profile_read", "lr_batch_destroy",
+           "lr_wait_limits", "lr_batch_wait_limits", "lr_apply_heff")
 
 
 class LrError(RuntimeError):
@@ -122,6 +123,10 @@ def _load():
         "lr_batch_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
         "lr_batch_destroy": (None, [vp]),
         "lr_destroy": (None, [vp]),
+        "lr_wait_limits": (ctypes.c_int, [vp, ctypes.c_uint32, i32]),
+        "lr_batch_wait_limits": (ctypes.c_int, [vp, ctypes.c_uint32, i32]),
+        "lr_apply_heff": (ctypes.c_int, [ctypes.POINTER(lr_model_t), ctypes.POINTER(lr_pulse_t), dbl, vp, i64, vp,
+                                         vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -290,6 +295,24 @@ def readout_loss(obs_g, obs_e, d_q, h, kappa_f, gamma_1, eta=0.6, stream=None):
     return dict(zip(LOSS_KEYS, vals))
 
 
+def apply_heff(model, pulse, t, B, Z=None, stream=None):
+    """Z = H_eff(t) B on the device (lr_apply_heff).  B: device complex128 tensor (ncols, N) (column j of
+    the factor is row j; several factors of one model may be stacked); Z: same shape, allocated if None."""
+    import torch
+    assert B.dtype == torch.complex128 and B.is_cuda and B.is_contiguous() and B.shape[-1] == model.N
+    if Z is None:
+        Z = torch.empty_like(B)
+    assert Z.shape == B.shape and Z.dtype == B.dtype and Z.is_contiguous()
+    ms, ps = model_struct(model), pulse_struct(pulse)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    ncols = B.numel() // model.N
+    rc = _lib.lr_apply_heff(ctypes.byref(ms), ctypes.byref(ps), float(t), B.data_ptr(), ncols, Z.data_ptr(),
+                            st.cuda_stream)
+    if rc != LR_OK:
+        raise LrError(rc, "lr_apply_heff")
+    return Z
+
+
 def dense_integrate(model, pulse, t0, dt, nsteps, rho, obs_stride=0, obs=None, workspace=None, stream=None):
     """Dense full-Lindblad RK4 on the device (lr_dense_integrate).
 
@@ -338,10 +361,10 @@ class Context:
         self.model, self.M, self.precision = model, M, precision
         self.handle = lr_init(model, M, precision)
         nbytes = lr_workspace_bytes(self.handle)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.workspace = _stream_buffer(nbytes + 256, self.stream)
         base = self.workspace.data_ptr()
         off = (-base) % 256
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
         rc = lr_bind(self.handle, base + off, nbytes, self.stream.cuda_stream)
         if rc != LR_OK:
             raise LrError(rc, "lr_bind")
@@ -374,21 +397,50 @@ class Context:
     def status(self):
         return lr_status(self.handle)
 
+    def wait_limits(self, spins=0, never=False):
+        """Bounded waits of the group barriers (lr_wait_limits): `spins` polls (0: the default);
+        never=True makes every wait expire (failure-handling tests)."""
+        self._check(_lib.lr_wait_limits(self.handle, int(spins), 1 if never else 0), "lr_wait_limits")
+
     def new_obs(self, nsteps, obs_stride):
         import torch
         n = nsteps // obs_stride + 1 if obs_stride > 0 else 0
         return torch.zeros((n, obs_len(self.model)), dtype=torch.float64, device="cuda")
 
     def close(self):
+        """Wait for the context's stream, then free the library handle and the workspace."""
         if self.handle:
+            self.stream.synchronize()
             lr_destroy(self.handle)
             self.handle = None
+        self.workspace = None
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self, lr_destroy)
+
+
+def _stream_buffer(nbytes, stream):
+    """Device workspace allocated on `stream` (the caching allocator then reuses it only after the work
+    queued on that stream, whichever stream is current when it is freed)."""
+    import torch
+    with torch.cuda.stream(stream):
+        return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+
+def _finalize(obj, destroy):
+    """Release of a handle by the garbage collector.  During interpreter shutdown the HIP runtime may
+    already be gone, so nothing is called then (the process is ending; the handle's host memory goes
+    with it)."""
+    import sys
+    h = getattr(obj, "handle", None)
+    if not h or sys.is_finalizing():
+        return
+    try:
+        obj.stream.synchronize()
+        destroy(h)
+        obj.handle = None
+    except Exception:
+        pass
 
 
 def traj_struct(model, M, pulse, t0, dt, nsteps, B_dev, obs_stride=0, obs_dev=None,
@@ -418,10 +470,10 @@ class Batch:
               for it in self.items]
         self.handle = lr_batch_init(ts, (LR_BATCH_PACKED if packed else 0) | int(flags), adaptive)
         nbytes = lr_batch_workspace_bytes(self.handle)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.workspace = _stream_buffer(nbytes + 256, self.stream)
         base = self.workspace.data_ptr()
         off = (-base) % 256
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
         rc = lr_batch_bind(self.handle, base + off, nbytes, self.stream.cuda_stream)
         if rc != LR_OK:
             raise LrError(rc, "lr_batch_bind")
@@ -433,6 +485,12 @@ class Batch:
 
     def status(self):
         return lr_batch_status(self.handle, len(self.items))
+
+    def wait_limits(self, spins=0, never=False):
+        """lr_batch_wait_limits: bounded waits of the spread schedule's group barriers."""
+        rc = _lib.lr_batch_wait_limits(self.handle, int(spins), 1 if never else 0)
+        if rc != LR_OK:
+            raise LrError(rc, "lr_batch_wait_limits")
 
     def graph(self, on=True):
         """Capture the launch sequence once and replay it on every run (packed batches)."""
@@ -463,12 +521,12 @@ class Batch:
         return ms, n
 
     def close(self):
+        """Wait for the batch's stream, then free the library handle and the workspace."""
         if self.handle:
+            self.stream.synchronize()
             lr_batch_destroy(self.handle)
             self.handle = None
+        self.workspace = None
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _finalize(self, lr_batch_destroy)

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 from oracle import loss, lowrank
+from oracle import pulses as opulses
 from paper_2508_18114_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -1202,3 +1203,59 @@ def test_transmon_model_few_layers(lr, d_r, M, frame):
     _, refa, acc_o, rej_o = adaptive.integrate(m, p, 0.0, 0.05, 4, ia["B0"], 1e-9, 1e-12, obs_stride=2)
     _assert_obs(ia["obs"].cpu().numpy(), refa, f"transmon adaptive d_r={d_r} M={M} frame={frame}")
     assert abs(acc[0] - acc_o) <= 3 and abs(rej[0] - rej_o) <= 3
+
+
+# ------------------------------------------------------------ operator application on its own
+
+@pytest.mark.parametrize("dims,ncols,frame", [((8, 50, 5), 40, 0), ((8, 50, 5), 40, 1), ((3, 7, 4), 13, 0),
+                                              ((2, 1, 1), 3, 1), ((8, 75, 5), 64, 0), ((4, 10, 5), 1, 1)])
+def test_apply_heff_matches_oracle(lr, dims, ncols, frame):
+    """Z = H_eff(t) B (lr_apply_heff) against the oracle's mode-wise operators, lab and drive frame,
+    several columns side by side (a ragged count included).  Each entry of Z is a sum of at most 11
+    products: the bound is a few ulps of the largest entry."""
+    m = I.readout_model(*dims).replace(kappa_f=0.7, gamma_1=0.3)
+    p = I.flattop_pulse(0.09, 6.0).replace(frame=frame)
+    B = _rand_B(m.N, ncols, 31 + ncols)
+    Bd = lr.to_device(B)
+    for t in (0.0, 1.3, 3.7):
+        d_t = opulses.drive(p, t)
+        ref = (lowrank.apply_heff_drive_frame(m, d_t, p.w_d, t, B) if frame else lowrank.apply_heff(m, d_t, B))
+        got = lr.from_device(lr.apply_heff(m, p, t, Bd))
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        print(f"[parity] apply_heff dims={dims} ncols={ncols} frame={frame} t={t}: rel err {err:.3e}")
+        assert err <= 1e-14
+
+
+def test_apply_heff_full_width_sampled(lr):
+    """The measured width: 512 factors of N = 2000, M = 20 side by side (10240 columns, 328 MB in and
+    out); sampled columns against the oracle, applied column by column."""
+    import torch
+    m = I.readout_model(8, 50, 5)
+    p = I.config_paper_size()[0].pulse
+    ncols = 512 * 20
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    Bd = torch.randn((ncols, m.N), dtype=torch.complex128, device="cuda", generator=gen)
+    t = 7.25
+    Z = lr.apply_heff(m, p, t, Bd)
+    torch.cuda.synchronize()
+    d_t = opulses.drive(p, t)
+    rs = np.random.default_rng(6)
+    for c in list(rs.choice(ncols, 12, replace=False)) + [0, ncols - 1]:
+        b = Bd[c].cpu().numpy()[:, None]
+        ref = lowrank.apply_heff(m, d_t, b)[:, 0]
+        got = Z[c].cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref)), c
+
+
+def test_apply_heff_rejections(lr):
+    import torch
+    m = I.readout_model(2, 3, 2)
+    p = I.flattop_pulse(0.05, 1.0)
+    B = torch.zeros((2, m.N), dtype=torch.complex128, device="cuda")
+    with pytest.raises(lr.LrError):
+        lr.apply_heff(m, I.flattop_pulse(0.5, 1.0), 0.0, B)        # drive above the bound
+    big = I.readout_model(8, 300, 5)                                   # N = 12000 > 8192
+    with pytest.raises(lr.LrError):
+        lr.apply_heff(big, p, 0.0, torch.zeros((1, big.N), dtype=torch.complex128, device="cuda"))
+    with pytest.raises(lr.LrError):                                    # B and Z overlap
+        lr.apply_heff(m, p, 0.0, B, B)
