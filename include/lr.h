@@ -261,6 +261,27 @@ int lr_dense_integrate(const lr_model_t* m, const lr_pulse_t* pulse, double t0, 
 int lr_apply_heff(const lr_model_t* model, const lr_pulse_t* pulse, double t, const lr_c64* d_B, int64_t ncols,
                   lr_c64* d_Z, void* stream);
 
+/* lr_integrate for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * integration -- the persistent on-chip path of lr_init + lr_bind +
+ * lr_integrate with this model, rank and precision, bitwise the same result --
+ * with no context, no caller workspace and no allocation of any kind.  Its
+ * workspace is a fixed 16 MiB array in device memory inside the library (one
+ * per GPU, held until the process ends); shapes whose persistent-path
+ * workspace exceeds it return LR_ERR_OOM (N = 2000 at M = 20 takes 3.7 MiB,
+ * N = 3000 at M = 32 11.6 MiB), shapes without a persistent configuration
+ * LR_ERR_ARG.  Arguments and
+ * records as lr_init and lr_integrate.  d_status (device, 2 int64, may be
+ * NULL) receives {status code, failing step} at the end of the enqueued work:
+ * the device-side errors lr_status would report.  Enqueued on `stream` (NULL:
+ * the null stream).  Every call on a GPU uses that GPU's one array, which
+ * keeps the last call's contents (every call re-initialises what it reads):
+ * calls that overlap on one GPU -- on different streams or from different
+ * threads -- race and must not be issued. */
+int lr_integrate_noalloc(const lr_model_t* model, int32_t M, int32_t precision, const lr_pulse_t* pulse, double t0,
+                         double dt, int64_t nsteps, lr_c64* d_B, int32_t obs_stride, double* d_obs,
+                         int64_t* d_status, void* stream);
+
 const char* lr_strerror(int code);
 void lr_destroy(lr_ctx_t* ctx);
 

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -31,6 +32,7 @@ struct lr_ctx {
   int P = 0, prt = 1, prows = 2;
   size_t pers_lds = 0;
   size_t off_ptilemap = 0, off_SP = 0, off_PART = 0, off_RED = 0, off_flagA = 0, off_flagB = 0;
+  bool persist_only = false;  // no multi-kernel buffers in the layout
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   TrajDev base{};
@@ -39,6 +41,25 @@ struct lr_ctx {
   std::vector<hipEvent_t> ev_stage, ev_solve;  // start/stop pairs
   int64_t n_stage = 0, n_solve = 0;
 };
+
+// Workspace of lr_integrate_noalloc: a fixed array in device memory, one copy
+// per GPU (each holds it until the process ends).  Host code never uses the
+// array's name as an address: the device address of each GPU's copy comes
+// from hipGetSymbolAddress on that device (scratch_ptr).
+constexpr size_t kNoallocScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+namespace lrk {
+// Device status of a trajectory (code, failing step) into caller memory.
+__global__ void k_copy_status(const TrajDev* __restrict__ T, int64_t* dst) {
+  dst[0] = *T->status;
+  dst[1] = *T->fail_step;
+}
+// Tile map of the persistent kernel of one trajectory: workgroup w -> (0, w).
+__global__ void k_fill_tilemap(int2* map, int P) {
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < P; w += gridDim.x * blockDim.x) map[w] = make_int2(0, w);
+}
+}  // namespace lrk
 
 namespace {
 
@@ -166,29 +187,9 @@ int prologue(lr_ctx* c, const TrajDev& v, const lr_c64* d_B) {
   return launch_ok();
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* lr_strerror(int code) {
-  switch (code) {
-    case LR_OK: return "ok";
-    case LR_ERR_ARG: return "invalid argument";
-    case LR_ERR_OOM: return "workspace too small";
-    case LR_ERR_HIP: return "HIP runtime error";
-    case LR_ERR_GRAM_NOT_PD: return "Gram matrix B^B not positive definite (elimination pivot <= 0)";
-    case LR_ERR_NONFINITE: return "non-finite state";
-    case LR_ERR_PULSE: return "invalid pulse (unknown kind or amplitude above 2*pi*0.4 rad/ns)";
-    case LR_ERR_STATE: return "invalid call order (no workspace bound)";
-    case LR_ERR_TIMEOUT: return "device-side wait expired";
-    case LR_ERR_STEP: return "adaptive step size underflow or step budget spent";
-    default: return "unknown error";
-  }
-}
-
-int lr_init(lr_ctx_t** out, const lr_model_t* m, int32_t M, int32_t precision) {
-  if (!out || !m) return LR_ERR_ARG;
-  *out = nullptr;
+// Validation and workspace layout of a context (lr_init); persist_only leaves
+// out the buffers of the multi-kernel path.
+int ctx_setup(lr_ctx* c, const lr_model_t* m, int32_t M, int32_t precision, bool persist_only) {
   if (m->kind != LR_MODEL_DUFFING) return LR_ERR_ARG;  // the eigenbasis model runs in packed batches only
   if (m->d_q < 2 || m->d_r < 1 || m->d_f < 1) return LR_ERR_ARG;
   const long long N = (long long)m->d_q * m->d_r * m->d_f;
@@ -202,8 +203,6 @@ int lr_init(lr_ctx_t** out, const lr_model_t* m, int32_t M, int32_t precision) {
   const int L = m->d_q * m->d_f;
   if ((long long)L * M > lrk::kMaxTileElems) return LR_ERR_ARG;
 
-  lr_ctx* c = new (std::nothrow) lr_ctx();
-  if (!c) return LR_ERR_OOM;
   c->model = *m;
   c->M = M;
   c->prec = precision;
@@ -236,16 +235,19 @@ int lr_init(lr_ctx_t** out, const lr_model_t* m, int32_t M, int32_t precision) {
   }
   const size_t a = 256, nm = (size_t)N * M * sizeof(double2), mm = (size_t)M * M * sizeof(double2);
   size_t o = 0;
+  c->persist_only = persist_only;
   c->off_traj = o;    o = align_up(o + sizeof(TrajDev), a);
-  c->off_tilemap = o; o = align_up(o + (size_t)c->ntiles * sizeof(int2), a);
-  c->off_rt = o;      o = align_up(o + sizeof(int), a);
   c->off_Bb = o;      o = align_up(o + nm, a);
-  c->off_S0 = o;      o = align_up(o + nm, a);
-  c->off_S1 = o;      o = align_up(o + nm, a);
-  c->off_acc = o;     o = align_up(o + nm, a);
-  c->off_W = o;       o = align_up(o + 4 * mm, a);
-  c->off_part = o;    o = align_up(o + (size_t)c->ntiles * 3 * mm, a);
   c->off_misc = o;    o = align_up(o + 64, a);
+  if (!persist_only) {  // the multi-kernel path (lr_rhs, lr_observables, fallback)
+    c->off_tilemap = o; o = align_up(o + (size_t)c->ntiles * sizeof(int2), a);
+    c->off_rt = o;      o = align_up(o + sizeof(int), a);
+    c->off_S0 = o;      o = align_up(o + nm, a);
+    c->off_S1 = o;      o = align_up(o + nm, a);
+    c->off_acc = o;     o = align_up(o + nm, a);
+    c->off_W = o;       o = align_up(o + 4 * mm, a);
+    c->off_part = o;    o = align_up(o + (size_t)c->ntiles * 3 * mm, a);
+  }
   if (c->P > 0) {
     const size_t npe = 3 * mm;
     c->off_ptilemap = o; o = align_up(o + (size_t)c->P * sizeof(int2), a);
@@ -263,25 +265,22 @@ int lr_init(lr_ctx_t** out, const lr_model_t* m, int32_t M, int32_t precision) {
   b.nsteps = 0;
   b.w_q = m->w_q; b.alpha = m->alpha; b.w_r = m->w_r; b.w_f = m->w_f;
   b.g = m->g; b.G = m->G; b.kappa = m->kappa_f; b.gamma = m->gamma_1;
-  *out = c;
   return LR_OK;
 }
 
-size_t lr_workspace_bytes(const lr_ctx_t* c) { return c ? c->total : 0; }
 
-int lr_bind(lr_ctx_t* c, void* d_ws, size_t bytes, void* stream) {
-  if (!c || !d_ws) return LR_ERR_ARG;
-  if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return LR_ERR_ARG;
-  if (bytes < c->total) return LR_ERR_OOM;
-  c->ws = static_cast<char*>(d_ws);
-  c->stream = static_cast<hipStream_t>(stream);
+// Device pointers of a context's descriptor into the workspace ws.
+void ctx_pointers(lr_ctx* c, char* ws, hipStream_t stream) {
+  c->ws = ws;
+  c->stream = stream;
   TrajDev& b = c->base;
-  b.Bb = reinterpret_cast<double2*>(c->ws + c->off_Bb);
-  b.S0 = reinterpret_cast<double2*>(c->ws + c->off_S0);
-  b.S1 = reinterpret_cast<double2*>(c->ws + c->off_S1);
-  b.acc = reinterpret_cast<double2*>(c->ws + c->off_acc);
-  b.W = reinterpret_cast<double2*>(c->ws + c->off_W);
-  b.part = reinterpret_cast<double2*>(c->ws + c->off_part);
+  auto at = [&](size_t off) { return reinterpret_cast<double2*>(c->ws + off); };
+  b.Bb = at(c->off_Bb);
+  b.S0 = c->persist_only ? nullptr : at(c->off_S0);
+  b.S1 = c->persist_only ? nullptr : at(c->off_S1);
+  b.acc = c->persist_only ? nullptr : at(c->off_acc);
+  b.W = c->persist_only ? nullptr : at(c->off_W);
+  b.part = c->persist_only ? nullptr : at(c->off_part);
   b.step = reinterpret_cast<int64_t*>(c->ws + c->off_misc);
   b.fail_step = reinterpret_cast<int64_t*>(c->ws + c->off_misc + 8);
   b.fro2 = reinterpret_cast<double*>(c->ws + c->off_misc + 16);
@@ -293,12 +292,109 @@ int lr_bind(lr_ctx_t* c, void* d_ws, size_t bytes, void* stream) {
   b.npe = 3 * c->M * c->M;
   b.prec = c->prec;
   if (c->P > 0) {
-    b.SP = reinterpret_cast<double2*>(c->ws + c->off_SP);
-    b.PART = reinterpret_cast<double2*>(c->ws + c->off_PART);
-    b.RED = reinterpret_cast<double2*>(c->ws + c->off_RED);
+    b.SP = at(c->off_SP);
+    b.PART = at(c->off_PART);
+    b.RED = at(c->off_RED);
     b.flagA = reinterpret_cast<uint32_t*>(c->ws + c->off_flagA);
     b.flagB = reinterpret_cast<uint32_t*>(c->ws + c->off_flagB);
   }
+}
+
+// Enqueue the integration of descriptor v (pulse, times, records set) on the
+// persistent on-chip path of a bound context: descriptor, resets, layout in,
+// prologue, chunks of steps with records, layout out.
+int integrate_persist(lr_ctx* c, const TrajDev& v, int64_t nsteps, lr_c64* d_B, int32_t obs_stride) {
+  hipLaunchKernelGGL(lrk::k_set_traj, dim3(1), dim3(1), 0, c->stream, dev_traj(c), v);
+  hipLaunchKernelGGL(lrk::k_reset, dim3(1), dim3(64), 0, c->stream, dev_traj(c), 1);
+  hipLaunchKernelGGL(lrk::k_reset_persist, dim3(1), dim3(256), 0, c->stream, dev_traj(c), 1);
+  hipLaunchKernelGGL(lrk::k_to_internal, dim3(grid_for(c)), dim3(lrk::kWG), 0, c->stream, dev_traj(c), 0,
+                     reinterpret_cast<const double2*>(d_B), c->base.Bb);
+  if (int e = launch_ok()) return e;
+  if (int e = launch_persist(c, 1, 0, 0)) return e;
+  if (obs_stride > 0)
+    hipLaunchKernelGGL(lrk::k_obs, dim3(1), dim3(lrk::kWG), 0, c->stream, dev_traj(c), (double*)nullptr);
+  const int64_t max_chunk = obs_stride > 0 ? obs_stride : 4096;
+  for (int64_t step = 0; step < nsteps;) {
+    const int64_t chunk = (nsteps - step < max_chunk) ? nsteps - step : max_chunk;
+    if (int e = launch_persist(c, 0, step, chunk)) return e;
+    step += chunk;
+    if (obs_stride > 0 && step % obs_stride == 0)
+      hipLaunchKernelGGL(lrk::k_obs, dim3(1), dim3(lrk::kWG), 0, c->stream, dev_traj(c), (double*)nullptr);
+  }
+  hipLaunchKernelGGL(lrk::k_to_abi, dim3(grid_for(c)), dim3(lrk::kWG), 0, c->stream, dev_traj(c), 0, c->base.Bb,
+                     reinterpret_cast<double2*>(d_B));
+  return launch_ok();
+}
+
+// Dynamic-LDS attribute of the persistent kernels of a context's variant.
+int persist_attributes(const lr_ctx* c) {
+  for (int pro = 0; pro < 2; ++pro) {
+    const void* fn = lrk::persist_kernel(c->prows, lrk::persist_ge(c->M), pro != 0, c->prec);
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->pers_lds) != hipSuccess)
+      return LR_ERR_HIP;
+  }
+  return LR_OK;
+}
+
+// Device address of the current GPU's copy of `scratch` (looked up once per
+// device, with that device current).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_ptr(char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return LR_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LR_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<char*>(g_scratch_ptr[dev]);
+  return LR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lr_strerror(int code) {
+  switch (code) {
+    case LR_OK: return "ok";
+    case LR_ERR_ARG: return "invalid argument";
+    case LR_ERR_OOM: return "workspace too small";
+    case LR_ERR_HIP: return "HIP runtime error";
+    case LR_ERR_GRAM_NOT_PD: return "Gram matrix B^B not positive definite (elimination pivot <= 0)";
+    case LR_ERR_NONFINITE: return "non-finite state";
+    case LR_ERR_PULSE: return "invalid pulse (unknown kind or amplitude above 2*pi*0.4 rad/ns)";
+    case LR_ERR_STATE: return "invalid call order (no workspace bound)";
+    case LR_ERR_TIMEOUT: return "device-side wait expired";
+    case LR_ERR_STEP: return "adaptive step size underflow or step budget spent";
+    default: return "unknown error";
+  }
+}
+
+int lr_init(lr_ctx_t** out, const lr_model_t* m, int32_t M, int32_t precision) {
+  if (!out || !m) return LR_ERR_ARG;
+  *out = nullptr;
+  lr_ctx* c = new (std::nothrow) lr_ctx();
+  if (!c) return LR_ERR_OOM;
+  if (int e = ctx_setup(c, m, M, precision, false)) {
+    delete c;
+    return e;
+  }
+  *out = c;
+  return LR_OK;
+}
+
+size_t lr_workspace_bytes(const lr_ctx_t* c) { return c ? c->total : 0; }
+
+int lr_bind(lr_ctx_t* c, void* d_ws, size_t bytes, void* stream) {
+  if (!c || !d_ws) return LR_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) return LR_ERR_ARG;
+  if (bytes < c->total) return LR_ERR_OOM;
+  ctx_pointers(c, static_cast<char*>(d_ws), static_cast<hipStream_t>(stream));
 
   // static tile map of this shape (one entry per workgroup of k_stage)
   const int nmap = c->ntiles > c->P ? c->ntiles : c->P;
@@ -316,13 +412,7 @@ int lr_bind(lr_ctx_t* c, void* d_ws, size_t bytes, void* stream) {
   hipError_t e3 = hipStreamSynchronize(c->stream);
   delete[] tm;
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) return LR_ERR_HIP;
-  if (c->P > 0) {
-    for (int pro = 0; pro < 2; ++pro) {
-      const void* fn = lrk::persist_kernel(c->prows, lrk::persist_ge(c->M), pro != 0, c->prec);
-      if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->pers_lds) != hipSuccess)
-        return LR_ERR_HIP;
-    }
-  }
+  if (c->P > 0) return persist_attributes(c);
   return LR_OK;
 }
 
@@ -359,28 +449,7 @@ int lr_integrate(lr_ctx_t* c, const lr_pulse_t* pulse, double t0, double dt, int
   v.obs_stride = obs_stride;
   // the reduced-precision modes exist on the persistent path only
   if (c->prec != LR_FP64 && (c->P == 0 || std::getenv("LR_NO_PERSIST"))) return LR_ERR_ARG;
-  if (c->P > 0 && !std::getenv("LR_NO_PERSIST")) {
-    hipLaunchKernelGGL(lrk::k_set_traj, dim3(1), dim3(1), 0, c->stream, dev_traj(c), v);
-    hipLaunchKernelGGL(lrk::k_reset, dim3(1), dim3(64), 0, c->stream, dev_traj(c), 1);
-    hipLaunchKernelGGL(lrk::k_reset_persist, dim3(1), dim3(256), 0, c->stream, dev_traj(c), 1);
-    hipLaunchKernelGGL(lrk::k_to_internal, dim3(grid_for(c)), dim3(lrk::kWG), 0, c->stream, dev_traj(c), 0,
-                       reinterpret_cast<const double2*>(d_B), c->base.Bb);
-    if (int e = launch_ok()) return e;
-    if (int e = launch_persist(c, 1, 0, 0)) return e;
-    if (obs_stride > 0)
-      hipLaunchKernelGGL(lrk::k_obs, dim3(1), dim3(lrk::kWG), 0, c->stream, dev_traj(c), (double*)nullptr);
-    const int64_t max_chunk = obs_stride > 0 ? obs_stride : 4096;
-    for (int64_t step = 0; step < nsteps;) {
-      const int64_t chunk = (nsteps - step < max_chunk) ? nsteps - step : max_chunk;
-      if (int e = launch_persist(c, 0, step, chunk)) return e;
-      step += chunk;
-      if (obs_stride > 0 && step % obs_stride == 0)
-        hipLaunchKernelGGL(lrk::k_obs, dim3(1), dim3(lrk::kWG), 0, c->stream, dev_traj(c), (double*)nullptr);
-    }
-    hipLaunchKernelGGL(lrk::k_to_abi, dim3(grid_for(c)), dim3(lrk::kWG), 0, c->stream, dev_traj(c), 0,
-                       c->base.Bb, reinterpret_cast<double2*>(d_B));
-    return launch_ok();
-  }
+  if (c->P > 0 && !std::getenv("LR_NO_PERSIST")) return integrate_persist(c, v, nsteps, d_B, obs_stride);
   if (int e = prologue(c, v, d_B)) return e;
   launch_solve(c, 0, 0, lrk::MODE_RHS);
   if (obs_stride > 0)
@@ -572,6 +641,36 @@ int lr_apply_heff(const lr_model_t* m, const lr_pulse_t* pulse, double t, const 
   else
     hipLaunchKernelGGL(lrk::k_apply_heff<false>, dim3((unsigned)grid), dim3(lrk::kApWG), lds, (hipStream_t)stream, D,
                        Bp, Zp, (int64_t)ncols);
+  return launch_ok();
+}
+
+int lr_integrate_noalloc(const lr_model_t* m, int32_t M, int32_t precision, const lr_pulse_t* pulse, double t0,
+                         double dt, int64_t nsteps, lr_c64* d_B, int32_t obs_stride, double* d_obs,
+                         int64_t* d_status, void* stream) {
+  if (!m || !d_B || !std::isfinite(t0) || !(dt > 0.0) || !std::isfinite(dt) || nsteps < 0 || obs_stride < 0)
+    return LR_ERR_ARG;
+  if (obs_stride > 0 && !d_obs) return LR_ERR_ARG;
+  if (int e = check_pulse(pulse)) return e;
+  lr_ctx c;  // host descriptor on the stack: no allocation
+  if (int e = ctx_setup(&c, m, M, precision, true)) return e;
+  if (c.P == 0) return LR_ERR_ARG;                        // no persistent configuration for this shape
+  if (c.total > kNoallocScratchBytes) return LR_ERR_OOM;  // above the fixed workspace
+  char* ws = nullptr;
+  if (int e = scratch_ptr(&ws)) return e;
+  ctx_pointers(&c, ws, static_cast<hipStream_t>(stream));
+  if (int e = persist_attributes(&c)) return e;
+  hipLaunchKernelGGL(lrk::k_fill_tilemap, dim3(1), dim3(256), 0, c.stream,
+                     reinterpret_cast<int2*>(c.ws + c.off_ptilemap), c.P);
+  TrajDev v = c.base;
+  set_pulse(v, pulse);
+  v.t0 = t0;
+  v.dt = dt;
+  v.nsteps = nsteps;
+  v.obs = obs_stride > 0 ? d_obs : nullptr;
+  v.obs_stride = obs_stride;
+  if (int e = integrate_persist(&c, v, nsteps, d_B, obs_stride)) return e;
+  if (d_status)
+    hipLaunchKernelGGL(lrk::k_copy_status, dim3(1), dim3(1), 0, c.stream, dev_traj(&c), d_status);
   return launch_ok();
 }
 

@@ -51,7 +51,7 @@ EXPORTS = ("lr_init", "lr_workspace_bytes", "lr_bind", "lr_rhs", "lr_integrate",
            "lr_batch_init", "lr_batch_init_ex", "lr_batch_init_adaptive", "lr_batch_adaptive_stats",
            "lr_batch_workspace_bytes", "lr_batch_graph", "lr_batch_bind", "lr_batch_run",
            "lr_batch_status", "lr_batch_profile_enable", "lr_batch_profile_read", "lr_batch_destroy",
-           "lr_wait_limits", "lr_batch_wait_limits", "lr_apply_heff")
+           "lr_wait_limits", "lr_batch_wait_limits", "lr_apply_heff", "lr_integrate_noalloc")
 
 
 class LrError(RuntimeError):
@@ -127,6 +127,8 @@ def _load():
         "lr_batch_wait_limits": (ctypes.c_int, [vp, ctypes.c_uint32, i32]),
         "lr_apply_heff": (ctypes.c_int, [ctypes.POINTER(lr_model_t), ctypes.POINTER(lr_pulse_t), dbl, vp, i64, vp,
                                          vp]),
+        "lr_integrate_noalloc": (ctypes.c_int, [ctypes.POINTER(lr_model_t), i32, i32, ctypes.POINTER(lr_pulse_t), dbl,
+                                                dbl, i64, vp, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -293,6 +295,14 @@ def readout_loss(obs_g, obs_e, d_q, h, kappa_f, gamma_1, eta=0.6, stream=None):
         raise LrError(rc, "lr_readout_loss")
     vals = out.cpu().tolist()
     return dict(zip(LOSS_KEYS, vals))
+
+
+def lr_integrate_noalloc(model, M, precision, pulse, t0, dt, nsteps, d_B: int, obs_stride: int, d_obs: int,
+                         d_status: int, stream: int) -> int:
+    """Raw call of lr_integrate_noalloc (device pointers as integers)."""
+    ms, ps = model_struct(model), pulse_struct(pulse)
+    return _lib.lr_integrate_noalloc(ctypes.byref(ms), M, precision, ctypes.byref(ps), t0, dt, nsteps, d_B,
+                                     obs_stride, d_obs or None, d_status or None, stream)
 
 
 def apply_heff(model, pulse, t, B, Z=None, stream=None):
