@@ -294,10 +294,10 @@ __device__ __forceinline__ double pivot_rcp(double p) {
 // M x (M + share) matrix on its own (the G columns are eliminated identically
 // in every wave).  Within a wave, H consecutive lanes own one column and lane
 // h of a column holds the RPL consecutive rows h RPL .. h RPL + RPL - 1 in
-// registers.  Per pivot the
-// multiplier column (column k) and the pivot row entries are handed between
-// lanes through a small per-wave LDS area (written by their owners during the
-// previous pivot; a wave's LDS accesses are performed in order).
+// registers.  Per pivot the multiplier column (column k) and the pivot row
+// entries are handed between lanes through a small per-wave LDS area (a
+// wave's LDS accesses are performed in order: no barrier).  The four waves'
+// LDS traffic shares the CU's one LDS unit, which bounds a pivot.
 constexpr int kSolveWaves = 4;
 constexpr int kWsLds = 4 * 64;  // LDS (complex entries) per solver wave: multiplier column and pivot row, two each
 constexpr int kWsRows = 10;     // register rows of a solver lane (ranks M <= 20)
@@ -354,6 +354,13 @@ __device__ __forceinline__ void wsolve_load(const g_double2* red, int M, const W
   }
 }
 
+// Value of v in lane `lane` of the wave (a uniform result).
+__device__ __forceinline__ double ws_readlane(double v, int lane) {
+  const uint64_t u = __double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane), hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -367,7 +374,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // non-positive pivot or -1.  The caller synchronises the workgroup before
 // reading Wl or the flags.  A lane holds RC rows (rows past M are zero and
 // stay zero); the pivots run in blocks of RC, so that within a block the
-// register of the pivot row is known at compile time.
+// register of the pivot row is known at compile time.  The multiplier column
+// and the pivot row of pivot k + 1 are written to the wave's LDS area by
+// their owners during pivot k and read back by every lane (broadcast reads).
 template <int RC>
 __device__ __forceinline__ void wsolve_run(WsRegs<RC>& R, const WsMap& m, double2* scratch, double2* Wl, int M,
                                            int* s_nonfinite, int* badk) {
@@ -389,49 +398,51 @@ __device__ __forceinline__ void wsolve_run(WsRegs<RC>& R, const WsMap& m, double
     for (int idx = 0; idx < RC; ++idx) myrows[idx] = R.a[idx];
   }
   if (h == 0) prow[slot] = R.a[0];
-  bool stop = false;
-  for (int kb = 0, hk = 0; kb < M && !stop; kb += RC, ++hk) {  // row block hk: pivots kb .. kb + RC - 1
+  // every pivot runs (straight-line code per pivot); the first non-positive one is recorded and the
+  // caller discards the result
+  int first_bad = -1;
+  for (int kb = 0, hk = 0; kb < M; kb += RC, ++hk) {  // row block hk: pivots kb .. kb + RC - 1
 #pragma unroll
     for (int j = 0; j < RC; ++j) {  // j, hence the register of the pivot row, is a constant per copy
       const int k = kb + j;
-      if (k < M && !stop) {  // uniform
+      if (k < M) {  // uniform
         const int par = k & 1;
         wave_lds_sync();
         const double2* mrow = myrows + par * 64;
         double2 mi[RC];
 #pragma unroll
         for (int idx = 0; idx < RC; ++idx) mi[idx] = mrow[idx];  // A[row][k] of the lane's rows
-        const double piv = mcol[par * 64 + k].x;
         const double2 pr = prow[par * 64 + slot];
-        const double rinv = pivot_rcp(piv > 0.0 ? piv : 1.0);  // (the reads above complete together)
-        if (!(piv > 0.0)) {  // uniform: every lane read the same pivot
-          *badk = k;
-          stop = true;
-        } else {
-          const double2 pc = make_double2(pr.x * rinv, pr.y * rinv);  // row k of the result, this column
+        // the pivot A[k][k] is register j of lane hk (column slot 0, row block hk): a uniform value
+        const double piv = ws_readlane(mi[j].x, hk);
+        if (!(piv > 0.0) && first_bad < 0) first_bad = k;
+        const double rinv = pivot_rcp(piv > 0.0 ? piv : 1.0);
+        const double2 pc = make_double2(pr.x * rinv, pr.y * rinv);  // row k of the result, this column
 #pragma unroll
-          for (int idx = 0; idx < RC; ++idx) {
-            double2 v = R.a[idx];
-            v.x = fma(-mi[idx].x, pc.x, v.x);
-            v.x = fma(mi[idx].y, pc.y, v.x);
-            v.y = fma(-mi[idx].x, pc.y, v.y);
-            v.y = fma(-mi[idx].y, pc.x, v.y);
-            R.a[idx] = v;
-          }
-          if (h == hk) R.a[j] = pc;  // the pivot row itself
-          // pivot row and multiplier column of the next pivot k + 1 (row block hn, register (j + 1) % RC)
-          const int hn = j + 1 < RC ? hk : hk + 1;
-          if (h == hn) prow[(par ^ 1) * 64 + slot] = R.a[(j + 1) % RC];
-          if (slot == k + 1) {
-            double2* mnext = myrows + (par ^ 1) * 64;
+        for (int idx = 0; idx < RC; ++idx) {
+          double2 v = R.a[idx];
+          v.x = fma(-mi[idx].x, pc.x, v.x);
+          v.x = fma(mi[idx].y, pc.y, v.x);
+          v.y = fma(-mi[idx].x, pc.y, v.y);
+          v.y = fma(-mi[idx].y, pc.x, v.y);
+          R.a[idx] = v;
+        }
+        if (h == hk) R.a[j] = pc;  // the pivot row itself
+        // pivot row and multiplier column of the next pivot k + 1 (row block hn, register (j + 1) % RC)
+        const int hn = j + 1 < RC ? hk : hk + 1;
+        if (h == hn) prow[(par ^ 1) * 64 + slot] = R.a[(j + 1) % RC];
+        if (slot == k + 1) {
+          double2* mnext = myrows + (par ^ 1) * 64;
 #pragma unroll
-            for (int idx = 0; idx < RC; ++idx) mnext[idx] = R.a[idx];
-          }
+          for (int idx = 0; idx < RC; ++idx) mnext[idx] = R.a[idx];
         }
       }
     }
   }
-  if (stop) return;
+  if (first_bad >= 0) {
+    *badk = first_bad;
+    return;
+  }
   // right-hand-side lanes hold X_k[:, i]: W_k[i][j] = conj(X_k[j][i])
   if (m.act && slot >= M) {
     const int cc = m.cbase + slot - M, kk = cc < M ? 0 : 1, i = cc - kk * M;

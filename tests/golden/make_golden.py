@@ -4,6 +4,8 @@ Calls only the CPU oracle and the seeded input generators.  Usage:
 
     OMP_NUM_THREADS=1 python tests/golden/make_golden.py [small|paper_size|all]
 
+    OMP_NUM_THREADS=1 python tests/golden/make_golden.py adaptive_paper_size
+
 Outputs (numpy .npz, one per named workload):
     tests/golden/config_small.npz       dims (4,10,5),  M=4,  1e4 steps of 1e-3 ns
     tests/golden/config_paper_size.npz  dims (8,50,5),  M=20, 8e4 steps of 5e-4 ns
@@ -11,6 +13,10 @@ Outputs (numpy .npz, one per named workload):
                                         the same with the paper's padding weight 1e-5
 each holding obs_g, obs_e (observable records every `stride` steps), the
 stride, dt, and the readout figures of merit from the g/e pair.
+    tests/golden/adaptive_paper_size.npz  dims (8,50,5), M=20, drive frame, 2 ns of adaptive
+                                        Dormand-Prince steps (rtol 1e-8, atol 1e-10; output grid
+                                        0.1 ns, records every 0.5 ns), g and e, with the accepted and
+                                        rejected step counts
 """
 import os
 import sys
@@ -25,7 +31,7 @@ import numpy as np  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-from oracle import loss, lowrank  # noqa: E402
+from oracle import adaptive, loss, lowrank  # noqa: E402
 from paper_2508_18114_amd import inputs as I  # noqa: E402
 
 STRIDES = {"small": 100, "paper_size": 200, "small_paper_padding": 100, "paper_size_paper_padding": 200}
@@ -57,7 +63,31 @@ def make(name):
     print(name, "written", out, f"{tg:.1f}s/{te:.1f}s", fm, flush=True)
 
 
+ADAPTIVE = dict(dt=0.1, nsteps=20, stride=5, rtol=1e-8, atol=1e-10)
+
+
+def _run_adaptive(idx):
+    tr = I.config_paper_size()[idx]
+    a = ADAPTIVE
+    t0 = time.time()
+    _, obs, acc, rej = adaptive.integrate(tr.model, tr.pulse.replace(frame=I.FRAME_DRIVE), 0.0, a["dt"], a["nsteps"],
+                                          tr.B0(), a["rtol"], a["atol"], obs_stride=a["stride"])
+    return obs, acc, rej, time.time() - t0
+
+
+def make_adaptive():
+    with Pool(2) as pool:
+        (og, ag, rg, tg), (oe, ae, re_, te) = pool.map(_run_adaptive, [0, 1])
+    out = os.path.join(HERE, "adaptive_paper_size.npz")
+    np.savez(out, obs_g=og, obs_e=oe, acc_g=ag, rej_g=rg, acc_e=ae, rej_e=re_, seconds_g=tg, seconds_e=te,
+             **ADAPTIVE)
+    print("adaptive_paper_size written", out, f"g {ag}+{rg} e {ae}+{re_} steps, {tg:.1f}s/{te:.1f}s", flush=True)
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "all"
-    for nm in (list(CONFIGS) if which == "all" else [which]):
-        make(nm)
+    if which == "adaptive_paper_size":
+        make_adaptive()
+    else:
+        for nm in (list(CONFIGS) if which == "all" else [which]):
+            make(nm)

@@ -8,7 +8,7 @@ largest difference is the floor below which no implementation can be judged;
 the GPU parity tolerances are 100 times this floor (capped by the bounds of
 the FP64 parity contract).  Calls only the oracle and the seeded inputs.
 
-    OMP_NUM_THREADS=1 python tests/golden/oracle_floor.py [small|paper_size|all]
+    OMP_NUM_THREADS=1 python tests/golden/oracle_floor.py [small|paper_size|small_paper_padding|...|all]
 
 Writes tests/golden/oracle_floor.json: per workload and order, the largest
 differences of
@@ -35,7 +35,9 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 from oracle import loss, lowrank  # noqa: E402
 from paper_2508_18114_amd import inputs as I  # noqa: E402
 
-CONFIGS = {"small": I.config_small, "paper_size": I.config_paper_size}
+CONFIGS = {"small": I.config_small, "paper_size": I.config_paper_size,
+           "small_paper_padding": I.config_small_paper_padding,
+           "paper_size_paper_padding": I.config_paper_size_paper_padding}
 ORDERS = ("reversed", "blocked")
 OUT = os.path.join(HERE, "oracle_floor.json")
 
@@ -94,5 +96,5 @@ def measure(names):
 
 
 if __name__ == "__main__":
-    which = sys.argv[1] if len(sys.argv) > 1 else "all"
-    measure(list(CONFIGS) if which == "all" else [which])
+    which = sys.argv[1:] or ["all"]
+    measure(list(CONFIGS) if which == ["all"] else which)
