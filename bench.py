@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--packed-sample", type=int, default=0, metavar="STEPS",
                     help="only run the packed schedule on 512 trajectories (N=2000, M=20) for STEPS steps "
                          "(a workload for kernel profiles) and print its rate")
+    ap.add_argument("--apply-sample", type=int, default=0, metavar="LAUNCHES",
+                    help="only time the operator application lr_apply_heff on 512 factors of N=2000, M=20 "
+                         "(10240 columns) for LAUNCHES launches (a workload for kernel profiles)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device three times (the reference that HBM byte "
                          "counters are calibrated against) and print the rate")
@@ -86,6 +89,33 @@ def packed_sample(lr, I, torch, steps):
                       "value": len(items) * steps / el, "unit": "RK steps*trajectories/s",
                       "kernel": "k_packed", "kernel_ms": ms, "launches": launches,
                       "achieved_tflops": fl / (ms * 1e-3) / 1e12, "peak": 78.6}), flush=True)
+
+
+def apply_sample(lr, I, torch, launches):
+    """Operator application Z = H_eff(t) B on its own (lr_apply_heff) over 512 factors of the paper-size
+    model side by side (N=2000, 10240 columns: 328 MB in, 328 MB out), timed with HIP events on the
+    launch stream; HBM roofline from the algorithmic bytes (one read of B, one write of Z)."""
+    m = I.readout_model(8, 50, 5)
+    p = I.config_paper_size()[0].pulse
+    ncols = 512 * 20
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    B = torch.randn((ncols, m.N), dtype=torch.complex128, device="cuda", generator=gen)
+    Z = torch.empty_like(B)
+    for _ in range(3):
+        lr.apply_heff(m, p, 1.0, B, Z)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(launches):
+        lr.apply_heff(m, p, 1.0 + 1e-3 * k, B, Z)
+    e1.record()
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / launches
+    by = 32.0 * m.N * ncols
+    return {"bound": "hbm", "achieved": by / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": by / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "kernel": "k_apply_heff", "kernel_mean_us": us,
+            "bytes_per_launch": by, "launches": launches,
+            "workload": f"Z = H_eff(t) B for 512 factors of N={m.N}, M=20 side by side ({ncols} columns), lab frame"}
 
 
 def _oracle_worker(args):
@@ -135,6 +165,8 @@ def comparisons(lr, I, torch, stream, plain_value):
             raise RuntimeError(f"batch failed: {lr.lr_strerror(rc)}")
         return sum(it["nsteps"] for it in items) / el, el
 
+    # operator application on its own, 512 factors of N=2000, M=20 (HBM-bound streaming pass)
+    out["operator_application"] = apply_sample(lr, I, torch, 20)
     # plain single trajectory (one Context, trajectory g)
     steps = 2000
     ctx = lr.Context(m, M, stream=stream)
@@ -516,6 +548,9 @@ def main():
         return
     if a.packed_sample > 0:
         packed_sample(lr, I, torch, a.packed_sample)
+        return
+    if a.apply_sample > 0:
+        print(json.dumps(apply_sample(lr, I, torch, a.apply_sample)), flush=True)
         return
     trajs = I.config_paper_size()
     m, M = trajs[0].model, trajs[0].M

@@ -37,10 +37,26 @@ def operators(model):
     return b, a, f
 
 
+def _normal_constants(model):
+    S = np.asarray(model.S, dtype=np.float64).reshape(2, 4)
+    return S, S[0, 2] - S[0, 1], S[0, 3] - S[0, 0], S[1, 2] - S[1, 1], S[1, 3] - S[1, 0]
+
+
 def hamiltonian(model, d_t):
     """Dense H(t) for the drive coefficient d_t (kind 1: the paper's
-    Hamiltonian with the transmon in its eigenbasis, see lowrank.apply_heff)."""
+    Hamiltonian with the transmon in its eigenbasis, see lowrank.apply_heff;
+    kind 2: the same in the normal-mode basis, modes c_l and c_u in the
+    resonator and filter slots)."""
     b, a, f = operators(model)
+    if getattr(model, "kind", 0) == 2:
+        cl, cu = a, f
+        _, mu_l, mu_u, nu_l, nu_u = _normal_constants(model)
+        Ht = _embed(model, np.diag(np.asarray(model.E_t, dtype=np.float64)).astype(np.complex128), 0)
+        Nt = _embed(model, np.asarray(model.n_t, dtype=np.float64).reshape(model.d_q, model.d_q).astype(np.complex128), 0)
+        Xl = cl.conj().T - cl
+        Xu = cu.conj().T - cu
+        H = Ht + model.w_r * cl.conj().T @ cl + model.w_f * cu.conj().T @ cu
+        return H + 1j * model.g * Nt @ (mu_l * Xl + mu_u * Xu) + 1j * d_t * (nu_l * Xl + nu_u * Xu)
     if getattr(model, "kind", 0) == 1:
         Ht = _embed(model, np.diag(np.asarray(model.E_t, dtype=np.float64)).astype(np.complex128), 0)
         Nt = _embed(model, np.asarray(model.n_t, dtype=np.float64).reshape(model.d_q, model.d_q).astype(np.complex128), 0)
@@ -64,7 +80,7 @@ def hamiltonian_drive_frame(model, d_t, w_d, t):
     """Dense H'(t) in the frame rotating at w_d: U H U^ - w_d (n_q + n_r + n_f)
     with U = exp(i w_d t (n_q + n_r + n_f)), built from the phased ladder
     operators b e^{-i w_d t}, a e^{-i w_d t}, f e^{-i w_d t} (all terms kept)."""
-    if getattr(model, "kind", 0) == 1:  # U H U^ - w_d n, n = q + n_r + n_f, from the lab-frame matrix
+    if getattr(model, "kind", 0) in (1, 2):  # U H U^ - w_d n, n = q + n_r + n_f, from the lab-frame matrix
         n = np.array([q + r + f for q in range(model.d_q) for r in range(model.d_r) for f in range(model.d_f)],
                      dtype=np.float64)
         u = np.exp(1j * w_d * t * n)
@@ -91,8 +107,21 @@ def frame_hamiltonian(model, pulse, t):
     return hamiltonian(model, d_t)
 
 
-def jump_operators(model):
-    b, _, f = operators(model)
+def jump_operators(model, pulse=None, t=0.0):
+    """sqrt(kappa_f) f and sqrt(gamma_1) b.  kind 2: f = s_21 c_u^ + s_22 c_l^ + s_23 c_l + s_24 c_u in the
+    normal-mode basis, turned into the frame of the pulse as U f U^ (U = exp(i w_d t n), n = q + n_r +
+    n_f) in the drive frame; for kinds 0 and 1 that rotation is a global phase, which leaves the
+    dissipator unchanged."""
+    b, a, f = operators(model)
+    if getattr(model, "kind", 0) == 2:
+        S = _normal_constants(model)[0]
+        fn = S[1, 0] * f.conj().T + S[1, 1] * a.conj().T + S[1, 2] * a + S[1, 3] * f
+        if pulse is not None and getattr(pulse, "frame", 0) == 1:
+            n = np.array([q + r + k for q in range(model.d_q) for r in range(model.d_r) for k in range(model.d_f)],
+                         dtype=np.float64)
+            u = np.exp(1j * pulse.w_d * t * n)
+            fn = u[:, None] * fn * np.conj(u)[None, :]
+        return [np.sqrt(model.kappa_f) * fn, np.sqrt(model.gamma_1) * b]
     return [np.sqrt(model.kappa_f) * f, np.sqrt(model.gamma_1) * b]
 
 
@@ -100,7 +129,7 @@ def lindbladian(model, pulse, t, rho):
     """Right-hand side of the master equation on a dense rho."""
     H = frame_hamiltonian(model, pulse, t)
     out = -1j * (H @ rho - rho @ H)
-    for L in jump_operators(model):
+    for L in jump_operators(model, pulse, t):
         LdL = L.conj().T @ L
         out = out + L @ rho @ L.conj().T - 0.5 * (LdL @ rho + rho @ LdL)
     return out
@@ -112,7 +141,7 @@ def lowrank_rhs_pinv(model, pulse, t, B):
     H = frame_hamiltonian(model, pulse, t)
     Bp = np.linalg.pinv(B)
     out = -1j * (H @ B)
-    for L in jump_operators(model):
+    for L in jump_operators(model, pulse, t):
         LB = L @ B
         out = out + 0.5 * (LB @ (Bp @ LB).conj().T - L.conj().T @ L @ B)
     return out

@@ -96,12 +96,71 @@ def diag_heff(model):
     q = np.arange(model.d_q, dtype=np.float64)[:, None, None]
     r = np.arange(model.d_r, dtype=np.float64)[None, :, None]
     f = np.arange(model.d_f, dtype=np.float64)[None, None, :]
-    if getattr(model, "kind", 0) == 1:
+    if getattr(model, "kind", 0) in (1, 2):
         hq = np.asarray(model.E_t, dtype=np.float64)[:, None, None]
     else:
         hq = model.w_q * q + 0.5 * model.alpha * q * (q - 1.0)
     h = hq + model.w_r * r + model.w_f * f
+    if getattr(model, "kind", 0) == 2:  # -1/2 L_1^ L_1 is not diagonal there (applied in apply_heff)
+        return h - 0.5j * (model.gamma_1 * q)
     return h - 0.5j * (model.kappa_f * f + model.gamma_1 * q)
+
+
+# ---------------------------------------------------------------- normal-mode basis (kind 2)
+
+def normal_mode_constants(model):
+    """(S rows, mu_l, mu_u, nu_l, nu_u): a = S[0] . (c_u^, c_l^, c_l, c_u), f = S[1] . (same), and the
+    coefficients of a^ - a = mu_u (c_u^ - c_u) + mu_l (c_l^ - c_l), f^ - f likewise with nu (S2.D)."""
+    S = np.asarray(model.S, dtype=np.float64).reshape(2, 4)
+    return S, S[0, 2] - S[0, 1], S[0, 3] - S[0, 0], S[1, 2] - S[1, 1], S[1, 3] - S[1, 0]
+
+
+def _frame_phase(pulse, t):
+    """e^{i w_d t} in the frame rotating at the drive carrier, 1 in the lab frame."""
+    if pulse is not None and getattr(pulse, "frame", 0) == 1:
+        return np.exp(1j * pulse.w_d * t)
+    return 1.0 + 0.0j
+
+
+def _filter_jump(model, T, e1, adjoint=False):
+    """sqrt(kappa_f) f T for kind 2, f = s_21 c_u^ + s_22 c_l^ + s_23 c_l + s_24 c_u (modes: l = axis 1,
+    u = axis 2); in the drive frame each creation term carries e1 = e^{i w_d t} and each annihilation
+    term its conjugate.  adjoint: the Hermitian adjoint f^ instead."""
+    S = normal_mode_constants(model)[0]
+    s21, s22, s23, s24 = S[1]
+    c = np.conj(e1)
+    if adjoint:  # f^ = s_21 c_u + s_22 c_l + s_23 c_l^ + s_24 c_u^ (phases conjugated)
+        out = s21 * c * lower(T, 2) + s22 * c * lower(T, 1) + s23 * e1 * raise_(T, 1) + s24 * e1 * raise_(T, 2)
+    else:
+        out = s21 * e1 * raise_(T, 2) + s22 * e1 * raise_(T, 1) + s23 * c * lower(T, 1) + s24 * c * lower(T, 2)
+    return np.sqrt(model.kappa_f) * out
+
+
+def _apply_heff_normal(model, d_t, B, pulse=None, t=0.0):
+    """H_eff B for kind 2 in the lab frame or, when pulse.frame is the drive frame, in the frame
+    U = exp(i w_d t (q + n_l + n_u)): levels E_q - w_d q, mode frequencies w - w_d, and every term
+    that changes the excitation count by D carries e^{i w_d t D} (nothing dropped)."""
+    T = _as_tensor(model, B)
+    dq = model.d_q
+    rot = pulse is not None and getattr(pulse, "frame", 0) == 1
+    w_d = pulse.w_d if rot else 0.0
+    e1 = _frame_phase(pulse, t)
+    _, mu_l, mu_u, nu_l, nu_u = normal_mode_constants(model)
+    m2 = model.replace(E_t=tuple(np.asarray(model.E_t) - w_d * np.arange(dq)), w_r=model.w_r - w_d,
+                       w_f=model.w_f - w_d)
+    Z = diag_heff(m2)[..., None] * T
+    nt = np.asarray(model.n_t, dtype=np.float64).reshape(dq, dq)
+    qd = np.arange(dq)[:, None] - np.arange(dq)[None, :]          # q' - q (row q', column q)
+    up = nt * (e1 ** (qd + 1) if rot else 1.0)                     # n_t x (raising of a mode)
+    dn = nt * (e1 ** (qd - 1) if rot else 1.0)                     # n_t x (lowering)
+    for mu, ax in ((mu_l, 1), (mu_u, 2)):
+        Z = Z + 1j * model.g * mu * (np.einsum("qp,prfj->qrfj", up, raise_(T, ax))
+                                     - np.einsum("qp,prfj->qrfj", dn, lower(T, ax)))
+    for nu, ax in ((nu_l, 1), (nu_u, 2)):
+        Z = Z + d_t * 1j * nu * (e1 * raise_(T, ax) - np.conj(e1) * lower(T, ax))
+    # -1/2 L_1^ L_1 B with the filter jump of this frame
+    Z = Z - 0.5j * _filter_jump(model, _filter_jump(model, T, e1), e1, adjoint=True)
+    return Z.reshape(B.shape)
 
 
 def apply_heff(model, d_t, B):
@@ -111,6 +170,8 @@ def apply_heff(model, d_t, B):
     eigenbasis, bare resonator and filter): i g n_t (a^ - a) - J (a^ - a)(f^ - f)
     + d(t) i (f^ - f), J held in model.G; the drive quadrature i (f^ - f) takes
     d(t) in place of the paper's Omega_d(t) sin(w_d t)."""
+    if getattr(model, "kind", 0) == 2:
+        return _apply_heff_normal(model, d_t, B)
     T = _as_tensor(model, B)
     Z = diag_heff(model)[..., None] * T
     if getattr(model, "kind", 0) == 1:
@@ -143,6 +204,9 @@ def apply_heff_drive_frame(model, d_t, w_d, t, B):
     gamma_1 n_q) as in the lab frame."""
     if getattr(model, "kind", 0) == 1:
         return _apply_heff_drive_frame_transmon(model, d_t, w_d, t, B)
+    if getattr(model, "kind", 0) == 2:
+        from types import SimpleNamespace
+        return _apply_heff_normal(model, d_t, B, SimpleNamespace(frame=1, w_d=w_d), t)
     T = _as_tensor(model, B)
     m2 = model.replace(w_q=model.w_q - w_d, w_r=model.w_r - w_d, w_f=model.w_f - w_d)
     e1 = np.exp(1j * w_d * t)
@@ -182,10 +246,15 @@ def _apply_heff_drive_frame_transmon(model, d_t, w_d, t, B):
     return Z.reshape(B.shape)
 
 
-def apply_jumps(model, B):
-    """[Y_1, Y_2] = [sqrt(kappa_f) f B, sqrt(gamma_1) b B]."""
+def apply_jumps(model, B, pulse=None, t=0.0):
+    """[Y_1, Y_2] = [sqrt(kappa_f) f B, sqrt(gamma_1) b B].  kind 2: f is the filter operator in the
+    normal-mode basis, in the frame of the pulse (its terms phased in the drive frame; a phase common
+    to a whole jump operator, as for kinds 0 and 1, leaves the dissipator unchanged and is dropped)."""
     T = _as_tensor(model, B)
-    Y1 = np.sqrt(model.kappa_f) * lower(T, 2)
+    if getattr(model, "kind", 0) == 2:
+        Y1 = _filter_jump(model, T, _frame_phase(pulse, t))
+    else:
+        Y1 = np.sqrt(model.kappa_f) * lower(T, 2)
     Y2 = np.sqrt(model.gamma_1) * lower(T, 0)
     return [Y1.reshape(B.shape), Y2.reshape(B.shape)]
 
@@ -251,7 +320,7 @@ def rhs(model, pulse, t, B, sum_order="matmul"):
         Z = apply_heff_drive_frame(model, d_t, pulse.w_d, t, B)
     else:
         Z = apply_heff(model, d_t, B)
-    Y = apply_jumps(model, B)
+    Y = apply_jumps(model, B, pulse, t)
     G = inner(B, B, sum_order)
     C = [inner(B, Yk, sum_order) for Yk in Y]
     X = gram_solve(G, C)
@@ -270,7 +339,9 @@ def observables(model, B, sum_order="matmul"):
     """[Re<a>, Im<a>, Re<f>, Im<f>, tr rho, tr rho^2, P_q(0..d_q-1)].
 
     <O> = tr(O rho) = sum_j b_j^ O b_j (unnormalised); tr rho^2 = ||B^ B||_F^2
-    (since tr (B B^)^2 = tr (B^ B)^2); P_q(k) = tr(|k><k|_q rho).
+    (since tr (B B^)^2 = tr (B^ B)^2); P_q(k) = tr(|k><k|_q rho).  The two fields
+    are those of the lowering operators of the resonator and filter slots: for
+    kind 2 the normal-mode fields <c_l>, <c_u>.
     """
     T = _as_tensor(model, B)
     a = total(T.conj() * lower(T, 1), sum_order)

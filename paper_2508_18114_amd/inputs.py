@@ -37,7 +37,7 @@ TWO_PI = 2.0 * math.pi
 PULSE_FLATTOP = 0
 PULSE_PIECEWISE6 = 1
 PULSE_STEPWISE = 2   # smoothed stepwise complex envelope (supplement S2.C)
-MODEL_DUFFING, MODEL_TRANSMON = 0, 1
+MODEL_DUFFING, MODEL_TRANSMON, MODEL_NORMAL = 0, 1, 2
 MAX_DQ = 8
 PULSE_MAX_HEIGHTS = 63
 FRAME_LAB = 0        # B and <a>, <f> in the lab frame
@@ -62,7 +62,16 @@ class ModelParams:
     charge operator n_t (d_q x d_q, row-major, real symmetric); couplings
     i g n_t (a^ - a) and -G (a^ - a)(f^ - f) (G plays J), drive d(t) i (f^ - f);
     w_q and alpha unused.  Jumps in both: sqrt(kappa_f) f, sqrt(gamma_1) b with
-    b the ladder sum_q sqrt(q) |q-1><q|."""
+    b the ladder sum_q sqrt(q) |q-1><q|.
+    kind MODEL_NORMAL: the paper's Hamiltonian in its normal-mode basis
+    (supplement S2.D): transmon levels E_t and charge operator n_t as for
+    MODEL_TRANSMON (d_q levels), the lower normal mode c_l in the resonator
+    slot (d_r levels, frequency w_r = w_l) and the upper mode c_u in the filter
+    slot (d_f levels, w_f = w_u); couplings i g n_t [mu_l (c_l^ - c_l) + mu_u
+    (c_u^ - c_u)], drive d(t) i [nu_l (c_l^ - c_l) + nu_u (c_u^ - c_u)], jumps
+    sqrt(kappa_f) f with f = s_21 c_u^ + s_22 c_l^ + s_23 c_l + s_24 c_u and
+    sqrt(gamma_1) b; mu_u = s_14 - s_11, mu_l = s_13 - s_12, nu_u = s_24 - s_21,
+    nu_l = s_23 - s_22 from the 8 entries of S; w_q, alpha and G unused."""
     d_q: int
     d_r: int
     d_f: int
@@ -77,6 +86,7 @@ class ModelParams:
     kind: int = 0
     E_t: tuple = ()
     n_t: tuple = ()
+    S: tuple = ()      # kind MODEL_NORMAL: a and f through (c_u^, c_l^, c_l, c_u), s_11 .. s_14, s_21 .. s_24
 
     @property
     def N(self) -> int:

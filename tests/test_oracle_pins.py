@@ -694,3 +694,107 @@ def test_transmon_model_drive_frame_is_the_transformed_lab_rhs():
     lhs = Bf @ dB.conj().T + dB @ Bf.conj().T
     ref = dense.lindbladian(mf, ROT, 3.1, Bf @ Bf.conj().T)
     assert np.max(np.abs(lhs - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+# ------------------------------------------------------------ the paper's Hamiltonian in its normal-mode basis (kind 2)
+
+def _normal_model(dq, dl, du, kappa_f=0.6, gamma_1=0.2, g=0.9, J=1.1):
+    """Kind 2 with a strong resonator-filter coupling (so that the creation admixtures s_21, s_22 of
+    the filter operator are far from zero) and the oracle's own normal modes."""
+    Ec = I.ghz(0.315)
+    w, nt = papermodel.transmon_levels(Ec, 51 * Ec, dq)
+    wl, wu, U, S = papermodel.normal_modes(I.ghz(7.2), I.ghz(7.21), J)
+    return I.readout_model(dq, dl, du).replace(kind=I.MODEL_NORMAL, E_t=tuple(w - w[0]), n_t=tuple(nt.ravel()),
+                                                w_r=wl, w_f=wu, g=g, G=0.0, kappa_f=kappa_f, gamma_1=gamma_1,
+                                                S=tuple(S[:2].ravel()))
+
+
+def test_normal_model_resonator_filter_pair_is_diagonal_in_its_modes():
+    """The normal-mode basis of kind 2 is the paper's S2.D transformation: the bare pair w_r a^a + w_f f^f
+    - J (a^ - a)(f^ - f), with a and f written through the normal-mode ladders by the rows of S, equals
+    w_l c_l^ c_l + w_u c_u^ c_u + const on the Fock states far from the truncation edge."""
+    J = 1.1
+    m = _normal_model(2, 7, 7, J=J)
+    cl, cu = dense.operators(m)[1:]
+    S = np.asarray(m.S).reshape(2, 4)
+    a = S[0, 0] * cu.conj().T + S[0, 1] * cl.conj().T + S[0, 2] * cl + S[0, 3] * cu
+    f = S[1, 0] * cu.conj().T + S[1, 1] * cl.conj().T + S[1, 2] * cl + S[1, 3] * cu
+    Xa, Xf = a.conj().T - a, f.conj().T - f
+    Hb = I.ghz(7.2) * a.conj().T @ a + I.ghz(7.21) * f.conj().T @ f - J * Xa @ Xf
+    Hn = m.w_r * cl.conj().T @ cl + m.w_f * cu.conj().T @ cu
+    low = [I.basis_index(m, 0, nl, nu) for nl in range(3) for nu in range(3) if nl + nu <= 2]
+    D = (Hb - Hn)[np.ix_(low, low)]
+    c0 = D[0, 0]
+    assert np.max(np.abs(D - c0 * np.eye(len(low)))) < 1e-9 * m.w_r
+    assert abs(S[1, 0]) > 1e-3 and abs(S[1, 1]) > 1e-3  # the creation admixtures are exercised
+
+
+def test_normal_model_hamiltonian_matrix_elements():
+    """Dense H of kind 2 (S2.E, eq. "hamiltonian_rotated" before the frame change): Hermitian, diagonal
+    E_q + w_l n_l + w_u n_u, <q', l+1|H|q, l> = i g mu_l n_t[q'][q] sqrt(l+1), <q', u+1|H|q, u> =
+    i g mu_u n_t[q'][q] sqrt(u+1) plus the drive i d nu_u sqrt(u+1) when q' = q."""
+    m = _normal_model(3, 3, 3)
+    d = 0.41
+    H = dense.hamiltonian(m, d)
+    assert np.max(np.abs(H - H.conj().T)) < 1e-12
+    _, mu_l, mu_u, nu_l, nu_u = lowrank.normal_mode_constants(m)
+    nt = np.asarray(m.n_t).reshape(3, 3)
+    idx = lambda q, r, f: I.basis_index(m, q, r, f)  # noqa: E731
+    for (q, r, f) in [(0, 0, 0), (1, 1, 1), (2, 0, 1)]:
+        assert abs(H[idx(q, r, f), idx(q, r, f)] - (m.E_t[q] + m.w_r * r + m.w_f * f)) < 1e-12
+        for qq in range(3):
+            el = 1j * m.g * mu_l * nt[qq, q] * math.sqrt(r + 1) + (1j * d * nu_l * math.sqrt(r + 1) if qq == q else 0)
+            eu = 1j * m.g * mu_u * nt[qq, q] * math.sqrt(f + 1) + (1j * d * nu_u * math.sqrt(f + 1) if qq == q else 0)
+            if r + 1 < 3:
+                assert abs(H[idx(qq, r + 1, f), idx(q, r, f)] - el) < 1e-12
+            if f + 1 < 3:
+                assert abs(H[idx(qq, r, f + 1), idx(q, r, f)] - eu) < 1e-12
+
+
+def test_normal_model_rhs_equals_literal_pinv_formula_and_full_rank_lindbladian():
+    """Both frames: the mode-wise right-hand side (the non-diagonal -1/2 L_1^ L_1 B applied as
+    -1/2 L_1^ (L_1 B), the filter jump with its c^ terms) against the literal pinv formula with dense
+    Kronecker operators, and at full rank against the dense Lindbladian.  A sign flip of s_21 (a
+    planted error in the oracle's operator) fails the first check."""
+    m = _normal_model(3, 3, 2)
+    B = _rand_B(m.N, 3, 81)
+    for p in (PULSE, ROT):
+        for t in (0.3, 1.7):
+            a = lowrank.rhs(m, p, t, B)
+            b = dense.lowrank_rhs_pinv(m, p, t, B)
+            assert np.max(np.abs(a - b)) <= 1e-11 * np.max(np.abs(b))
+    Sbad = np.asarray(m.S).copy()
+    Sbad[4] = -Sbad[4]
+    bad = lowrank.rhs(m.replace(S=tuple(Sbad)), PULSE, 0.3, B)
+    assert np.max(np.abs(bad - dense.lowrank_rhs_pinv(m, PULSE, 0.3, B))) > 1e-6 * np.max(np.abs(bad))
+    mf = _normal_model(2, 3, 2)
+    Bf = _rand_B(mf.N, mf.N, 82)
+    for p in (PULSE, ROT):
+        dB = lowrank.rhs(mf, p, 2.2, Bf)
+        lhs = Bf @ dB.conj().T + dB @ Bf.conj().T
+        ref = dense.lindbladian(mf, p, 2.2, Bf @ Bf.conj().T)
+        assert np.max(np.abs(lhs - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_normal_model_drive_frame_is_the_transformed_lab_rhs():
+    """Kind 2, U = exp(i w_d t (q + n_l + n_u)): rhs'(t, U B) = i w_d n U B + U rhs(t, B) exactly; in the
+    drive frame the filter jump's creation and annihilation terms carry opposite phases."""
+    m = _normal_model(3, 3, 3)
+    B = _rand_B(m.N, 3, 83)
+    for t in (0.0, 1.37, 4.2):
+        u, n = _frame_phase(m, PULSE.w_d, t)
+        lhs = lowrank.rhs(m, ROT, t, u[:, None] * B)
+        ref = 1j * PULSE.w_d * (n * u)[:, None] * B + u[:, None] * lowrank.rhs(m, PULSE, t, B)
+        assert np.max(np.abs(lhs - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_package_normal_modes_match_the_oracle():
+    """The package's normal modes (model input for the device) equal the oracle's pinned ones."""
+    from paper_2508_18114_amd import transmon
+    for J in (I.ghz(0.03), 1.1):
+        wl, wu, S2 = transmon.normal_modes(I.ghz(7.2), I.ghz(7.21), J)
+        a, b, U, S = papermodel.normal_modes(I.ghz(7.2), I.ghz(7.21), J)
+        assert abs(wl - a) < 1e-12 * a and abs(wu - b) < 1e-12 * b
+        np.testing.assert_allclose(S2, S[:2], atol=1e-12)
+    m = transmon.paper_model_normal(6, 8, 4)
+    assert m.kind == I.MODEL_NORMAL and len(m.S) == 8 and m.N == 6 * 8 * 4
