@@ -61,19 +61,35 @@ typedef struct { double re, im; } lr_c64;
  *   number (levels E_q - w_d q), every term kept.  This kind runs in the
  *   packed batch schedule only (fixed RK4 or adaptive steps; LR_ERR_ARG
  *   elsewhere).
- * Both kinds: L_1 = sqrt(kappa_f) f, L_2 = sqrt(gamma_1) b, b the ladder
- * sum_n sqrt(n) |n-1><n| of the transmon levels. */
+ * kind LR_MODEL_NORMAL (2): the same Hamiltonian in the resonator-filter
+ *   normal-mode basis (supplement S2.D; S2.E, eq. "hamiltonian_rotated"):
+ *   the d_r slot holds the lower mode c_l (frequency w_r), the d_f slot the
+ *   upper mode c_u (frequency w_f), and S[0..3], S[4..7] are the rows of the
+ *   transformation a = S[0] c_u^ + S[1] c_l^ + S[2] c_l + S[3] c_u and
+ *   f = S[4] c_u^ + S[5] c_l^ + S[6] c_l + S[7] c_u.  H = E_q + w_l n_l +
+ *   w_u n_u + i g n_t (mu_l (c_l^ - c_l) + mu_u (c_u^ - c_u)) + d(t) i (nu_l
+ *   (c_l^ - c_l) + nu_u (c_u^ - c_u)) with mu_l = S[2] - S[1], mu_u = S[3] -
+ *   S[0], nu_l = S[6] - S[5], nu_u = S[7] - S[4] (G unused).  The filter jump
+ *   L_1 = sqrt(kappa_f) f moves the state across resonator layers and raises
+ *   as well as lowers; -1/2 L_1^ L_1 is applied as the product of the
+ *   truncated operators.  In the drive frame every creation term of f carries
+ *   e^{i w_d t} and every annihilation term e^{-i w_d t}.  Packed fixed-step
+ *   RK4 batches only (LR_ERR_ARG elsewhere), FP64, d_q <= LR_MAX_DQ.
+ * Kinds 0 and 1: L_1 = sqrt(kappa_f) f; every kind: L_2 = sqrt(gamma_1) b, b
+ * the ladder sum_n sqrt(n) |n-1><n| of the transmon levels. */
 #define LR_MODEL_DUFFING 0
 #define LR_MODEL_TRANSMON 1
+#define LR_MODEL_NORMAL 2
 #define LR_MAX_DQ 8
 typedef struct {
   int32_t d_q, d_r, d_f;
-  int32_t kind;                   /* LR_MODEL_DUFFING or LR_MODEL_TRANSMON                */
+  int32_t kind;                   /* LR_MODEL_DUFFING, LR_MODEL_TRANSMON or LR_MODEL_NORMAL */
   double  w_q, alpha, w_r, w_f;   /* Duffing transmon w_q n + alpha/2 n(n-1); bare modes */
   double  g, G;                   /* g (b+b^)(a+a^),  G (a+a^)(f+f^)  (kind 0)           */
   double  kappa_f, gamma_1;       /* L_1 = sqrt(kappa_f) f,  L_2 = sqrt(gamma_1) b      */
-  double  E_t[LR_MAX_DQ];         /* kind 1: transmon levels                            */
-  double  n_t[LR_MAX_DQ * LR_MAX_DQ];  /* kind 1: charge operator, row-major d_q x d_q   */
+  double  E_t[LR_MAX_DQ];         /* kinds 1, 2: transmon levels                        */
+  double  n_t[LR_MAX_DQ * LR_MAX_DQ];  /* kinds 1, 2: charge operator, row-major d_q x d_q */
+  double  S[8];                   /* kind 2: rows of a and f over (c_u^, c_l^, c_l, c_u)  */
 } lr_model_t;
 
 /* Drive coefficient d(t) multiplying (f + f^).

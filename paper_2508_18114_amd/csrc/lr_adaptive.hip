@@ -103,7 +103,7 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
   const int NGe = kTW / M;
   const int ej = tid % M, eg = tid / M;
   const bool eact = eg < NGe;
-  const int NGp = kTW / C3, KPe = packed_kpe(M);
+  const int NGp = kTW / C3, KPe = packed_kpe(M, C3);
   const int pc = tid % C3, pg = tid / C3, pi0 = pg * KPe;
   const bool pact = pg < NGp && pi0 < M;
   const int pkind = pc / M, pcc = pc - pkind * M;

@@ -41,6 +41,7 @@ struct lr_batch {
     size_t lds;
     int64_t max_steps, chunk;
     int packed, kp;
+    int nm;  // packed group of the normal-mode model (its own kernels)
   };
   std::vector<Group> groups;
   bool prof = false;
@@ -83,8 +84,13 @@ bool persist_config(const lr_model_t& m, int M, int layers, int& prt, int& P, in
 
 int check_model(const lr_model_t& m, int M, int precision) {
   if (m.d_q < 2 || m.d_r < 1 || m.d_f < 1) return LR_ERR_ARG;
-  if (m.kind != LR_MODEL_DUFFING && m.kind != LR_MODEL_TRANSMON) return LR_ERR_ARG;
-  if (m.kind == LR_MODEL_TRANSMON) {
+  if (m.kind != LR_MODEL_DUFFING && m.kind != LR_MODEL_TRANSMON && m.kind != LR_MODEL_NORMAL) return LR_ERR_ARG;
+  if (m.kind == LR_MODEL_NORMAL) {
+    if (precision != LR_FP64) return LR_ERR_ARG;
+    for (double x : m.S)
+      if (!std::isfinite(x)) return LR_ERR_ARG;
+  }
+  if (m.kind == LR_MODEL_TRANSMON || m.kind == LR_MODEL_NORMAL) {
     if (m.d_q > LR_MAX_DQ) return LR_ERR_ARG;
     double big = 0.0;
     for (int i = 0; i < m.d_q * m.d_q; ++i) {
@@ -166,7 +172,8 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
           LM <= lrk::kTMaxLM && x.model.d_r >= 1 && x.model.d_r <= (1 << 20)))
       return false;
     const int dmax = std::max(std::max(x.model.d_q, x.model.d_r), x.model.d_f);
-    return lrk::packed_lds_elems(x.model.d_q * x.model.d_f, x.M, dmax) * sizeof(double2) <= lrk::kPackedLdsMax;
+    return lrk::packed_lds_elems(x.model.d_q * x.model.d_f, x.M, dmax, x.model.kind) * sizeof(double2) <=
+           lrk::kPackedLdsMax;
   };
   auto work = [&](const lr_traj_t& x) {
     return (double)x.nsteps * x.model.d_q * x.model.d_r * x.model.d_f * x.M;
@@ -178,7 +185,11 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     const bool px = packs(trajs[x]), py = packs(trajs[y]);
     if (px != py) return px;
-    if (px) return work(trajs[x]) > work(trajs[y]);
+    if (px) {
+      const bool nx = trajs[x].model.kind == LR_MODEL_NORMAL, ny = trajs[y].model.kind == LR_MODEL_NORMAL;
+      if (nx != ny) return ny;
+      return work(trajs[x]) > work(trajs[y]);
+    }
     if (trajs[x].precision != trajs[y].precision) return trajs[x].precision < trajs[y].precision;
     return trajs[x].nsteps > trajs[y].nsteps;
   });
@@ -204,8 +215,9 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
         delete b;
         return LR_ERR_ARG;
       }
-  for (int k = 0; k < n; ++k)  // the eigenbasis model runs packed
-    if (b->tr[k].model.kind == LR_MODEL_TRANSMON && !b->packed[k]) {
+  for (int k = 0; k < n; ++k)  // the eigenbasis models run packed; the normal-mode one with fixed steps only
+    if ((b->tr[k].model.kind != LR_MODEL_DUFFING && !b->packed[k]) ||
+        (b->tr[k].model.kind == LR_MODEL_NORMAL && adaptive)) {
       delete b;
       return LR_ERR_ARG;
     }
@@ -228,7 +240,7 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
       b->P[t] = 1;
       b->rows[t] = 0;
       b->lds[t] = lrk::packed_lds_elems(x.model.d_q * x.model.d_f, x.M,
-                                        std::max(std::max(x.model.d_q, x.model.d_r), x.model.d_f)) *
+                                        std::max(std::max(x.model.d_q, x.model.d_r), x.model.d_f), x.model.kind) *
                   sizeof(double2);
     } else if (!e && !persist_config(x.model, x.M, (flags >> 8) & 0xff, b->prt[t], b->P[t], b->rows[t], b->lds[t])) {
       e = LR_ERR_ARG;
@@ -308,9 +320,16 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
     v.w_q = m.w_q; v.alpha = m.alpha; v.w_r = m.w_r; v.w_f = m.w_f;
     v.g = m.g; v.G = m.G; v.kappa = m.kappa_f; v.gamma = m.gamma_1;
     v.mkind = m.kind;
-    if (m.kind == LR_MODEL_TRANSMON) {
+    if (m.kind == LR_MODEL_TRANSMON || m.kind == LR_MODEL_NORMAL) {
       for (int i = 0; i < m.d_q; ++i) v.Et[i] = m.E_t[i];
       for (int i = 0; i < m.d_q * m.d_q; ++i) v.ntq[i] = m.n_t[i];
+    }
+    if (m.kind == LR_MODEL_NORMAL) {  // s_21 .. s_24; mu_l, mu_u, nu_l, nu_u (supplement S2.D)
+      for (int i = 0; i < 4; ++i) v.nm[i] = m.S[4 + i];
+      v.nm[4] = m.S[2] - m.S[1];
+      v.nm[5] = m.S[3] - m.S[0];
+      v.nm[6] = m.S[6] - m.S[5];
+      v.nm[7] = m.S[7] - m.S[4];
     }
     set_pulse(v, &x.pulse);
     v.t0 = x.t0;
@@ -388,6 +407,8 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
       if (max_lds_packed > 0 &&
           (hipFuncSetAttribute(lrk::packed_kernel(kp, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)max_lds_packed) != hipSuccess ||
+           hipFuncSetAttribute(lrk::packed_kernel(kp, pro != 0, true), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)max_lds_packed) != hipSuccess ||
            hipFuncSetAttribute(lrk::dp5_kernel(kp, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)max_lds_packed) != hipSuccess))
         return LR_ERR_HIP;
@@ -407,10 +428,11 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
   };
   b->groups.clear();
   int t = 0;
-  if (t < b->n && b->packed[t]) {  // one launch per chunk holds every packed trajectory
-    lr_batch::Group g{t, t, 0, 0, 0, LR_FP64, 0, 0, 0, 1, 2};
-    while (t < b->n && b->packed[t]) {
-      g.kp = std::max(g.kp, lrk::packed_kp(b->tr[t].M));
+  while (t < b->n && b->packed[t]) {  // one launch per chunk holds every packed trajectory of a kernel family
+    const int nm = b->tr[t].model.kind == LR_MODEL_NORMAL;
+    lr_batch::Group g{t, t, 0, 0, 0, LR_FP64, 0, 0, 0, 1, 2, nm};
+    while (t < b->n && b->packed[t] && (b->tr[t].model.kind == LR_MODEL_NORMAL) == (nm != 0)) {
+      g.kp = std::max(g.kp, lrk::packed_kp(b->tr[t].M, b->tr[t].model.kind));
       g.lds = std::max(g.lds, b->lds[t]);
       g.wgs += 1;
       g.max_steps = std::max(g.max_steps, b->tr[t].nsteps);
@@ -422,7 +444,7 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
     b->groups.push_back(g);
   }
   while (t < b->n) {
-    lr_batch::Group g{t, t, 0, 2, 1, b->tr[t].precision, 0, 0, 0, 0, 0};
+    lr_batch::Group g{t, t, 0, 2, 1, b->tr[t].precision, 0, 0, 0, 0, 0, 0};
     while (t < b->n) {
       if (b->tr[t].precision != g.prec) break;
       const int rows = std::max(g.rows, b->rows[t]);
@@ -537,8 +559,8 @@ int enqueue(lr_batch* b) {
                                 b->stream);
         } else {
           void* pargs[] = {(void*)&ptr, (void*)&step0, (void*)&nchunk};
-          err = hipLaunchKernel(lrk::packed_kernel(g.kp, prologue != 0), dim3(g.wgs), dim3(lrk::kTW), pargs,
-                                g.lds, b->stream);
+          err = hipLaunchKernel(lrk::packed_kernel(g.kp, prologue != 0, g.nm != 0), dim3(g.wgs), dim3(lrk::kTW),
+                                pargs, g.lds, b->stream);
         }
       } else {
         err = hipLaunchCooperativeKernel(persist_fn(g.rows, g.ge, g.prec, prologue != 0), dim3(g.wgs),

@@ -59,9 +59,11 @@ struct TrajDev {
   uint32_t* flagA;      // [P * kFlagStride] "partials of stage g published" = g + 1
   uint32_t* flagB;      // [P * kFlagStride] "reduction of stage g done"     = g + 1
   uint32_t* abort_flag; // set when a bounded wait expires
-  // model kind 1 (transmon eigenbasis): levels and charge operator (row-major d_q x d_q)
+  // model kinds 1, 2 (transmon eigenbasis): levels and charge operator (row-major d_q x d_q)
   double Et[kMaxDq];
   double ntq[kMaxDq * kMaxDq];
+  // model kind 2 (normal-mode basis): s_21 .. s_24 of the filter operator, mu_l, mu_u, nu_l, nu_u
+  double nm[8];
   // bounded waits of the group barriers: polls before a wait expires (0: kSpinLimit), and an offset
   // added to every barrier target (nonzero only to make every wait expire, for failure-handling tests)
   uint32_t spin_limit, wait_bias;

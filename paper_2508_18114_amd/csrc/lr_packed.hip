@@ -46,23 +46,27 @@ constexpr int kTDriveWin = 32;      // steps per drive table refill
 // matrix; W_1, W_2; the drive table (kTDriveWin steps x 4 stages x 5 doubles)
 // and the pivot row of the elimination (3M); per-row tables (jump
 // coefficients and the diagonal of H_eff without its resonator term, 5 L
-// doubles) and sqrt(0 .. dmax), dmax = max(d_q, d_r, d_f).
-__host__ __device__ inline size_t packed_lds_elems(int L, int M, int dmax) {
-  const size_t tiles = 4 * (size_t)L * M, aug = 3 * (size_t)M * M;
+// doubles) and sqrt(0 .. dmax), dmax = max(d_q, d_r, d_f).  The normal-mode
+// model (kind 2) holds nine tiles (five input layers, the filter jump of two
+// layers, the output of two) and stages its M x 4M Gram terms beside the
+// elimination matrix.
+__host__ __device__ inline size_t packed_lds_elems(int L, int M, int dmax, int kind = 0) {
+  const size_t tiles = (kind == 2 ? 9 : 4) * (size_t)L * M, aug = (kind == 2 ? 7 : 3) * (size_t)M * M;
   // (+16: the Gram-term row blocks may read up to 15 elements past the output tile)
   return (tiles > aug ? tiles : aug) + 2 * (size_t)M * M + 10 * kTDriveWin + 3 * (size_t)M +
          (5 * (size_t)L + dmax + 2) / 2 + 16;
 }
-// Entries of [G | C_1 | C_2] per thread: thread t owns column t mod 3M and
-// the block of KPe consecutive rows from (t / 3M) KPe, KPe = ceil(M / NG),
-// NG = 256 / (3M) row groups.  Kernel variants exist for a few block sizes
-// KP >= KPe (the entries past KPe are computed and dropped).
-__host__ __device__ inline int packed_kpe(int M) {
-  const int ng = kTW / (3 * M);
+// Entries of the Gram terms per thread: thread t owns column t mod C (C = 3M
+// columns [G | C_1 | C_2], or 4M for kind 2) and the block of KPe consecutive
+// rows from (t / C) KPe, KPe = ceil(M / NG), NG = 256 / C row groups.  Kernel
+// variants exist for a few block sizes KP >= KPe (the entries past KPe are
+// computed and dropped).
+__host__ __device__ inline int packed_kpe(int M, int C) {
+  const int ng = kTW / C;
   return (M + ng - 1) / ng;
 }
-inline int packed_kp(int M) {
-  const int need = packed_kpe(M);
+inline int packed_kp(int M, int kind = 0) {
+  const int need = packed_kpe(M, (kind == 2 ? 4 : 3) * M);
   return need <= 2 ? 2 : need <= 3 ? 3 : need <= 5 ? 5 : need <= 8 ? 8 : need <= 12 ? 12 : 16;
 }
 
@@ -83,6 +87,20 @@ __device__ __forceinline__ void gram_rows(double2 (&acc)[KP], const double2* Ot,
   }
 }
 
+// Kind 2: K rows of Q = O^ sqrt(kappa) c_l^ O over one layer pair, acc[k] +=
+// c sum_rl conj(Ot[rl][pi0 + k]) Op[rl][pcc], Ot the output of layer r, Op that
+// of layer r - 1 and c = sqrt(kappa r).
+template <int K, int KP>
+__device__ __forceinline__ void gram_rows_q(double2 (&acc)[KP], const double2* Ot, const double2* Op, double c,
+                                            int L, int M, int pcc, int pi0) {
+  for (int rl = 0; rl < L; ++rl) {
+    const double2 x = cscale(c, Op[rl * M + pcc]);
+    const double2* o = Ot + rl * M + pi0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = cjmac(acc[k], o[k], x);
+  }
+}
+
 // Mapping of a packed workgroup's threads onto [G | C_1 | C_2] (M x 3M): thread
 // t owns column pc = t mod 3M of [O | L_1 O | L_2 O] (pkind 0, 1, 2 = G, filter,
 // transmon; pcc its column within) and rows pi0 .. pi0 + KPe - 1.
@@ -96,7 +114,7 @@ struct PackedMap {
 template <int KP>
 __device__ __forceinline__ void packed_terms(double2 (&acc)[KP], const PackedMap& P, const double2* Ot,
                                              const double* coef) {
-  if (!P.pact) return;
+  if (!P.pact || P.pkind > 2) return;
   const int L = P.L, M = P.M, KPe = P.KPe, pcc = P.pcc, pi0 = P.pi0;
   const int shift = P.pkind == 0 ? 0 : (P.pkind == 1 ? 1 : P.d_f);
   const double* cr = coef + P.pkind * L;
@@ -115,43 +133,31 @@ __device__ __forceinline__ void packed_terms(double2 (&acc)[KP], const PackedMap
   }
 }
 
-// [G | C_1 | C_2] (the threads' entries) -> W_1, W_2 in Wl, through the M x 3M
-// elimination in Aug; returns 0, or -4 (pivot <= 0) / -5 (non-finite).
+// Kind 2: the Q columns (pkind 3) of the layer pair (Ot, Op), c = sqrt(kappa r).
 template <int KP>
-__device__ __forceinline__ int packed_solve(double2 (&acc)[KP], const PackedMap& P, double2* Aug, double2* Wl,
-                                            double2* s_prow, double* s_red, int* s_flag, bool want_fro2,
-                                            double* fro2) {
-  const int tid = threadIdx.x, M = P.M, MM = M * M, C3 = P.C3, KPe = P.KPe, pi0 = P.pi0, pc = P.pc;
-  const bool pact = P.pact;
-  const int pkind = P.pkind;
-  __syncthreads();  // the tiles are free
-  int bad = 0;
-  double f2 = 0.0;
-  if (pact) {
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      const int i = pi0 + k;
-      if (k < KPe && i < M) {
-        Aug[i * C3 + pc] = acc[k];
-        if (!isfinite(acc[k].x) || !isfinite(acc[k].y)) bad = 1;
-        if (pkind == 0) f2 += acc[k].x * acc[k].x + acc[k].y * acc[k].y;
-      }
-    }
+__device__ __forceinline__ void packed_terms_q(double2 (&acc)[KP], const PackedMap& P, const double2* Ot,
+                                               const double2* Op, double c) {
+  if (!P.pact || P.pkind != 3) return;
+  const int L = P.L, M = P.M, KPe = P.KPe, pcc = P.pcc, pi0 = P.pi0;
+  if (KPe <= 2 || KP == 2) {
+    gram_rows_q<2>(acc, Ot, Op, c, L, M, pcc, pi0);
+  } else if (KPe <= 3 || KP == 3) {
+    if constexpr (KP >= 3) gram_rows_q<3>(acc, Ot, Op, c, L, M, pcc, pi0);
+  } else if (KPe <= 5 || KP == 5) {
+    if constexpr (KP >= 5) gram_rows_q<5>(acc, Ot, Op, c, L, M, pcc, pi0);
+  } else if (KPe <= 8 || KP == 8) {
+    if constexpr (KP >= 8) gram_rows_q<8>(acc, Ot, Op, c, L, M, pcc, pi0);
+  } else if (KPe <= 12 || KP == 12) {
+    if constexpr (KP >= 12) gram_rows_q<12>(acc, Ot, Op, c, L, M, pcc, pi0);
+  } else {
+    if constexpr (KP >= 16) gram_rows_q<16>(acc, Ot, Op, c, L, M, pcc, pi0);
   }
-  if (tid == 0) *s_flag = 0;
-  __syncthreads();
-  if (bad) *s_flag = 1;
-  if (want_fro2) {
-    for (int off = 32; off > 0; off >>= 1) f2 += __shfl_xor(f2, off);
-    if ((tid & 63) == 0) s_red[tid >> 6] = f2;
-  }
-  __syncthreads();
-  if (want_fro2) {
-    double tot = 0.0;
-    for (int w = 0; w < kTW / 64; ++w) tot += s_red[w];
-    *fro2 = tot;
-  }
-  if (*s_flag) return -5;
+}
+
+// Gauss-Jordan elimination of the M x 3M matrix [G | C_1 | C_2] in Aug into
+// [I | X_1 | X_2], then W_k = X_k^ into Wl; returns 0 or -4 (pivot <= 0).
+__device__ __forceinline__ int packed_eliminate(double2* Aug, double2* Wl, double2* s_prow, int M) {
+  const int tid = threadIdx.x, C3 = 3 * M, MM = M * M;
   // pivot p: the scaled pivot row goes to s_prow, then every entry right of
   // the pivot column takes x - Aug[i][p] prow[c] (the pivot row: prow[c]);
   // the pivot column is only read
@@ -184,6 +190,79 @@ __device__ __forceinline__ int packed_solve(double2 (&acc)[KP], const PackedMap&
   }
   __syncthreads();
   return 0;
+}
+
+// The threads' entries of the Gram terms into St (row stride P.C3), with the
+// non-finite check and, on request, ||G||_F^2; returns 0 or -5.
+template <int KP>
+__device__ __forceinline__ int packed_store(double2 (&acc)[KP], const PackedMap& P, double2* St, double* s_red,
+                                            int* s_flag, bool want_fro2, double* fro2) {
+  const int tid = threadIdx.x, M = P.M, C = P.C3, KPe = P.KPe, pi0 = P.pi0, pc = P.pc;
+  __syncthreads();  // the tiles are free
+  int bad = 0;
+  double f2 = 0.0;
+  if (P.pact) {
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int i = pi0 + k;
+      if (k < KPe && i < M) {
+        St[i * C + pc] = acc[k];
+        if (!isfinite(acc[k].x) || !isfinite(acc[k].y)) bad = 1;
+        if (P.pkind == 0) f2 += acc[k].x * acc[k].x + acc[k].y * acc[k].y;
+      }
+    }
+  }
+  if (tid == 0) *s_flag = 0;
+  __syncthreads();
+  if (bad) *s_flag = 1;
+  if (want_fro2) {
+    for (int off = 32; off > 0; off >>= 1) f2 += __shfl_xor(f2, off);
+    if ((tid & 63) == 0) s_red[tid >> 6] = f2;
+  }
+  __syncthreads();
+  if (want_fro2) {
+    double tot = 0.0;
+    for (int w = 0; w < kTW / 64; ++w) tot += s_red[w];
+    *fro2 = tot;
+  }
+  return *s_flag ? -5 : 0;
+}
+
+// Kind 2: [G | P_u | C_2 | Q] (staged in St, M x 4M) -> [G | C_1 | C_2] in
+// Aug, with P_u = sqrt(kappa) O^ c_u O and Q = sqrt(kappa) O^ c_l^ O:
+// O^ L_1 O = e1 (s_21 P_u^ + s_22 Q) + conj(e1) (s_23 Q^ + s_24 P_u), e1 the
+// frame phase e^{i w_d t} of the time the W_k are used at (1 in the lab frame).
+__device__ __forceinline__ void packed_form_c1(const double2* St, double2* Aug, int M, const double* nm,
+                                               double2 e1) {
+  const int C3 = 3 * M, C4 = 4 * M;
+  const double2 e1c = make_double2(e1.x, -e1.y);
+  for (int e = threadIdx.x; e < M * C3; e += kTW) {
+    const int i = e / C3, c = e - i * C3;
+    double2 v;
+    if (c < M || c >= 2 * M) {
+      v = St[i * C4 + c];
+    } else {
+      const int j = c - M;
+      const double2 pij = St[i * C4 + M + j], pji = St[j * C4 + M + i];
+      const double2 qij = St[i * C4 + 3 * M + j], qji = St[j * C4 + 3 * M + i];
+      // s_21 conj(P_u[j][i]) + s_22 Q[i][j] and s_23 conj(Q[j][i]) + s_24 P_u[i][j]
+      const double2 cr = make_double2(nm[0] * pji.x + nm[1] * qij.x, -nm[0] * pji.y + nm[1] * qij.y);
+      const double2 an = make_double2(nm[2] * qji.x + nm[3] * pij.x, -nm[2] * qji.y + nm[3] * pij.y);
+      v = cadd(cmul(e1, cr), cmul(e1c, an));
+    }
+    Aug[e] = v;
+  }
+  __syncthreads();
+}
+
+// [G | C_1 | C_2] (the threads' entries) -> W_1, W_2 in Wl, through the M x 3M
+// elimination in Aug; returns 0, or -4 (pivot <= 0) / -5 (non-finite).
+template <int KP>
+__device__ __forceinline__ int packed_solve(double2 (&acc)[KP], const PackedMap& P, double2* Aug, double2* Wl,
+                                            double2* s_prow, double* s_red, int* s_flag, bool want_fro2,
+                                            double* fro2) {
+  const int rc = packed_store<KP>(acc, P, Aug, s_red, s_flag, want_fro2, fro2);
+  return rc ? rc : packed_eliminate(Aug, Wl, s_prow, P.M);
 }
 
 // Element (rl, j) of layer r: z = H_eff Y (stencil and drive) from the layers
@@ -271,30 +350,121 @@ __device__ __forceinline__ double2 packed_stencil_tm(const TrajDev& T, const dou
   return make_double2(z.x - drv * v.y, z.y + drv * v.x);
 }
 
+// Element (rl, j) of layer r for the normal-mode model (kind 2): z = H_eff Y with
+// H_eff = diag(E_q + w_l r + w_u f) + i g n_t (mu_l (c_l^ - c_l) + mu_u (c_u^ -
+// c_u)) + d(t) i (nu_l (c_l^ - c_l) + nu_u (c_u^ - c_u)) - i/2 (gamma b^b +
+// L_1^ L_1).  The diagonal of L_1^ L_1 (the products of the truncated ladders:
+// c c^ is n + 1 below the top level and 0 on it) is in hd (row part) and him
+// (layer part); its off-diagonal part, kappa times
+//   (s21 s22 + s23 s24)(c_l^ c_u + c_u^ c_l)
+//   + (s22 s23 c_l^2 + (s21 s23 + s22 s24) c_l c_u + s21 s24 c_u^2) e^{-2 i w_d t}
+//   + (the adjoint terms, raising twice) e^{2 i w_d t},
+// reaches two layers up and down (Y[0..4] = layers r - 2 .. r + 2).  Phases as
+// in packed_stencil_tm: a tap from a neighbour with dn more excitations
+// carries e^{-i w_d t dn} in the rotating frame.
+template <bool ROT>
+__device__ __forceinline__ double2 packed_stencil_nm(const TrajDev& T, const double2* const* Y, const double* sq,
+                                                     const double2* hd, const double* nt, const double2* ph,
+                                                     int ph0, int r, int rl, int q, int f, int j, double drv,
+                                                     double him) {
+  const int M = T.M, d_f = T.d_f, d_q = T.d_q, d_r = T.d_r;
+  const double2 *Ym2 = Y[0], *Ym1 = Y[1], *Y0 = Y[2], *Yp1 = Y[3], *Yp2 = Y[4];
+  const double s21 = T.nm[0], s22 = T.nm[1], s23 = T.nm[2], s24 = T.nm[3];
+  const double mu_l = T.nm[4], mu_u = T.nm[5], nu_l = T.nm[6], nu_u = T.nm[7];
+  const double2 h = hd[rl];
+  double2 z = cmul(make_double2(h.x + T.w_r * r, h.y + him), Y0[rl * M + j]);
+  const double sr0 = sq[r], sr1 = sq[min(r + 1, d_r)], sf0 = sq[f], sf1 = sq[min(f + 1, d_f)];
+  const bool rdn = r > 0, rup = r + 1 < d_r, fdn = f > 0, fup = f + 1 < d_f;
+  auto tap = [&](double2 acc, double c, int dn, double2 nb) {
+    if (!ROT || dn == 0) return cfma(c, nb, acc);
+    const double2 e = ph[dn + ph0];
+    return cadd(acc, cmul(make_double2(c * e.x, -c * e.y), nb));
+  };
+  // i g n_t (mu_l (c_l^ - c_l) + mu_u (c_u^ - c_u))
+  double2 s = make_double2(0.0, 0.0);
+  for (int p = 0; p < d_q; ++p) {
+    const double c = nt[q * d_q + p];
+    if (c == 0.0) continue;
+    const int row = p * d_f + f;
+    if (rdn) s = tap(s, c * mu_l * sr0, p - q - 1, Ym1[row * M + j]);
+    if (rup) s = tap(s, -c * mu_l * sr1, p - q + 1, Yp1[row * M + j]);
+    if (fdn) s = tap(s, c * mu_u * sf0, p - q - 1, Y0[(row - 1) * M + j]);
+    if (fup) s = tap(s, -c * mu_u * sf1, p - q + 1, Y0[(row + 1) * M + j]);
+  }
+  z = make_double2(z.x - T.g * s.y, z.y + T.g * s.x);
+  // d(t) i (nu_l (c_l^ - c_l) + nu_u (c_u^ - c_u))
+  double2 v = make_double2(0.0, 0.0);
+  if (rdn) v = tap(v, nu_l * sr0, -1, Ym1[rl * M + j]);
+  if (rup) v = tap(v, -nu_l * sr1, 1, Yp1[rl * M + j]);
+  if (fdn) v = tap(v, nu_u * sf0, -1, Y0[(rl - 1) * M + j]);
+  if (fup) v = tap(v, -nu_u * sf1, 1, Y0[(rl + 1) * M + j]);
+  z = make_double2(z.x - drv * v.y, z.y + drv * v.x);
+  // -i/2 kappa (off-diagonal part of f^ f)
+  const double cx = s21 * s22 + s23 * s24, cb = s21 * s23 + s22 * s24, cl2 = s22 * s23, cu2 = s21 * s24;
+  double2 w = make_double2(0.0, 0.0);
+  if (rdn && fup) w = tap(w, cx * sr0 * sf1, 0, Ym1[(rl + 1) * M + j]);   // c_l^ c_u
+  if (rup && fdn) w = tap(w, cx * sr1 * sf0, 0, Yp1[(rl - 1) * M + j]);   // c_u^ c_l
+  if (r + 2 < d_r) w = tap(w, cl2 * sr1 * sq[r + 2], 2, Yp2[rl * M + j]);           // c_l c_l
+  if (rup && fup) w = tap(w, cb * sr1 * sf1, 2, Yp1[(rl + 1) * M + j]);            // c_l c_u
+  if (f + 2 < d_f) w = tap(w, cu2 * sf1 * sq[f + 2], 2, Y0[(rl + 2) * M + j]);      // c_u c_u
+  if (r >= 2) w = tap(w, cl2 * sr0 * sq[r - 1], -2, Ym2[rl * M + j]);               // c_l^ c_l^
+  if (rdn && fdn) w = tap(w, cb * sr0 * sf0, -2, Ym1[(rl - 1) * M + j]);           // c_l^ c_u^
+  if (f >= 2) w = tap(w, cu2 * sf0 * sq[f - 1], -2, Y0[(rl - 2) * M + j]);          // c_u^ c_u^
+  const double hk = 0.5 * T.kappa;
+  return make_double2(z.x + hk * w.y, z.y - hk * w.x);
+}
+
+// Kind 2: element (rl, j) of L_1 Y at layer r, L_1 = sqrt(kappa) (s21 e1 c_u^ +
+// s22 e1 c_l^ + s23 conj(e1) c_l + s24 conj(e1) c_u), from the layers r - 1,
+// r, r + 1 (e1 = e^{i w_d t} in the rotating frame, 1 in the lab frame).
+__device__ __forceinline__ double2 packed_jump_nm(const TrajDev& T, const double2* Ym1, const double2* Y0,
+                                                  const double2* Yp1, const double* sq, int r, int rl, int f, int j,
+                                                  double2 e1) {
+  const int M = T.M, d_f = T.d_f, d_r = T.d_r;
+  double2 up = make_double2(0.0, 0.0), dn = make_double2(0.0, 0.0);
+  if (f > 0) up = cfma(T.nm[0] * sq[f], Y0[(rl - 1) * M + j], up);
+  if (r > 0) up = cfma(T.nm[1] * sq[r], Ym1[rl * M + j], up);
+  if (r + 1 < d_r) dn = cfma(T.nm[2] * sq[r + 1], Yp1[rl * M + j], dn);
+  if (f + 1 < d_f) dn = cfma(T.nm[3] * sq[f + 1], Y0[(rl + 1) * M + j], dn);
+  const double sk = sqrt(T.kappa);
+  return cscale(sk, cadd(cmul(e1, up), cmulc(dn, e1)));
+}
+
 // The kernel body: prologue (Gram terms and W of the initial state, no step)
-// or a chunk of nchunk RK4 steps from step0.  KP = entries of [G|C_1|C_2] per
-// thread (packed_kp).
+// or a chunk of nchunk RK4 steps from step0.  KP = entries of the Gram terms
+// per thread (packed_kp).  MK = model kind; kind 2 keeps five input layers,
+// the filter jump L_1 Y of the current and the next layer, and the outputs of
+// the current and the previous layer (for the cross-layer term Q).
 template <int KP, bool ROT, int MK = 0>
 __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int64_t step0, int64_t nchunk) {
   extern __shared__ double2 lds[];
   __shared__ double s_red[kTW / 64];
   __shared__ double s_nt[kMaxDq * kMaxDq];
-  __shared__ double2 s_ph[2 * kMaxDq + 3];  // e^{i w_d t m}, m = -(d_q + 1) .. d_q + 1, of the stage (kind 1, rotating frame)
+  __shared__ double2 s_ph[2 * kMaxDq + 3];  // e^{i w_d t m}, m = -(d_q + 1) .. d_q + 1, of the stage (kinds 1, 2, rotating frame)
   __shared__ int s_flag;
+  constexpr bool NM = MK == 2;
+  constexpr int NTILE = NM ? 9 : 4;
   const int tid = threadIdx.x;
   const int M = T.M, MM = M * M, L = T.L, d_f = T.d_f, d_q = T.d_q, d_r = T.d_r;
-  const int LM = L * M, C3 = 3 * M;
+  const int LM = L * M, CT = (NM ? 4 : 3) * M;
   const double dt = T.dt;
   const double sk = sqrt(T.kappa), sg = sqrt(T.gamma);
+  double2* Ym2 = lds;                                 // kind 2: layer r - 2 of the stage input
   double2* Yp = lds;                                  // layers r - 1, r, r + 1 of the stage input
   double2* Yc = lds + LM;
   double2* Yn = lds + 2 * LM;
-  double2* Ot = lds + 3 * LM;                         // layer r of the stage output
-  double2* Aug = lds;                                 // M x 3M elimination (after the layer loop)
-  double2* Wl = lds + (4 * LM > 3 * MM ? 4 * LM : 3 * MM);  // W_1, W_2 (M x M each, row i, column j)
+  double2* Yp2 = lds;                                 // kind 2: layer r + 2
+  double2* Y1c = lds + 5 * LM;                        // kind 2: L_1 Y of layers r, r + 1
+  double2* Y1n = lds + 6 * LM;
+  double2* Ot = lds + (NM ? 7 : 3) * LM;              // layer r of the stage output
+  double2* Op = lds + 8 * LM;                         // kind 2: layer r - 1 of the stage output
+  const int areg = (NM ? 7 : 3) * MM;
+  double2* St = lds;                                  // Gram terms as formed (M x CT)
+  double2* Aug = NM ? lds + 4 * MM : lds;             // M x 3M elimination (after the layer loop)
+  double2* Wl = lds + (NTILE * LM > areg ? NTILE * LM : areg);  // W_1, W_2 (M x M each, row i, column j)
   double (*s_dtab)[5] = reinterpret_cast<double (*)[5]>(Wl + 2 * MM);  // [4 kTDriveWin][5] drive table
   double2* s_prow = Wl + 2 * MM + 10 * kTDriveWin;          // [3M] pivot row
-  double2* hd = s_prow + 3 * M;                             // [L] diagonal of H_eff without w_r r
+  double2* hd = s_prow + 3 * M;                             // [L] diagonal of H_eff without its layer term
   double* coef = reinterpret_cast<double*>(hd + L);         // [3][L]: 1, filter jump, transmon jump
   double* sq = coef + 3 * L;                                // sqrt(0 .. dmax)
   g_double2* gBb = (g_double2*)T.Bb;
@@ -302,12 +472,14 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
   g_double2* gW = (g_double2*)T.W;
 
   if (tid == 0) s_flag = *T.status;
-  if constexpr (MK == 1)
+  if constexpr (MK >= 1)
     for (int i = tid; i < d_q * d_q; i += kTW) s_nt[i] = T.ntq[i];
   for (int rl = tid; rl < L; rl += kTW) {
     const int q = rl / d_f, f = rl - q * d_f;
-    const double eq = MK == 1 ? T.Et[q] - (ROT ? T.w_d * q : 0.0) : T.w_q * q + 0.5 * T.alpha * q * (q - 1);
-    hd[rl] = make_double2(eq + T.w_f * f, -0.5 * (T.kappa * f + T.gamma * q));
+    const double eq = MK >= 1 ? T.Et[q] - (ROT ? T.w_d * q : 0.0) : T.w_q * q + 0.5 * T.alpha * q * (q - 1);
+    // kind 2: the f-dependent diagonal of f^ f, s21^2 c_u c_u^ + s24^2 c_u^ c_u
+    const double ff = NM ? T.nm[0] * T.nm[0] * (f + 1 < d_f ? f + 1.0 : 0.0) + T.nm[3] * T.nm[3] * f : (double)f;
+    hd[rl] = make_double2(eq + T.w_f * f, -0.5 * (T.kappa * ff + T.gamma * q));
     coef[rl] = 1.0;
     coef[L + rl] = (f + 1 < d_f) ? sk * sqrt((double)(f + 1)) : 0.0;
     coef[2 * L + rl] = (q + 1 < d_q) ? sg * sqrt((double)(q + 1)) : 0.0;
@@ -322,11 +494,11 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
   const int NGe = kTW / M;
   const int ej = tid % M, eg = tid / M;
   const bool eact = eg < NGe;
-  // Gram-term mapping: column c of [O | L_1 O | L_2 O], rows i = pi0 + k
-  const int NGp = kTW / C3, KPe = packed_kpe(M);
-  const int pc = tid % C3, pg = tid / C3, pi0 = pg * KPe;
+  // Gram-term mapping: column c of [O | L_1 O | L_2 O] (kind 2: [O | c_u O | L_2 O | c_l^ O]), rows i = pi0 + k
+  const int NGp = kTW / CT, KPe = packed_kpe(M, CT);
+  const int pc = tid % CT, pg = tid / CT, pi0 = pg * KPe;
   const bool pact = pg < NGp && pi0 < M;
-  const int pkind = pc / M, pcc = pc - pkind * M;  // 0: G, 1: C_1 (filter), 2: C_2 (transmon)
+  const int pkind = pc / M, pcc = pc - pkind * M;  // 0: G, 1: C_1 (filter), 2: C_2 (transmon), 3: Q (kind 2)
 
   if (!prologue)
     for (int e = tid; e < 2 * MM; e += kTW) Wl[e] = ld_g(gW + e);
@@ -349,10 +521,30 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
     __syncthreads();
   };
 
-  const PackedMap PM{M, C3, L, d_f, KPe, pc, pi0, pkind, pcc, pact};
-  auto add_terms = [&](double2 (&acc)[KP]) { packed_terms<KP>(acc, PM, Ot, coef); };
-  auto solve = [&](double2 (&acc)[KP], bool want_fro2, double* fro2) -> int {
-    return packed_solve<KP>(acc, PM, Aug, Wl, s_prow, s_red, &s_flag, want_fro2, fro2);
+  const PackedMap PM{M, CT, L, d_f, KPe, pc, pi0, pkind, pcc, pact};
+  // Gram terms of the output layer r in Ot (kind 2: and of the pair (Op, Ot))
+  auto add_terms = [&](double2 (&acc)[KP], int r) {
+    packed_terms<KP>(acc, PM, Ot, coef);
+    if constexpr (NM)
+      if (r > 0) packed_terms_q<KP>(acc, PM, Ot, Op, sk * sq[r]);
+  };
+  // W_k of the state whose Gram terms the threads hold, for use at time t_use
+  auto solve = [&](double2 (&acc)[KP], bool want_fro2, double* fro2, double t_use) -> int {
+    if constexpr (NM) {
+      const int rc = packed_store<KP>(acc, PM, St, s_red, &s_flag, want_fro2, fro2);
+      if (rc) return rc;
+      packed_form_c1(St, Aug, M, T.nm, ROT ? frame_phase(T.w_d, t_use) : make_double2(1.0, 0.0));
+      return packed_eliminate(Aug, Wl, s_prow, M);
+    } else {
+      return packed_solve<KP>(acc, PM, Aug, Wl, s_prow, s_red, &s_flag, want_fro2, fro2);
+    }
+  };
+  // kind 2: L_1 Y of layer r into dst from the layers r - 1, r, r + 1
+  auto jump_tile = [&](double2* dst, const double2* ym, const double2* y0, const double2* yp, int r, double2 e1j) {
+    for (int e = tid; e < LM; e += kTW) {
+      const int rl = e / M, j = e - rl * M;
+      dst[e] = packed_jump_nm(T, ym, y0, yp, sq, r, rl, rl % d_f, j, e1j);
+    }
   };
 
   double2 acc[KP];
@@ -364,10 +556,15 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
       __syncthreads();
       for (int e = tid; e < LM; e += kTW) Ot[e] = ld_g(gBb + (size_t)r * LM + e);
       __syncthreads();
-      add_terms(acc);
+      add_terms(acc, r);
+      if constexpr (NM) {
+        double2* t = Ot;
+        Ot = Op;
+        Op = t;
+      }
     }
     double f2 = 0.0;
-    const int rc = solve(acc, true, &f2);
+    const int rc = solve(acc, true, &f2, stage_time(step0, 0));
     if (rc) {
       if (tid == 0) report(T, rc, step0);
       return;
@@ -389,21 +586,44 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
       const int ds = (int)(n % kTDriveWin) * 4 + s;
       const double drv = s_dtab[ds][0];
       const double2 e1 = make_double2(s_dtab[ds][1], s_dtab[ds][2]), e2 = make_double2(s_dtab[ds][3], s_dtab[ds][4]);
+      const double2 e1j = ROT ? e1 : make_double2(1.0, 0.0);  // phase of the kind-2 filter jump
 #pragma unroll
       for (int k = 0; k < KP; ++k) acc[k] = make_double2(0.0, 0.0);
-      if constexpr (MK == 1 && ROT)
+      if constexpr (MK >= 1 && ROT)
         if (tid < 2 * d_q + 3) s_ph[tid] = frame_phase((tid - d_q - 1) * T.w_d, stage_time(step, s));
       __syncthreads();  // Wl of this stage written; tiles free
-      Yp = lds;
-      Yc = lds + LM;
-      Yn = lds + 2 * LM;
+      if constexpr (NM) {
+        Ym2 = lds;
+        Yp = lds + LM;
+        Yc = lds + 2 * LM;
+        Yn = lds + 3 * LM;
+        Yp2 = lds + 4 * LM;
+        Y1c = lds + 5 * LM;
+        Y1n = lds + 6 * LM;
+        Ot = lds + 7 * LM;
+        Op = lds + 8 * LM;
+      } else {
+        Yp = lds;
+        Yc = lds + LM;
+        Yn = lds + 2 * LM;
+      }
       for (int e = tid; e < LM; e += kTW) Yc[e] = ld_g(in + e);
       if (d_r > 1)
         for (int e = tid; e < LM; e += kTW) Yn[e] = ld_g(in + LM + e);
+      if constexpr (NM) {
+        if (d_r > 2)
+          for (int e = tid; e < LM; e += kTW) Yp2[e] = ld_g(in + 2 * LM + e);
+        __syncthreads();
+        jump_tile(Y1c, Yp, Yc, Yn, 0, e1j);
+      }
       __syncthreads();
       for (int r = 0; r < d_r; ++r) {
+        const double him = NM ? -0.5 * T.kappa *
+                                    (T.nm[1] * T.nm[1] * (r + 1 < d_r ? r + 1.0 : 0.0) + T.nm[2] * T.nm[2] * r)
+                              : 0.0;
         // 1. stage output of layer r, in blocks of kTRowBlock rows per thread
         if (eact) {
+          const double2* A1 = NM ? Y1c : Yc;  // source tile of the filter jump rows
           for (int rb = eg; rb < L; rb += kTRowBlock * NGe) {
             // B_n and the RK4 accumulator of the block are in flight during the jump assembly
             double2 pb[kTRowBlock], pa[kTRowBlock];
@@ -422,14 +642,14 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
             for (int k = 0; k < kTRowBlock; ++k) {
               a1[k] = a2[k] = make_double2(0.0, 0.0);
               const int rl = min(rb + k * NGe, L - 1);
-              s1[k] = min(rl + 1, L - 1) * M;
+              s1[k] = (NM ? rl : min(rl + 1, L - 1)) * M;
               s2[k] = min(rl + d_f, L - 1) * M;
             }
             for (int i = 0; i < M; ++i) {
               const double2 w1 = Wl[i * M + ej], w2 = Wl[MM + i * M + ej];
 #pragma unroll
               for (int k = 0; k < kTRowBlock; ++k) {
-                a1[k] = cmac(a1[k], Yc[s1[k] + i], w1);
+                a1[k] = cmac(a1[k], A1[s1[k] + i], w1);
                 a2[k] = cmac(a2[k], Yc[s2[k] + i], w2);
               }
             }
@@ -438,12 +658,16 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
               const int rl = rb + k * NGe;
               if (rl < L) {
                 const int q = rl / d_f, f = rl - q * d_f;
-                const double2 a = cfma(coef[L + rl], a1[k], cscale(coef[2 * L + rl], a2[k]));
+                const double2 a = cfma(NM ? 1.0 : coef[L + rl], a1[k], cscale(coef[2 * L + rl], a2[k]));
                 double2 z;
-                if constexpr (MK == 1)
+                if constexpr (MK == 2) {
+                  const double2* Yw[5] = {Ym2, Yp, Yc, Yn, Yp2};
+                  z = packed_stencil_nm<ROT>(T, Yw, sq, hd, s_nt, s_ph, d_q + 1, r, rl, q, f, ej, drv, him);
+                } else if constexpr (MK == 1) {
                   z = packed_stencil_tm<ROT>(T, Yp, Yc, Yn, sq, hd, s_nt, s_ph, d_q + 1, r, rl, q, f, ej, drv);
-                else
+                } else {
                   z = packed_stencil<ROT>(T, Yp, Yc, Yn, sq, hd, r, rl, q, f, ej, drv, e1, e2);
+                }
                 const double2 kk = make_double2(z.y + 0.5 * a.x, -z.x + 0.5 * a.y);
                 const size_t gi = ((size_t)r * L + rl) * M + ej;
                 double2 o;
@@ -466,35 +690,56 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
           }
         }
         __syncthreads();
-        // 2. layer r + 2 of the stage input is in flight while the Gram terms
-        //    of layer r are formed; it replaces layer r - 1
-        if (r + 2 < d_r) {
-          const g_double2* nx = in + (size_t)(r + 2) * LM;
+        // 2. the next input layer (r + 2; kind 2: r + 3) is in flight while the
+        //    Gram terms of layer r are formed; it replaces the oldest layer
+        const int rnx = NM ? r + 3 : r + 2;
+        double2* dstl = NM ? Ym2 : Yp;
+        if (rnx < d_r) {
+          const g_double2* nx = in + (size_t)rnx * LM;
           double2 pf[kTPrefetch];
 #pragma unroll
           for (int u = 0; u < kTPrefetch; ++u) {
             const int e = tid + u * kTW;
             if (e < LM) pf[u] = ld_g(nx + e);
           }
-          add_terms(acc);
+          if constexpr (NM)
+            if (r + 1 < d_r) jump_tile(Y1n, Yc, Yn, Yp2, r + 1, e1j);
+          add_terms(acc, r);
 #pragma unroll
           for (int u = 0; u < kTPrefetch; ++u) {
             const int e = tid + u * kTW;
-            if (e < LM) Yp[e] = pf[u];
+            if (e < LM) dstl[e] = pf[u];
           }
-          for (int e = tid + kTPrefetch * kTW; e < LM; e += kTW) Yp[e] = ld_g(nx + e);
+          for (int e = tid + kTPrefetch * kTW; e < LM; e += kTW) dstl[e] = ld_g(nx + e);
         } else {
-          add_terms(acc);
+          if constexpr (NM)
+            if (r + 1 < d_r) jump_tile(Y1n, Yc, Yn, Yp2, r + 1, e1j);
+          add_terms(acc, r);
         }
         __syncthreads();
-        double2* t = Yp;
-        Yp = Yc;
-        Yc = Yn;
-        Yn = t;
+        if constexpr (NM) {
+          double2* t = Ym2;
+          Ym2 = Yp;
+          Yp = Yc;
+          Yc = Yn;
+          Yn = Yp2;
+          Yp2 = t;
+          t = Y1c;
+          Y1c = Y1n;
+          Y1n = t;
+          t = Ot;
+          Ot = Op;
+          Op = t;
+        } else {
+          double2* t = Yp;
+          Yp = Yc;
+          Yc = Yn;
+          Yn = t;
+        }
       }
       double f2 = 0.0;
       const bool last = (s == 3) && (n + 1 == nrun);
-      const int rc = solve(acc, last, &f2);
+      const int rc = solve(acc, last, &f2, s < 3 ? stage_time(step, s + 1) : stage_time(step + 1, 0));
       if (rc) {
         if (tid == 0) {
           report(T, rc, step);
@@ -510,7 +755,9 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
 }
 
 // blockIdx.x = trajectory of trajs[]; the RK4 chunk and the prologue are
-// separate kernels so that timing tools see the step kernel alone.
+// separate kernels so that timing tools see the step kernel alone.  The
+// normal-mode model has kernels of its own (its larger window would raise the
+// register allocation, and so lower the occupancy, of the other kinds).
 template <int KP>
 __global__ __launch_bounds__(kTW) void k_packed(const TrajDev* __restrict__ trajs, int64_t step0, int64_t nchunk) {
   const TrajDev& T = trajs[blockIdx.x];
@@ -529,13 +776,32 @@ __global__ __launch_bounds__(kTW) void k_packed_prologue(const TrajDev* __restri
                                                          int64_t nchunk) {
   packed_body<KP, false>(trajs[blockIdx.x], 1, step0, nchunk);
 }
+template <int KP>
+__global__ __launch_bounds__(kTW) void k_packed_nm(const TrajDev* __restrict__ trajs, int64_t step0,
+                                                   int64_t nchunk) {
+  const TrajDev& T = trajs[blockIdx.x];
+  if (T.frame)
+    packed_body<KP, true, 2>(T, 0, step0, nchunk);
+  else
+    packed_body<KP, false, 2>(T, 0, step0, nchunk);
+}
+template <int KP>
+__global__ __launch_bounds__(kTW) void k_packed_nm_prologue(const TrajDev* __restrict__ trajs, int64_t step0,
+                                                            int64_t nchunk) {
+  const TrajDev& T = trajs[blockIdx.x];
+  if (T.frame)
+    packed_body<KP, true, 2>(T, 1, step0, nchunk);
+  else
+    packed_body<KP, false, 2>(T, 1, step0, nchunk);
+}
 
 constexpr int kPackedKP[] = {2, 3, 5, 8, 12, 16};
 template <int I = 0>
-inline const void* packed_kernel(int kp, bool prologue) {
+inline const void* packed_kernel(int kp, bool prologue, bool nm = false) {
   if constexpr (I + 1 < (int)(sizeof(kPackedKP) / sizeof(int))) {
-    if (kp > kPackedKP[I]) return packed_kernel<I + 1>(kp, prologue);
+    if (kp > kPackedKP[I]) return packed_kernel<I + 1>(kp, prologue, nm);
   }
+  if (nm) return prologue ? (const void*)k_packed_nm_prologue<kPackedKP[I]> : (const void*)k_packed_nm<kPackedKP[I]>;
   return prologue ? (const void*)k_packed_prologue<kPackedKP[I]> : (const void*)k_packed<kPackedKP[I]>;
 }
 

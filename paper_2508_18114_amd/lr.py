@@ -68,7 +68,8 @@ class lr_model_t(ctypes.Structure):
                 ("g", ctypes.c_double), ("G", ctypes.c_double),
                 ("kappa_f", ctypes.c_double), ("gamma_1", ctypes.c_double),
                 ("E_t", ctypes.c_double * _inp.MAX_DQ),
-                ("n_t", ctypes.c_double * (_inp.MAX_DQ * _inp.MAX_DQ))]
+                ("n_t", ctypes.c_double * (_inp.MAX_DQ * _inp.MAX_DQ)),
+                ("S", ctypes.c_double * 8)]
 
 
 class lr_pulse_t(ctypes.Structure):
@@ -143,13 +144,18 @@ _lib = _load()
 def model_struct(m: _inp.ModelParams) -> lr_model_t:
     s = lr_model_t(m.d_q, m.d_r, m.d_f, int(getattr(m, "kind", 0)), m.w_q, m.alpha, m.w_r, m.w_f,
                    m.g, m.G, m.kappa_f, m.gamma_1)
-    if s.kind == _inp.MODEL_TRANSMON:
+    if s.kind in (_inp.MODEL_TRANSMON, _inp.MODEL_NORMAL):
         if m.d_q > _inp.MAX_DQ or len(m.E_t) != m.d_q or len(m.n_t) != m.d_q * m.d_q:
             raise ValueError("transmon model: E_t needs d_q values and n_t d_q * d_q (d_q <= MAX_DQ)")
         for k, x in enumerate(m.E_t):
             s.E_t[k] = float(x)
         for k, x in enumerate(m.n_t):
             s.n_t[k] = float(x)
+    if s.kind == _inp.MODEL_NORMAL:
+        if len(m.S) != 8:
+            raise ValueError("normal-mode model: S needs the two rows of a and f (8 values)")
+        for k, x in enumerate(m.S):
+            s.S[k] = float(x)
     return s
 
 
