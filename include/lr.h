@@ -144,7 +144,9 @@ typedef struct {
  * The M x M solve, the reduction of the Gram partials across the state and
  * the RK4 accumulation of B are FP64 in every mode.  lr_rhs and
  * lr_observables always evaluate in FP64; the reduced modes need the
- * persistent on-chip integrator (LR_ERR_ARG from lr_integrate otherwise). */
+ * persistent on-chip integrator (LR_ERR_ARG from lr_integrate otherwise).
+ * In the packed batch schedule the modes apply to the Gram and cross
+ * products only, which run on the matrix cores (LR_BATCH_PACKED_VALU_GRAM). */
 enum { LR_FP64 = 0, LR_FP32 = 1, LR_BF16X3 = 2 };
 
 enum {
@@ -331,7 +333,8 @@ typedef struct lr_batch lr_batch_t;
  * device pointers inside the descriptors are used by lr_batch_run. */
 int lr_batch_init(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n);
 /* lr_batch_init with schedule flags.  0 is lr_batch_init.  LR_BATCH_PACKED:
- * every LR_FP64 trajectory with d_q d_f M <= LR_PACKED_MAX_LM (and whose
+ * every trajectory (LR_FP64; LR_FP32 and LR_BF16X3 for model kinds 0 and 1,
+ * see LR_BATCH_PACKED_VALU_GRAM) with d_q d_f M <= LR_PACKED_MAX_LM (and whose
  * workgroup's LDS, about 16 (4 d_q d_f M + 2 M^2 + 2.5 d_q d_f) bytes, fits
  * 159 KiB) runs in a workgroup of its own (all of them in one launch per chunk of steps, as many
  * per CU as fit), which fills the GPU with many trajectories at once instead
@@ -342,6 +345,16 @@ int lr_batch_init(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n);
  * Unknown flag bits: LR_ERR_ARG. */
 #define LR_BATCH_PACKED 1
 #define LR_PACKED_MAX_LM 1536
+/* Packed schedule, Gram and cross products [G | C_1 | C_2] of model kinds 0
+ * and 1: by default on the matrix cores (v_mfma 16 x 16 output tiles; FP64
+ * trajectories with the FP64 instruction, LR_FP32 with the FP32 one and
+ * FP32 accumulation, LR_BF16X3 with three BF16 part products per real
+ * product and FP32 accumulation for C_k and the FP64 instruction for G).
+ * LR_BATCH_PACKED_VALU_GRAM forms them for the FP64 trajectories on the
+ * vector ALU instead (one thread per entry block, rows in order).  The
+ * stencil, the jump assembly, the solve and the RK4 state are FP64 in every
+ * packed mode.  Model kind 2 and adaptive batches: vector ALU, FP64 only. */
+#define LR_BATCH_PACKED_VALU_GRAM 2
 /* Tile height of the spread schedule: resonator layers per workgroup
  * (1..255; 0 or absent: one).  A height whose tile does not fit the kernel's
  * register rows or LDS is lowered to the largest that fits.  Combined with the

@@ -11,8 +11,9 @@
 // proceed independently, and each result is bitwise that of the trajectory
 // alone.
 //
-// Packed schedule (LR_BATCH_PACKED): every FP64 trajectory whose layer fits
-// the packed kernel gets one workgroup of its own (lr_packed.hip); all of them
+// Packed schedule (LR_BATCH_PACKED): every trajectory whose layer fits the
+// packed kernel gets one workgroup of its own (lr_packed.hip); the packed
+// trajectories of one kernel family (model kind 2 or not, arithmetic mode)
 // go into one ordinary launch per chunk, largest work first, and the hardware
 // fills each CU with as many as fit.  The others run in spread groups.
 
@@ -41,8 +42,11 @@ struct lr_batch {
     size_t lds;
     int64_t max_steps, chunk;
     int packed, kp;
-    int nm;  // packed group of the normal-mode model (its own kernels)
+    int nm;     // packed group of the normal-mode model (its own kernels)
+    int gm;     // packed: Gram terms on the vector ALU (-1) or matrix-core mode (0 FP64, 1 FP32, 2 BF16x3)
+    int slots;  // packed matrix-core modes: output tiles per wave
   };
+  bool valu_gram = false;  // LR_BATCH_PACKED_VALU_GRAM
   std::vector<Group> groups;
   bool prof = false;
   std::vector<hipEvent_t> ev;  // start/stop pairs of timed chunk launches
@@ -158,17 +162,21 @@ namespace {
 int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flags, bool adaptive, double rtol,
                double atol) {
   if (!out || !trajs || n < 1) return LR_ERR_ARG;
-  if (flags & ~(LR_BATCH_PACKED | LR_BATCH_SPREAD_LAYERS(0xff))) return LR_ERR_ARG;
+  if (flags & ~(LR_BATCH_PACKED | LR_BATCH_PACKED_VALU_GRAM | LR_BATCH_SPREAD_LAYERS(0xff))) return LR_ERR_ARG;
   *out = nullptr;
   lr_batch* b = new (std::nothrow) lr_batch();
   if (!b) return LR_ERR_OOM;
   b->n = n;
   b->adaptive = adaptive;
+  b->valu_gram = (flags & LR_BATCH_PACKED_VALU_GRAM) != 0;
   b->rtol = rtol;
   b->atol = atol;
   auto packs = [&](const lr_traj_t& x) {
     const long long LM = (long long)x.model.d_q * x.model.d_f * x.M;
-    if (!((flags & LR_BATCH_PACKED) && x.precision == LR_FP64 && x.M >= 1 && x.M <= lrk::kMaxM && LM >= 1 &&
+    // reduced arithmetic: kinds 0 and 1 (matrix-core Gram terms); adaptive steps: FP64
+    const bool prec_ok = x.precision == LR_FP64 || (!adaptive && x.model.kind != LR_MODEL_NORMAL &&
+                                                   (x.precision == LR_FP32 || x.precision == LR_BF16X3));
+    if (!((flags & LR_BATCH_PACKED) && prec_ok && x.M >= 1 && x.M <= lrk::kMaxM && LM >= 1 &&
           LM <= lrk::kTMaxLM && x.model.d_r >= 1 && x.model.d_r <= (1 << 20)))
       return false;
     const int dmax = std::max(std::max(x.model.d_q, x.model.d_r), x.model.d_f);
@@ -185,9 +193,10 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     const bool px = packs(trajs[x]), py = packs(trajs[y]);
     if (px != py) return px;
-    if (px) {
+    if (px) {  // kernel families together: kind 2 last, then by arithmetic mode
       const bool nx = trajs[x].model.kind == LR_MODEL_NORMAL, ny = trajs[y].model.kind == LR_MODEL_NORMAL;
       if (nx != ny) return ny;
+      if (trajs[x].precision != trajs[y].precision) return trajs[x].precision < trajs[y].precision;
       return work(trajs[x]) > work(trajs[y]);
     }
     if (trajs[x].precision != trajs[y].precision) return trajs[x].precision < trajs[y].precision;
@@ -409,9 +418,17 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
                                (int)max_lds_packed) != hipSuccess ||
            hipFuncSetAttribute(lrk::packed_kernel(kp, pro != 0, true), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)max_lds_packed) != hipSuccess ||
+
            hipFuncSetAttribute(lrk::dp5_kernel(kp, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)max_lds_packed) != hipSuccess))
         return LR_ERR_HIP;
+  for (int gm = 0; gm <= 2; ++gm)  // the matrix-core Gram kernels of the packed schedule
+    for (int slots = 2; slots <= 3; ++slots)
+      for (int pro = 0; pro < 2; ++pro)
+        if (max_lds_packed > 0 && hipFuncSetAttribute(lrk::packed_kernel(0, pro != 0, false, gm, slots),
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                      (int)max_lds_packed) != hipSuccess)
+          return LR_ERR_HIP;
   for (int prec = 0; prec <= 2; ++prec)
     for (int rows = 2; rows <= 3; ++rows)
       for (int ge = 1; ge <= 2; ++ge)
@@ -429,10 +446,13 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
   b->groups.clear();
   int t = 0;
   while (t < b->n && b->packed[t]) {  // one launch per chunk holds every packed trajectory of a kernel family
-    const int nm = b->tr[t].model.kind == LR_MODEL_NORMAL;
-    lr_batch::Group g{t, t, 0, 0, 0, LR_FP64, 0, 0, 0, 1, 2, nm};
-    while (t < b->n && b->packed[t] && (b->tr[t].model.kind == LR_MODEL_NORMAL) == (nm != 0)) {
+    const int nm = b->tr[t].model.kind == LR_MODEL_NORMAL, prec = b->tr[t].precision;
+    const int gm = nm ? -1 : (prec == LR_FP64 ? (b->valu_gram || b->adaptive ? -1 : 0) : prec);
+    lr_batch::Group g{t, t, 0, 0, 0, prec, 0, 0, 0, 1, 2, nm, gm, 2};
+    while (t < b->n && b->packed[t] && (b->tr[t].model.kind == LR_MODEL_NORMAL) == (nm != 0) &&
+           b->tr[t].precision == prec) {
       g.kp = std::max(g.kp, lrk::packed_kp(b->tr[t].M, b->tr[t].model.kind));
+      g.slots = std::max(g.slots, lrk::mg_slots(b->tr[t].M));
       g.lds = std::max(g.lds, b->lds[t]);
       g.wgs += 1;
       g.max_steps = std::max(g.max_steps, b->tr[t].nsteps);
@@ -444,7 +464,7 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
     b->groups.push_back(g);
   }
   while (t < b->n) {
-    lr_batch::Group g{t, t, 0, 2, 1, b->tr[t].precision, 0, 0, 0, 0, 0, 0};
+    lr_batch::Group g{t, t, 0, 2, 1, b->tr[t].precision, 0, 0, 0, 0, 0, 0, -1, 2};
     while (t < b->n) {
       if (b->tr[t].precision != g.prec) break;
       const int rows = std::max(g.rows, b->rows[t]);
@@ -559,8 +579,8 @@ int enqueue(lr_batch* b) {
                                 b->stream);
         } else {
           void* pargs[] = {(void*)&ptr, (void*)&step0, (void*)&nchunk};
-          err = hipLaunchKernel(lrk::packed_kernel(g.kp, prologue != 0, g.nm != 0), dim3(g.wgs), dim3(lrk::kTW),
-                                pargs, g.lds, b->stream);
+          err = hipLaunchKernel(lrk::packed_kernel(g.kp, prologue != 0, g.nm != 0, g.gm, g.slots), dim3(g.wgs),
+                                dim3(lrk::kTW), pargs, g.lds, b->stream);
         }
       } else {
         err = hipLaunchCooperativeKernel(persist_fn(g.rows, g.ge, g.prec, prologue != 0), dim3(g.wgs),

@@ -30,6 +30,8 @@
 // tolerances of the oracle comparison.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lr_device.h"
 
 namespace lrk {
@@ -265,6 +267,289 @@ __device__ __forceinline__ int packed_solve(double2 (&acc)[KP], const PackedMap&
   return rc ? rc : packed_eliminate(Aug, Wl, s_prow, P.M);
 }
 
+// ---------------------------------------------------------------- Gram terms on the matrix cores
+//
+// The products [G | C_1 | C_2] += O^ [O | L_1 O | L_2 O] of one output layer O
+// (L x M, in LDS) as 16 x 16 output tiles of v_mfma instructions.  Per chunk
+// of layer rows an output tile (rows i = columns of O, columns c of
+// [O | L_1 O | L_2 O]) gains
+//   Re += A_re B_re + A_im B_im,   Im += A_re B_im - A_im B_re,
+// A[i][k] = O[n0 + k][i], B[k][c] = [O | L_1 O | L_2 O][n0 + k][c]: four real
+// products.  Arithmetic by mode:
+//   0 FP64:   v_mfma_f64_16x16x4f64 (rows in chunks of 4);
+//   1 FP32:   v_mfma_f32_16x16x4f32, operands rounded to FP32, FP32 accumulation;
+//   2 BF16x3: C_k from the three leading products hi hi + hi lo + lo hi of the
+//             BF16 parts of the FP32-rounded operands (v_mfma_f32_16x16x16_bf16,
+//             rows in chunks of 16, FP32 accumulation); G in FP64 (as in the
+//             spread schedule: the split products do not resolve the smallest
+//             eigenvalues of G).
+// Lane layouts: A[i][k] at lane i + 16 k and B[k][c] at lane c + 16 k (BF16:
+// lane c + 16 (k / 4), element k mod 4); D[4 v + l / 16][l mod 16] for FP64
+// and D[4 (l / 16) + v][l mod 16] for FP32 / BF16, v = 0..3, at lane l.
+// Tiles: IT = ceil(M / 16) row tiles.  Modes 0 and 1 tile the 3M columns
+// densely (tile t: row tile t mod IT, column tile t / IT, wave t mod 4, slot
+// t / 4: two slots for M <= 21, three for M <= 32); mode 2 gives each of the IT^2 G tiles a
+// wave and tiles [C_1 | C_2] per block (2 IT^2 tiles, two slots).  With IT
+// dividing 4, every slot of a wave has the same row tile: A is loaded once
+// per chunk.
+typedef double mg_d4 __attribute__((ext_vector_type(4)));
+typedef float mg_f4 __attribute__((ext_vector_type(4)));
+typedef short mg_s4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ mg_d4 mg_mm(double a, double b, mg_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ mg_f4 mg_mm(float a, float b, mg_f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ mg_f4 mg_mm(mg_s4 a, mg_s4 b, mg_f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+// BF16 parts of x rounded to FP32: x ~ hi + lo (bit patterns)
+__device__ __forceinline__ void mg_split(double x, short& hi, short& lo) {
+  const float f = (float)x;
+  const float h = bf16_rne(f);
+  hi = (short)(__float_as_uint(h) >> 16);
+  lo = (short)(__float_as_uint(bf16_rne(f - h)) >> 16);
+}
+// the jump row of column block pk: coefficient and source row of row n of
+// [O | L_1 O | L_2 O] (coef[0 .. L) = 1; 0 where the jump leaves the mode)
+__device__ __forceinline__ double2 mg_bval(const double2* Ot, const double* coef, int L, int M, int d_f, int pk,
+                                           int cc, int n) {
+  const int sh = pk == 0 ? 0 : (pk == 1 ? 1 : d_f);
+  return cscale(coef[pk * L + n], Ot[min(n + sh, L - 1) * M + cc]);
+}
+
+// Entry (i, pk M + cc) of [G | C_1 | C_2] into Aug (row stride 3M) with the
+// non-finite check and ||G||_F^2.
+__device__ __forceinline__ void mg_put(double2* Aug, int M, int i, int pk, int cc, double re, double im, int& bad,
+                                       double& f2) {
+  Aug[i * 3 * M + pk * M + cc] = make_double2(re, im);
+  if (!isfinite(re) || !isfinite(im)) bad = 1;
+  if (pk == 0) f2 += re * re + im * im;
+}
+
+// Flag and ||G||_F^2 of the stored entries across the workgroup; returns 0 or -5.
+__device__ __forceinline__ int mg_finish(int bad, double f2, double* s_red, int* s_flag, bool want_fro2,
+                                         double* fro2) {
+  const int tid = threadIdx.x;
+  if (tid == 0) *s_flag = 0;
+  __syncthreads();
+  if (bad) *s_flag = 1;
+  if (want_fro2) {
+    for (int off = 32; off > 0; off >>= 1) f2 += __shfl_xor(f2, off);
+    if ((tid & 63) == 0) s_red[tid >> 6] = f2;
+  }
+  __syncthreads();
+  if (want_fro2) {
+    double tot = 0.0;
+    for (int w = 0; w < kTW / 64; ++w) tot += s_red[w];
+    *fro2 = tot;
+  }
+  return *s_flag ? -5 : 0;
+}
+
+// Modes 0 (FP64) and 1 (FP32), NS output tiles per wave.
+template <int GP, int NS>
+struct MGramDense {
+  typedef typename std::conditional<GP == 0, mg_d4, mg_f4>::type Acc;
+  typedef typename std::conditional<GP == 0, double, float>::type R;
+  static constexpr int kMgSlots = NS;
+  Acc re[kMgSlots], im[kMgSlots];
+
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int u = 0; u < kMgSlots; ++u) re[u] = im[u] = Acc{0, 0, 0, 0};
+  }
+  __device__ __forceinline__ void add_layer(const double2* Ot, const double* coef, int L, int M, int d_f) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int IT = (M + 15) >> 4, tot = IT * ((3 * M + 15) >> 4);
+    const int acol = (w % IT) * 16 + li;  // column of O in the A operand (the same for every slot)
+    int pk[kMgSlots], cc[kMgSlots];
+    bool bv[kMgSlots];
+#pragma unroll
+    for (int u = 0; u < kMgSlots; ++u) {
+      const int t = w + 4 * u, c = (t / IT) * 16 + li;
+      pk[u] = c / M;
+      cc[u] = c - pk[u] * M;
+      bv[u] = t < tot && c < 3 * M;
+    }
+    for (int n0 = 0; n0 < L; n0 += 4) {
+      const int n = n0 + lk;
+      const double2 a = (n < L && acol < M) ? Ot[n * M + acol] : make_double2(0.0, 0.0);
+      const R ar = (R)a.x, ai = (R)a.y, ain = -ai;
+#pragma unroll
+      for (int u = 0; u < kMgSlots; ++u) {
+        if (w + 4 * u < tot) {  // uniform in the wave
+          const double2 b = (n < L && bv[u]) ? mg_bval(Ot, coef, L, M, d_f, pk[u], cc[u], n) : make_double2(0.0, 0.0);
+          const R br = (R)b.x, bi = (R)b.y;
+          re[u] = mg_mm(ar, br, re[u]);
+          re[u] = mg_mm(ai, bi, re[u]);
+          im[u] = mg_mm(ar, bi, im[u]);
+          im[u] = mg_mm(ain, br, im[u]);
+        }
+      }
+    }
+  }
+  // the entries into Aug (M x 3M); returns 0 or -5
+  __device__ __forceinline__ int store(double2* Aug, int M, double* s_red, int* s_flag, bool want_fro2,
+                                       double* fro2) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int IT = (M + 15) >> 4, tot = IT * ((3 * M + 15) >> 4);
+    __syncthreads();  // the tiles are free
+    int bad = 0;
+    double f2 = 0.0;
+#pragma unroll
+    for (int u = 0; u < kMgSlots; ++u) {
+      const int t = w + 4 * u;
+      if (t >= tot) continue;
+      const int c = (t / IT) * 16 + li;
+      if (c >= 3 * M) continue;
+      const int pk = c / M, cc = c - pk * M;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = (t % IT) * 16 + (GP == 0 ? 4 * v + lk : 4 * lk + v);
+        if (i < M) mg_put(Aug, M, i, pk, cc, (double)re[u][v], (double)im[u][v], bad, f2);
+      }
+    }
+    return mg_finish(bad, f2, s_red, s_flag, want_fro2, fro2);
+  }
+};
+
+// Mode 2 (BF16x3 C_k, FP64 G).
+struct MGramSplit {
+  mg_d4 gre, gim;            // the wave's G tile
+  mg_f4 cre[2], cim[2];      // its two C tiles
+
+  __device__ __forceinline__ void zero() {
+    gre = gim = mg_d4{0, 0, 0, 0};
+    cre[0] = cre[1] = cim[0] = cim[1] = mg_f4{0, 0, 0, 0};
+  }
+  __device__ __forceinline__ void add_layer(const double2* Ot, const double* coef, int L, int M, int d_f) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int IT = (M + 15) >> 4;
+    const int acol = (w % IT) * 16 + li;
+    // G tile w (row tile w mod IT, column tile w / IT): FP64, rows in chunks of 4
+    if (w < IT * IT) {
+      const int bcol = (w / IT) * 16 + li;
+      for (int n0 = 0; n0 < L; n0 += 4) {
+        const int n = n0 + lk;
+        const double2 a = (n < L && acol < M) ? Ot[n * M + acol] : make_double2(0.0, 0.0);
+        const double2 b = (n < L && bcol < M) ? Ot[n * M + bcol] : make_double2(0.0, 0.0);
+        gre = mg_mm(a.x, b.x, gre);
+        gre = mg_mm(a.y, b.y, gre);
+        gim = mg_mm(a.x, b.y, gim);
+        gim = mg_mm(-a.y, b.x, gim);
+      }
+    }
+    // C tiles t = w, w + 4 of [C_1 | C_2] (row tile t mod IT, column tile t / IT of 2 IT): BF16x3,
+    // rows in chunks of 16 (lane rows n0 + 4 lk + e)
+    const int ntc = 2 * IT * IT;
+    int pk[2], cc[2];
+    bool bv[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int t = w + 4 * u, ct = t / IT;
+      pk[u] = 1 + ct / IT;
+      cc[u] = (ct % IT) * 16 + li;
+      bv[u] = t < ntc && cc[u] < M;
+    }
+    if (w >= ntc) return;
+    for (int n0 = 0; n0 < L; n0 += 16) {
+      mg_s4 arh, arl, aih, ail, ainh, ainl;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int n = n0 + 4 * lk + e;
+        const double2 a = (n < L && acol < M) ? Ot[n * M + acol] : make_double2(0.0, 0.0);
+        short h, l;
+        mg_split(a.x, h, l);
+        arh[e] = h;
+        arl[e] = l;
+        mg_split(a.y, h, l);
+        aih[e] = h;
+        ail[e] = l;
+        ainh[e] = (short)(h ^ (short)0x8000);  // -a_im: the sign bit of each part
+        ainl[e] = (short)(l ^ (short)0x8000);
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (w + 4 * u < ntc) {  // uniform in the wave
+          mg_s4 brh, brl, bih, bil;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int n = n0 + 4 * lk + e;
+            const double2 b =
+                (n < L && bv[u]) ? mg_bval(Ot, coef, L, M, d_f, pk[u], cc[u], n) : make_double2(0.0, 0.0);
+            short h, l;
+            mg_split(b.x, h, l);
+            brh[e] = h;
+            brl[e] = l;
+            mg_split(b.y, h, l);
+            bih[e] = h;
+            bil[e] = l;
+          }
+          // each real product from its three leading part products (smallest first)
+          cre[u] = mg_mm(arl, brh, cre[u]);
+          cre[u] = mg_mm(arh, brl, cre[u]);
+          cre[u] = mg_mm(arh, brh, cre[u]);
+          cre[u] = mg_mm(ail, bih, cre[u]);
+          cre[u] = mg_mm(aih, bil, cre[u]);
+          cre[u] = mg_mm(aih, bih, cre[u]);
+          cim[u] = mg_mm(arl, bih, cim[u]);
+          cim[u] = mg_mm(arh, bil, cim[u]);
+          cim[u] = mg_mm(arh, bih, cim[u]);
+          cim[u] = mg_mm(ainl, brh, cim[u]);
+          cim[u] = mg_mm(ainh, brl, cim[u]);
+          cim[u] = mg_mm(ainh, brh, cim[u]);
+        }
+      }
+    }
+  }
+  __device__ __forceinline__ int store(double2* Aug, int M, double* s_red, int* s_flag, bool want_fro2,
+                                       double* fro2) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int IT = (M + 15) >> 4;
+    __syncthreads();  // the tiles are free
+    int bad = 0;
+    double f2 = 0.0;
+    if (w < IT * IT) {
+      const int j = (w / IT) * 16 + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = (w % IT) * 16 + 4 * v + lk;
+        if (i < M && j < M) mg_put(Aug, M, i, 0, j, gre[v], gim[v], bad, f2);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int t = w + 4 * u, ct = t / IT;
+      if (t >= 2 * IT * IT) continue;
+      const int pk = 1 + ct / IT, cc = (ct % IT) * 16 + li;
+      if (cc >= M) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = (t % IT) * 16 + 4 * lk + v;
+        if (i < M) mg_put(Aug, M, i, pk, cc, (double)cre[u][v], (double)cim[u][v], bad, f2);
+      }
+    }
+    return mg_finish(bad, f2, s_red, s_flag, want_fro2, fro2);
+  }
+};
+
+template <int GM, int NS>
+struct MGramOf {
+  typedef MGramDense<GM, NS> type;
+};
+template <int NS>
+struct MGramOf<2, NS> {
+  typedef MGramSplit type;
+};
+// Output tiles per wave of the dense modes for rank M.
+__host__ __device__ inline int mg_slots(int M) {
+  const int it = (M + 15) / 16;
+  return (it * ((3 * M + 15) / 16) + 3) / 4;
+}
+
 // Element (rl, j) of layer r: z = H_eff Y (stencil and drive) from the layers
 // r - 1, r, r + 1 of the stage input in LDS (Yp, Yc, Yn).  sq[k] = sqrt(k);
 // hd[rl] = diagonal of H_eff at row rl without w_r r.
@@ -435,7 +720,7 @@ __device__ __forceinline__ double2 packed_jump_nm(const TrajDev& T, const double
 // per thread (packed_kp).  MK = model kind; kind 2 keeps five input layers,
 // the filter jump L_1 Y of the current and the next layer, and the outputs of
 // the current and the previous layer (for the cross-layer term Q).
-template <int KP, bool ROT, int MK = 0>
+template <int KP, bool ROT, int MK = 0, int GM = -1, int NS = 2>
 __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int64_t step0, int64_t nchunk) {
   extern __shared__ double2 lds[];
   __shared__ double s_red[kTW / 64];
@@ -522,15 +807,35 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
   };
 
   const PackedMap PM{M, CT, L, d_f, KPe, pc, pi0, pkind, pcc, pact};
+  // the Gram terms: entries held by the threads (vector ALU, GM < 0) or
+  // output tiles of the matrix cores (GM = arithmetic mode of MGramDense /
+  // MGramSplit)
+  double2 acc[KP];
+  typename MGramOf<(GM < 0 ? 0 : GM), NS>::type mg;
+  auto zero_terms = [&]() {
+    if constexpr (GM >= 0) {
+      mg.zero();
+    } else {
+#pragma unroll
+      for (int k = 0; k < KP; ++k) acc[k] = make_double2(0.0, 0.0);
+    }
+  };
   // Gram terms of the output layer r in Ot (kind 2: and of the pair (Op, Ot))
-  auto add_terms = [&](double2 (&acc)[KP], int r) {
-    packed_terms<KP>(acc, PM, Ot, coef);
-    if constexpr (NM)
-      if (r > 0) packed_terms_q<KP>(acc, PM, Ot, Op, sk * sq[r]);
+  auto add_terms = [&](int r) {
+    if constexpr (GM >= 0) {
+      mg.add_layer(Ot, coef, L, M, d_f);
+    } else {
+      packed_terms<KP>(acc, PM, Ot, coef);
+      if constexpr (NM)
+        if (r > 0) packed_terms_q<KP>(acc, PM, Ot, Op, sk * sq[r]);
+    }
   };
   // W_k of the state whose Gram terms the threads hold, for use at time t_use
-  auto solve = [&](double2 (&acc)[KP], bool want_fro2, double* fro2, double t_use) -> int {
-    if constexpr (NM) {
+  auto solve = [&](bool want_fro2, double* fro2, double t_use) -> int {
+    if constexpr (GM >= 0) {
+      const int rc = mg.store(Aug, M, s_red, &s_flag, want_fro2, fro2);
+      return rc ? rc : packed_eliminate(Aug, Wl, s_prow, M);
+    } else if constexpr (NM) {
       const int rc = packed_store<KP>(acc, PM, St, s_red, &s_flag, want_fro2, fro2);
       if (rc) return rc;
       packed_form_c1(St, Aug, M, T.nm, ROT ? frame_phase(T.w_d, t_use) : make_double2(1.0, 0.0));
@@ -547,16 +852,13 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
     }
   };
 
-  double2 acc[KP];
-
   if (prologue) {
-#pragma unroll
-    for (int k = 0; k < KP; ++k) acc[k] = make_double2(0.0, 0.0);
+    zero_terms();
     for (int r = 0; r < d_r; ++r) {
       __syncthreads();
       for (int e = tid; e < LM; e += kTW) Ot[e] = ld_g(gBb + (size_t)r * LM + e);
       __syncthreads();
-      add_terms(acc, r);
+      add_terms(r);
       if constexpr (NM) {
         double2* t = Ot;
         Ot = Op;
@@ -564,7 +866,7 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
       }
     }
     double f2 = 0.0;
-    const int rc = solve(acc, true, &f2, stage_time(step0, 0));
+    const int rc = solve(true, &f2, stage_time(step0, 0));
     if (rc) {
       if (tid == 0) report(T, rc, step0);
       return;
@@ -587,8 +889,7 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
       const double drv = s_dtab[ds][0];
       const double2 e1 = make_double2(s_dtab[ds][1], s_dtab[ds][2]), e2 = make_double2(s_dtab[ds][3], s_dtab[ds][4]);
       const double2 e1j = ROT ? e1 : make_double2(1.0, 0.0);  // phase of the kind-2 filter jump
-#pragma unroll
-      for (int k = 0; k < KP; ++k) acc[k] = make_double2(0.0, 0.0);
+      zero_terms();
       if constexpr (MK >= 1 && ROT)
         if (tid < 2 * d_q + 3) s_ph[tid] = frame_phase((tid - d_q - 1) * T.w_d, stage_time(step, s));
       __syncthreads();  // Wl of this stage written; tiles free
@@ -704,7 +1005,7 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
           }
           if constexpr (NM)
             if (r + 1 < d_r) jump_tile(Y1n, Yc, Yn, Yp2, r + 1, e1j);
-          add_terms(acc, r);
+          add_terms(r);
 #pragma unroll
           for (int u = 0; u < kTPrefetch; ++u) {
             const int e = tid + u * kTW;
@@ -714,7 +1015,7 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
         } else {
           if constexpr (NM)
             if (r + 1 < d_r) jump_tile(Y1n, Yc, Yn, Yp2, r + 1, e1j);
-          add_terms(acc, r);
+          add_terms(r);
         }
         __syncthreads();
         if constexpr (NM) {
@@ -739,7 +1040,7 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
       }
       double f2 = 0.0;
       const bool last = (s == 3) && (n + 1 == nrun);
-      const int rc = solve(acc, last, &f2, s < 3 ? stage_time(step, s + 1) : stage_time(step + 1, 0));
+      const int rc = solve(last, &f2, s < 3 ? stage_time(step, s + 1) : stage_time(step + 1, 0));
       if (rc) {
         if (tid == 0) {
           report(T, rc, step);
@@ -795,9 +1096,62 @@ __global__ __launch_bounds__(kTW) void k_packed_nm_prologue(const TrajDev* __res
     packed_body<KP, false, 2>(T, 1, step0, nchunk);
 }
 
+// Kinds 0 and 1 with the Gram terms on the matrix cores, arithmetic mode GM
+// (0 FP64, 1 FP32, 2 BF16x3; the stencil, the jump assembly, the solve and
+// the RK4 state stay FP64) and NS output tiles per wave.  Two tiles per wave
+// (M <= 21) keep two workgroups per CU in registers; three (M <= 32) come
+// with layer tiles that hold one workgroup per CU in LDS anyway.
+template <int GM, int NS>
+__device__ __forceinline__ void packed_mg_body(const TrajDev& T, int prologue, int64_t step0, int64_t nchunk) {
+  if (prologue) {
+    packed_body<2, false, 0, GM, NS>(T, 1, step0, nchunk);
+  } else if (T.mkind == 1) {
+    if (T.frame)
+      packed_body<2, true, 1, GM, NS>(T, 0, step0, nchunk);
+    else
+      packed_body<2, false, 1, GM, NS>(T, 0, step0, nchunk);
+  } else if (T.frame) {
+    packed_body<2, true, 0, GM, NS>(T, 0, step0, nchunk);
+  } else {
+    packed_body<2, false, 0, GM, NS>(T, 0, step0, nchunk);
+  }
+}
+template <int GM>
+__global__ __launch_bounds__(kTW, 2) void k_packed_mg(const TrajDev* __restrict__ trajs, int64_t step0,
+                                                      int64_t nchunk) {
+  packed_mg_body<GM, 2>(trajs[blockIdx.x], 0, step0, nchunk);
+}
+template <int GM>
+__global__ __launch_bounds__(kTW, 2) void k_packed_mg_prologue(const TrajDev* __restrict__ trajs, int64_t step0,
+                                                               int64_t nchunk) {
+  packed_mg_body<GM, 2>(trajs[blockIdx.x], 1, step0, nchunk);
+}
+template <int GM>
+__global__ __launch_bounds__(kTW) void k_packed_mg3(const TrajDev* __restrict__ trajs, int64_t step0,
+                                                    int64_t nchunk) {
+  packed_mg_body<GM, 3>(trajs[blockIdx.x], 0, step0, nchunk);
+}
+template <int GM>
+__global__ __launch_bounds__(kTW) void k_packed_mg3_prologue(const TrajDev* __restrict__ trajs, int64_t step0,
+                                                             int64_t nchunk) {
+  packed_mg_body<GM, 3>(trajs[blockIdx.x], 1, step0, nchunk);
+}
+template <int GM>
+inline const void* packed_mg_kernel(int slots, bool prologue) {
+  if (slots <= 2 || GM == 2)
+    return prologue ? (const void*)k_packed_mg_prologue<GM> : (const void*)k_packed_mg<GM>;
+  return prologue ? (const void*)k_packed_mg3_prologue<GM> : (const void*)k_packed_mg3<GM>;
+}
+
 constexpr int kPackedKP[] = {2, 3, 5, 8, 12, 16};
+// The packed kernel for block size kp (vector-ALU Gram terms, gm < 0) or
+// matrix-core mode gm; nm: the normal-mode model.
+// slots: output tiles per wave of the matrix-core modes (mg_slots of the largest rank).
 template <int I = 0>
-inline const void* packed_kernel(int kp, bool prologue, bool nm = false) {
+inline const void* packed_kernel(int kp, bool prologue, bool nm = false, int gm = -1, int slots = 2) {
+  if (gm == 0) return packed_mg_kernel<0>(slots, prologue);
+  if (gm == 1) return packed_mg_kernel<1>(slots, prologue);
+  if (gm == 2) return packed_mg_kernel<2>(slots, prologue);
   if constexpr (I + 1 < (int)(sizeof(kPackedKP) / sizeof(int))) {
     if (kp > kPackedKP[I]) return packed_kernel<I + 1>(kp, prologue, nm);
   }
