@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--packed-sample", type=int, default=0, metavar="STEPS",
                     help="only run the packed schedule on 512 trajectories (N=2000, M=20) for STEPS steps "
                          "(a workload for kernel profiles) and print its rate")
+    ap.add_argument("--packed-precision", type=int, default=0, choices=(0, 1, 2),
+                    help="with --packed-sample: arithmetic of the Gram terms (0 FP64, 1 FP32, 2 BF16x3)")
+    ap.add_argument("--packed-mfma64", action="store_true",
+                    help="with --packed-sample: FP64 Gram terms on the matrix cores instead of the vector ALU")
     ap.add_argument("--apply-sample", type=int, default=0, metavar="LAUNCHES",
                     help="only time the operator application lr_apply_heff on 512 factors of N=2000, M=20 "
                          "(10240 columns) for LAUNCHES launches (a workload for kernel profiles)")
@@ -67,12 +71,15 @@ def copy_calibration(torch, mib):
               flush=True)
 
 
-def packed_sample(lr, I, torch, steps):
+def packed_sample(lr, I, torch, steps, precision=0, mfma64=False):
     """512 trajectories (256 piecewise pulses x g/e, N=2000, M=20) in the packed schedule, kernel time
-    from HIP events on the batch stream."""
+    from HIP events on the batch stream; precision: arithmetic of the Gram terms (FP32 / BF16x3 on the
+    matrix cores), mfma64: FP64 Gram terms on the matrix cores instead of the vector ALU."""
     tl = I.batch_uniform(256)
-    items = [dict(model=t.model, M=t.M, pulse=t.pulse, dt=t.dt, nsteps=steps, B=lr.to_device(t.B0())) for t in tl]
-    b = lr.Batch(items, packed=True)
+    # the reduced modes need the rank padding above their rounding: the paper's padding weight
+    items = [dict(model=t.model, M=t.M, pulse=t.pulse, dt=t.dt, nsteps=steps, precision=precision,
+                  B=lr.to_device(t.B0(I.PAPER_PAD_SCALE if precision else None))) for t in tl]
+    b = lr.Batch(items, packed=True, flags=lr.LR_BATCH_PACKED_MFMA64 if mfma64 else 0)
     b.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -85,9 +92,12 @@ def packed_sample(lr, I, torch, steps):
     b.close()
     m, M = tl[0].model, tl[0].M
     fl = 4 * m.N * M * (58 + 40 * M) * steps * len(items)
-    print(json.dumps({"workload": f"packed schedule, {len(items)} trajectories, N={m.N}, M={M}, {steps} steps",
+    valu = precision == 0 and not mfma64
+    kern = "k_packed<5>" if valu else ("k_packed_mg<%d>" % precision)
+    print(json.dumps({"workload": f"packed schedule, {len(items)} trajectories, N={m.N}, M={M}, {steps} steps, "
+                                  f"precision {precision}, Gram terms on the {'vector ALU' if valu else 'matrix cores'}",
                       "value": len(items) * steps / el, "unit": "RK steps*trajectories/s",
-                      "kernel": "k_packed", "kernel_ms": ms, "launches": launches,
+                      "kernel": kern, "kernel_ms": ms, "launches": launches,
                       "achieved_tflops": fl / (ms * 1e-3) / 1e12, "peak": 78.6}), flush=True)
 
 
@@ -150,10 +160,11 @@ def comparisons(lr, I, torch, stream, plain_value):
     trajs = I.config_paper_size()
     m, M = trajs[0].model, trajs[0].M
 
-    def run_batch(tr_list, nsteps_cap, packed=False):
+    def run_batch(tr_list, nsteps_cap, packed=False, precision=0, flags=0):
         items = [dict(model=t.model, M=t.M, pulse=t.pulse, dt=t.dt, nsteps=min(t.nsteps, nsteps_cap),
-                      B=lr.to_device(t.B0())) for t in tr_list]
-        b = lr.Batch(items, stream=stream, packed=packed)
+                      B=lr.to_device(t.B0(I.PAPER_PAD_SCALE if precision else None)), precision=precision)
+                 for t in tr_list]
+        b = lr.Batch(items, stream=stream, packed=packed, flags=flags)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         b.run()
@@ -194,11 +205,16 @@ def comparisons(lr, I, torch, stream, plain_value):
     n512 = I.batch_uniform(256)
     v_s, el_s = run_batch(n512, 40)
     v_p, el_p = run_batch(n512, 200, packed=True)
+    # the same with the FP64 Gram terms on the matrix cores, and the reduced modes (Gram terms on the matrix cores)
+    v_pm, _ = run_batch(n512, 200, packed=True, flags=lr.LR_BATCH_PACKED_MFMA64)
+    v_p32, _ = run_batch(n512, 200, packed=True, precision=1)
+    v_pbf, _ = run_batch(n512, 200, packed=True, precision=2)
     # algorithmic FP64 flops per RK step and trajectory (same count as the main line's roofline)
     fl = 4 * m.N * M * (58 + 40 * M)
     by = 17 * 16 * m.N * M
     out["batched_512_same_shape"] = {
         "spread": v_s, "packed": v_p, "packed_vs_spread": v_p / v_s, "packed_vs_plain_g_e": v_p / plain_value,
+        "packed_fp64_mfma_gram": v_pm, "packed_fp32_gram": v_p32, "packed_bf16x3_gram": v_pbf,
         "packed_roofline": {"bound": "alu", "achieved": v_p * fl / 1e12, "peak": 78.6, "unit": "TFLOP/s",
                             "frac": v_p * fl / 1e12 / 78.6,
                             "note": "whole-batch wall time (launch overhead and the prologue included)"},
@@ -261,6 +277,31 @@ def comparisons(lr, I, torch, stream, plain_value):
                                  "workload": "the paper's Hamiltonian (transmon eigenbasis N_t=6, resonator 60, "
                                              "filter 10: N=3600), M=20, 256 stepwise pulses x g/e, 100 steps "
                                              f"each, packed schedule ({pel:.2f} s)"}
+    # the paper's Hamiltonian in its normal-mode basis at the paper's own size (N_t = 5, lower mode 100,
+    # upper mode 4: N = 2000), M = 20, in the frame rotating at the drive; 256 pulses x g/e
+    nm = transmon.paper_model_normal(5, 100, 4)
+    nitems = []
+    for k in range(256):
+        hts = I.ghz(0.15) * rng.uniform(0.3, 1.0, 4) * np.exp(1j * rng.uniform(0, 2 * np.pi, 4))
+        pp = I.stepwise_pulse(hts, 40.0, w_d=transmon.PAPER_W_DRIVE).replace(frame=I.FRAME_DRIVE)
+        for which in ("g", "e"):
+            nitems.append(dict(model=nm, M=20, pulse=pp, dt=2e-3, nsteps=100,
+                               B=lr.to_device(I.initial_state(nm, 20, which, 300 + k, I.PAPER_PAD_SCALE))))
+    nb = lr.Batch(nitems, stream=stream, packed=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nb.run()
+    torch.cuda.synchronize()
+    nel = time.perf_counter() - t0
+    if nb.status()[0] != lr.LR_OK:
+        raise RuntimeError("normal-mode model batch failed")
+    nb.close()
+    del nitems
+    out["paper_model_normal_packed"] = {"value": 512 * 100 / nel, "unit": "RK steps*trajectories/s",
+                                        "workload": "the paper's Hamiltonian in its normal-mode basis at its own "
+                                                    "size (N_t=5, lower mode 100, upper mode 4: N=2000), M=20, drive "
+                                                    "frame, 256 stepwise pulses x g/e, 100 steps each, packed "
+                                                    f"schedule ({nel:.2f} s)"}
     # batched mixed shapes: the 512 trajectories of the batched configuration, capped step count
     steps = 150
     c4 = I.config_batched()
@@ -547,7 +588,7 @@ def main():
         copy_calibration(torch, a.copy_calibration)
         return
     if a.packed_sample > 0:
-        packed_sample(lr, I, torch, a.packed_sample)
+        packed_sample(lr, I, torch, a.packed_sample, a.packed_precision, a.packed_mfma64)
         return
     if a.apply_sample > 0:
         print(json.dumps(apply_sample(lr, I, torch, a.apply_sample)), flush=True)

@@ -146,7 +146,7 @@ typedef struct {
  * lr_observables always evaluate in FP64; the reduced modes need the
  * persistent on-chip integrator (LR_ERR_ARG from lr_integrate otherwise).
  * In the packed batch schedule the modes apply to the Gram and cross
- * products only, which run on the matrix cores (LR_BATCH_PACKED_VALU_GRAM). */
+ * products only, which run on the matrix cores (LR_BATCH_PACKED_MFMA64). */
 enum { LR_FP64 = 0, LR_FP32 = 1, LR_BF16X3 = 2 };
 
 enum {
@@ -334,7 +334,7 @@ typedef struct lr_batch lr_batch_t;
 int lr_batch_init(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n);
 /* lr_batch_init with schedule flags.  0 is lr_batch_init.  LR_BATCH_PACKED:
  * every trajectory (LR_FP64; LR_FP32 and LR_BF16X3 for model kinds 0 and 1,
- * see LR_BATCH_PACKED_VALU_GRAM) with d_q d_f M <= LR_PACKED_MAX_LM (and whose
+ * see LR_BATCH_PACKED_MFMA64) with d_q d_f M <= LR_PACKED_MAX_LM (and whose
  * workgroup's LDS, about 16 (4 d_q d_f M + 2 M^2 + 2.5 d_q d_f) bytes, fits
  * 159 KiB) runs in a workgroup of its own (all of them in one launch per chunk of steps, as many
  * per CU as fit), which fills the GPU with many trajectories at once instead
@@ -346,15 +346,17 @@ int lr_batch_init(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n);
 #define LR_BATCH_PACKED 1
 #define LR_PACKED_MAX_LM 1536
 /* Packed schedule, Gram and cross products [G | C_1 | C_2] of model kinds 0
- * and 1: by default on the matrix cores (v_mfma 16 x 16 output tiles; FP64
- * trajectories with the FP64 instruction, LR_FP32 with the FP32 one and
- * FP32 accumulation, LR_BF16X3 with three BF16 part products per real
- * product and FP32 accumulation for C_k and the FP64 instruction for G).
- * LR_BATCH_PACKED_VALU_GRAM forms them for the FP64 trajectories on the
- * vector ALU instead (one thread per entry block, rows in order).  The
- * stencil, the jump assembly, the solve and the RK4 state are FP64 in every
- * packed mode.  Model kind 2 and adaptive batches: vector ALU, FP64 only. */
-#define LR_BATCH_PACKED_VALU_GRAM 2
+ * and 1: LR_FP32 and LR_BF16X3 trajectories form them on the matrix cores
+ * (v_mfma 16 x 16 output tiles: LR_FP32 with the FP32 instruction and FP32
+ * accumulation; LR_BF16X3 with three BF16 part products per real product and
+ * FP32 accumulation for C_k, the FP64 instruction for G).  FP64 trajectories
+ * form them on the vector ALU (one thread per entry block, rows in order), or
+ * with LR_BATCH_PACKED_MFMA64 on the matrix cores with the FP64 instruction
+ * (slower at M = 20: the tiles are padded to 32 x 64 and the FP64 matrix rate
+ * equals the vector rate).  The stencil, the jump assembly, the solve and the
+ * RK4 state are FP64 in every packed mode.  Model kind 2 and adaptive
+ * batches: vector ALU, FP64 only. */
+#define LR_BATCH_PACKED_MFMA64 2
 /* Tile height of the spread schedule: resonator layers per workgroup
  * (1..255; 0 or absent: one).  A height whose tile does not fit the kernel's
  * register rows or LDS is lowered to the largest that fits.  Combined with the

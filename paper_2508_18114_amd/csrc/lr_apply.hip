@@ -8,13 +8,17 @@
 // once.  Columns are independent, so the factors of many trajectories of one
 // model at one time can be applied in one launch side by side (ncols = K M).
 //
-// One workgroup takes one column at a time: it streams the column (N complex
-// entries, coalesced 16-byte loads) into LDS, then every thread forms its rows
-// of Z from LDS -- the diagonal of H_eff, the couplings g (b+b^)(a+a^) and
+// A workgroup takes one column at a time: the column (N complex entries,
+// coalesced 16-byte loads) goes into LDS, then every thread forms its rows of
+// Z from LDS -- the diagonal of H_eff, the couplings g (b+b^)(a+a^) and
 // G (a+a^)(f+f^) (four taps each) and the drive d(t) (f+f^) (two taps), in
 // the lab frame or the frame rotating at the carrier -- and writes them
-// coalesced.  Basis index n = (q d_r + r) d_f + f: filter neighbours are
-// n +- 1, resonator n +- d_f, transmon n +- d_r d_f.
+// coalesced.  The workgroups stride over the columns; the loads of a
+// workgroup's next column (up to kApPf entries per thread) are in flight in
+// registers while it forms the current one, and both streams bypass the
+// caches' retention (non-temporal: every byte is touched once).  Basis index
+// n = (q d_r + r) d_f + f: filter neighbours are n +- 1, resonator n +- d_f,
+// transmon n +- d_r d_f.
 #include <hip/hip_runtime.h>
 
 #include "lr_device.h"
@@ -23,6 +27,7 @@ namespace lrk {
 
 constexpr int kApWG = 256;
 constexpr int kApMaxN = 8192;  // a column in LDS (128 KiB)
+constexpr int kApPf = 8;       // entries per thread of the next column held in registers (N <= 2048 whole)
 
 struct ApplyDev {
   int d_q, d_r, d_f, N;
@@ -30,6 +35,18 @@ struct ApplyDev {
   double drv;      // d(t)
   double2 e1, e2;  // e^{i w_d t}, e^{2 i w_d t} (drive frame)
 };
+
+typedef double ap_d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ap_load(const double2* p) {
+  const ap_d2 v = __builtin_nontemporal_load(reinterpret_cast<const ap_d2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void ap_store(double2* p, double2 v) {
+  ap_d2 w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<ap_d2*>(p));
+}
 
 template <bool ROT>
 __global__ __launch_bounds__(kApWG) void k_apply_heff(ApplyDev D, const double2* __restrict__ B,
@@ -42,11 +59,27 @@ __global__ __launch_bounds__(kApWG) void k_apply_heff(ApplyDev D, const double2*
   const int sq_ = d_r * d_f;  // transmon stride
   const double2 e1 = D.e1, e2 = D.e2;
   const double2 e1c = make_double2(e1.x, -e1.y), e2c = make_double2(e2.x, -e2.y);
-  for (int64_t c = blockIdx.x; c < ncols; c += gridDim.x) {
+  double2 pf[kApPf];
+  auto fetch = [&](int64_t c) {
     const double2* src = B + (size_t)c * N;
+#pragma unroll
+    for (int u = 0; u < kApPf; ++u) {
+      const int n = tid + u * kApWG;
+      if (n < N) pf[u] = ap_load(src + n);
+    }
+  };
+  int64_t c = blockIdx.x;
+  if (c < ncols) fetch(c);
+  for (; c < ncols; c += gridDim.x) {
     __syncthreads();  // the previous column is consumed
-    for (int n = tid; n < N; n += kApWG) col[n] = src[n];
+#pragma unroll
+    for (int u = 0; u < kApPf; ++u) {
+      const int n = tid + u * kApWG;
+      if (n < N) col[n] = pf[u];
+    }
+    for (int n = tid + kApPf * kApWG; n < N; n += kApWG) col[n] = ap_load(B + (size_t)c * N + n);
     __syncthreads();
+    if (c + gridDim.x < ncols) fetch(c + gridDim.x);  // in flight while this column is formed
     double2* dst = Z + (size_t)c * N;
     for (int n = tid; n < N; n += kApWG) {
       const int q = n / sq_, rem = n - q * sq_, r = rem / d_f, f = rem - r * d_f;
@@ -90,7 +123,7 @@ __global__ __launch_bounds__(kApWG) void k_apply_heff(ApplyDev D, const double2*
         if (r + 1 < d_r) tap(D.G * sf1 * sr1, e2c, col[n + d_f + 1]);
         tap(D.drv * sf1, e1c, col[n + 1]);  // d(t) f
       }
-      dst[n] = z;
+      ap_store(dst + n, z);
     }
   }
 }

@@ -46,7 +46,7 @@ struct lr_batch {
     int gm;     // packed: Gram terms on the vector ALU (-1) or matrix-core mode (0 FP64, 1 FP32, 2 BF16x3)
     int slots;  // packed matrix-core modes: output tiles per wave
   };
-  bool valu_gram = false;  // LR_BATCH_PACKED_VALU_GRAM
+  bool mfma64 = false;  // LR_BATCH_PACKED_MFMA64
   std::vector<Group> groups;
   bool prof = false;
   std::vector<hipEvent_t> ev;  // start/stop pairs of timed chunk launches
@@ -162,13 +162,13 @@ namespace {
 int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flags, bool adaptive, double rtol,
                double atol) {
   if (!out || !trajs || n < 1) return LR_ERR_ARG;
-  if (flags & ~(LR_BATCH_PACKED | LR_BATCH_PACKED_VALU_GRAM | LR_BATCH_SPREAD_LAYERS(0xff))) return LR_ERR_ARG;
+  if (flags & ~(LR_BATCH_PACKED | LR_BATCH_PACKED_MFMA64 | LR_BATCH_SPREAD_LAYERS(0xff))) return LR_ERR_ARG;
   *out = nullptr;
   lr_batch* b = new (std::nothrow) lr_batch();
   if (!b) return LR_ERR_OOM;
   b->n = n;
   b->adaptive = adaptive;
-  b->valu_gram = (flags & LR_BATCH_PACKED_VALU_GRAM) != 0;
+  b->mfma64 = (flags & LR_BATCH_PACKED_MFMA64) != 0;
   b->rtol = rtol;
   b->atol = atol;
   auto packs = [&](const lr_traj_t& x) {
@@ -447,7 +447,7 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
   int t = 0;
   while (t < b->n && b->packed[t]) {  // one launch per chunk holds every packed trajectory of a kernel family
     const int nm = b->tr[t].model.kind == LR_MODEL_NORMAL, prec = b->tr[t].precision;
-    const int gm = nm ? -1 : (prec == LR_FP64 ? (b->valu_gram || b->adaptive ? -1 : 0) : prec);
+    const int gm = nm ? -1 : (prec == LR_FP64 ? (b->mfma64 && !b->adaptive ? 0 : -1) : prec);
     lr_batch::Group g{t, t, 0, 0, 0, prec, 0, 0, 0, 1, 2, nm, gm, 2};
     while (t < b->n && b->packed[t] && (b->tr[t].model.kind == LR_MODEL_NORMAL) == (nm != 0) &&
            b->tr[t].precision == prec) {

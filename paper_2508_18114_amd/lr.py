@@ -37,7 +37,7 @@ LR_ERR_TIMEOUT = -8
 LR_ERR_STEP = -9
 LR_MAX_M = 32
 LR_BATCH_PACKED = 1       # lr_batch_init_ex flag: one workgroup per trajectory
-LR_BATCH_PACKED_VALU_GRAM = 2  # packed FP64 Gram terms on the vector ALU instead of the matrix cores
+LR_BATCH_PACKED_MFMA64 = 2    # packed FP64 Gram terms on the matrix cores instead of the vector ALU
 LR_PACKED_MAX_LM = 1536
 
 

@@ -934,7 +934,7 @@ def test_packed_result_does_not_depend_on_the_batch(lr):
 def test_packed_paper_size_matches_oracle(lr, gram):
     """Paper size (N = 2000, M = 20), g and e in the packed schedule for the first 6000 steps (3 ns),
     against the cached oracle run's records over the same span, with the paper-size floor tolerances;
-    Gram terms on the matrix cores (FP64 instruction, the default) and on the vector ALU."""
+    Gram terms on the vector ALU (the default) and on the matrix cores (FP64 instruction)."""
     import torch
     trajs = I.config_paper_size()
     gd = _golden("paper_size")
@@ -944,7 +944,7 @@ def test_packed_paper_size_matches_oracle(lr, gram):
                   obs_stride=stride, obs=torch.zeros((n // stride + 1, 6 + t.model.d_q), dtype=torch.float64,
                                                      device="cuda"))
              for t in trajs]
-    rc, codes, _ = _run_packed(lr, items, flags=lr.LR_BATCH_PACKED_VALU_GRAM if gram == "valu" else 0)
+    rc, codes, _ = _run_packed(lr, items, flags=lr.LR_BATCH_PACKED_MFMA64 if gram == "mfma" else 0)
     assert rc == lr.LR_OK, codes
     for it, key in zip(items, ("obs_g", "obs_e")):
         _assert_obs(it["obs"].cpu().numpy(), gd[key][:n // stride + 1], f"packed ({gram}) paper size {key} (3 ns)",
@@ -963,7 +963,7 @@ def test_packed_limits_and_fallback(lr):
     p = I.flattop_pulse(0.05, 0.1, t_ramp=0.02)
     B0 = I.initial_state(m, 32, "g", seed=91, scale=1e-2)
     Bo, ref, tol = oracle_with_tol(m, p, 0.0, 1e-3, 40, B0, 10)
-    for flags in (0, lr.LR_BATCH_PACKED_VALU_GRAM):
+    for flags in (0, lr.LR_BATCH_PACKED_MFMA64):
         it = dict(model=m, M=32, pulse=p, dt=1e-3, nsteps=40, B=lr.to_device(B0), obs_stride=10,
                   obs=torch.zeros((5, 6 + 8), dtype=torch.float64, device="cuda"))
         assert _run_packed(lr, [it], flags=flags)[0] == lr.LR_OK
