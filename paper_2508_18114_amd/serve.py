@@ -333,17 +333,26 @@ def pulse_loss_batch(model: I.ModelParams, M: int, pulses, dt: float, nsteps: in
     return out
 
 
+def square_start(model: I.ModelParams, nh: int, amp: float = I.ghz(0.15)) -> np.ndarray:
+    """SPSA start: every height amp, the square pulse of supplement S3.C.  The
+    paper's drive Omega_d(t) sin(w_d t) on i (f^ - f) (kinds 1 and 2, which put
+    d(t) = Re[Omega e^{-i w_d t}] on that quadrature) is a real paper amplitude
+    only for an imaginary height here (d = Im Omega sin(w_d t)); the Duffing
+    model's drive on (f + f^) takes real heights (a cos carrier)."""
+    theta = np.zeros(2 * nh)
+    theta[(1 if getattr(model, "kind", 0) in (I.MODEL_TRANSMON, I.MODEL_NORMAL) else 0)::2] = amp
+    return theta
+
+
 def spsa_optimize(model: I.ModelParams, M: int, T: float, nh: int, iters: int, dt: float, obs_stride: int,
                   seed: int = 1, a: float = 0.05, c: float = 0.05, sigma: float = 0.5,
                   frame: int = I.FRAME_DRIVE, stream=None, w_d: float = I.W_DRIVE, adaptive=None):
     """The optimisation loop of supplement S3.C on the device: SPSA over the nh
     complex heights of the smoothed stepwise pulse, started from the square shape
-    (all heights real, 2 pi 150 MHz), each step evaluating theta +- c_k Delta in
-    one batch of four trajectories.  Returns (theta, history) with the loss at
-    both probes of every step."""
-    theta0 = np.zeros(2 * nh)
-    theta0[0::2] = I.ghz(0.15)
-    opt = SPSA(theta0, seed, a=a, c=c, project=project_heights)
+    of amplitude 2 pi 150 MHz (square_start), each step evaluating theta +- c_k
+    Delta in one batch of four trajectories.  Returns (theta, history) with the
+    loss at both probes of every step."""
+    opt = SPSA(square_start(model, nh), seed, a=a, c=c, project=project_heights)
     hist = []
     for _ in range(iters):
         tp, tm = opt.ask()

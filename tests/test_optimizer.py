@@ -92,3 +92,21 @@ def test_autotune_signature_and_candidates():
     assert [c["schedule"] for c in cands] == ["spread"] * 3 + ["packed"]
     assert autotune.flags_of(cands[1]) == lr.LR_BATCH_SPREAD_LAYERS(2) == 2 << 8
     assert autotune.flags_of(cands[-1]) == lr.LR_BATCH_PACKED
+
+
+def test_square_start_is_the_papers_square_pulse_in_each_model():
+    """Kinds 1 and 2 carry the drive on i (f^ - f): the paper's real square amplitude is an imaginary
+    height there, so d(t) = Re[Omega e^{-i w_d t}] = A sin(w_d t) (its sin carrier); the Duffing model's
+    (f + f^) drive starts from real heights (cos carrier)."""
+    from oracle import pulses as opulses
+    from paper_2508_18114_amd import serve, transmon
+    A = I.ghz(0.15)
+    for model, imag in ((I.readout_model(3, 4, 3), False), (transmon.paper_model(4, 3, 3), True),
+                        (transmon.paper_model_normal(4, 3, 3), True)):
+        h = serve.heights_from(serve.square_start(model, 3))
+        assert np.allclose(h, 1j * A if imag else A)
+        p = I.stepwise_pulse(h, 40.0, sigma=0.5, w_d=transmon.PAPER_W_DRIVE)
+        t = 20.0  # on the plateau, far from every step
+        d = opulses.drive(p, t)
+        expect = A * (np.sin(p.w_d * t) if imag else np.cos(p.w_d * t))
+        assert abs(d - expect) < 1e-8 * A  # the outer steps, 10 ns = 20 sigma away, leave e^-20
