@@ -46,6 +46,17 @@ def parse():
                     help="with --packed-sample: arithmetic of the Gram terms (0 FP64, 1 FP32, 2 BF16x3)")
     ap.add_argument("--packed-mfma64", action="store_true",
                     help="with --packed-sample: FP64 Gram terms on the matrix cores instead of the vector ALU")
+    ap.add_argument("--serving", type=int, default=0, metavar="REQUESTS",
+                    help="only run the serving form on REQUESTS loss evaluations of the uncapped serving workload "
+                         "(saturation, 50/s, 0.7 x capacity) and print its summary")
+    ap.add_argument("--serving-only", choices=("saturation", "literal", "sub"), default=None,
+                    help="with --serving: run one scenario only")
+    ap.add_argument("--serving-policy", choices=("hybrid", "spread", "packed"), default="spread",
+                    help="with --serving: schedule of the requests")
+    ap.add_argument("--serving-layers", type=int, default=3,
+                    help="with --serving: resonator layers per workgroup of the spread schedule")
+    ap.add_argument("--serving-capacity", type=float, default=None, metavar="EVALS_PER_S",
+                    help="with --serving-only sub: the capacity measured by a saturation run")
     ap.add_argument("--apply-sample", type=int, default=0, metavar="LAUNCHES",
                     help="only time the operator application lr_apply_heff on 512 factors of N=2000, M=20 "
                          "(10240 columns) for LAUNCHES launches (a workload for kernel profiles)")
@@ -357,31 +368,66 @@ def comparisons(lr, I, torch, stream, plain_value):
         out.setdefault("precision_modes", {})[name] = {
             "value": 2 * steps / el, "unit": "RK steps*trajectories/s",
             "workload": f"g+e, N=2000, M=20, padding weight 1e-5, {steps} steps"}
-    # serving: requests of the serving workload (step count capped), saturation,
-    # the literal 50/s arrival rate, and 0.7 x the measured capacity
-    from paper_2508_18114_amd import serve
-    n_req, cap = 12, 4000
-    budget = 64 << 30
-
-    def serve_run(rate, packed=False):
-        reqs = serve.serving_requests(5, n_req, rate, step_cap=cap)
-        srv = serve.Server(hbm_budget_bytes=budget, chunk=2000, stream=stream, packed=packed)
-        st = srv.run(reqs)
-        st["offered_rate_per_s"] = rate
-        return st, reqs
-
-    sat, reqs = serve_run(1e9)
-    mean_steps = float(np.mean([r.nsteps for r in reqs]))
-    capacity = sat["traj_steps_per_s"] / (2 * mean_steps)
-    lit, _ = serve_run(50.0)
-    sub, _ = serve_run(0.7 * capacity)
     out["validity_rank_study"] = validity_study(lr, I, torch)
     out["drive_frame_step_size"] = drive_frame_study(lr, I, torch)
-    out["serving"] = {"saturation": sat, "literal_50_per_s": lit, "sub_saturation_0.7x": sub,
-                      "capacity_evals_per_s": capacity,
-                      "workload": f"{n_req} loss evaluations (g+e each) with the serving shapes (d_r 13-75, "
-                                  f"M 4-32, FP32/FP64), step count capped at {cap}, padding weight 1e-5, "
-                                  f"HBM budget {budget >> 30} GiB"}
+    # serving, a CAPPED sample (12 requests, at most 4000 steps each) that keeps this run short; the
+    # uncapped serving workload is `bench.py --serving N`
+    out["serving_capped_sample"] = serving(lr, I, torch, stream, 12, cap=4000, progress=False)
+    return out
+
+
+def serving(lr, I, torch, stream, n_req, cap=None, progress=True, only=None, capacity=None, policy="spread",
+            spread_layers=3):
+    """The serving form on the serving workload: n_req loss evaluations (g + e each) with the serving
+    shapes (d_r 13-75, M 4-32, T 10-60 ns at dt 5e-4: 2e4 - 1.2e5 steps, FP32 / FP64), uncapped unless
+    cap is given, with asynchronous cost-balanced ticks.  Three runs: saturation (every request at t = 0;
+    its throughput gives the capacity), the literal 50 requests/s, and 0.7 x the capacity.  only: one of
+    "saturation", "literal", "sub" (with capacity: requests/s from an earlier saturation run).  policy:
+    "hybrid" (packed, spread above 60 s of packed time), "spread" or "packed" (every request).  Each run's
+    statistics are printed as a JSON line when it ends."""
+    import numpy as np
+    from paper_2508_18114_amd import serve
+    budget = 64 << 30
+    steps = [r.nsteps for r in serve.serving_requests(5, n_req, 1.0, step_cap=cap)]
+    workload = (f"{n_req} loss evaluations (g+e each) with the serving shapes (d_r 13-75, M 4-32, FP32/FP64), "
+                f"{'step count capped at %d' % cap if cap else 'full step counts'} ({min(steps)}-{max(steps)} "
+                f"steps, {sum(steps) * 2:.3g} trajectory-steps), padding weight 1e-5, packed schedule (spread "
+                f"for requests whose packed duration would exceed 60 s), asynchronous cost-balanced ticks "
+                f"(2000 paper-size packed steps), HBM budget {budget >> 30} GiB")
+
+    def serve_run(rate, label):
+        reqs = serve.serving_requests(5, n_req, rate, step_cap=cap)
+        t0 = time.perf_counter()
+
+        def on_tick(srv):
+            if progress:
+                done = sum(1 for res in srv.results.values() if "done" in res)
+                print(f"[serving {label}] tick {srv.ticks} completed at {time.perf_counter() - t0:.1f} s: "
+                      f"{len(srv.active) // 2} active, {len(srv.queue)} queued, {done} done, "
+                      f"{srv.steps_done} trajectory-steps", file=sys.stderr, flush=True)
+
+        srv = serve.Server(hbm_budget_bytes=budget, chunk=2000, stream=stream, on_tick=on_tick,
+                           packed=policy != "spread", max_packed_s=float("inf") if policy == "packed" else 60.0,
+                           spread_layers=spread_layers)
+        st = srv.run(reqs)
+        st["offered_rate_per_s"] = rate
+        st["routed_spread"] = sum(1 for r in reqs if not srv._packs(r))
+        if progress:
+            print(json.dumps({"serving_run": label, **st, "workload": workload}), flush=True)
+        return st
+
+    out = {"capped": cap is not None, "workload": workload, "policy": policy, "spread_layers": spread_layers}
+    if only in (None, "saturation"):
+        out["saturation"] = sat = serve_run(1e9, "saturation")
+        capacity = sat["requests"] / sat["wall_s"]
+    if capacity is not None:
+        out["capacity_evals_per_s"] = capacity
+    if only in (None, "literal"):
+        out["literal_50_per_s"] = serve_run(50.0, "50/s")
+    if only in (None, "sub"):
+        if capacity is None:
+            raise ValueError("the 0.7 x capacity run needs the capacity of a saturation run")
+        out["sub_saturation_0.7x"] = serve_run(0.7 * capacity, "0.7x capacity")
     return out
 
 
@@ -592,6 +638,11 @@ def main():
         return
     if a.apply_sample > 0:
         print(json.dumps(apply_sample(lr, I, torch, a.apply_sample)), flush=True)
+        return
+    if a.serving > 0:
+        print(json.dumps(serving(lr, I, torch, torch.cuda.current_stream(), a.serving, only=a.serving_only,
+                                 capacity=a.serving_capacity, policy=a.serving_policy,
+                                 spread_layers=a.serving_layers)), flush=True)
         return
     trajs = I.config_paper_size()
     m, M = trajs[0].model, trajs[0].M

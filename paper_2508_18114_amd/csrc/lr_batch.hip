@@ -15,7 +15,9 @@
 // packed kernel gets one workgroup of its own (lr_packed.hip); the packed
 // trajectories of one kernel family (model kind 2 or not, arithmetic mode)
 // go into one ordinary launch per chunk, largest work first, and the hardware
-// fills each CU with as many as fit.  The others run in spread groups.
+// fills each CU with as many as fit; the launch sequences of different
+// families run concurrently on forked streams.  The others run in spread
+// groups.
 
 struct lr_batch {
   int n = 0;
@@ -37,6 +39,10 @@ struct lr_batch {
   int total_wg = 0;
   char* ws = nullptr;
   hipStream_t stream = nullptr;
+  // packed groups after the first run concurrently on streams of their own
+  // (forked from and joined back into `stream` by events)
+  std::vector<hipStream_t> aux;
+  std::vector<hipEvent_t> aux_ev;  // [0]: fork; [1 + i]: join of aux[i]
   struct Group {
     int begin, end, wgs, rows, ge, prec;
     size_t lds;
@@ -463,6 +469,20 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
     if (g.chunk == 0) g.chunk = 4096;
     b->groups.push_back(g);
   }
+  {  // one forked stream per packed group after the first (default priority)
+    int npk = 0;
+    for (const auto& g : b->groups) npk += g.packed ? 1 : 0;
+    while ((int)b->aux.size() < npk - 1) {
+      hipStream_t sx = nullptr;
+      if (hipStreamCreateWithFlags(&sx, hipStreamNonBlocking) != hipSuccess) return LR_ERR_HIP;
+      b->aux.push_back(sx);
+    }
+    while (b->aux_ev.size() < b->aux.size() + 1) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return LR_ERR_HIP;
+      b->aux_ev.push_back(e);
+    }
+  }
   while (t < b->n) {
     lr_batch::Group g{t, t, 0, 2, 1, b->tr[t].precision, 0, 0, 0, 0, 0, 0, -1, 2};
     while (t < b->n) {
@@ -554,9 +574,19 @@ int enqueue(lr_batch* b) {
                        reinterpret_cast<const double2*>(b->tr[t].d_B), v.Bb);
   }
   if (hipGetLastError() != hipSuccess) return LR_ERR_HIP;
+  int npk = 0;  // packed groups launched so far
+  std::vector<int> joins;
   for (const auto& g : b->groups) {
     const TrajDev* gtr = trajs;
     const int2* gmap = tmap + b->wg_offset[g.begin];
+    hipStream_t gs = b->stream;
+    if (g.packed && npk > 0 && npk - 1 < (int)b->aux.size()) {  // fork
+      gs = b->aux[npk - 1];
+      if (npk == 1 && hipEventRecord(b->aux_ev[0], b->stream) != hipSuccess) return LR_ERR_HIP;
+      if (hipStreamWaitEvent(gs, b->aux_ev[0], 0) != hipSuccess) return LR_ERR_HIP;
+      joins.push_back(npk - 1);
+    }
+    if (g.packed) ++npk;
     auto launch = [&](int prologue, int64_t step0, int64_t nchunk) -> int {
       void* args[] = {(void*)&gtr, (void*)&gmap, (void*)&step0, (void*)&nchunk};
       int64_t k = -1;
@@ -567,7 +597,7 @@ int enqueue(lr_batch* b) {
           b->ev.push_back(e);
         }
         k = b->n_ev++;
-        (void)hipEventRecord(b->ev[2 * k], b->stream);
+        (void)hipEventRecord(b->ev[2 * k], gs);
       }
       hipError_t err;
       if (g.packed) {
@@ -576,29 +606,33 @@ int enqueue(lr_batch* b) {
           const lrk::AdaptDev* aptr = ads + g.begin;
           void* pargs[] = {(void*)&ptr, (void*)&aptr, (void*)&step0, (void*)&nchunk};
           err = hipLaunchKernel(lrk::dp5_kernel(g.kp, prologue != 0), dim3(g.wgs), dim3(lrk::kTW), pargs, g.lds,
-                                b->stream);
+                                gs);
         } else {
           void* pargs[] = {(void*)&ptr, (void*)&step0, (void*)&nchunk};
           err = hipLaunchKernel(lrk::packed_kernel(g.kp, prologue != 0, g.nm != 0, g.gm, g.slots), dim3(g.wgs),
-                                dim3(lrk::kTW), pargs, g.lds, b->stream);
+                                dim3(lrk::kTW), pargs, g.lds, gs);
         }
       } else {
         err = hipLaunchCooperativeKernel(persist_fn(g.rows, g.ge, g.prec, prologue != 0), dim3(g.wgs),
                                          dim3(lrk::kPW), args, (unsigned)g.lds, b->stream);
       }
-      if (k >= 0) (void)hipEventRecord(b->ev[2 * k + 1], b->stream);
+      if (k >= 0) (void)hipEventRecord(b->ev[2 * k + 1], gs);
       return err == hipSuccess ? LR_OK : LR_ERR_HIP;
     };
     if (int e = launch(1, 0, 0)) return e;
-    hipLaunchKernelGGL(lrk::k_obs, dim3(g.end - g.begin), dim3(lrk::kWG), 0, b->stream, trajs + g.begin,
+    hipLaunchKernelGGL(lrk::k_obs, dim3(g.end - g.begin), dim3(lrk::kWG), 0, gs, trajs + g.begin,
                        (double*)nullptr);
     for (int64_t step = 0; step < g.max_steps;) {
       const int64_t chunk = std::min(g.chunk, g.max_steps - step);
       if (int e = launch(0, step, chunk)) return e;
       step += chunk;
-      hipLaunchKernelGGL(lrk::k_obs, dim3(g.end - g.begin), dim3(lrk::kWG), 0, b->stream, trajs + g.begin,
+      hipLaunchKernelGGL(lrk::k_obs, dim3(g.end - g.begin), dim3(lrk::kWG), 0, gs, trajs + g.begin,
                          (double*)nullptr);
     }
+  }
+  for (int i : joins) {  // join the forked packed groups
+    if (hipEventRecord(b->aux_ev[1 + i], b->aux[i]) != hipSuccess) return LR_ERR_HIP;
+    if (hipStreamWaitEvent(b->stream, b->aux_ev[1 + i], 0) != hipSuccess) return LR_ERR_HIP;
   }
   for (int t = 0; t < b->n; ++t) {
     const TrajDev& v = b->dev[t];
@@ -669,6 +703,8 @@ void lr_batch_destroy(lr_batch_t* b) {
   if (!b) return;
   drop_graph(b);
   for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : b->aux_ev) (void)hipEventDestroy(e);
+  for (hipStream_t sx : b->aux) (void)hipStreamDestroy(sx);
   delete b;
 }
 

@@ -53,7 +53,8 @@ class _Traj:
     which: str
     B: object                     # device tensor (M, N) complex128
     obs: object                   # device tensor (records, 6 + d_q)
-    done: int = 0
+    done: int = 0                 # steps of completed ticks
+    enq: int = 0                  # steps enqueued
 
 
 def trajectory_footprint(model: I.ModelParams, M: int, obs_records: int, packed: bool = False,
@@ -71,21 +72,62 @@ def trajectory_footprint(model: I.ModelParams, M: int, obs_records: int, packed:
     return ws + model.N * M * 16 + obs_records * (6 + model.d_q) * 8
 
 
+# Per-step time models of the two schedules (seconds), for routing and for
+# cost-balanced ticks: a packed workgroup takes about T_PACKED_REF per RK4 step
+# on the paper-size trajectory (N = 2000, M = 20) and scales with the flop count
+# N M (58 + 40 M); the spread schedule's step is latency-bound, about
+# T_SPREAD_REF at M = 20 and roughly linear in M (the solve).
+T_PACKED_REF = 2.0e-3
+T_SPREAD_REF = 120e-6
+COST_REF = 2000 * 20 * (58 + 40 * 20)
+
+
+def step_cost(model: I.ModelParams, M: int) -> float:
+    return float(model.N * M * (58 + 40 * M))
+
+
+def packed_step_s(model: I.ModelParams, M: int) -> float:
+    return T_PACKED_REF * step_cost(model, M) / COST_REF
+
+
+def spread_step_s(model: I.ModelParams, M: int) -> float:
+    return T_SPREAD_REF * max(M, 4) / 20.0
+
+
 class Server:
-    """packed=True runs the FP64 trajectories of every tick in the packed
-    schedule (one workgroup each, LR_BATCH_PACKED); they then count one
-    workgroup each against the workgroup cap instead of d_r."""
+    """Continuous batching of loss evaluations.
+
+    Routing: with packed=True (the default) a request runs in the packed
+    schedule (one workgroup per trajectory, LR_BATCH_PACKED: the most
+    trajectory-steps per second, but one workgroup's pace per trajectory)
+    unless its estimated packed duration exceeds max_packed_s; then it runs in
+    the spread schedule (one workgroup per resonator layer, the shortest time
+    per step).  packed=False: every request spread, in tiles of spread_layers
+    resonator layers per workgroup (LR_BATCH_SPREAD_LAYERS).  A packed request
+    counts two workgroups against the cap (default: two per CU, the packed
+    kernel's occupancy), a spread one 2 ceil(d_r / spread_layers).
+
+    Ticks are asynchronous and cost-balanced: tick k gives every active
+    trajectory the steps that take about `chunk` steps of the paper-size
+    packed trajectory in its schedule, is built and enqueued on one of two
+    alternating streams (after an event of tick k - 1, whose states it
+    continues) before tick k - 1 is synchronised and retired, and queued
+    requests are admitted on the host while the GPU runs.  A trajectory's
+    result does not depend on the tick lengths or the mix (step0 continues the
+    stage-time grid exactly; both schedules sum in fixed orders)."""
 
     def __init__(self, hbm_budget_bytes: int, chunk: int = 2000, max_workgroups: Optional[int] = None,
-                 stream=None, packed: bool = False):
+                 stream=None, packed: bool = True, max_packed_s: float = 60.0, on_tick=None,
+                 spread_layers: int = 1):
         import torch
         self.torch = torch
         self.packed = bool(packed)
         self.budget = int(hbm_budget_bytes)
         self.chunk = int(chunk)
         props = torch.cuda.get_device_properties(0)
-        self.wg_cap = int(max_workgroups or props.multi_processor_count)
+        self.wg_cap = int(max_workgroups or props.multi_processor_count * (2 if self.packed else 1))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.tick_streams = [torch.cuda.Stream(), torch.cuda.Stream()]
         self.queue: List[Request] = []
         self.active: List[_Traj] = []
         self.in_use = 0
@@ -94,13 +136,28 @@ class Server:
         self.t_start = None
         self.steps_done = 0
         self.ticks = 0
+        self._last_event = None
+        self.max_packed_s = float(max_packed_s)
+        self.on_tick = on_tick
+        self.spread_layers = max(1, int(spread_layers))
 
     # -------------------------------------------------------------- admission
+    def _packs(self, r: Request) -> bool:
+        if not self.packed or (r.precision != I.FP64 and getattr(r.model, "kind", 0) == I.MODEL_NORMAL):
+            return False
+        return r.nsteps * packed_step_s(r.model, r.M) <= self.max_packed_s
+
+    def _tick_steps(self, r: Request) -> int:
+        t_tick = self.chunk * T_PACKED_REF
+        per = packed_step_s(r.model, r.M) if self._packs(r) else spread_step_s(r.model, r.M)
+        return max(1, int(t_tick / per))
+
     def _need(self, r: Request):
         nrec = r.nsteps // r.obs_stride + 1
-        packs = self.packed and r.precision == I.FP64
+        packs = self._packs(r)
         fp = 2 * trajectory_footprint(r.model, r.M, nrec, packs, r.precision)
-        wgs = 2 if packs else 2 * r.model.d_r  # one workgroup per trajectory, or per resonator layer
+        # one workgroup per trajectory, or per tile of spread_layers resonator layers
+        wgs = 2 if packs else 2 * -(-r.model.d_r // self.spread_layers)
         return fp, wgs
 
     def submit(self, r: Request):
@@ -125,42 +182,78 @@ class Server:
             for which in ("g", "e"):
                 B0 = I.initial_state(r.model, r.M, which, r.seed, r.pad_scale)
                 obs = torch.zeros((nrec, 6 + r.model.d_q), dtype=torch.float64, device="cuda")
-                self.active.append(_Traj(r, which, lr.to_device(B0), obs))
+                t = _Traj(r, which, lr.to_device(B0), obs)
+                self.active.append(t)
             self.in_use += fp
             self.wg_in_use += wgs
             self.results[r.rid] = {"arrival": r.arrival, "admitted": now}
         self.queue = keep
 
-    # -------------------------------------------------------------- one tick
-    def tick(self):
-        """Advance every active trajectory by up to `chunk` steps (one batch launch sequence)."""
+    # -------------------------------------------------------------- ticks
+    def _enqueue(self):
+        """Build and enqueue the next tick: every active trajectory with steps not yet enqueued moves
+        ahead by up to `chunk` steps.  Returns the pending tick or None."""
         torch = self.torch
         items = []
         for t in self.active:
             r = t.req
-            n = min(self.chunk, r.nsteps - t.done)
+            n = min(self._tick_steps(r), r.nsteps - t.enq)
             if n <= 0:
                 continue
-            if n < r.nsteps - t.done:
+            if n < r.nsteps - t.enq:
                 n -= n % r.obs_stride  # keep record boundaries aligned
                 n = max(n, r.obs_stride)
             items.append((t, dict(model=r.model, M=r.M, pulse=r.pulse, t0=0.0, dt=r.dt, nsteps=n, B=t.B,
-                                  obs_stride=r.obs_stride, obs=t.obs[t.done // r.obs_stride:],
-                                  precision=r.precision, step0=t.done)))
+                                  obs_stride=r.obs_stride, obs=t.obs[t.enq // r.obs_stride:],
+                                  precision=r.precision, step0=t.enq)))
         if not items:
-            return
-        b = lr.Batch([it for _, it in items], stream=self.stream, packed=self.packed)
-        b.run()
-        rc, codes, steps = b.status()
-        for (t, it), c in zip(items, codes):
-            if c != lr.LR_OK:
-                self.results[t.req.rid]["error"] = lr.lr_strerror(c)
-                t.done = t.req.nsteps
-            else:
-                t.done += it["nsteps"]
-                self.steps_done += it["nsteps"]
-        b.close()
+            return None
+        s = self.tick_streams[self.ticks % 2]
+        # plan and bind first (binding synchronises this stream, which holds only finished ticks) ...
+        items = [x for x in items if self._packs(x[0].req)] + [x for x in items if not self._packs(x[0].req)]
+        npk = sum(1 for x in items if self._packs(x[0].req))
+        batches = []
+        if npk:
+            batches.append((lr.Batch([it for _, it in items[:npk]], stream=s, packed=True), items[:npk]))
+        if npk < len(items):
+            batches.append((lr.Batch([it for _, it in items[npk:]], stream=s, packed=False,
+                                     flags=lr.LR_BATCH_SPREAD_LAYERS(self.spread_layers)), items[npk:]))
+        # ... then order the launches after the admissions' copies and the previous tick
+        s.wait_stream(torch.cuda.current_stream())
+        if self._last_event is not None:
+            s.wait_event(self._last_event)
+        for b, _ in batches:
+            b.run()
+        ev = torch.cuda.Event()
+        ev.record(s)
+        self._last_event = ev
+        for t, it in items:
+            t.enq += it["nsteps"]
+            t.B.record_stream(s)
+            t.obs.record_stream(s)
         self.ticks += 1
+        return batches
+
+    def _complete(self, tick):
+        """Synchronise a tick (its stream only) and account its steps and errors."""
+        for b, items in tick:
+            rc, codes, steps = b.status()
+            for (t, it), c in zip(items, codes):
+                if c != lr.LR_OK:
+                    self.results[t.req.rid]["error"] = lr.lr_strerror(c)
+                    t.done = t.enq = t.req.nsteps
+                else:
+                    t.done += it["nsteps"]
+                    self.steps_done += it["nsteps"]
+            b.close()
+        if self.on_tick is not None:
+            self.on_tick(self)
+
+    def tick(self):
+        """One synchronous tick (enqueue and complete)."""
+        pend = self._enqueue()
+        if pend is not None:
+            self._complete(pend)
 
     def _retire(self, now: float):
         by_req: Dict[int, List[_Traj]] = {}
@@ -197,20 +290,23 @@ class Server:
         t0 = time.perf_counter()
         self.t_start = t0
         reported = set()
-        while self.queue or self.active:
+        pending = None
+        while self.queue or self.active or pending is not None:
             now = time.perf_counter() - t0
-            self._admit(now)
-            if not self.active:
-                nxt = min(r.arrival for r in self.queue)
-                time.sleep(max(0.0, min(nxt - now, 0.05)))
-                continue
-            self.tick()
-            self._retire(time.perf_counter() - t0)
-            if on_result is not None:
-                for rid, res in list(self.results.items()):
-                    if "done" in res and rid not in reported:
-                        reported.add(rid)
-                        on_result(rid, res)
+            self._admit(now)  # host work while the pending tick runs
+            nxt = self._enqueue() if self.active else None
+            if pending is not None:
+                self._complete(pending)
+                self._retire(time.perf_counter() - t0)
+                if on_result is not None:
+                    for rid, res in list(self.results.items()):
+                        if "done" in res and rid not in reported:
+                            reported.add(rid)
+                            on_result(rid, res)
+            pending = nxt
+            if pending is None and not self.active and self.queue:
+                nxt_arr = min(r.arrival for r in self.queue)
+                time.sleep(max(0.0, min(nxt_arr - (time.perf_counter() - t0), 0.05)))
         wall = time.perf_counter() - t0
         lat = np.array([res["latency"] for res in self.results.values() if "latency" in res])
         return {"requests": len(lat), "wall_s": wall, "traj_steps": self.steps_done,

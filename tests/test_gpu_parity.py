@@ -575,20 +575,21 @@ def _serving_reqs():
 
 
 def test_serving_result_alone_equals_mix(lr):
-    """A request served alone, and in a mix with others that arrive later and run with a different tick
-    length, gives bitwise the same state, observation series and loss; a continued run equals one call."""
+    """Spread-schedule serving: a request served alone, and in a mix with others that arrive later and
+    run with a different tick length, gives bitwise the same state, observation series and loss; a
+    continued run equals one call."""
     import copy
     import torch
     from paper_2508_18114_amd import serve
     reqs = _serving_reqs()
-    alone = serve.Server(hbm_budget_bytes=1 << 34, chunk=1000)
+    alone = serve.Server(hbm_budget_bytes=1 << 34, chunk=1000, packed=False)
     st1 = alone.run([copy.deepcopy(reqs[0])])
     r_alone = alone.results[0]
     assert st1["errors"] == 0 and st1["requests"] == 1
     mixed = [copy.deepcopy(r) for r in reqs]
     for k, r in enumerate(mixed):
         r.arrival = 0.0 if k < 2 else 0.01 * k
-    mix = serve.Server(hbm_budget_bytes=1 << 34, chunk=600)
+    mix = serve.Server(hbm_budget_bytes=1 << 34, chunk=600, packed=False)
     st2 = mix.run(mixed)
     assert st2["errors"] == 0 and st2["requests"] == len(reqs)
     r_mix = mix.results[0]
@@ -609,8 +610,9 @@ def test_serving_result_alone_equals_mix(lr):
 
 
 def test_serving_packed_alone_equals_mix(lr):
-    """Packed serving: request 1 (FP64) alone and in the mix (the FP32 ones run in the spread schedule)
-    gives bitwise the same result, and agrees with the spread server to the FP64 tolerances."""
+    """Packed serving (the default, asynchronous ticks on two streams): request 1 (FP64) alone and in
+    the mix (FP32 requests in their own packed launches, concurrent on a forked stream) gives bitwise
+    the same result, and agrees with the spread server to the FP64 tolerances."""
     import copy
     import torch
     from paper_2508_18114_amd import serve
@@ -627,7 +629,7 @@ def test_serving_packed_alone_equals_mix(lr):
     assert st2["errors"] == 0 and st2["requests"] == len(reqs)
     for key in ("B_g", "B_e", "obs_g", "obs_e"):
         assert torch.equal(alone.results[1][key], mix.results[1][key]), key
-    spread = serve.Server(hbm_budget_bytes=1 << 34, chunk=1000)
+    spread = serve.Server(hbm_budget_bytes=1 << 34, chunk=1000, packed=False)
     assert spread.run([copy.deepcopy(reqs[1])])["errors"] == 0
     for key in ("obs_g", "obs_e"):
         _assert_obs(mix.results[1][key].cpu().numpy(), spread.results[1][key].cpu().numpy(), f"packed serving {key}")
