@@ -46,6 +46,9 @@ def parse():
                     help="with --packed-sample: arithmetic of the Gram terms (0 FP64, 1 FP32, 2 BF16x3)")
     ap.add_argument("--packed-mfma64", action="store_true",
                     help="with --packed-sample: FP64 Gram terms on the matrix cores instead of the vector ALU")
+    ap.add_argument("--config4-subset", type=int, default=0, metavar="PULSES",
+                    help="only run configuration 4 to completion on a stratified subset (PULSES pulses x g/e "
+                         "per (d_r, M) stratum) and print its rate")
     ap.add_argument("--serving", type=int, default=0, metavar="REQUESTS",
                     help="only run the serving form on REQUESTS loss evaluations of the uncapped serving workload "
                          "(saturation, 50/s, 0.7 x capacity) and print its summary")
@@ -134,7 +137,8 @@ def apply_sample(lr, I, torch, launches):
     us = 1e3 * e0.elapsed_time(e1) / launches
     by = 32.0 * m.N * ncols
     return {"bound": "hbm", "achieved": by / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": by / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "kernel": "k_apply_heff", "kernel_mean_us": us,
+            "frac": by / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "traffic": measured_apply_traffic_per_launch(),
+            "kernel": "k_apply_heff", "kernel_mean_us": us,
             "bytes_per_launch": by, "launches": launches,
             "workload": f"Z = H_eff(t) B for 512 factors of N={m.N}, M=20 side by side ({ncols} columns), lab frame"}
 
@@ -431,6 +435,45 @@ def serving(lr, I, torch, stream, n_req, cap=None, progress=True, only=None, cap
     return out
 
 
+def config4_subset(lr, I, torch, per_stratum):
+    """Configuration 4 run to completion on a stratified subset: the 512 trajectories (256 pulses x g/e)
+    fall into 12 strata (d_r in {25, 38, 50, 75} x M in 8-15, 16-23, 24-32); the first per_stratum
+    pulses of each stratum (with both g and e) are integrated over their whole step counts in one
+    batch (spread schedule: with a few dozen trajectories one workgroup per layer is the faster form).
+    Reports the rate beside the whole configuration's step total."""
+    import numpy as np
+    allt = I.config_batched()
+    strata = {}
+    for k in range(0, len(allt), 2):
+        t = allt[k]
+        key = (t.model.d_r, 0 if t.M < 16 else (1 if t.M < 24 else 2))
+        strata.setdefault(key, []).append(k)
+    pick = []
+    for key in sorted(strata):
+        for k in strata[key][:per_stratum]:
+            pick += [allt[k], allt[k + 1]]
+    items = [dict(model=t.model, M=t.M, pulse=t.pulse, dt=t.dt, nsteps=t.nsteps, B=lr.to_device(t.B0()))
+             for t in pick]
+    b = lr.Batch(items)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rc, codes, _ = b.status()
+    b.close()
+    if rc != lr.LR_OK:
+        raise RuntimeError(f"config 4 subset failed: {lr.lr_strerror(rc)}")
+    steps = sum(t.nsteps for t in pick)
+    total = sum(t.nsteps for t in allt)
+    return {"value": steps / el, "unit": "RK steps*trajectories/s", "wall_s": el, "trajectories": len(pick),
+            "trajectory_steps": steps, "config4_trajectory_steps": total,
+            "strata": {f"d_r={k[0]},M-bin={k[1]}": len(v) for k, v in sorted(strata.items())},
+            "workload": f"stratified subset of configuration 4: {per_stratum} pulse(s) x g/e from each of the "
+                        f"{len(strata)} (d_r, M) strata, {len(pick)} trajectories to completion "
+                        f"({steps:.3g} of the configuration's {total:.3g} trajectory-steps), spread schedule"}
+
+
 def validity_study(lr, I, torch):
     """Supplement S1.B on the small readout model (N=200, flat-top drive, 1e4
     steps, padding weight 1e-5): the control quantity p_M/p_1 and the purity
@@ -612,6 +655,12 @@ def measured_traffic_per_step():
                              ("lr_persistent.hip", "lr_device.h"))
 
 
+def measured_apply_traffic_per_launch():
+    """HBM bytes per k_apply_heff launch on 10240 columns of N=2000 (measured), or None."""
+    return _profiled_traffic("k_apply_heff_512_factors_traffic.md", "traffic_bytes_per_launch",
+                             ("lr_apply.hip", "lr_device.h"))
+
+
 def measured_packed_traffic_per_traj_step():
     """HBM bytes per trajectory-step of k_packed on 512 trajectories (measured), or None."""
     return _profiled_traffic("k_packed_512_same_shape_traffic.md", "traffic_bytes_per_traj_step",
@@ -638,6 +687,9 @@ def main():
         return
     if a.apply_sample > 0:
         print(json.dumps(apply_sample(lr, I, torch, a.apply_sample)), flush=True)
+        return
+    if a.config4_subset > 0:
+        print(json.dumps(config4_subset(lr, I, torch, a.config4_subset)), flush=True)
         return
     if a.serving > 0:
         print(json.dumps(serving(lr, I, torch, torch.cuda.current_stream(), a.serving, only=a.serving_only,

@@ -192,6 +192,14 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
   auto work = [&](const lr_traj_t& x) {
     return (double)x.nsteps * x.model.d_q * x.model.d_r * x.model.d_f * x.M;
   };
+  // packed footprint class: 0 if two workgroups fit a CU's LDS, 1 if only one does
+  auto fclass = [&](const lr_traj_t& x) {
+    const int dmax = std::max(std::max(x.model.d_q, x.model.d_r), x.model.d_f);
+    return lrk::packed_lds_elems(x.model.d_q * x.model.d_f, x.M, dmax, x.model.kind) * sizeof(double2) >
+                   lrk::kPackedLdsMax / 2
+               ? 1
+               : 0;
+  };
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
   // packed trajectories first, largest work first; then one precision mode
@@ -199,10 +207,12 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     const bool px = packs(trajs[x]), py = packs(trajs[y]);
     if (px != py) return px;
-    if (px) {  // kernel families together: kind 2 last, then by arithmetic mode
+    if (px) {  // kernel families together (kind 2 last, then by arithmetic mode), then footprint class
       const bool nx = trajs[x].model.kind == LR_MODEL_NORMAL, ny = trajs[y].model.kind == LR_MODEL_NORMAL;
       if (nx != ny) return ny;
       if (trajs[x].precision != trajs[y].precision) return trajs[x].precision < trajs[y].precision;
+      const int cx = fclass(trajs[x]), cy = fclass(trajs[y]);
+      if (cx != cy) return cx < cy;
       return work(trajs[x]) > work(trajs[y]);
     }
     if (trajs[x].precision != trajs[y].precision) return trajs[x].precision < trajs[y].precision;
@@ -455,8 +465,9 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
     const int nm = b->tr[t].model.kind == LR_MODEL_NORMAL, prec = b->tr[t].precision;
     const int gm = nm ? -1 : (prec == LR_FP64 ? (b->mfma64 && !b->adaptive ? 0 : -1) : prec);
     lr_batch::Group g{t, t, 0, 0, 0, prec, 0, 0, 0, 1, 2, nm, gm, 2};
+    const bool big = b->lds[t] > lrk::kPackedLdsMax / 2;  // footprint class (see lr_batch_init)
     while (t < b->n && b->packed[t] && (b->tr[t].model.kind == LR_MODEL_NORMAL) == (nm != 0) &&
-           b->tr[t].precision == prec) {
+           b->tr[t].precision == prec && (b->lds[t] > lrk::kPackedLdsMax / 2) == big) {
       g.kp = std::max(g.kp, lrk::packed_kp(b->tr[t].M, b->tr[t].model.kind));
       g.slots = std::max(g.slots, lrk::mg_slots(b->tr[t].M));
       g.lds = std::max(g.lds, b->lds[t]);
@@ -469,9 +480,13 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
     if (g.chunk == 0) g.chunk = 4096;
     b->groups.push_back(g);
   }
-  {  // one forked stream per packed group after the first (default priority)
-    int npk = 0;
-    for (const auto& g : b->groups) npk += g.packed ? 1 : 0;
+  {  // one forked stream per packed kernel family after the first (default priority)
+    int npk = 0, prev = -1;
+    for (const auto& g : b->groups)
+      if (g.packed && g.nm * 4 + g.prec != prev) {
+        ++npk;
+        prev = g.nm * 4 + g.prec;
+      }
     while ((int)b->aux.size() < npk - 1) {
       hipStream_t sx = nullptr;
       if (hipStreamCreateWithFlags(&sx, hipStreamNonBlocking) != hipSuccess) return LR_ERR_HIP;
@@ -574,19 +589,40 @@ int enqueue(lr_batch* b) {
                        reinterpret_cast<const double2*>(b->tr[t].d_B), v.Bb);
   }
   if (hipGetLastError() != hipSuccess) return LR_ERR_HIP;
-  int npk = 0;  // packed groups launched so far
+  // packed kernel families run concurrently, the first on the batch stream and each further one on a
+  // forked stream; the footprint classes of one family run one after the other on its stream
+  int nfam = 0, prev_fam = -1;
   std::vector<int> joins;
+  // join the forked streams back into the batch stream (before any spread group: its cooperative
+  // launch must find the chip free of packed work, or its group barriers could wait on workgroups
+  // that cannot be resident yet)
+  auto join_all = [&]() -> int {
+    for (int i : joins) {
+      if (hipEventRecord(b->aux_ev[1 + i], b->aux[i]) != hipSuccess) return LR_ERR_HIP;
+      if (hipStreamWaitEvent(b->stream, b->aux_ev[1 + i], 0) != hipSuccess) return LR_ERR_HIP;
+    }
+    joins.clear();
+    return LR_OK;
+  };
   for (const auto& g : b->groups) {
     const TrajDev* gtr = trajs;
     const int2* gmap = tmap + b->wg_offset[g.begin];
     hipStream_t gs = b->stream;
-    if (g.packed && npk > 0 && npk - 1 < (int)b->aux.size()) {  // fork
-      gs = b->aux[npk - 1];
-      if (npk == 1 && hipEventRecord(b->aux_ev[0], b->stream) != hipSuccess) return LR_ERR_HIP;
-      if (hipStreamWaitEvent(gs, b->aux_ev[0], 0) != hipSuccess) return LR_ERR_HIP;
-      joins.push_back(npk - 1);
+    if (!g.packed)
+      if (int e = join_all()) return e;
+    if (g.packed) {
+      const int fam = g.nm * 4 + g.prec;
+      if (fam != prev_fam) {
+        ++nfam;
+        prev_fam = fam;
+        if (nfam > 1 && nfam - 2 < (int)b->aux.size()) {  // fork
+          if (nfam == 2 && hipEventRecord(b->aux_ev[0], b->stream) != hipSuccess) return LR_ERR_HIP;
+          if (hipStreamWaitEvent(b->aux[nfam - 2], b->aux_ev[0], 0) != hipSuccess) return LR_ERR_HIP;
+          joins.push_back(nfam - 2);
+        }
+      }
+      if (nfam > 1 && nfam - 2 < (int)b->aux.size()) gs = b->aux[nfam - 2];
     }
-    if (g.packed) ++npk;
     auto launch = [&](int prologue, int64_t step0, int64_t nchunk) -> int {
       void* args[] = {(void*)&gtr, (void*)&gmap, (void*)&step0, (void*)&nchunk};
       int64_t k = -1;
@@ -630,10 +666,7 @@ int enqueue(lr_batch* b) {
                          (double*)nullptr);
     }
   }
-  for (int i : joins) {  // join the forked packed groups
-    if (hipEventRecord(b->aux_ev[1 + i], b->aux[i]) != hipSuccess) return LR_ERR_HIP;
-    if (hipStreamWaitEvent(b->stream, b->aux_ev[1 + i], 0) != hipSuccess) return LR_ERR_HIP;
-  }
+  if (int e = join_all()) return e;
   for (int t = 0; t < b->n; ++t) {
     const TrajDev& v = b->dev[t];
     long long e = (long long)v.N * v.M;

@@ -798,3 +798,20 @@ def test_package_normal_modes_match_the_oracle():
         np.testing.assert_allclose(S2, S[:2], atol=1e-12)
     m = transmon.paper_model_normal(6, 8, 4)
     assert m.kind == I.MODEL_NORMAL and len(m.S) == 8 and m.N == 6 * 8 * 4
+
+
+def test_summation_order_variants_are_the_same_sums():
+    """The row-sum orders the floor measurement uses (reversed, blocks of 40 rows) give the reference
+    sums to rounding, and exactly on integer-valued data (every partial sum is exact there); a dropped
+    block would fail both."""
+    r = np.random.default_rng(5)
+    X = r.standard_normal((203, 6)) + 1j * r.standard_normal((203, 6))
+    Y = r.standard_normal((203, 4)) + 1j * r.standard_normal((203, 4))
+    ref = X.conj().T @ Y
+    for order in ("reversed", "blocked"):
+        got = lowrank.inner(X, Y, order)
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+        Xi, Yi = np.round(4 * X), np.round(4 * Y)
+        assert np.array_equal(lowrank.inner(Xi, Yi, order), Xi.conj().T @ Yi)
+        v = np.round(8 * r.standard_normal(5000))
+        assert lowrank.total(v, order) == np.sum(v)
