@@ -56,7 +56,7 @@ def parse():
                     help="with --serving: run one scenario only")
     ap.add_argument("--serving-policy", choices=("hybrid", "spread", "packed"), default="spread",
                     help="with --serving: schedule of the requests")
-    ap.add_argument("--serving-layers", type=int, default=3,
+    ap.add_argument("--serving-layers", type=int, default=4,
                     help="with --serving: resonator layers per workgroup of the spread schedule")
     ap.add_argument("--serving-capacity", type=float, default=None, metavar="EVALS_PER_S",
                     help="with --serving-only sub: the capacity measured by a saturation run")
@@ -381,7 +381,7 @@ def comparisons(lr, I, torch, stream, plain_value):
 
 
 def serving(lr, I, torch, stream, n_req, cap=None, progress=True, only=None, capacity=None, policy="spread",
-            spread_layers=3):
+            spread_layers=4):
     """The serving form on the serving workload: n_req loss evaluations (g + e each) with the serving
     shapes (d_r 13-75, M 4-32, T 10-60 ns at dt 5e-4: 2e4 - 1.2e5 steps, FP32 / FP64), uncapped unless
     cap is given, with asynchronous cost-balanced ticks.  Three runs: saturation (every request at t = 0;
@@ -393,11 +393,13 @@ def serving(lr, I, torch, stream, n_req, cap=None, progress=True, only=None, cap
     from paper_2508_18114_amd import serve
     budget = 64 << 30
     steps = [r.nsteps for r in serve.serving_requests(5, n_req, 1.0, step_cap=cap)]
+    schedule = {"spread": f"spread schedule ({spread_layers} resonator layers per workgroup)",
+                "packed": "packed schedule",
+                "hybrid": "packed schedule, spread for requests whose packed duration would exceed 60 s"}[policy]
     workload = (f"{n_req} loss evaluations (g+e each) with the serving shapes (d_r 13-75, M 4-32, FP32/FP64), "
                 f"{'step count capped at %d' % cap if cap else 'full step counts'} ({min(steps)}-{max(steps)} "
-                f"steps, {sum(steps) * 2:.3g} trajectory-steps), padding weight 1e-5, packed schedule (spread "
-                f"for requests whose packed duration would exceed 60 s), asynchronous cost-balanced ticks "
-                f"(2000 paper-size packed steps), HBM budget {budget >> 30} GiB")
+                f"steps, {sum(steps) * 2:.3g} trajectory-steps), padding weight 1e-5, {schedule}, asynchronous "
+                f"cost-balanced ticks (2000 paper-size packed steps), HBM budget {budget >> 30} GiB")
 
     def serve_run(rate, label):
         reqs = serve.serving_requests(5, n_req, rate, step_cap=cap)
@@ -413,7 +415,13 @@ def serving(lr, I, torch, stream, n_req, cap=None, progress=True, only=None, cap
         srv = serve.Server(hbm_budget_bytes=budget, chunk=2000, stream=stream, on_tick=on_tick,
                            packed=policy != "spread", max_packed_s=float("inf") if policy == "packed" else 60.0,
                            spread_layers=spread_layers)
-        st = srv.run(reqs)
+
+        def on_result(rid, res):
+            if progress:
+                print(f"[serving {label}] request {rid} arrival {res['arrival']:.1f} s latency "
+                      f"{res.get('latency', float('nan')):.1f} s", file=sys.stderr, flush=True)
+
+        st = srv.run(reqs, on_result=on_result)
         st["offered_rate_per_s"] = rate
         st["routed_spread"] = sum(1 for r in reqs if not srv._packs(r))
         if progress:

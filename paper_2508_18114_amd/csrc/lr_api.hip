@@ -632,8 +632,8 @@ int lr_apply_heff(const lr_model_t* m, const lr_pulse_t* pulse, double t, const 
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, lrk::kApWG, lds) != hipSuccess || per_cu < 1)
     return LR_ERR_HIP;
-  // one resident wave of workgroups, each striding over its columns with the next one in flight
-  const long long grid = std::min<long long>(ncols, (long long)per_cu * ncu);
+  // two resident waves of workgroups, each striding over its columns with the next one in flight
+  const long long grid = std::min<long long>(ncols, 2LL * per_cu * ncu);
   const double2* Bp = reinterpret_cast<const double2*>(d_B);
   double2* Zp = reinterpret_cast<double2*>(d_Z);
   if (rot)

@@ -1058,7 +1058,10 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
 // blockIdx.x = trajectory of trajs[]; the RK4 chunk and the prologue are
 // separate kernels so that timing tools see the step kernel alone.  The
 // normal-mode model has kernels of its own (its larger window would raise the
-// register allocation, and so lower the occupancy, of the other kinds).
+// register allocation, and so lower the occupancy, of the other kinds); up to
+// entry blocks of 8 (M <= 21) they are held to two workgroups per CU, which
+// spills ~30 VGPRs to scratch and measured 1.9x faster at the paper's size
+// than one workgroup per CU without spills.
 template <int KP>
 __global__ __launch_bounds__(kTW) void k_packed(const TrajDev* __restrict__ trajs, int64_t step0, int64_t nchunk) {
   const TrajDev& T = trajs[blockIdx.x];
@@ -1078,8 +1081,8 @@ __global__ __launch_bounds__(kTW) void k_packed_prologue(const TrajDev* __restri
   packed_body<KP, false>(trajs[blockIdx.x], 1, step0, nchunk);
 }
 template <int KP>
-__global__ __launch_bounds__(kTW) void k_packed_nm(const TrajDev* __restrict__ trajs, int64_t step0,
-                                                   int64_t nchunk) {
+__global__ __launch_bounds__(kTW, (KP <= 8 ? 2 : 1)) void k_packed_nm(const TrajDev* __restrict__ trajs,
+                                                                      int64_t step0, int64_t nchunk) {
   const TrajDev& T = trajs[blockIdx.x];
   if (T.frame)
     packed_body<KP, true, 2>(T, 0, step0, nchunk);
@@ -1087,8 +1090,8 @@ __global__ __launch_bounds__(kTW) void k_packed_nm(const TrajDev* __restrict__ t
     packed_body<KP, false, 2>(T, 0, step0, nchunk);
 }
 template <int KP>
-__global__ __launch_bounds__(kTW) void k_packed_nm_prologue(const TrajDev* __restrict__ trajs, int64_t step0,
-                                                            int64_t nchunk) {
+__global__ __launch_bounds__(kTW, (KP <= 8 ? 2 : 1)) void k_packed_nm_prologue(const TrajDev* __restrict__ trajs,
+                                                                               int64_t step0, int64_t nchunk) {
   const TrajDev& T = trajs[blockIdx.x];
   if (T.frame)
     packed_body<KP, true, 2>(T, 1, step0, nchunk);
