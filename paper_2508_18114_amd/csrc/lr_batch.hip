@@ -192,14 +192,6 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
   auto work = [&](const lr_traj_t& x) {
     return (double)x.nsteps * x.model.d_q * x.model.d_r * x.model.d_f * x.M;
   };
-  // packed footprint class: 0 if two workgroups fit a CU's LDS, 1 if only one does
-  auto fclass = [&](const lr_traj_t& x) {
-    const int dmax = std::max(std::max(x.model.d_q, x.model.d_r), x.model.d_f);
-    return lrk::packed_lds_elems(x.model.d_q * x.model.d_f, x.M, dmax, x.model.kind) * sizeof(double2) >
-                   lrk::kPackedLdsMax / 2
-               ? 1
-               : 0;
-  };
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
   // packed trajectories first, largest work first; then one precision mode
@@ -207,12 +199,10 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     const bool px = packs(trajs[x]), py = packs(trajs[y]);
     if (px != py) return px;
-    if (px) {  // kernel families together (kind 2 last, then by arithmetic mode), then footprint class
+    if (px) {  // kernel families together: kind 2 last, then by arithmetic mode
       const bool nx = trajs[x].model.kind == LR_MODEL_NORMAL, ny = trajs[y].model.kind == LR_MODEL_NORMAL;
       if (nx != ny) return ny;
       if (trajs[x].precision != trajs[y].precision) return trajs[x].precision < trajs[y].precision;
-      const int cx = fclass(trajs[x]), cy = fclass(trajs[y]);
-      if (cx != cy) return cx < cy;
       return work(trajs[x]) > work(trajs[y]);
     }
     if (trajs[x].precision != trajs[y].precision) return trajs[x].precision < trajs[y].precision;
@@ -465,9 +455,10 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
     const int nm = b->tr[t].model.kind == LR_MODEL_NORMAL, prec = b->tr[t].precision;
     const int gm = nm ? -1 : (prec == LR_FP64 ? (b->mfma64 && !b->adaptive ? 0 : -1) : prec);
     lr_batch::Group g{t, t, 0, 0, 0, prec, 0, 0, 0, 1, 2, nm, gm, 2};
-    const bool big = b->lds[t] > lrk::kPackedLdsMax / 2;  // footprint class (see lr_batch_init)
+    // one launch for the family, sized by its largest LDS footprint (launches split by footprint
+    // class, in order on one stream or concurrently on two, measured slower on mixed batches)
     while (t < b->n && b->packed[t] && (b->tr[t].model.kind == LR_MODEL_NORMAL) == (nm != 0) &&
-           b->tr[t].precision == prec && (b->lds[t] > lrk::kPackedLdsMax / 2) == big) {
+           b->tr[t].precision == prec) {
       g.kp = std::max(g.kp, lrk::packed_kp(b->tr[t].M, b->tr[t].model.kind));
       g.slots = std::max(g.slots, lrk::mg_slots(b->tr[t].M));
       g.lds = std::max(g.lds, b->lds[t]);
@@ -590,7 +581,7 @@ int enqueue(lr_batch* b) {
   }
   if (hipGetLastError() != hipSuccess) return LR_ERR_HIP;
   // packed kernel families run concurrently, the first on the batch stream and each further one on a
-  // forked stream; the footprint classes of one family run one after the other on its stream
+  // forked stream
   int nfam = 0, prev_fam = -1;
   std::vector<int> joins;
   // join the forked streams back into the batch stream (before any spread group: its cooperative

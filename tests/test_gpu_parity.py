@@ -1137,13 +1137,13 @@ def test_packed_and_adaptive_few_layers(lr, d_r, M):
 def test_graph_replays_equal_eager_run(lr):
     """A packed batch (several chunks and records) captured once and replayed three times, with eager
     work (state resets, another batch) between the replays: every replay bitwise equals the eager run;
-    the same for an adaptive batch and for a batch of three kernel families and two footprint classes
-    (launch sequences forked onto streams of their own and joined back inside the capture)."""
+    the same for an adaptive batch and for a batch of three kernel families (launch sequences forked
+    onto streams of their own and joined back inside the capture)."""
     import torch
     for adaptive in (None, (1e-8, 1e-11), "families"):
         if adaptive == "families":
-            # three kernel families (FP64, FP32, BF16x3: forked streams inside the capture) and two
-            # footprint classes of the FP64 family (M = 32 holds one workgroup per CU)
+            # three kernel families (FP64, FP32, BF16x3: forked streams inside the capture), the FP64
+            # one with a large-footprint member (M = 32 holds one workgroup per CU)
             items = _batch_items(lr, BATCH_SPECS[:3] + [((8, 4, 5), 32, "g", 40, 10, 6)])
             items[0]["precision"], items[1]["precision"] = 1, 2
             adaptive = None
