@@ -46,6 +46,9 @@ def parse():
                     help="with --packed-sample: arithmetic of the Gram terms (0 FP64, 1 FP32, 2 BF16x3)")
     ap.add_argument("--packed-mfma64", action="store_true",
                     help="with --packed-sample: FP64 Gram terms on the matrix cores instead of the vector ALU")
+    ap.add_argument("--paper-setup", type=int, default=0, metavar="PULSES",
+                    help="only run the paper's own set-up (normal-mode basis, N=2000, M=20, drive frame, "
+                         "tau=40 ns, adaptive steps) alone and for PULSES pulses x g/e, and print wall times")
     ap.add_argument("--config4-subset", type=int, default=0, metavar="PULSES",
                     help="only run configuration 4 to completion on a stratified subset (PULSES pulses x g/e "
                          "per (d_r, M) stratum) and print its rate")
@@ -482,6 +485,62 @@ def config4_subset(lr, I, torch, per_stratum):
                         f"({steps:.3g} of the configuration's {total:.3g} trajectory-steps), spread schedule"}
 
 
+def paper_setup(lr, I, torch, n_pulses, rtol=1e-8, atol=1e-10):
+    """The paper's own set-up end to end: its Hamiltonian in the resonator-filter normal-mode basis at
+    its size (N_t = 5, lower mode 100, upper mode 4: N = 2000), M = 20, the frame rotating at the
+    drive, tau = 40 ns, adaptive Dormand-Prince steps.  n_pulses stepwise pulses (the square start of
+    the SPSA loop and seeded variations of it) x g/e in one packed adaptive batch; also one pulse (g and
+    e) alone.  Context only: the paper's figure for this workload is a CPU wall time per trajectory."""
+    import numpy as np
+    from paper_2508_18114_amd import serve, transmon
+    nm = transmon.paper_model_normal(5, 100, 4)
+    rng = np.random.default_rng(21)
+    T, nh, grid = 40.0, 4, 0.5
+
+    nseg = 8  # tau in segments of 5 ns (one adaptive batch each, continuing the state; progress lines)
+
+    def run(npulse, label):
+        items = []
+        for k in range(npulse):
+            theta = serve.square_start(nm, nh) * (1.0 + (0.3 * rng.uniform(-1, 1, 2 * nh) if k else 0.0))
+            pp = I.stepwise_pulse(serve.heights_from(theta), T, sigma=0.5,
+                                  w_d=transmon.PAPER_W_DRIVE).replace(frame=I.FRAME_DRIVE)
+            for which in ("g", "e"):
+                items.append(dict(model=nm, M=20, pulse=pp, dt=grid, nsteps=int(T / grid) // nseg, obs_stride=1,
+                                  B=lr.to_device(I.initial_state(nm, 20, which, 700 + k, I.PAPER_PAD_SCALE))))
+        el, acc_t, rej_t = 0.0, np.zeros(len(items)), np.zeros(len(items))
+        for seg in range(nseg):
+            for it in items:
+                it["step0"] = seg * it["nsteps"]
+                it["obs"] = torch.zeros((it["nsteps"] + 1, 6 + nm.d_q), dtype=torch.float64, device="cuda")
+            b = lr.Batch(items, packed=True, adaptive=(rtol, atol))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.run()
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t0
+            rc, codes, _ = b.status()
+            acc, rej = b.adaptive_stats()
+            b.close()
+            if rc != lr.LR_OK:
+                raise RuntimeError(f"paper set-up failed: {lr.lr_strerror(rc)}")
+            acc_t += np.asarray(acc)
+            rej_t += np.asarray(rej)
+            print(f"[paper set-up {label}] {(seg + 1) * T / nseg:.0f} ns done, {el:.1f} s, steps per trajectory "
+                  f"{np.mean(acc_t):.0f} accepted + {np.mean(rej_t):.0f} rejected", file=sys.stderr, flush=True)
+        return el, float(np.mean(acc_t)), float(np.mean(rej_t))
+
+    el1, a1, r1 = run(1, "one pulse")
+    eln, an, rn = run(n_pulses, f"{n_pulses} pulses")
+    return {"single_pair_wall_s": el1, "single_pair_steps": [a1, r1],
+            "batch_trajectories": 2 * n_pulses, "batch_wall_s": eln, "batch_steps_mean": [an, rn],
+            "batch_wall_per_trajectory_s": eln / (2 * n_pulses),
+            "workload": f"the paper's Hamiltonian in its normal-mode basis, N_t=5, lower mode 100, upper mode 4 "
+                        f"(N=2000), M=20, drive frame, tau=40 ns, adaptive Dormand-Prince (rtol {rtol}, atol "
+                        f"{atol}), records every {grid} ns, in {nseg} batches of {T / nseg:.0f} ns; one pulse x g/e "
+                        f"alone, and {n_pulses} pulses x g/e in one packed adaptive batch"}
+
+
 def validity_study(lr, I, torch):
     """Supplement S1.B on the small readout model (N=200, flat-top drive, 1e4
     steps, padding weight 1e-5): the control quantity p_M/p_1 and the purity
@@ -695,6 +754,9 @@ def main():
         return
     if a.apply_sample > 0:
         print(json.dumps(apply_sample(lr, I, torch, a.apply_sample)), flush=True)
+        return
+    if a.paper_setup > 0:
+        print(json.dumps(paper_setup(lr, I, torch, a.paper_setup)), flush=True)
         return
     if a.config4_subset > 0:
         print(json.dumps(config4_subset(lr, I, torch, a.config4_subset)), flush=True)

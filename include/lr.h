@@ -73,8 +73,9 @@ typedef struct { double re, im; } lr_c64;
  *   L_1 = sqrt(kappa_f) f moves the state across resonator layers and raises
  *   as well as lowers; -1/2 L_1^ L_1 is applied as the product of the
  *   truncated operators.  In the drive frame every creation term of f carries
- *   e^{i w_d t} and every annihilation term e^{-i w_d t}.  Packed fixed-step
- *   RK4 batches only (LR_ERR_ARG elsewhere), FP64, d_q <= LR_MAX_DQ.
+ *   e^{i w_d t} and every annihilation term e^{-i w_d t}.  Packed batches
+ *   only, fixed RK4 or adaptive steps (LR_ERR_ARG elsewhere), FP64,
+ *   d_q <= LR_MAX_DQ.
  * Kinds 0 and 1: L_1 = sqrt(kappa_f) f; every kind: L_2 = sqrt(gamma_1) b, b
  * the ladder sum_n sqrt(n) |n-1><n| of the transmon levels. */
 #define LR_MODEL_DUFFING 0

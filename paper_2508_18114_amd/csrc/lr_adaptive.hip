@@ -69,14 +69,19 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
   __shared__ int s_flag;
   __shared__ double s_nt[kMaxDq * kMaxDq];
   __shared__ double2 s_ph[2 * kMaxDq + 3];
+  constexpr bool NM = MK == 2;  // normal-mode model: the layer window and Gram terms of packed_body
+  constexpr int NTILE = NM ? 9 : 4;
   const int tid = threadIdx.x;
   const int M = T.M, MM = M * M, L = T.L, d_f = T.d_f, d_q = T.d_q, d_r = T.d_r;
-  const int LM = L * M, C3 = 3 * M;
-  const size_t NM = (size_t)T.N * M;
+  const int LM = L * M, CT = (NM ? 4 : 3) * M;
+  const size_t NM_ = (size_t)T.N * M;
   const double sk = sqrt(T.kappa), sg = sqrt(T.gamma);
-  double2* Aug = lds;
-  double2* Ot = lds + 3 * LM;
-  double2* Wl = lds + (4 * LM > 3 * MM ? 4 * LM : 3 * MM);
+  const int areg = (NM ? 7 : 3) * MM;
+  double2* St = lds;                               // Gram terms as formed (M x CT)
+  double2* Aug = NM ? lds + 4 * MM : lds;          // M x 3M elimination
+  double2* Ot = lds + (NM ? 7 : 3) * LM;           // output layer r (kind 2: and r - 1 in Op)
+  double2* Op = lds + 8 * LM;
+  double2* Wl = lds + (NTILE * LM > areg ? NTILE * LM : areg);
   double* s_drv = reinterpret_cast<double*>(Wl + 2 * MM);  // drive value and frame phases of the pass
   double2* s_prow = Wl + 2 * MM + 10 * kTDriveWin;
   double2* hd = s_prow + 3 * M;
@@ -87,14 +92,15 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
   if (tid == 0) s_flag = *T.status;
   for (int rl = tid; rl < L; rl += kTW) {
     const int q = rl / d_f, f = rl - q * d_f;
-    const double eq = MK == 1 ? T.Et[q] - (ROT ? T.w_d * q : 0.0) : T.w_q * q + 0.5 * T.alpha * q * (q - 1);
-    hd[rl] = make_double2(eq + T.w_f * f, -0.5 * (T.kappa * f + T.gamma * q));
+    const double eq = MK >= 1 ? T.Et[q] - (ROT ? T.w_d * q : 0.0) : T.w_q * q + 0.5 * T.alpha * q * (q - 1);
+    const double ff = NM ? T.nm[0] * T.nm[0] * (f + 1 < d_f ? f + 1.0 : 0.0) + T.nm[3] * T.nm[3] * f : (double)f;
+    hd[rl] = make_double2(eq + T.w_f * f, -0.5 * (T.kappa * ff + T.gamma * q));
     coef[rl] = 1.0;
     coef[L + rl] = (f + 1 < d_f) ? sk * sqrt((double)(f + 1)) : 0.0;
     coef[2 * L + rl] = (q + 1 < d_q) ? sg * sqrt((double)(q + 1)) : 0.0;
   }
   for (int k = tid; k <= max(max(d_q, d_r), d_f); k += kTW) sq[k] = sqrt((double)k);
-  if constexpr (MK == 1)
+  if constexpr (MK >= 1)
     for (int i = tid; i < d_q * d_q; i += kTW) s_nt[i] = T.ntq[i];
   __syncthreads();
   if (s_flag != 0) return;
@@ -103,19 +109,51 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
   const int NGe = kTW / M;
   const int ej = tid % M, eg = tid / M;
   const bool eact = eg < NGe;
-  const int NGp = kTW / C3, KPe = packed_kpe(M, C3);
-  const int pc = tid % C3, pg = tid / C3, pi0 = pg * KPe;
+  const int NGp = kTW / CT, KPe = packed_kpe(M, CT);
+  const int pc = tid % CT, pg = tid / CT, pi0 = pg * KPe;
   const bool pact = pg < NGp && pi0 < M;
   const int pkind = pc / M, pcc = pc - pkind * M;
-  const PackedMap PM{M, C3, L, d_f, KPe, pc, pi0, pkind, pcc, pact};
+  const PackedMap PM{M, CT, L, d_f, KPe, pc, pi0, pkind, pcc, pact};
   double2 acc[KP];
   auto zero_terms = [&]() {
 #pragma unroll
     for (int k = 0; k < KP; ++k) acc[k] = make_double2(0.0, 0.0);
   };
+  // Gram terms of the output layer r in Ot (kind 2: and of the pair (Op, Ot)), then (kind 2) the
+  // output tiles swap so that Op holds layer r
+  auto add_terms = [&](int r) {
+    packed_terms<KP>(acc, PM, Ot, coef);
+    if constexpr (NM) {
+      if (r > 0) packed_terms_q<KP>(acc, PM, Ot, Op, sk * sq[r]);
+    }
+  };
+  auto swap_out = [&]() {
+    if constexpr (NM) {
+      double2* t = Ot;
+      Ot = Op;
+      Op = t;
+    }
+  };
+  // W_k of the state whose Gram terms the threads hold, for a right-hand side at time t_use
+  auto solve = [&](bool want_fro2, double* fro2, double t_use) -> int {
+    if constexpr (NM) {
+      const int rc = packed_store<KP>(acc, PM, St, s_red, &s_flag, want_fro2, fro2);
+      if (rc) return rc;
+      packed_form_c1(St, Aug, M, T.nm, ROT ? frame_phase(T.w_d, t_use) : make_double2(1.0, 0.0));
+      return packed_eliminate(Aug, Wl, s_prow, M);
+    } else {
+      return packed_solve<KP>(acc, PM, Aug, Wl, s_prow, s_red, &s_flag, want_fro2, fro2);
+    }
+  };
+  auto jump_tile = [&](double2* dst, const double2* ym, const double2* y0, const double2* yp, int r, double2 e1j) {
+    for (int e = tid; e < LM; e += kTW) {
+      const int rl = e / M, j = e - rl * M;
+      dst[e] = packed_jump_nm(T, ym, y0, yp, sq, r, rl, rl % d_f, j, e1j);
+    }
+  };
 
-  // Gram terms and W of the state in `src` (and optional copy to dst); fro2 of it
-  auto gram_pass = [&](const g_double2* src, g_double2* dst, double* fro2) -> int {
+  // Gram terms and W of the state in `src` (and optional copy to dst), W for time t_use; fro2 of it
+  auto gram_pass = [&](const g_double2* src, g_double2* dst, double* fro2, double t_use) -> int {
     zero_terms();
     for (int r = 0; r < d_r; ++r) {
       __syncthreads();
@@ -125,14 +163,15 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
         if (dst) st_g(dst + (size_t)r * LM + e, v);
       }
       __syncthreads();
-      packed_terms<KP>(acc, PM, Ot, coef);
+      add_terms(r);
+      swap_out();
     }
-    return packed_solve<KP>(acc, PM, Aug, Wl, s_prow, s_red, &s_flag, fro2 != nullptr, fro2);
+    return solve(fro2 != nullptr, fro2, t_use);
   };
 
   if (prologue) {  // Gram of the initial state for its observation record
     double f2 = 0.0;
-    const int rc = gram_pass(gBb, nullptr, &f2);
+    const int rc = gram_pass(gBb, nullptr, &f2, A.st[0]);
     if (rc) {
       if (tid == 0) report(T, rc, 0);
       return;
@@ -151,15 +190,15 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
   int k1slot = (int)A.cnt[2];
   int k1valid = (int)A.cnt[3];
   g_double2* gS[2] = {(g_double2*)T.S0, (g_double2*)T.S1};
-  auto Kbuf = [&](int slot) { return (g_double2*)(A.K + (size_t)slot * NM); };
+  auto Kbuf = [&](int slot) { return (g_double2*)(A.K + (size_t)slot * NM_); };
   const g_double2* ysrc = gBb;  // where y lives (B_n, or the accepted Y_7 until copied)
   int code = 0;
 
   // One pass: k = f(ts, Y) with Y = `in` (W of Y in Wl), k stored to slot
   // kslot[s - 1]; mode s < 7: Y_{s+1} = y + hc sum_{j <= s} a_{s+1,j} k_j to out,
-  // with its Gram terms and W; s == 7: the error sum.
+  // with its Gram terms and W (for the next pass's time t_next); s == 7: the error sum.
   auto stage_pass = [&](int s, double ts, double hc, const g_double2* in, g_double2* out, const int* kslot,
-                        double* errsum) -> int {
+                        double* errsum, double t_next) -> int {
     __syncthreads();
     if (tid == 0) {
       s_drv[0] = drive_at(T, ts);
@@ -169,22 +208,48 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
       s_drv[3] = p2.x;
       s_drv[4] = p2.y;
     }
-    if constexpr (MK == 1 && ROT)
+    if constexpr (MK >= 1 && ROT)
       if (tid < 2 * d_q + 3) s_ph[tid] = frame_phase((tid - d_q - 1) * T.w_d, ts);
-    double2* Yp = lds;
-    double2* Yc = lds + LM;
-    double2* Yn = lds + 2 * LM;
+    double2 *Ym2, *Yp, *Yc, *Yn, *Yp2, *Y1c, *Y1n;
+    if constexpr (NM) {
+      Ym2 = lds;
+      Yp = lds + LM;
+      Yc = lds + 2 * LM;
+      Yn = lds + 3 * LM;
+      Yp2 = lds + 4 * LM;
+      Y1c = lds + 5 * LM;
+      Y1n = lds + 6 * LM;
+      Ot = lds + 7 * LM;
+      Op = lds + 8 * LM;
+    } else {
+      Ym2 = Yp2 = Y1c = Y1n = lds;
+      Yp = lds;
+      Yc = lds + LM;
+      Yn = lds + 2 * LM;
+    }
     for (int e = tid; e < LM; e += kTW) Yc[e] = ld_g(in + e);
     if (d_r > 1)
       for (int e = tid; e < LM; e += kTW) Yn[e] = ld_g(in + LM + e);
+    if constexpr (NM)
+      if (d_r > 2)
+        for (int e = tid; e < LM; e += kTW) Yp2[e] = ld_g(in + 2 * LM + e);
     __syncthreads();
     const double drv = s_drv[0];
     const double2 e1 = make_double2(s_drv[1], s_drv[2]), e2 = make_double2(s_drv[3], s_drv[4]);
+    const double2 e1j = ROT ? e1 : make_double2(1.0, 0.0);  // phase of the kind-2 filter jump
+    if constexpr (NM) {
+      jump_tile(Y1c, Yp, Yc, Yn, 0, e1j);
+      __syncthreads();
+    }
     g_double2* kout = Kbuf(kslot[s - 1]);
     double es = 0.0;
     zero_terms();
     for (int r = 0; r < d_r; ++r) {
+      const double him = NM ? -0.5 * T.kappa *
+                                  (T.nm[1] * T.nm[1] * (r + 1 < d_r ? r + 1.0 : 0.0) + T.nm[2] * T.nm[2] * r)
+                            : 0.0;
       if (eact) {
+        const double2* A1 = NM ? Y1c : Yc;  // source tile of the filter jump rows
         for (int rb = eg; rb < L; rb += kTRowBlock * NGe) {
           double2 a1[kTRowBlock], a2[kTRowBlock];
           int s1[kTRowBlock], s2[kTRowBlock];
@@ -192,14 +257,14 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
           for (int k = 0; k < kTRowBlock; ++k) {
             a1[k] = a2[k] = make_double2(0.0, 0.0);
             const int rl = min(rb + k * NGe, L - 1);
-            s1[k] = min(rl + 1, L - 1) * M;
+            s1[k] = (NM ? rl : min(rl + 1, L - 1)) * M;
             s2[k] = min(rl + d_f, L - 1) * M;
           }
           for (int i = 0; i < M; ++i) {
             const double2 w1 = Wl[i * M + ej], w2 = Wl[MM + i * M + ej];
 #pragma unroll
             for (int k = 0; k < kTRowBlock; ++k) {
-              a1[k] = cmac(a1[k], Yc[s1[k] + i], w1);
+              a1[k] = cmac(a1[k], A1[s1[k] + i], w1);
               a2[k] = cmac(a2[k], Yc[s2[k] + i], w2);
             }
           }
@@ -208,12 +273,16 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
             const int rl = rb + k * NGe;
             if (rl < L) {
               const int q = rl / d_f, f = rl - q * d_f;
-              const double2 a = cfma(coef[L + rl], a1[k], cscale(coef[2 * L + rl], a2[k]));
+              const double2 a = cfma(NM ? 1.0 : coef[L + rl], a1[k], cscale(coef[2 * L + rl], a2[k]));
               double2 z;
-              if constexpr (MK == 1)
+              if constexpr (MK == 2) {
+                const double2* Yw[5] = {Ym2, Yp, Yc, Yn, Yp2};
+                z = packed_stencil_nm<ROT>(T, Yw, sq, hd, s_nt, s_ph, d_q + 1, r, rl, q, f, ej, drv, him);
+              } else if constexpr (MK == 1) {
                 z = packed_stencil_tm<ROT>(T, Yp, Yc, Yn, sq, hd, s_nt, s_ph, d_q + 1, r, rl, q, f, ej, drv);
-              else
+              } else {
                 z = packed_stencil<ROT>(T, Yp, Yc, Yn, sq, hd, r, rl, q, f, ej, drv, e1, e2);
+              }
               const double2 kk = make_double2(z.y + 0.5 * a.x, -z.x + 0.5 * a.y);
               const size_t gi = ((size_t)r * L + rl) * M + ej;
               st_g(kout + gi, kk);
@@ -238,14 +307,33 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
         }
       }
       __syncthreads();
-      if (r + 2 < d_r)
-        for (int e = tid; e < LM; e += kTW) Yp[e] = ld_g(in + (size_t)(r + 2) * LM + e);
-      if (s < 7) packed_terms<KP>(acc, PM, Ot, coef);
+      // the next input layer (r + 2; kind 2: r + 3) replaces the oldest one; kind 2 also forms the
+      // filter jump of layer r + 1
+      const int rnx = NM ? r + 3 : r + 2;
+      double2* dstl = NM ? Ym2 : Yp;
+      if (rnx < d_r)
+        for (int e = tid; e < LM; e += kTW) dstl[e] = ld_g(in + (size_t)rnx * LM + e);
+      if constexpr (NM)
+        if (r + 1 < d_r) jump_tile(Y1n, Yc, Yn, Yp2, r + 1, e1j);
+      if (s < 7) add_terms(r);
       __syncthreads();
-      double2* tp = Yp;
-      Yp = Yc;
-      Yc = Yn;
-      Yn = tp;
+      if constexpr (NM) {
+        double2* tq = Ym2;
+        Ym2 = Yp;
+        Yp = Yc;
+        Yc = Yn;
+        Yn = Yp2;
+        Yp2 = tq;
+        tq = Y1c;
+        Y1c = Y1n;
+        Y1n = tq;
+        swap_out();
+      } else {
+        double2* tp = Yp;
+        Yp = Yc;
+        Yc = Yn;
+        Yn = tp;
+      }
     }
     if (s == 7) {  // fixed-order workgroup sum
       for (int off = 32; off > 0; off >>= 1) es += __shfl_xor(es, off);
@@ -257,7 +345,7 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
       *errsum = tot;
       return 0;
     }
-    return packed_solve<KP>(acc, PM, Aug, Wl, s_prow, s_red, &s_flag, false, nullptr);
+    return solve(false, nullptr, t_next);
   };
 
   int64_t attempts = 0;
@@ -270,8 +358,8 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
     }
     int kslot[7] = {k1slot, 1, 2, 3, 4, 5, 6 - k1slot};
     if (!k1valid) {
-      int rc = gram_pass(gBb, nullptr, nullptr);
-      if (!rc) rc = stage_pass(1, t, hc, gBb, gS[0], kslot, nullptr);
+      int rc = gram_pass(gBb, nullptr, nullptr, t);
+      if (!rc) rc = stage_pass(1, t, hc, gBb, gS[0], kslot, nullptr, t + kDpC[1] * hc);
       if (rc) {
         code = rc;
         break;
@@ -281,6 +369,10 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
       const g_double2* k1 = Kbuf(k1slot);
       const bool copy = ysrc != gBb;
       zero_terms();
+      if constexpr (NM) {
+        Ot = lds + 7 * LM;
+        Op = lds + 8 * LM;
+      }
       for (int r = 0; r < d_r; ++r) {
         __syncthreads();
         for (int e = tid; e < LM; e += kTW) {
@@ -292,10 +384,11 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
           Ot[e] = o;
         }
         __syncthreads();
-        packed_terms<KP>(acc, PM, Ot, coef);
+        add_terms(r);
+        swap_out();
       }
       ysrc = gBb;
-      const int rc = packed_solve<KP>(acc, PM, Aug, Wl, s_prow, s_red, &s_flag, false, nullptr);
+      const int rc = solve(false, nullptr, t + kDpC[1] * hc);
       if (rc) {
         code = rc;
         break;
@@ -303,14 +396,15 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
     }
     int rc = 0;
     // stage inputs alternate: Y_2, Y_4, Y_6 in S0; Y_3, Y_5, Y_7 in S1
-    for (int s = 2; s <= 6 && !rc; ++s) rc = stage_pass(s, t + kDpC[s - 1] * hc, hc, gS[s & 1], gS[(s + 1) & 1], kslot, nullptr);
+    for (int s = 2; s <= 6 && !rc; ++s)
+      rc = stage_pass(s, t + kDpC[s - 1] * hc, hc, gS[s & 1], gS[(s + 1) & 1], kslot, nullptr, t + kDpC[s] * hc);
     double es = 0.0;
-    if (!rc) rc = stage_pass(7, t + hc, hc, gS[1], nullptr, kslot, &es);
+    if (!rc) rc = stage_pass(7, t + hc, hc, gS[1], nullptr, kslot, &es, t + hc);
     if (rc) {
       code = rc;
       break;
     }
-    const double err = sqrt(es / (double)NM);
+    const double err = sqrt(es / (double)NM_);
     if (err <= 1.0) {
       t = last ? t_end : t + hc;
       ++nacc;
@@ -325,7 +419,11 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
   }
   // the state back in B_n, its Gram for the record
   double f2 = 0.0;
-  const int rc = code ? 0 : gram_pass(ysrc, ysrc != gBb ? gBb : nullptr, &f2);
+  if constexpr (NM) {
+    Ot = lds + 7 * LM;
+    Op = lds + 8 * LM;
+  }
+  const int rc = code ? 0 : gram_pass(ysrc, ysrc != gBb ? gBb : nullptr, &f2, t);
   if (tid == 0) {
     if (code || rc) report(T, code ? code : rc, step0);
     A.st[0] = t;
@@ -360,12 +458,34 @@ __global__ __launch_bounds__(kTW) void k_dp5_prologue(const TrajDev* __restrict_
                                                       int64_t nchunk) {
   dp5_body<KP, false>(trajs[blockIdx.x], ads[blockIdx.x], 1, step0, nchunk);
 }
+// The normal-mode model (its own kernels, as in the fixed-step schedule).
+template <int KP>
+__global__ __launch_bounds__(kTW, (KP <= 8 ? 2 : 1)) void k_dp5_nm(const TrajDev* __restrict__ trajs,
+                                                                   const AdaptDev* __restrict__ ads, int64_t step0,
+                                                                   int64_t nchunk) {
+  const TrajDev& T = trajs[blockIdx.x];
+  if (T.frame)
+    dp5_body<KP, true, 2>(T, ads[blockIdx.x], 0, step0, nchunk);
+  else
+    dp5_body<KP, false, 2>(T, ads[blockIdx.x], 0, step0, nchunk);
+}
+template <int KP>
+__global__ __launch_bounds__(kTW, (KP <= 8 ? 2 : 1)) void k_dp5_nm_prologue(const TrajDev* __restrict__ trajs,
+                                                                            const AdaptDev* __restrict__ ads,
+                                                                            int64_t step0, int64_t nchunk) {
+  const TrajDev& T = trajs[blockIdx.x];
+  if (T.frame)
+    dp5_body<KP, true, 2>(T, ads[blockIdx.x], 1, step0, nchunk);
+  else
+    dp5_body<KP, false, 2>(T, ads[blockIdx.x], 1, step0, nchunk);
+}
 
 template <int I = 0>
-inline const void* dp5_kernel(int kp, bool prologue) {
+inline const void* dp5_kernel(int kp, bool prologue, bool nm = false) {
   if constexpr (I + 1 < (int)(sizeof(kPackedKP) / sizeof(int))) {
-    if (kp > kPackedKP[I]) return dp5_kernel<I + 1>(kp, prologue);
+    if (kp > kPackedKP[I]) return dp5_kernel<I + 1>(kp, prologue, nm);
   }
+  if (nm) return prologue ? (const void*)k_dp5_nm_prologue<kPackedKP[I]> : (const void*)k_dp5_nm<kPackedKP[I]>;
   return prologue ? (const void*)k_dp5_prologue<kPackedKP[I]> : (const void*)k_dp5<kPackedKP[I]>;
 }
 

@@ -230,9 +230,8 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
         delete b;
         return LR_ERR_ARG;
       }
-  for (int k = 0; k < n; ++k)  // the eigenbasis models run packed; the normal-mode one with fixed steps only
-    if ((b->tr[k].model.kind != LR_MODEL_DUFFING && !b->packed[k]) ||
-        (b->tr[k].model.kind == LR_MODEL_NORMAL && adaptive)) {
+  for (int k = 0; k < n; ++k)  // the eigenbasis models run packed
+    if (b->tr[k].model.kind != LR_MODEL_DUFFING && !b->packed[k]) {
       delete b;
       return LR_ERR_ARG;
     }
@@ -426,6 +425,8 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
                                (int)max_lds_packed) != hipSuccess ||
 
            hipFuncSetAttribute(lrk::dp5_kernel(kp, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)max_lds_packed) != hipSuccess ||
+           hipFuncSetAttribute(lrk::dp5_kernel(kp, pro != 0, true), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)max_lds_packed) != hipSuccess))
         return LR_ERR_HIP;
   for (int gm = 0; gm <= 2; ++gm)  // the matrix-core Gram kernels of the packed schedule
@@ -632,8 +633,8 @@ int enqueue(lr_batch* b) {
         if (b->adaptive) {
           const lrk::AdaptDev* aptr = ads + g.begin;
           void* pargs[] = {(void*)&ptr, (void*)&aptr, (void*)&step0, (void*)&nchunk};
-          err = hipLaunchKernel(lrk::dp5_kernel(g.kp, prologue != 0), dim3(g.wgs), dim3(lrk::kTW), pargs, g.lds,
-                                gs);
+          err = hipLaunchKernel(lrk::dp5_kernel(g.kp, prologue != 0, g.nm != 0), dim3(g.wgs), dim3(lrk::kTW), pargs,
+                                g.lds, gs);
         } else {
           void* pargs[] = {(void*)&ptr, (void*)&step0, (void*)&nchunk};
           err = hipLaunchKernel(lrk::packed_kernel(g.kp, prologue != 0, g.nm != 0, g.gm, g.slots), dim3(g.wgs),

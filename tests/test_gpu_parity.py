@@ -1387,17 +1387,40 @@ def test_normal_model_few_layers(lr, d_l, d_u, M, frame):
     _assert_obs(it0["obs"].cpu().numpy(), ref0, "kind-0 trajectory beside the normal-mode one", tol0)
 
 
+@pytest.mark.parametrize("d_l,frame", [(8, 1), (3, 0), (1, 1)])
+def test_normal_model_adaptive_matches_oracle(lr, d_l, frame):
+    """The paper's own set-up: its Hamiltonian in the normal-mode basis with adaptive Dormand-Prince
+    steps (drive frame; also the lab frame and a single layer), against the oracle's adaptive
+    integration: the same accepted and rejected step counts (within 3) and the records."""
+    from oracle import adaptive
+    from paper_2508_18114_amd import transmon
+    m = _nm_model(4, d_l, 3, J=1.1, kappa_f=0.4, gamma_1=0.02, g=0.8)
+    p = I.stepwise_pulse(I.ghz(0.15) * np.array([1.0j, 0.8j]), 1.0, sigma=0.1,
+                         w_d=transmon.PAPER_W_DRIVE).replace(frame=frame)
+    dt, n, stride = (0.1, 8, 2) if frame else (0.02, 4, 2)
+    it = _tm_items(lr, m, 4, p, dt, n, stride, seed=230 + d_l)
+    b = lr.Batch([it], adaptive=(1e-9, 1e-12))
+    b.run()
+    rc, codes, _ = b.status()
+    assert rc == lr.LR_OK, codes
+    acc, rej = b.adaptive_stats()
+    _, ref, acc_o, rej_o = adaptive.integrate(m, p, 0.0, dt, n, it["B0"], 1e-9, 1e-12, obs_stride=stride)
+    print(f"[parity] normal-mode adaptive d_l={d_l} frame {frame}: steps gpu {acc[0]}+{rej[0]}, "
+          f"oracle {acc_o}+{rej_o}")
+    _assert_obs(it["obs"].cpu().numpy(), ref, f"normal-mode adaptive d_l={d_l} frame {frame}")
+    assert abs(acc[0] - acc_o) <= 3 and abs(rej[0] - rej_o) <= 3
+    b.close()
+
+
 def test_normal_model_rejections(lr):
-    """Kind 2 runs in packed fixed-step batches in FP64 only: a Context, a spread batch, an adaptive
-    batch and reduced precision are refused, and so is a non-finite S."""
+    """Kind 2 runs in packed batches (fixed or adaptive steps) in FP64 only: a Context, a spread batch
+    and reduced precision are refused, and so is a non-finite S."""
     m = _nm_model(3, 3, 3)
     p = I.flattop_pulse(0.05, 0.2)
     with pytest.raises(lr.LrError):
         lr.Context(m, 2)
     with pytest.raises(lr.LrError):
         lr.Batch([_tm_items(lr, m, 2, p, 1e-3, 10, 5)])
-    with pytest.raises(lr.LrError):
-        lr.Batch([_tm_items(lr, m, 2, p, 1e-3, 10, 5)], adaptive=(1e-8, 1e-10))
     it = _tm_items(lr, m, 2, p, 1e-3, 10, 5)
     it["precision"] = I.FP32
     with pytest.raises(lr.LrError):
