@@ -1387,6 +1387,24 @@ def test_normal_model_few_layers(lr, d_l, d_u, M, frame):
     _assert_obs(it0["obs"].cpu().numpy(), ref0, "kind-0 trajectory beside the normal-mode one", tol0)
 
 
+@pytest.mark.parametrize("M", [13, 20, 27, 32])
+def test_normal_model_large_ranks(lr, M):
+    """Kind 2 at the ranks of the bench and beyond (4M Gram-term columns: entry blocks of 5 to 16 rows,
+    the kernels held to two workgroups per CU up to blocks of 8), both frames, against the oracle."""
+    from paper_2508_18114_amd import transmon
+    m = _nm_model(4, 6, 4, J=1.1, kappa_f=0.5, gamma_1=0.05, g=0.8)
+    items = []
+    for frame in (0, 1):
+        p = I.stepwise_pulse(I.ghz(0.15) * np.array([1.0j, 0.6]), 0.2, sigma=0.02,
+                             w_d=transmon.PAPER_W_DRIVE).replace(frame=frame)
+        items.append(_tm_items(lr, m, M, p, 2e-4 if frame == 0 else 1e-3, 60, 30, seed=250 + M))
+    assert _run_packed(lr, items)[0] == lr.LR_OK
+    for it in items:
+        Bo, ref, tol = oracle_with_tol(m, it["pulse"], 0.0, it["dt"], it["nsteps"], it["B0"], 30)
+        _assert_obs(it["obs"].cpu().numpy(), ref, f"normal-mode M={M} frame {it['pulse'].frame}", tol)
+        assert np.max(np.abs(lr.from_device(it["B"]) - Bo)) <= 1e-10
+
+
 @pytest.mark.parametrize("d_l,frame", [(8, 1), (3, 0), (1, 1)])
 def test_normal_model_adaptive_matches_oracle(lr, d_l, frame):
     """The paper's own set-up: its Hamiltonian in the normal-mode basis with adaptive Dormand-Prince
