@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--paper-setup", type=int, default=0, metavar="PULSES",
                     help="only run the paper's own set-up (normal-mode basis, N=2000, M=20, drive frame, "
                          "tau=40 ns, adaptive steps) alone and for PULSES pulses x g/e, and print wall times")
+    ap.add_argument("--paper-setup-parts", type=int, default=100, metavar="P",
+                    help="workgroups per trajectory of the lone g/e pair of --paper-setup (layer-split packed "
+                         "kernel; 1: one workgroup)")
     ap.add_argument("--config4-subset", type=int, default=0, metavar="PULSES",
                     help="only run configuration 4 to completion on a stratified subset (PULSES pulses x g/e "
                          "per (d_r, M) stratum) and print its rate")
@@ -485,12 +488,14 @@ def config4_subset(lr, I, torch, per_stratum):
                         f"({steps:.3g} of the configuration's {total:.3g} trajectory-steps), spread schedule"}
 
 
-def paper_setup(lr, I, torch, n_pulses, rtol=1e-8, atol=1e-10):
+def paper_setup(lr, I, torch, n_pulses, rtol=1e-8, atol=1e-10, parts=100):
     """The paper's own set-up end to end: its Hamiltonian in the resonator-filter normal-mode basis at
     its size (N_t = 5, lower mode 100, upper mode 4: N = 2000), M = 20, the frame rotating at the
     drive, tau = 40 ns, adaptive Dormand-Prince steps.  n_pulses stepwise pulses (the square start of
     the SPSA loop and seeded variations of it) x g/e in one packed adaptive batch; also one pulse (g and
-    e) alone.  Context only: the paper's figure for this workload is a CPU wall time per trajectory."""
+    e) alone, each trajectory split over `parts` workgroups (layer ranges), and one workgroup per
+    trajectory in the batch.  Context only: the paper's figure for this workload is a CPU wall time per
+    trajectory."""
     import numpy as np
     from paper_2508_18114_amd import serve, transmon
     nm = transmon.paper_model_normal(5, 100, 4)
@@ -499,7 +504,7 @@ def paper_setup(lr, I, torch, n_pulses, rtol=1e-8, atol=1e-10):
 
     nseg = 8  # tau in segments of 5 ns (one adaptive batch each, continuing the state; progress lines)
 
-    def run(npulse, label):
+    def run(npulse, label, split=0):
         items = []
         for k in range(npulse):
             theta = serve.square_start(nm, nh) * (1.0 + (0.3 * rng.uniform(-1, 1, 2 * nh) if k else 0.0))
@@ -513,7 +518,7 @@ def paper_setup(lr, I, torch, n_pulses, rtol=1e-8, atol=1e-10):
             for it in items:
                 it["step0"] = seg * it["nsteps"]
                 it["obs"] = torch.zeros((it["nsteps"] + 1, 6 + nm.d_q), dtype=torch.float64, device="cuda")
-            b = lr.Batch(items, packed=True, adaptive=(rtol, atol))
+            b = lr.Batch(items, packed=True, adaptive=(rtol, atol), parts=split)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             b.run()
@@ -530,15 +535,16 @@ def paper_setup(lr, I, torch, n_pulses, rtol=1e-8, atol=1e-10):
                   f"{np.mean(acc_t):.0f} accepted + {np.mean(rej_t):.0f} rejected", file=sys.stderr, flush=True)
         return el, float(np.mean(acc_t)), float(np.mean(rej_t))
 
-    el1, a1, r1 = run(1, "one pulse")
+    el1, a1, r1 = run(1, f"one pulse, {parts} parts per trajectory", parts)
     eln, an, rn = run(n_pulses, f"{n_pulses} pulses")
-    return {"single_pair_wall_s": el1, "single_pair_steps": [a1, r1],
+    return {"single_pair_wall_s": el1, "single_pair_steps": [a1, r1], "single_pair_parts": parts,
             "batch_trajectories": 2 * n_pulses, "batch_wall_s": eln, "batch_steps_mean": [an, rn],
             "batch_wall_per_trajectory_s": eln / (2 * n_pulses),
             "workload": f"the paper's Hamiltonian in its normal-mode basis, N_t=5, lower mode 100, upper mode 4 "
                         f"(N=2000), M=20, drive frame, tau=40 ns, adaptive Dormand-Prince (rtol {rtol}, atol "
                         f"{atol}), records every {grid} ns, in {nseg} batches of {T / nseg:.0f} ns; one pulse x g/e "
-                        f"alone, and {n_pulses} pulses x g/e in one packed adaptive batch"}
+                        f"alone ({parts} workgroups per trajectory), and {n_pulses} pulses x g/e in one packed adaptive "
+                        f"batch (one workgroup per trajectory)"}
 
 
 def validity_study(lr, I, torch):
@@ -756,7 +762,7 @@ def main():
         print(json.dumps(apply_sample(lr, I, torch, a.apply_sample)), flush=True)
         return
     if a.paper_setup > 0:
-        print(json.dumps(paper_setup(lr, I, torch, a.paper_setup)), flush=True)
+        print(json.dumps(paper_setup(lr, I, torch, a.paper_setup, parts=a.paper_setup_parts)), flush=True)
         return
     if a.config4_subset > 0:
         print(json.dumps(config4_subset(lr, I, torch, a.config4_subset)), flush=True)

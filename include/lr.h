@@ -363,6 +363,22 @@ int lr_batch_init(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n);
  * register rows or LDS is lowered to the largest that fits.  Combined with the
  * other flags by |; the autotuner of the Python package searches it. */
 #define LR_BATCH_SPREAD_LAYERS(k) ((int32_t)((k) & 0xff) << 8)
+/* Layer-split packed trajectories, for latency when few trajectories are in
+ * flight: with LR_BATCH_PACKED (or in an adaptive batch), every LR_FP64
+ * packed trajectory runs on p workgroups (2..255, at most d_r; 0 or absent:
+ * one), each over a contiguous range of about d_r / p resonator layers.  After
+ * every pass the parts' Gram and cross terms are summed in a fixed order
+ * (partials, group barrier, a slice reduction per part, group barrier), and
+ * every part solves the same M x M system; model kind 2 pairs the layers across
+ * a part boundary after the part above has published its first layer.  The
+ * parts of a trajectory and of the batch's other split trajectories run
+ * co-resident (cooperative launches, as in the spread schedule; not captured by
+ * lr_batch_graph), and their bounded waits end in LR_ERR_TIMEOUT as there.
+ * The result depends on p only through the rounding of the sums over the parts
+ * (it agrees with the one-workgroup form to the FP64 tolerances of
+ * lr_integrate).  Reduced-precision trajectories stay one workgroup each.  A
+ * trajectory whose p parts cannot be co-resident: LR_ERR_ARG at lr_batch_bind. */
+#define LR_BATCH_PACKED_PARTS(p) ((int32_t)((p) & 0xff) << 16)
 int lr_batch_init_ex(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n, int32_t flags);
 /* Adaptive-step batch (main text, "Computational performance": the paper's
  * solver has an adaptive time step): every trajectory takes Dormand-Prince
@@ -371,12 +387,18 @@ int lr_batch_init_ex(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n, int3
  * entries of B and the step controller min(5, max(0.2, 0.9 err^(-1/5))).
  * For an adaptive trajectory, dt is the output grid and the first trial
  * step: it is integrated from t0 + step0 dt to t0 + (step0 + nsteps) dt and
- * recorded every obs_stride grid points (steps land on those times).  Every
+ * recorded every obs_stride grid points (steps land on those times and on no
+ * others, whatever the other trajectories of the batch; with obs_stride 0, on
+ * the end time only).  Every
  * trajectory must qualify for LR_BATCH_PACKED (LR_FP64, layer size), and
  * rtol, atol > 0; else LR_ERR_ARG.  A step size below 1e-14 max(1, |t|), or
  * more than 2^22 attempts within one output interval, stops the trajectory
  * with LR_ERR_STEP. */
 int lr_batch_init_adaptive(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n, double rtol, double atol);
+/* lr_batch_init_adaptive with schedule flags: 0, LR_BATCH_PACKED or
+ * LR_BATCH_PACKED_PARTS(p) (layer-split trajectories); other bits: LR_ERR_ARG. */
+int lr_batch_init_adaptive_ex(lr_batch_t** batch, const lr_traj_t* trajs, int32_t n, int32_t flags, double rtol,
+                              double atol);
 /* Accepted and rejected step counts of an adaptive batch after lr_batch_run
  * (arrays of n, caller order; synchronises).  LR_ERR_STATE for other batches. */
 int lr_batch_adaptive_stats(lr_batch_t* batch, int64_t* accepted, int64_t* rejected);

@@ -4,9 +4,11 @@
 // The paper integrates eq. "nosse" with an adaptive-timestep solver (main
 // text, "Computational performance").  Here every trajectory of a batch runs
 // in one workgroup, as in the packed schedule (lr_packed.hip), and carries its
-// own time t and step proposal h across launches; a launch advances it to the
-// next output time of its grid (t0 + (step0 + n) dt, records every obs_stride
-// grid steps).  One step from (t, y) with k_1 = f(t, y):
+// own time t and step proposal h across launches; a launch advances it to its
+// next record time at or after the launch's end (t0 + (step0 + n) dt, records
+// every obs_stride grid steps; with no records, the end of the integration),
+// so that its steps land on its own record times only.  A trajectory may also
+// be split over several workgroups (layer ranges, lr_packed.hip).  One step from (t, y) with k_1 = f(t, y):
 //   Y_2 = y + hc a_21 k_1                      (a light pass, no stencil)
 //   pass s = 2..6: k_s = f(t + c_s hc, Y_s),  Y_{s+1} = y + hc sum_j a_{s+1,j} k_j
 //   pass 7:        k_7 = f(t + hc, Y_7)  with Y_7 the fifth-order solution,
@@ -61,12 +63,13 @@ __global__ void k_dp5_reset(const TrajDev* __restrict__ trajs, const AdaptDev* _
   }
 }
 
-template <int KP, bool ROT, int MK = 0>
+template <int KP, bool ROT, int MK = 0, bool SPLIT = false>
 __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, int prologue, int64_t step0,
-                                         int64_t nchunk) {
+                                         int64_t nchunk, int part = 0) {
   extern __shared__ double2 lds[];
   __shared__ double s_red[kTW / 64];
   __shared__ int s_flag;
+  __shared__ int s_ok;
   __shared__ double s_nt[kMaxDq * kMaxDq];
   __shared__ double2 s_ph[2 * kMaxDq + 3];
   constexpr bool NM = MK == 2;  // normal-mode model: the layer window and Gram terms of packed_body
@@ -105,6 +108,18 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
   __syncthreads();
   if (s_flag != 0) return;
   if (!prologue && step0 >= T.nsteps) return;
+  // layers of this workgroup: all of them, or those of its part of a split trajectory
+  const int r_lo = SPLIT ? split_lo(part, T.P, d_r) : 0;
+  const int r_hi = SPLIT ? split_lo(part + 1, T.P, d_r) : d_r;
+  SplitSync SS{part, 0u, 0u, 0u};
+  auto ldS = [](const g_double2* p) -> double2 {
+    if constexpr (SPLIT) return ld_ag(p);
+    else return ld_g(p);
+  };
+  auto stS = [](g_double2* p, double2 v) {
+    if constexpr (SPLIT) st_ag(p, v);
+    else st_g(p, v);
+  };
 
   const int NGe = kTW / M;
   const int ej = tid % M, eg = tid / M;
@@ -124,7 +139,7 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
   auto add_terms = [&](int r) {
     packed_terms<KP>(acc, PM, Ot, coef);
     if constexpr (NM) {
-      if (r > 0) packed_terms_q<KP>(acc, PM, Ot, Op, sk * sq[r]);
+      if (r > r_lo) packed_terms_q<KP>(acc, PM, Ot, Op, sk * sq[r]);
     }
   };
   auto swap_out = [&]() {
@@ -133,6 +148,24 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
       Ot = Op;
       Op = t;
     }
+  };
+  // split trajectories: the Gram terms of the parts summed into every part (kind 2: with the pair
+  // across the upper boundary, its upper layer read from `upper`, after the part above has
+  // published it when `wait`); 0 or -8 (LR_ERR_TIMEOUT)
+  auto split_terms = [&](const g_double2* upper, bool wait) -> int {
+    if constexpr (SPLIT) {
+      if constexpr (NM) {
+        if (r_hi < d_r) {
+          __syncthreads();
+          if (wait && !split_wait_above(T, SS, &s_ok)) return -8;
+          for (int e = tid; e < LM; e += kTW) Ot[e] = ldS(upper + (size_t)r_hi * LM + e);
+          __syncthreads();
+          packed_terms_q<KP>(acc, PM, Ot, Op, sk * sq[r_hi]);
+        }
+      }
+      if (!split_sum<KP>(T, acc, PM, SS, &s_ok)) return -8;
+    }
+    return 0;
   };
   // W_k of the state whose Gram terms the threads hold, for a right-hand side at time t_use
   auto solve = [&](bool want_fro2, double* fro2, double t_use) -> int {
@@ -155,21 +188,22 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
   // Gram terms and W of the state in `src` (and optional copy to dst), W for time t_use; fro2 of it
   auto gram_pass = [&](const g_double2* src, g_double2* dst, double* fro2, double t_use) -> int {
     zero_terms();
-    for (int r = 0; r < d_r; ++r) {
+    for (int r = r_lo; r < r_hi; ++r) {
       __syncthreads();
       for (int e = tid; e < LM; e += kTW) {
-        const double2 v = ld_g(src + (size_t)r * LM + e);
+        const double2 v = ldS(src + (size_t)r * LM + e);
         Ot[e] = v;
-        if (dst) st_g(dst + (size_t)r * LM + e, v);
+        if (dst) stS(dst + (size_t)r * LM + e, v);
       }
       __syncthreads();
       add_terms(r);
       swap_out();
     }
+    if (const int rs = split_terms(src, false)) return rs;
     return solve(fro2 != nullptr, fro2, t_use);
   };
 
-  if (prologue) {  // Gram of the initial state for its observation record
+  if (!SPLIT && prologue) {  // Gram of the initial state for its observation record
     double f2 = 0.0;
     const int rc = gram_pass(gBb, nullptr, &f2, A.st[0]);
     if (rc) {
@@ -183,9 +217,13 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
     return;
   }
 
-  const int64_t n_end = min(step0 + nchunk, T.nsteps);
+  // the trajectory's next record time at or after the launch's end: its steps land on its own record
+  // times only, whatever the strides of the other trajectories of the batch (which set the launches)
+  const int64_t st = T.obs_stride, n_launch = min(step0 + nchunk, T.nsteps);
+  const int64_t n_end = st > 0 ? min(T.nsteps, (n_launch + st - 1) / st * st) : T.nsteps;
   const double t_end = T.t0 + (double)(T.step_base + n_end) * T.dt;
   double t = A.st[0], h = A.st[1];
+  const bool moves = t < t_end;  // false: an earlier launch has already reached t_end
   int64_t nacc = A.cnt[0], nrej = A.cnt[1];
   int k1slot = (int)A.cnt[2];
   int k1valid = (int)A.cnt[3];
@@ -227,24 +265,34 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
       Yc = lds + LM;
       Yn = lds + 2 * LM;
     }
-    for (int e = tid; e < LM; e += kTW) Yc[e] = ld_g(in + e);
-    if (d_r > 1)
-      for (int e = tid; e < LM; e += kTW) Yn[e] = ld_g(in + LM + e);
-    if constexpr (NM)
-      if (d_r > 2)
-        for (int e = tid; e < LM; e += kTW) Yp2[e] = ld_g(in + 2 * LM + e);
+    const g_double2* in0 = in + (size_t)r_lo * LM;
+    for (int e = tid; e < LM; e += kTW) Yc[e] = ldS(in0 + e);
+    if (r_lo + 1 < d_r)
+      for (int e = tid; e < LM; e += kTW) Yn[e] = ldS(in0 + LM + e);
+    if constexpr (SPLIT)
+      if (r_lo > 0)
+        for (int e = tid; e < LM; e += kTW) Yp[e] = ldS(in0 - LM + e);
+    if constexpr (NM) {
+      if (r_lo + 2 < d_r)
+        for (int e = tid; e < LM; e += kTW) Yp2[e] = ldS(in0 + 2 * LM + e);
+      if constexpr (SPLIT)
+        if (r_lo > 1)
+          for (int e = tid; e < LM; e += kTW) Ym2[e] = ldS(in0 - 2 * LM + e);
+    }
+    if constexpr (SPLIT)
+      if (s < 7) ++SS.c;
     __syncthreads();
     const double drv = s_drv[0];
     const double2 e1 = make_double2(s_drv[1], s_drv[2]), e2 = make_double2(s_drv[3], s_drv[4]);
     const double2 e1j = ROT ? e1 : make_double2(1.0, 0.0);  // phase of the kind-2 filter jump
     if constexpr (NM) {
-      jump_tile(Y1c, Yp, Yc, Yn, 0, e1j);
+      jump_tile(Y1c, Yp, Yc, Yn, r_lo, e1j);
       __syncthreads();
     }
     g_double2* kout = Kbuf(kslot[s - 1]);
     double es = 0.0;
     zero_terms();
-    for (int r = 0; r < d_r; ++r) {
+    for (int r = r_lo; r < r_hi; ++r) {
       const double him = NM ? -0.5 * T.kappa *
                                   (T.nm[1] * T.nm[1] * (r + 1 < d_r ? r + 1.0 : 0.0) + T.nm[2] * T.nm[2] * r)
                             : 0.0;
@@ -285,19 +333,19 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
               }
               const double2 kk = make_double2(z.y + 0.5 * a.x, -z.x + 0.5 * a.y);
               const size_t gi = ((size_t)r * L + rl) * M + ej;
-              st_g(kout + gi, kk);
+              stS(kout + gi, kk);
               if (s < 7) {
                 double2 sum = cscale(kDpA[s][s - 1], kk);
                 for (int j = 0; j < s - 1; ++j)
-                  if (kDpA[s][j] != 0.0) sum = cfma(kDpA[s][j], ld_g(Kbuf(kslot[j]) + gi), sum);
-                const double2 o = cfma(hc, sum, ld_g(ysrc + gi));
-                st_g(out + gi, o);
+                  if (kDpA[s][j] != 0.0) sum = cfma(kDpA[s][j], ldS(Kbuf(kslot[j]) + gi), sum);
+                const double2 o = cfma(hc, sum, ldS(ysrc + gi));
+                stS(out + gi, o);
                 Ot[rl * M + ej] = o;
               } else {
                 double2 ev = cscale(kDpE[6], kk);
                 for (int j = 0; j < 6; ++j)
-                  if (kDpE[j] != 0.0) ev = cfma(kDpE[j], ld_g(Kbuf(kslot[j]) + gi), ev);
-                const double2 yo = ld_g(ysrc + gi), yn = Yc[rl * M + ej];
+                  if (kDpE[j] != 0.0) ev = cfma(kDpE[j], ldS(Kbuf(kslot[j]) + gi), ev);
+                const double2 yo = ldS(ysrc + gi), yn = Yc[rl * M + ej];
                 const double sc = A.atol + A.rtol * fmax(sqrt(yo.x * yo.x + yo.y * yo.y), sqrt(yn.x * yn.x + yn.y * yn.y));
                 const double ex = hc * ev.x / sc, ey = hc * ev.y / sc;
                 es += ex * ex + ey * ey;
@@ -307,14 +355,16 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
         }
       }
       __syncthreads();
+      if constexpr (SPLIT && NM)
+        if (s < 7 && r == r_lo) split_publish_first(T, SS);
       // the next input layer (r + 2; kind 2: r + 3) replaces the oldest one; kind 2 also forms the
       // filter jump of layer r + 1
       const int rnx = NM ? r + 3 : r + 2;
       double2* dstl = NM ? Ym2 : Yp;
-      if (rnx < d_r)
-        for (int e = tid; e < LM; e += kTW) dstl[e] = ld_g(in + (size_t)rnx * LM + e);
+      if (rnx < (SPLIT ? min(d_r, r_hi + (NM ? 2 : 1)) : d_r))
+        for (int e = tid; e < LM; e += kTW) dstl[e] = ldS(in + (size_t)rnx * LM + e);
       if constexpr (NM)
-        if (r + 1 < d_r) jump_tile(Y1n, Yc, Yn, Yp2, r + 1, e1j);
+        if (r + 1 < r_hi) jump_tile(Y1n, Yc, Yn, Yp2, r + 1, e1j);
       if (s < 7) add_terms(r);
       __syncthreads();
       if constexpr (NM) {
@@ -342,9 +392,12 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
       double tot = 0.0;
       for (int w = 0; w < kTW / 64; ++w) tot += s_red[w];
       __syncthreads();
+      if constexpr (SPLIT)
+        if (!split_sum_value(T, tot, &tot, SS, &s_ok)) return -8;
       *errsum = tot;
       return 0;
     }
+    if (const int rs = split_terms(out, true)) return rs;
     return solve(false, nullptr, t_next);
   };
 
@@ -373,22 +426,26 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
         Ot = lds + 7 * LM;
         Op = lds + 8 * LM;
       }
-      for (int r = 0; r < d_r; ++r) {
+      if constexpr (SPLIT) ++SS.c;
+      for (int r = r_lo; r < r_hi; ++r) {
         __syncthreads();
         for (int e = tid; e < LM; e += kTW) {
           const size_t gi = (size_t)r * LM + e;
-          const double2 y = ld_g(ysrc + gi);
-          if (copy) st_g(gBb + gi, y);
-          const double2 o = cfma(hc * kDpA[1][0], ld_g(k1 + gi), y);
-          st_g(gS[0] + gi, o);
+          const double2 y = ldS(ysrc + gi);
+          if (copy) stS(gBb + gi, y);
+          const double2 o = cfma(hc * kDpA[1][0], ldS(k1 + gi), y);
+          stS(gS[0] + gi, o);
           Ot[e] = o;
         }
         __syncthreads();
+        if constexpr (SPLIT && NM)
+          if (r == r_lo) split_publish_first(T, SS);
         add_terms(r);
         swap_out();
       }
       ysrc = gBb;
-      const int rc = solve(false, nullptr, t + kDpC[1] * hc);
+      int rc = split_terms(gS[0], true);
+      if (!rc) rc = solve(false, nullptr, t + kDpC[1] * hc);
       if (rc) {
         code = rc;
         break;
@@ -423,16 +480,16 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
     Ot = lds + 7 * LM;
     Op = lds + 8 * LM;
   }
-  const int rc = code ? 0 : gram_pass(ysrc, ysrc != gBb ? gBb : nullptr, &f2, t);
-  if (tid == 0) {
-    if (code || rc) report(T, code ? code : rc, step0);
+  const int rc = (code || !moves) ? 0 : gram_pass(ysrc, ysrc != gBb ? gBb : nullptr, &f2, t);
+  if (tid == 0 && (code || rc)) report(T, code ? code : rc, step0);
+  if (tid == 0 && (!SPLIT || part == 0)) {
     A.st[0] = t;
     A.st[1] = h;
     A.cnt[0] = nacc;
     A.cnt[1] = nrej;
     A.cnt[2] = k1slot;
     A.cnt[3] = k1valid;
-    if (!code && !rc) *T.fro2 = f2;
+    if (!code && !rc && moves) *T.fro2 = f2;
     *T.step = n_end;
   }
 }
@@ -478,6 +535,46 @@ __global__ __launch_bounds__(kTW, (KP <= 8 ? 2 : 1)) void k_dp5_nm_prologue(cons
     dp5_body<KP, true, 2>(T, ads[blockIdx.x], 1, step0, nchunk);
   else
     dp5_body<KP, false, 2>(T, ads[blockIdx.x], 1, step0, nchunk);
+}
+
+// Layer-split trajectories (blockIdx.x -> (trajectory, part) by the tile map;
+// chunks only: the prologue is the one-workgroup kernel).
+template <int KP>
+__global__ __launch_bounds__(kTW) void k_dp5_split(const TrajDev* __restrict__ trajs,
+                                                   const AdaptDev* __restrict__ ads, const int2* __restrict__ tilemap,
+                                                   int64_t step0, int64_t nchunk) {
+  const int2 tw = tilemap[blockIdx.x];
+  const TrajDev& T = trajs[tw.x];
+  const AdaptDev& A = ads[tw.x];
+  if (T.mkind == 1) {
+    if (T.frame)
+      dp5_body<KP, true, 1, true>(T, A, 0, step0, nchunk, tw.y);
+    else
+      dp5_body<KP, false, 1, true>(T, A, 0, step0, nchunk, tw.y);
+  } else if (T.frame) {
+    dp5_body<KP, true, 0, true>(T, A, 0, step0, nchunk, tw.y);
+  } else {
+    dp5_body<KP, false, 0, true>(T, A, 0, step0, nchunk, tw.y);
+  }
+}
+template <int KP>
+__global__ __launch_bounds__(kTW) void k_dp5_split_nm(const TrajDev* __restrict__ trajs,
+                                                      const AdaptDev* __restrict__ ads,
+                                                      const int2* __restrict__ tilemap, int64_t step0,
+                                                      int64_t nchunk) {
+  const int2 tw = tilemap[blockIdx.x];
+  const TrajDev& T = trajs[tw.x];
+  if (T.frame)
+    dp5_body<KP, true, 2, true>(T, ads[tw.x], 0, step0, nchunk, tw.y);
+  else
+    dp5_body<KP, false, 2, true>(T, ads[tw.x], 0, step0, nchunk, tw.y);
+}
+template <int I = 0>
+inline const void* dp5_split_kernel(int kp, bool nm) {
+  if constexpr (I + 1 < (int)(sizeof(kPackedKP) / sizeof(int))) {
+    if (kp > kPackedKP[I]) return dp5_split_kernel<I + 1>(kp, nm);
+  }
+  return nm ? (const void*)k_dp5_split_nm<kPackedKP[I]> : (const void*)k_dp5_split<kPackedKP[I]>;
 }
 
 template <int I = 0>

@@ -18,6 +18,12 @@
 // fills each CU with as many as fit; the launch sequences of different
 // families run concurrently on forked streams.  The others run in spread
 // groups.
+//
+// Layer-split packed trajectories (LR_BATCH_PACKED_PARTS): each FP64 packed
+// trajectory runs on P workgroups of the packed kernel (lr_packed.hip,
+// lr_adaptive.hip), in co-resident groups of one cooperative launch per
+// chunk, like the spread groups; the one-workgroup prologue forms the Gram
+// terms of the initial state.
 
 struct lr_batch {
   int n = 0;
@@ -28,6 +34,7 @@ struct lr_batch {
   std::vector<size_t> lds, region, region_bytes;
   std::vector<int> wg_offset;  // first tilemap entry of each trajectory
   std::vector<char> packed;    // trajectory runs in the packed kernel
+  std::vector<char> split;     // packed trajectory split over P[t] workgroups (layer ranges)
   bool graph_on = false;       // lr_batch_run captures its launch sequence once and replays it
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -51,6 +58,7 @@ struct lr_batch {
     int nm;     // packed group of the normal-mode model (its own kernels)
     int gm;     // packed: Gram terms on the vector ALU (-1) or matrix-core mode (0 FP64, 1 FP32, 2 BF16x3)
     int slots;  // packed matrix-core modes: output tiles per wave
+    int split;  // packed, layer-split trajectories (cooperative launch, wgs = sum of the parts)
   };
   bool mfma64 = false;  // LR_BATCH_PACKED_MFMA64
   std::vector<Group> groups;
@@ -144,8 +152,14 @@ int lr_batch_init_ex(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_
 }
 
 int lr_batch_init_adaptive(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, double rtol, double atol) {
+  return lr_batch_init_adaptive_ex(out, trajs, n, 0, rtol, atol);
+}
+
+int lr_batch_init_adaptive_ex(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flags, double rtol,
+                              double atol) {
   if (!(rtol > 0.0) || !(atol > 0.0) || !std::isfinite(rtol) || !std::isfinite(atol)) return LR_ERR_ARG;
-  return batch_init(out, trajs, n, LR_BATCH_PACKED, true, rtol, atol);
+  if (flags & ~(LR_BATCH_PACKED | LR_BATCH_PACKED_PARTS(0xff))) return LR_ERR_ARG;
+  return batch_init(out, trajs, n, flags | LR_BATCH_PACKED, true, rtol, atol);
 }
 
 int lr_batch_adaptive_stats(lr_batch_t* b, int64_t* accepted, int64_t* rejected) {
@@ -168,7 +182,9 @@ namespace {
 int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flags, bool adaptive, double rtol,
                double atol) {
   if (!out || !trajs || n < 1) return LR_ERR_ARG;
-  if (flags & ~(LR_BATCH_PACKED | LR_BATCH_PACKED_MFMA64 | LR_BATCH_SPREAD_LAYERS(0xff))) return LR_ERR_ARG;
+  if (flags & ~(LR_BATCH_PACKED | LR_BATCH_PACKED_MFMA64 | LR_BATCH_SPREAD_LAYERS(0xff) | LR_BATCH_PACKED_PARTS(0xff)))
+    return LR_ERR_ARG;
+  const int parts = (flags >> 16) & 0xff;
   *out = nullptr;
   lr_batch* b = new (std::nothrow) lr_batch();
   if (!b) return LR_ERR_OOM;
@@ -211,10 +227,12 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
   b->tr.resize(n);
   b->pos.resize(n);
   b->packed.resize(n);
+  b->split.resize(n);
   for (int k = 0; k < n; ++k) {
     b->tr[k] = trajs[order[k]];
     b->pos[order[k]] = k;
     b->packed[k] = packs(b->tr[k]);
+    b->split[k] = b->packed[k] && parts >= 2 && b->tr[k].precision == LR_FP64;
   }
   b->dev.resize(n);
   b->P.resize(n);
@@ -251,7 +269,7 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
       e = LR_ERR_ARG;
     if (!e && b->packed[t]) {
       b->prt[t] = 0;
-      b->P[t] = 1;
+      b->P[t] = b->split[t] ? std::min(parts, x.model.d_r) : 1;
       b->rows[t] = 0;
       b->lds[t] = lrk::packed_lds_elems(x.model.d_q * x.model.d_f, x.M,
                                         std::max(std::max(x.model.d_q, x.model.d_r), x.model.d_f), x.model.kind) *
@@ -281,6 +299,13 @@ int batch_init(lr_batch_t** out, const lr_traj_t* trajs, int32_t n, int32_t flag
       if (adaptive) {
         r = align_up(r + 7 * nm, a);                       // k_1 .. k_7
         r = align_up(r + 64, a);                           // t, h, counters
+      }
+      if (b->split[t]) {
+        const size_t spe = lrk::split_npe(x.M, x.model.kind) * sizeof(double2);
+        r = align_up(r + P * spe, a);                      // PART
+        r = align_up(r + spe + P * sizeof(double), a);     // RED, one value per part
+        r = align_up(r + P * lrk::kFlagStride * 4, a);     // flagA
+        r = align_up(r + 2 * P * lrk::kFlagStride * 4, a); // flagB, flagC
       }
       r = align_up(r + 64, a);                             // step, fail_step, fro2, status, abort
       b->region[t] = o;
@@ -365,6 +390,18 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
         d.cnt = reinterpret_cast<int64_t*>(base + r + 16);
         r = align_up(r + 64, a);
       }
+      v.P = 0;
+      v.rt = 0;
+      if (b->split[t]) {
+        const int spn = lrk::split_npe(x.M, m.kind);
+        const size_t spe = (size_t)spn * sizeof(double2);
+        v.PART = reinterpret_cast<double2*>(base + r);  r = align_up(r + P * spe, a);
+        v.RED = reinterpret_cast<double2*>(base + r);   r = align_up(r + spe + P * sizeof(double), a);
+        v.flagA = reinterpret_cast<uint32_t*>(base + r); r = align_up(r + P * lrk::kFlagStride * 4, a);
+        v.flagB = reinterpret_cast<uint32_t*>(base + r); r = align_up(r + 2 * P * lrk::kFlagStride * 4, a);
+        v.P = (int)P;
+        v.npe = spn;
+      }
       if (r + 64 > b->region_bytes[t]) return LR_ERR_STATE;  // layout of lr_batch_init_ex
       v.step = reinterpret_cast<int64_t*>(base + r);
       v.fail_step = reinterpret_cast<int64_t*>(base + r + 8);
@@ -372,9 +409,7 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
       v.status = reinterpret_cast<int32_t*>(base + r + 24);
       v.abort_flag = reinterpret_cast<uint32_t*>(base + r + 28);
       v.obs = x.obs_stride > 0 ? x.d_obs : nullptr;
-      v.P = 0;
-      v.rt = 0;
-      tmap[(size_t)b->wg_offset[t]] = make_int2(t, 0);
+      for (int w = 0; w < (int)P; ++w) tmap[(size_t)b->wg_offset[t] + w] = make_int2(t, w);
       continue;
     }
     v.Bb = reinterpret_cast<double2*>(base + r);        r = align_up(r + nm, a);
@@ -427,6 +462,10 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
            hipFuncSetAttribute(lrk::dp5_kernel(kp, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)max_lds_packed) != hipSuccess ||
            hipFuncSetAttribute(lrk::dp5_kernel(kp, pro != 0, true), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)max_lds_packed) != hipSuccess ||
+           hipFuncSetAttribute(lrk::packed_split_kernel(kp, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)max_lds_packed) != hipSuccess ||
+           hipFuncSetAttribute(lrk::dp5_split_kernel(kp, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)max_lds_packed) != hipSuccess))
         return LR_ERR_HIP;
   for (int gm = 0; gm <= 2; ++gm)  // the matrix-core Gram kernels of the packed schedule
@@ -454,11 +493,35 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
   int t = 0;
   while (t < b->n && b->packed[t]) {  // one launch per chunk holds every packed trajectory of a kernel family
     const int nm = b->tr[t].model.kind == LR_MODEL_NORMAL, prec = b->tr[t].precision;
+    if (b->split[t]) {  // layer-split trajectories: co-resident groups of one kernel family
+      lr_batch::Group g{t, t, 0, 0, 0, prec, 0, 0, 0, 1, 2, nm, -1, 2, 1};
+      while (t < b->n && b->split[t] && (b->tr[t].model.kind == LR_MODEL_NORMAL) == (nm != 0)) {
+        const int kp = std::max(g.kp, lrk::packed_kp(b->tr[t].M, b->tr[t].model.kind));
+        const size_t lds = std::max(g.lds, b->lds[t]);
+        const void* fn = b->adaptive ? lrk::dp5_split_kernel(kp, nm != 0) : lrk::packed_split_kernel(kp, nm != 0);
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, lrk::kTW, lds) != hipSuccess) return LR_ERR_HIP;
+        if (g.wgs + b->P[t] > per_cu * ncu) {
+          if (g.end == g.begin) return LR_ERR_ARG;  // a single trajectory that cannot be co-resident
+          break;
+        }
+        g.kp = kp;
+        g.lds = lds;
+        g.wgs += b->P[t];
+        g.max_steps = std::max(g.max_steps, b->tr[t].nsteps);
+        const int64_t s = b->tr[t].obs_stride;
+        if (s > 0) g.chunk = g.chunk ? gcd64(g.chunk, s) : s;
+        g.end = ++t;
+      }
+      if (g.chunk == 0) g.chunk = 4096;
+      b->groups.push_back(g);
+      continue;
+    }
     const int gm = nm ? -1 : (prec == LR_FP64 ? (b->mfma64 && !b->adaptive ? 0 : -1) : prec);
-    lr_batch::Group g{t, t, 0, 0, 0, prec, 0, 0, 0, 1, 2, nm, gm, 2};
+    lr_batch::Group g{t, t, 0, 0, 0, prec, 0, 0, 0, 1, 2, nm, gm, 2, 0};
     // one launch for the family, sized by its largest LDS footprint (launches split by footprint
     // class, in order on one stream or concurrently on two, measured slower on mixed batches)
-    while (t < b->n && b->packed[t] && (b->tr[t].model.kind == LR_MODEL_NORMAL) == (nm != 0) &&
+    while (t < b->n && b->packed[t] && !b->split[t] && (b->tr[t].model.kind == LR_MODEL_NORMAL) == (nm != 0) &&
            b->tr[t].precision == prec) {
       g.kp = std::max(g.kp, lrk::packed_kp(b->tr[t].M, b->tr[t].model.kind));
       g.slots = std::max(g.slots, lrk::mg_slots(b->tr[t].M));
@@ -475,7 +538,7 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
   {  // one forked stream per packed kernel family after the first (default priority)
     int npk = 0, prev = -1;
     for (const auto& g : b->groups)
-      if (g.packed && g.nm * 4 + g.prec != prev) {
+      if (g.packed && !g.split && g.nm * 4 + g.prec != prev) {
         ++npk;
         prev = g.nm * 4 + g.prec;
       }
@@ -491,7 +554,7 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
     }
   }
   while (t < b->n) {
-    lr_batch::Group g{t, t, 0, 2, 1, b->tr[t].precision, 0, 0, 0, 0, 0, 0, -1, 2};
+    lr_batch::Group g{t, t, 0, 2, 1, b->tr[t].precision, 0, 0, 0, 0, 0, 0, -1, 2, 0};
     while (t < b->n) {
       if (b->tr[t].precision != g.prec) break;
       const int rows = std::max(g.rows, b->rows[t]);
@@ -535,7 +598,7 @@ int lr_batch_graph(lr_batch_t* b, int32_t on) {
   if (!on) return LR_OK;
   if (!b->stream) return LR_ERR_STATE;  // the null stream cannot be captured
   for (int t = 0; t < b->n; ++t)
-    if (!b->packed[t]) return LR_ERR_STATE;  // cooperative launches are not captured
+    if (!b->packed[t] || b->split[t]) return LR_ERR_STATE;  // cooperative launches are not captured
   b->graph_on = true;
   return LR_OK;
 }
@@ -600,9 +663,9 @@ int enqueue(lr_batch* b) {
     const TrajDev* gtr = trajs;
     const int2* gmap = tmap + b->wg_offset[g.begin];
     hipStream_t gs = b->stream;
-    if (!g.packed)
+    if (!g.packed || g.split)
       if (int e = join_all()) return e;
-    if (g.packed) {
+    if (g.packed && !g.split) {
       const int fam = g.nm * 4 + g.prec;
       if (fam != prev_fam) {
         ++nfam;
@@ -628,7 +691,26 @@ int enqueue(lr_batch* b) {
         (void)hipEventRecord(b->ev[2 * k], gs);
       }
       hipError_t err;
-      if (g.packed) {
+      if (g.split) {  // one-workgroup prologue; chunks cooperative over the parts (flags zeroed first)
+        const TrajDev* ptr = trajs + g.begin;
+        const lrk::AdaptDev* aptr = ads + g.begin;
+        const int ntr = g.end - g.begin;
+        if (prologue) {
+          void* pargs_a[] = {(void*)&ptr, (void*)&aptr, (void*)&step0, (void*)&nchunk};
+          void* pargs_p[] = {(void*)&ptr, (void*)&step0, (void*)&nchunk};
+          err = b->adaptive ? hipLaunchKernel(lrk::dp5_kernel(g.kp, true, g.nm != 0), dim3(ntr), dim3(lrk::kTW),
+                                              pargs_a, g.lds, gs)
+                            : hipLaunchKernel(lrk::packed_kernel(g.kp, true, g.nm != 0), dim3(ntr), dim3(lrk::kTW),
+                                              pargs_p, g.lds, gs);
+        } else {
+          hipLaunchKernelGGL(lrk::k_reset_split, dim3(ntr), dim3(256), 0, gs, ptr, ntr);
+          void* sargs_a[] = {(void*)&gtr, (void*)&ads, (void*)&gmap, (void*)&step0, (void*)&nchunk};
+          err = b->adaptive ? hipLaunchCooperativeKernel(lrk::dp5_split_kernel(g.kp, g.nm != 0), dim3(g.wgs),
+                                                         dim3(lrk::kTW), sargs_a, (unsigned)g.lds, gs)
+                            : hipLaunchCooperativeKernel(lrk::packed_split_kernel(g.kp, g.nm != 0), dim3(g.wgs),
+                                                         dim3(lrk::kTW), args, (unsigned)g.lds, gs);
+        }
+      } else if (g.packed) {
         const TrajDev* ptr = trajs + g.begin;
         if (b->adaptive) {
           const lrk::AdaptDev* aptr = ads + g.begin;

@@ -715,18 +715,141 @@ __device__ __forceinline__ double2 packed_jump_nm(const TrajDev& T, const double
   return cscale(sk, cadd(cmul(e1, up), cmulc(dn, e1)));
 }
 
+// ---------------------------------------------------------------- layer-split trajectories
+//
+// A trajectory can also be split over P workgroups ("parts") of one
+// cooperative launch, for latency when few trajectories are in flight: part w
+// owns the layers [w d_r / P, (w + 1) d_r / P) and runs the packed layer loop
+// over them, reading its neighbour layers of the stage input from global
+// memory.  After each pass the parts' Gram terms are summed (partials, group
+// barrier A, a 1/P slice of the entries reduced in fixed order, group barrier
+// B, the reduced entries back into every thread's registers), so that every
+// part holds the same terms and solves the same M x M system.  Kind 2 pairs
+// each layer with the one below it in the term Q: a part adds the pair across
+// its upper boundary once the part above has published its first output
+// layer (a point-to-point flag C).  Every buffer that another part reads goes
+// through agent-coherent accesses; every wait is bounded as in the spread
+// schedule.
+
+// Part w's layer range.
+__device__ __forceinline__ int split_lo(int w, int P, int d_r) { return (int)(((int64_t)w * d_r) / P); }
+// Entries of the Gram terms a part publishes (M x 3M; kind 2: M x 4M).
+__host__ __device__ inline int split_npe(int M, int kind) { return M * (kind == 2 ? 4 : 3) * M; }
+
+// Wait until one flag reaches target (bounded; raises the group's abort flag
+// when the wait expires).
+__device__ __forceinline__ bool flag_wait_one(const TrajDev& T, const g_u32* flag, uint32_t target, int* s_ok) {
+  g_u32* abort_flag = (g_u32*)T.abort_flag;
+  const uint32_t limit = T.spin_limit ? T.spin_limit : kSpinLimit;
+  target += T.wait_bias;
+  if (threadIdx.x == 0) {
+    bool ok = true;
+    uint32_t n = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++n > limit) {
+        __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = false;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    *s_ok = ok ? 1 : 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+// Barrier counters of a part within one launch (the flags are zeroed before
+// every launch; all parts pass the same barriers in the same order).
+struct SplitSync {
+  int w;
+  uint32_t a, b, c;
+};
+
+// Sum of the parts' Gram terms (entry (i, c) of the M x C terms at i C + c)
+// into the registers of every part; false when a group wait expired.
+template <int KP>
+__device__ bool split_sum(const TrajDev& T, double2 (&acc)[KP], const PackedMap& P, SplitSync& S, int* s_ok) {
+  const int tid = threadIdx.x, C = P.C3, npe = P.M * C, np = T.P;
+  g_double2* part = (g_double2*)T.PART;
+  g_double2* red = (g_double2*)T.RED;
+  if (P.pact) {
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int i = P.pi0 + k;
+      if (k < P.KPe && i < P.M) st_ag(part + (size_t)S.w * npe + i * C + P.pc, acc[k]);
+    }
+  }
+  g_u32* fA = (g_u32*)T.flagA;
+  g_u32* fB = (g_u32*)T.flagB;
+  flag_arrive(fA + (size_t)S.w * kFlagStride, ++S.a);
+  if (!flag_wait(T, fA, S.a, s_ok)) return false;
+  // slice of the entries: a 16-lane group per entry, lane l adds the parts l,
+  // l + 16, ... in order, then a butterfly over the group (order fixed by P)
+  const int cs = (npe + np - 1) / np, e0 = S.w * cs, e1 = min(npe, e0 + cs);
+  const int sub = tid & 15, grp = tid >> 4;
+  for (int e = e0 + grp; e < e1; e += kTW / 16) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int q = sub; q < np; q += 16) s = cadd(s, ld_ag(part + (size_t)q * npe + e));
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+      s.x += __shfl_xor(s.x, off, 16);
+      s.y += __shfl_xor(s.y, off, 16);
+    }
+    if (sub == 0) st_ag(red + e, s);
+  }
+  flag_arrive(fB + (size_t)S.w * kFlagStride, ++S.b);
+  if (!flag_wait(T, fB, S.b, s_ok)) return false;
+  if (P.pact) {
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int i = P.pi0 + k;
+      acc[k] = (k < P.KPe && i < P.M) ? ld_ag(red + i * C + P.pc) : make_double2(0.0, 0.0);
+    }
+  }
+  return true;
+}
+
+// Sum of one value per part, the same in every part (parts in order); false
+// when the group wait expired.
+__device__ bool split_sum_value(const TrajDev& T, double v, double* out, SplitSync& S, int* s_ok) {
+  g_double* vals = (g_double*)(T.RED + T.npe);
+  if (threadIdx.x == 0) __hip_atomic_store(vals + S.w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  g_u32* fA = (g_u32*)T.flagA;
+  flag_arrive(fA + (size_t)S.w * kFlagStride, ++S.a);
+  if (!flag_wait(T, fA, S.a, s_ok)) return false;
+  double tot = 0.0;
+  for (int q = 0; q < T.P; ++q) tot += __hip_atomic_load(vals + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  *out = tot;
+  return true;
+}
+
+// Kind 2: publish the first output layer of the pass (flag C of the part).
+__device__ __forceinline__ void split_publish_first(const TrajDev& T, SplitSync& S) {
+  g_u32* fC = (g_u32*)T.flagB + (size_t)T.P * kFlagStride;
+  flag_arrive(fC + (size_t)S.w * kFlagStride, S.c);
+}
+// Kind 2: wait for the first output layer of the part above.
+__device__ __forceinline__ bool split_wait_above(const TrajDev& T, const SplitSync& S, int* s_ok) {
+  const g_u32* fC = (const g_u32*)T.flagB + (size_t)T.P * kFlagStride;
+  return flag_wait_one(T, fC + (size_t)(S.w + 1) * kFlagStride, S.c, s_ok);
+}
+
 // The kernel body: prologue (Gram terms and W of the initial state, no step)
 // or a chunk of nchunk RK4 steps from step0.  KP = entries of the Gram terms
 // per thread (packed_kp).  MK = model kind; kind 2 keeps five input layers,
 // the filter jump L_1 Y of the current and the next layer, and the outputs of
 // the current and the previous layer (for the cross-layer term Q).
-template <int KP, bool ROT, int MK = 0, int GM = -1, int NS = 2>
-__device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int64_t step0, int64_t nchunk) {
+template <int KP, bool ROT, int MK = 0, int GM = -1, int NS = 2, bool SPLIT = false>
+__device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int64_t step0, int64_t nchunk,
+                                            int part = 0) {
   extern __shared__ double2 lds[];
   __shared__ double s_red[kTW / 64];
   __shared__ double s_nt[kMaxDq * kMaxDq];
   __shared__ double2 s_ph[2 * kMaxDq + 3];  // e^{i w_d t m}, m = -(d_q + 1) .. d_q + 1, of the stage (kinds 1, 2, rotating frame)
   __shared__ int s_flag;
+  __shared__ int s_ok;
   constexpr bool NM = MK == 2;
   constexpr int NTILE = NM ? 9 : 4;
   const int tid = threadIdx.x;
@@ -774,6 +897,18 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
   if (s_flag != 0) return;
   const int64_t nrun = prologue ? 0 : (step0 < T.nsteps ? min(nchunk, T.nsteps - step0) : 0);
   if (!prologue && nrun <= 0) return;
+  // layers of this workgroup: all of them, or those of its part of a split trajectory
+  const int r_lo = SPLIT ? split_lo(part, T.P, d_r) : 0;
+  const int r_hi = SPLIT ? split_lo(part + 1, T.P, d_r) : d_r;
+  SplitSync SS{part, 0u, 0u, 0u};
+  auto ldS = [](const g_double2* p) -> double2 {
+    if constexpr (SPLIT) return ld_ag(p);
+    else return ld_g(p);
+  };
+  auto stS = [](g_double2* p, double2 v) {
+    if constexpr (SPLIT) st_ag(p, v);
+    else st_g(p, v);
+  };
 
   // element mapping: column j, rows g, g + NGe, ...
   const int NGe = kTW / M;
@@ -827,7 +962,7 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
     } else {
       packed_terms<KP>(acc, PM, Ot, coef);
       if constexpr (NM)
-        if (r > 0) packed_terms_q<KP>(acc, PM, Ot, Op, sk * sq[r]);
+        if (r > r_lo) packed_terms_q<KP>(acc, PM, Ot, Op, sk * sq[r]);
     }
   };
   // W_k of the state whose Gram terms the threads hold, for use at time t_use
@@ -852,7 +987,7 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
     }
   };
 
-  if (prologue) {
+  if (!SPLIT && prologue) {
     zero_terms();
     for (int r = 0; r < d_r; ++r) {
       __syncthreads();
@@ -908,17 +1043,25 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
         Yc = lds + LM;
         Yn = lds + 2 * LM;
       }
-      for (int e = tid; e < LM; e += kTW) Yc[e] = ld_g(in + e);
-      if (d_r > 1)
-        for (int e = tid; e < LM; e += kTW) Yn[e] = ld_g(in + LM + e);
+      const g_double2* in0 = in + (size_t)r_lo * LM;
+      for (int e = tid; e < LM; e += kTW) Yc[e] = ldS(in0 + e);
+      if (r_lo + 1 < d_r)
+        for (int e = tid; e < LM; e += kTW) Yn[e] = ldS(in0 + LM + e);
+      if constexpr (SPLIT)
+        if (r_lo > 0)
+          for (int e = tid; e < LM; e += kTW) Yp[e] = ldS(in0 - LM + e);
       if constexpr (NM) {
-        if (d_r > 2)
-          for (int e = tid; e < LM; e += kTW) Yp2[e] = ld_g(in + 2 * LM + e);
+        if (r_lo + 2 < d_r)
+          for (int e = tid; e < LM; e += kTW) Yp2[e] = ldS(in0 + 2 * LM + e);
+        if constexpr (SPLIT)
+          if (r_lo > 1)
+            for (int e = tid; e < LM; e += kTW) Ym2[e] = ldS(in0 - 2 * LM + e);
         __syncthreads();
-        jump_tile(Y1c, Yp, Yc, Yn, 0, e1j);
+        jump_tile(Y1c, Yp, Yc, Yn, r_lo, e1j);
       }
+      if constexpr (SPLIT) ++SS.c;
       __syncthreads();
-      for (int r = 0; r < d_r; ++r) {
+      for (int r = r_lo; r < r_hi; ++r) {
         const double him = NM ? -0.5 * T.kappa *
                                     (T.nm[1] * T.nm[1] * (r + 1 < d_r ? r + 1.0 : 0.0) + T.nm[2] * T.nm[2] * r)
                               : 0.0;
@@ -933,8 +1076,8 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
               for (int k = 0; k < kTRowBlock; ++k) {
                 const int rl = min(rb + k * NGe, L - 1);
                 const size_t gi = ((size_t)r * L + rl) * M + ej;
-                pb[k] = ld_g(gBb + gi);
-                pa[k] = ld_g(gacc + gi);
+                pb[k] = ldS(gBb + gi);
+                pa[k] = ldS(gacc + gi);
               }
             }
             double2 a1[kTRowBlock], a2[kTRowBlock];
@@ -973,48 +1116,50 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
                 const size_t gi = ((size_t)r * L + rl) * M + ej;
                 double2 o;
                 if (s == 0) {
-                  st_g(gacc + gi, kk);
+                  stS(gacc + gi, kk);
                   o = cfma(0.5 * dt, kk, Yc[rl * M + ej]);
                 } else if (s == 1) {
-                  st_g(gacc + gi, cfma(2.0, kk, pa[k]));
+                  stS(gacc + gi, cfma(2.0, kk, pa[k]));
                   o = cfma(0.5 * dt, kk, pb[k]);
                 } else if (s == 2) {
-                  st_g(gacc + gi, cfma(2.0, kk, pa[k]));
+                  stS(gacc + gi, cfma(2.0, kk, pa[k]));
                   o = cfma(dt, kk, pb[k]);
                 } else {
                   o = cfma(dt / 6.0, cadd(pa[k], kk), pb[k]);
                 }
-                st_g(out + gi, o);
+                stS(out + gi, o);
                 Ot[rl * M + ej] = o;
               }
             }
           }
         }
         __syncthreads();
+        if constexpr (SPLIT && NM)
+          if (r == r_lo) split_publish_first(T, SS);
         // 2. the next input layer (r + 2; kind 2: r + 3) is in flight while the
         //    Gram terms of layer r are formed; it replaces the oldest layer
         const int rnx = NM ? r + 3 : r + 2;
         double2* dstl = NM ? Ym2 : Yp;
-        if (rnx < d_r) {
+        if (rnx < (SPLIT ? min(d_r, r_hi + (NM ? 2 : 1)) : d_r)) {
           const g_double2* nx = in + (size_t)rnx * LM;
           double2 pf[kTPrefetch];
 #pragma unroll
           for (int u = 0; u < kTPrefetch; ++u) {
             const int e = tid + u * kTW;
-            if (e < LM) pf[u] = ld_g(nx + e);
+            if (e < LM) pf[u] = ldS(nx + e);
           }
           if constexpr (NM)
-            if (r + 1 < d_r) jump_tile(Y1n, Yc, Yn, Yp2, r + 1, e1j);
+            if (r + 1 < r_hi) jump_tile(Y1n, Yc, Yn, Yp2, r + 1, e1j);
           add_terms(r);
 #pragma unroll
           for (int u = 0; u < kTPrefetch; ++u) {
             const int e = tid + u * kTW;
             if (e < LM) dstl[e] = pf[u];
           }
-          for (int e = tid + kTPrefetch * kTW; e < LM; e += kTW) dstl[e] = ld_g(nx + e);
+          for (int e = tid + kTPrefetch * kTW; e < LM; e += kTW) dstl[e] = ldS(nx + e);
         } else {
           if constexpr (NM)
-            if (r + 1 < d_r) jump_tile(Y1n, Yc, Yn, Yp2, r + 1, e1j);
+            if (r + 1 < r_hi) jump_tile(Y1n, Yc, Yn, Yp2, r + 1, e1j);
           add_terms(r);
         }
         __syncthreads();
@@ -1038,6 +1183,24 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
           Yn = t;
         }
       }
+      if constexpr (SPLIT) {
+        bool ok = true;
+        if constexpr (NM) {
+          if (r_hi < d_r) {  // the pair (r_hi - 1, r_hi) across the upper boundary
+            ok = split_wait_above(T, SS, &s_ok);
+            if (ok) {
+              for (int e = tid; e < LM; e += kTW) Ot[e] = ldS(out + (size_t)r_hi * LM + e);
+              __syncthreads();
+              packed_terms_q<KP>(acc, PM, Ot, Op, sk * sq[r_hi]);
+            }
+          }
+        }
+        if (ok) ok = split_sum<KP>(T, acc, PM, SS, &s_ok);
+        if (!ok) {
+          if (tid == 0) report(T, -8 /* LR_ERR_TIMEOUT */, step);
+          return;
+        }
+      }
       double f2 = 0.0;
       const bool last = (s == 3) && (n + 1 == nrun);
       const int rc = solve(last, &f2, s < 3 ? stage_time(step, s + 1) : stage_time(step + 1, 0));
@@ -1048,11 +1211,13 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
         }
         return;
       }
-      if (last && tid == 0) *T.fro2 = f2;
+      if (last && tid == 0 && (!SPLIT || part == 0)) *T.fro2 = f2;
     }
   }
-  for (int e = tid; e < 2 * MM; e += kTW) st_g(gW + e, Wl[e]);
-  if (tid == 0) *T.step = step0 + nrun;
+  if (!SPLIT || part == 0) {
+    for (int e = tid; e < 2 * MM; e += kTW) st_g(gW + e, Wl[e]);
+    if (tid == 0) *T.step = step0 + nrun;
+  }
 }
 
 // blockIdx.x = trajectory of trajs[]; the RK4 chunk and the prologue are
@@ -1160,6 +1325,58 @@ inline const void* packed_kernel(int kp, bool prologue, bool nm = false, int gm 
   }
   if (nm) return prologue ? (const void*)k_packed_nm_prologue<kPackedKP[I]> : (const void*)k_packed_nm<kPackedKP[I]>;
   return prologue ? (const void*)k_packed_prologue<kPackedKP[I]> : (const void*)k_packed<kPackedKP[I]>;
+}
+
+// Chunks of layer-split trajectories: blockIdx.x -> (trajectory, part) by the
+// tile map.  Their prologue is the one-workgroup kernel (the Gram terms of
+// the initial state are formed once per run).  One workgroup per CU suffices
+// (few trajectories are split at a time), so the normal-mode kernel keeps its
+// registers free of spills.
+template <int KP>
+__global__ __launch_bounds__(kTW) void k_packed_split(const TrajDev* __restrict__ trajs,
+                                                      const int2* __restrict__ tilemap, int64_t step0,
+                                                      int64_t nchunk) {
+  const int2 tw = tilemap[blockIdx.x];
+  const TrajDev& T = trajs[tw.x];
+  if (T.mkind == 1) {
+    if (T.frame)
+      packed_body<KP, true, 1, -1, 2, true>(T, 0, step0, nchunk, tw.y);
+    else
+      packed_body<KP, false, 1, -1, 2, true>(T, 0, step0, nchunk, tw.y);
+  } else if (T.frame) {
+    packed_body<KP, true, 0, -1, 2, true>(T, 0, step0, nchunk, tw.y);
+  } else {
+    packed_body<KP, false, 0, -1, 2, true>(T, 0, step0, nchunk, tw.y);
+  }
+}
+template <int KP>
+__global__ __launch_bounds__(kTW) void k_packed_split_nm(const TrajDev* __restrict__ trajs,
+                                                         const int2* __restrict__ tilemap, int64_t step0,
+                                                         int64_t nchunk) {
+  const int2 tw = tilemap[blockIdx.x];
+  const TrajDev& T = trajs[tw.x];
+  if (T.frame)
+    packed_body<KP, true, 2, -1, 2, true>(T, 0, step0, nchunk, tw.y);
+  else
+    packed_body<KP, false, 2, -1, 2, true>(T, 0, step0, nchunk, tw.y);
+}
+template <int I = 0>
+inline const void* packed_split_kernel(int kp, bool nm) {
+  if constexpr (I + 1 < (int)(sizeof(kPackedKP) / sizeof(int))) {
+    if (kp > kPackedKP[I]) return packed_split_kernel<I + 1>(kp, nm);
+  }
+  return nm ? (const void*)k_packed_split_nm<kPackedKP[I]> : (const void*)k_packed_split<kPackedKP[I]>;
+}
+
+// Zero the barrier flags (A, B and C) of the split trajectories trajs[0 .. n).
+__global__ void k_reset_split(const TrajDev* __restrict__ trajs, int n) {
+  if ((int)blockIdx.x >= n) return;
+  const TrajDev& T = trajs[blockIdx.x];
+  for (int i = threadIdx.x; i < T.P * kFlagStride; i += blockDim.x) {
+    T.flagA[i] = 0u;
+    T.flagB[i] = 0u;
+    T.flagB[T.P * kFlagStride + i] = 0u;
+  }
 }
 
 }  // namespace lrk

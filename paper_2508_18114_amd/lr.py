@@ -45,11 +45,17 @@ def LR_BATCH_SPREAD_LAYERS(k: int) -> int:
     """lr_batch_init_ex flag: resonator layers per workgroup of the spread schedule."""
     return (int(k) & 0xFF) << 8
 
+
+def LR_BATCH_PACKED_PARTS(p: int) -> int:
+    """Packed-schedule flag: every FP64 packed trajectory split over p workgroups (layer ranges)."""
+    return (int(p) & 0xFF) << 16
+
 # every symbol include/lr.h declares
 EXPORTS = ("lr_init", "lr_workspace_bytes", "lr_bind", "lr_rhs", "lr_integrate",
            "lr_observables", "lr_spectrum", "lr_status", "lr_profile_enable", "lr_profile_read",
            "lr_readout_loss", "lr_dense_workspace_bytes", "lr_dense_integrate", "lr_strerror", "lr_destroy",
-           "lr_batch_init", "lr_batch_init_ex", "lr_batch_init_adaptive", "lr_batch_adaptive_stats",
+           "lr_batch_init", "lr_batch_init_ex", "lr_batch_init_adaptive", "lr_batch_init_adaptive_ex",
+           "lr_batch_adaptive_stats",
            "lr_batch_workspace_bytes", "lr_batch_graph", "lr_batch_bind", "lr_batch_run",
            "lr_batch_status", "lr_batch_profile_enable", "lr_batch_profile_read", "lr_batch_destroy",
            "lr_wait_limits", "lr_batch_wait_limits", "lr_apply_heff", "lr_integrate_noalloc")
@@ -115,6 +121,8 @@ def _load():
         "lr_batch_init": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lr_traj_t), i32]),
         "lr_batch_init_ex": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lr_traj_t), i32, i32]),
         "lr_batch_init_adaptive": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lr_traj_t), i32, dbl, dbl]),
+        "lr_batch_init_adaptive_ex": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lr_traj_t), i32, i32, dbl,
+                                                     dbl]),
         "lr_batch_adaptive_stats": (ctypes.c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "lr_batch_graph": (ctypes.c_int, [vp, i32]),
         "lr_batch_workspace_bytes": (sz, [vp]),
@@ -235,10 +243,13 @@ def lr_destroy(ctx: int) -> None:
 
 def lr_batch_init(trajs, flags: int = 0, adaptive=None) -> int:
     """trajs: sequence of lr_traj_t; flags: 0 or LR_BATCH_PACKED (lr_batch_init_ex);
-    adaptive: (rtol, atol) for lr_batch_init_adaptive."""
+    adaptive: (rtol, atol) for lr_batch_init_adaptive (with flags: lr_batch_init_adaptive_ex)."""
     arr = (lr_traj_t * len(trajs))(*trajs)
     h = ctypes.c_void_p()
-    if adaptive is not None:
+    if adaptive is not None and flags & ~LR_BATCH_PACKED:
+        rc = _lib.lr_batch_init_adaptive_ex(ctypes.byref(h), arr, len(trajs), int(flags), float(adaptive[0]),
+                                            float(adaptive[1]))
+    elif adaptive is not None:
         rc = _lib.lr_batch_init_adaptive(ctypes.byref(h), arr, len(trajs), float(adaptive[0]), float(adaptive[1]))
     elif flags:
         rc = _lib.lr_batch_init_ex(ctypes.byref(h), arr, len(trajs), flags)
@@ -476,16 +487,19 @@ class Batch:
     batch is used.  packed=True: the packed schedule (LR_BATCH_PACKED), one
     workgroup per FP64 trajectory.  adaptive=(rtol, atol): adaptive
     Dormand-Prince steps (lr_batch_init_adaptive); dt is then the output grid.
+    parts=p (p >= 2): every FP64 packed trajectory split over p workgroups
+    (LR_BATCH_PACKED_PARTS), for latency when few trajectories are in flight.
     """
 
-    def __init__(self, items, stream=None, packed=False, adaptive=None, flags=0):
+    def __init__(self, items, stream=None, packed=False, adaptive=None, flags=0, parts=0):
         import torch
         self.items = list(items)
         ts = [traj_struct(it["model"], it["M"], it["pulse"], it.get("t0", 0.0), it["dt"], it["nsteps"],
                           it["B"], it.get("obs_stride", 0), it.get("obs"), it.get("precision", _inp.FP64),
                           it.get("step0", 0))
               for it in self.items]
-        self.handle = lr_batch_init(ts, (LR_BATCH_PACKED if packed else 0) | int(flags), adaptive)
+        flags = int(flags) | (LR_BATCH_PACKED_PARTS(parts) if parts else 0)
+        self.handle = lr_batch_init(ts, (LR_BATCH_PACKED if packed else 0) | flags, adaptive)
         nbytes = lr_batch_workspace_bytes(self.handle)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.workspace = _stream_buffer(nbytes + 256, self.stream)

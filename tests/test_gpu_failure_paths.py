@@ -92,3 +92,34 @@ def test_batch_wait_expiry_stops_only_spread_trajectories(lr):
     b.close()
     b2.close()
     bp.close()
+
+
+def test_split_wait_expiry_reports_timeout_and_recovers(lr):
+    """Layer-split packed trajectories (fixed-step and adaptive) have group barriers: with expiring waits
+    every part's kernel ends and the trajectory reports LR_ERR_TIMEOUT; with the defaults restored the
+    same batch completes and equals a fresh one bitwise."""
+    import torch
+    m, p, B0 = _case()
+
+    def items():
+        return [dict(model=m, M=4, pulse=p, dt=1e-3, nsteps=60, B=lr.to_device(B0))]
+
+    for adaptive in (None, (1e-8, 1e-11)):
+        its = items()
+        b = lr.Batch(its, packed=True, parts=4, adaptive=adaptive, stream=torch.cuda.current_stream())
+        b.wait_limits(spins=2000, never=True)
+        b.run()
+        rc, codes, steps = b.status()
+        print(f"[failure] split batch (adaptive {adaptive}) with expiring waits: codes {codes}, steps {steps}")
+        assert codes == [lr.LR_ERR_TIMEOUT]
+        b.wait_limits()
+        its[0]["B"].copy_(lr.to_device(B0))
+        b.run()
+        assert b.status()[0] == lr.LR_OK
+        its2 = items()
+        b2 = lr.Batch(its2, packed=True, parts=4, adaptive=adaptive)
+        b2.run()
+        assert b2.status()[0] == lr.LR_OK
+        assert np.array_equal(lr.from_device(its[0]["B"]), lr.from_device(its2[0]["B"]))
+        b.close()
+        b2.close()

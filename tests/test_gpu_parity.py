@@ -1503,3 +1503,154 @@ def test_apply_heff_rejections(lr):
         lr.apply_heff(big, p, 0.0, torch.zeros((1, big.N), dtype=torch.complex128, device="cuda"))
     with pytest.raises(lr.LrError):                                    # B and Z overlap
         lr.apply_heff(m, p, 0.0, B, B)
+
+
+# ------------------------------------------------------------ layer-split packed trajectories
+
+def _run_split(lr, items, parts, adaptive=None):
+    b = lr.Batch(items, packed=True, parts=parts, adaptive=adaptive)
+    b.run()
+    rc, codes, steps = b.status()
+    stats = b.adaptive_stats() if adaptive is not None else None
+    b.close()
+    return rc, codes, stats
+
+
+@pytest.mark.parametrize("parts", [2, 3, 13, 255])
+def test_split_matches_oracle(lr, parts):
+    """Packed trajectories split over `parts` workgroups each (ragged layer ranges; more parts than
+    layers gives one layer per part; a one-layer model runs as one part), mixed shapes and ranks in one
+    cooperative launch, a drive-frame stepwise pulse, against the oracle."""
+    import torch
+    items = _batch_items(lr, BATCH_SPECS)
+    m = I.readout_model(3, 7, 4).replace(kappa_f=0.5, gamma_1=0.05)
+    p = _stepwise(20, 83).replace(frame=1)
+    B0 = I.initial_state(m, 4, "e", seed=84, scale=1e-3)
+    items.append(dict(model=m, M=4, pulse=p, dt=1e-3, nsteps=203, B0=B0, B=lr.to_device(B0), obs_stride=7,
+                      obs=torch.zeros((203 // 7 + 1, 6 + 3), dtype=torch.float64, device="cuda")))
+    m1 = I.readout_model(4, 1, 5).replace(kappa_f=0.5, gamma_1=0.05)
+    B1 = I.initial_state(m1, 3, "g", seed=85, scale=1e-2)
+    items.append(dict(model=m1, M=3, pulse=p, dt=1e-3, nsteps=90, B0=B1, B=lr.to_device(B1), obs_stride=30,
+                      obs=torch.zeros((4, 6 + 4), dtype=torch.float64, device="cuda")))
+    rc, codes, _ = _run_split(lr, items, parts)
+    assert rc == lr.LR_OK, codes
+    for it in items:
+        Bo, ref, tol = oracle_with_tol(it["model"], it["pulse"], 0.0, it["dt"], it["nsteps"], it["B0"],
+                                       it["obs_stride"])
+        err = np.max(np.abs(lr.from_device(it["B"]) - Bo))
+        what = f"split x{parts} dims {it['model'].d_q, it['model'].d_r, it['model'].d_f} M={it['M']}"
+        print(f"[parity] {what}: |dB| {err:.3e}")
+        assert err <= 1e-10
+        if it["obs_stride"]:
+            _assert_obs(it["obs"].cpu().numpy(), ref, what, tol)
+
+
+@pytest.mark.parametrize("parts", [2, 5, 255])
+def test_split_model_kinds_1_2_match_oracle(lr, parts):
+    """The paper's Hamiltonian with the transmon in its eigenbasis (kind 1) and in the normal-mode basis
+    (kind 2: the cross-layer term Q across every part boundary, one-layer parts at 255), split over
+    `parts` workgroups, both frames, against the oracle."""
+    from paper_2508_18114_amd import transmon
+    small1 = transmon.paper_model(4, 6, 4).replace(kappa_f=0.5, gamma_1=0.05, g=0.9, G=0.4)
+    small2 = _nm_model(4, 7, 4, J=1.1, kappa_f=0.6, gamma_1=0.05, g=0.9)
+    paper2 = _nm_model(5, 14, 4)
+    pw = I.stepwise_pulse(I.ghz(0.15) * np.array([1.0, 1.0j, 0.7]), 0.5, sigma=0.05, w_d=transmon.PAPER_W_DRIVE)
+    cases = [(small1, 4, _stepwise(8, 102, T=0.3).replace(w_d=transmon.PAPER_W_DRIVE), 1e-3, 240, 40),
+             (small1, 4, _stepwise(8, 103, T=0.3).replace(w_d=transmon.PAPER_W_DRIVE, frame=1), 1e-3, 240, 40),
+             (small2, 4, _stepwise(8, 202, T=0.3).replace(w_d=transmon.PAPER_W_DRIVE), 1e-3, 240, 40),
+             (small2, 4, _stepwise(8, 203, T=0.3).replace(w_d=transmon.PAPER_W_DRIVE, frame=1), 1e-3, 240, 40),
+             (paper2, 8, pw.replace(frame=1), 5e-4, 600, 100)]
+    items = [_tm_items(lr, m, M, p, dt, n, s) for (m, M, p, dt, n, s) in cases]
+    rc, codes, _ = _run_split(lr, items, parts)
+    assert rc == lr.LR_OK, codes
+    for it in items:
+        Bo, ref, tol = oracle_with_tol(it["model"], it["pulse"], 0.0, it["dt"], it["nsteps"], it["B0"],
+                                       it["obs_stride"])
+        _assert_obs(it["obs"].cpu().numpy(), ref,
+                    f"split x{parts} kind {it['model'].kind} dims {it['model'].d_q, it['model'].d_r, it['model'].d_f} "
+                    f"frame {it['pulse'].frame}", tol)
+        assert np.max(np.abs(lr.from_device(it["B"]) - Bo)) <= 1e-10
+
+
+@pytest.mark.parametrize("parts", [2, 255])
+def test_split_adaptive_matches_oracle(lr, parts):
+    """Adaptive Dormand-Prince steps of split trajectories (kinds 0, 1 and 2; the error norm summed over
+    the parts), against the oracle's adaptive integration: step counts within 3 and the records."""
+    from oracle import adaptive
+    from paper_2508_18114_amd import transmon
+    it0 = _adaptive_case(lr, I.FRAME_DRIVE)
+    m1 = transmon.paper_model(4, 8, 4).replace(kappa_f=0.3, gamma_1=0.02)
+    p1 = I.stepwise_pulse(I.ghz(0.15) * np.array([1.0j, 0.8j]), 1.0, sigma=0.1,
+                          w_d=transmon.PAPER_W_DRIVE).replace(frame=1)
+    it1 = _tm_items(lr, m1, 4, p1, 0.1, 10, 2)
+    m2 = _nm_model(4, 8, 3, J=1.1, kappa_f=0.4, gamma_1=0.02, g=0.8)
+    it2 = _tm_items(lr, m2, 4, p1, 0.1, 8, 2, seed=238)
+    items = [it0, it1, it2]
+    rc, codes, (acc, rej) = _run_split(lr, items, parts, adaptive=(1e-9, 1e-12))
+    assert rc == lr.LR_OK, codes
+    for k, it in enumerate(items):
+        _, ref, acc_o, rej_o = adaptive.integrate(it["model"], it["pulse"], 0.0, it["dt"], it["nsteps"], it["B0"],
+                                                  1e-9, 1e-12, obs_stride=it["obs_stride"])
+        what = f"split x{parts} adaptive kind {it['model'].kind}"
+        print(f"[parity] {what}: steps gpu {acc[k]}+{rej[k]}, oracle {acc_o}+{rej_o}")
+        got = it["obs"].cpu().numpy()
+        if it["model"].kind == 0:  # the case of test_adaptive_matches_oracle: records to 1e-7
+            scale = max(1.0, np.max(np.abs(ref[:, 0:4])))
+            assert np.max(np.abs(got[:, 0:4] - ref[:, 0:4])) / scale <= 1e-7
+            assert np.max(np.abs(got[:, 4:] - ref[:, 4:])) <= 1e-7
+        else:
+            _assert_obs(got, ref, what)
+        assert abs(acc[k] - acc_o) <= 3 and abs(rej[k] - rej_o) <= 3
+
+
+def test_split_paper_size_matches_oracle(lr):
+    """Paper size (N = 2000, M = 20), g and e split over 25 workgroups each (two layers per part), the
+    first 6000 RK4 steps against the cached oracle run with the paper-size floor tolerances; and 2 ns of
+    adaptive steps in the drive frame over 50 parts against the cached adaptive oracle run."""
+    import torch
+    trajs = I.config_paper_size()
+    gd = _golden("paper_size")
+    tol = _golden_tol("paper_size")
+    stride, n = int(gd["stride"]), 6000
+    items = [dict(model=t.model, M=t.M, pulse=t.pulse, dt=t.dt, nsteps=n, B=lr.to_device(t.B0()),
+                  obs_stride=stride, obs=torch.zeros((n // stride + 1, 6 + t.model.d_q), dtype=torch.float64,
+                                                     device="cuda"))
+             for t in trajs]
+    rc, codes, _ = _run_split(lr, items, 25)
+    assert rc == lr.LR_OK, codes
+    for it, key in zip(items, ("obs_g", "obs_e")):
+        _assert_obs(it["obs"].cpu().numpy(), gd[key][:n // stride + 1], f"split x25 paper size {key} (3 ns)", tol)
+    ga = np.load(os.path.join(HERE, "golden", "adaptive_paper_size.npz"))
+    dt, n, stride = float(ga["dt"]), int(ga["nsteps"]), int(ga["stride"])
+    items = [dict(model=t.model, M=t.M, pulse=t.pulse.replace(frame=I.FRAME_DRIVE), dt=dt, nsteps=n,
+                  B=lr.to_device(t.B0()), obs_stride=stride,
+                  obs=torch.zeros((n // stride + 1, 6 + t.model.d_q), dtype=torch.float64, device="cuda"))
+             for t in trajs]
+    rc, codes, (acc, rej) = _run_split(lr, items, 50, adaptive=(float(ga["rtol"]), float(ga["atol"])))
+    assert rc == lr.LR_OK, codes
+    for k, (it, key) in enumerate(zip(items, ("g", "e"))):
+        e = _obs_errors(it["obs"].cpu().numpy(), ga["obs_" + key])
+        print(f"[adaptive] split x50 paper size 2 ns drive frame {key}: gpu {acc[k]} + {rej[k]} rejected, oracle "
+              f"{int(ga['acc_' + key])} + {int(ga['rej_' + key])}; field err {e['field']:.3e}, populations err "
+              f"{e['pop']:.3e}")
+        assert abs(acc[k] - int(ga["acc_" + key])) <= 3 and abs(rej[k] - int(ga["rej_" + key])) <= 3
+        assert e["field"] <= 1e-9 and e["pop"] <= 1e-9 and e["trace"] <= 1e-9
+
+
+def test_split_rejections_and_graph(lr):
+    """A split batch refuses graph capture (cooperative launches); reduced-precision trajectories stay
+    one workgroup each in a split batch; unknown adaptive flags are refused."""
+    import torch
+    m = I.readout_model(4, 6, 5)
+    p = I.flattop_pulse(0.05, 0.1, t_ramp=0.02)
+    b = lr.Batch([dict(model=m, M=4, pulse=p, dt=1e-3, nsteps=10, B=lr.to_device(I.initial_state(m, 4, "e", 1)))],
+                 packed=True, parts=3, stream=torch.cuda.Stream())
+    with pytest.raises(lr.LrError):
+        b.graph(True)
+    b.close()
+    its = [dict(model=m, M=6, pulse=p, dt=1e-3, nsteps=30, precision=prec,
+                B=lr.to_device(I.initial_state(m, 6, "e", 92, scale=1e-2))) for prec in (0, 1)]
+    rc, codes, _ = _run_split(lr, its, 3)
+    assert rc == lr.LR_OK, codes
+    with pytest.raises(lr.LrError):
+        lr.Batch([_adaptive_case(lr, I.FRAME_DRIVE)], adaptive=(1e-8, 1e-11), flags=lr.LR_BATCH_PACKED_MFMA64)
