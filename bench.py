@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--paper-setup", type=int, default=0, metavar="PULSES",
                     help="only run the paper's own set-up (normal-mode basis, N=2000, M=20, drive frame, "
                          "tau=40 ns, adaptive steps) alone and for PULSES pulses x g/e, and print wall times")
+    ap.add_argument("--paper-spsa", type=int, default=0, metavar="EPOCHS",
+                    help="only run EPOCHS steps of the paper's SPSA loop on its own set-up (normal-mode basis, "
+                         "N=2000, M=20, drive frame, tau=40 ns, adaptive steps; four trajectories per step, each "
+                         "split over 50 workgroups) and print the wall time per step and the losses")
     ap.add_argument("--paper-setup-parts", type=int, default=100, metavar="P",
                     help="workgroups per trajectory of the lone g/e pair of --paper-setup (layer-split packed "
                          "kernel; 1: one workgroup)")
@@ -547,6 +551,39 @@ def paper_setup(lr, I, torch, n_pulses, rtol=1e-8, atol=1e-10, parts=100):
                         f"batch (one workgroup per trajectory)"}
 
 
+def paper_spsa(lr, I, torch, epochs, parts=50, rtol=1e-8, atol=1e-10):
+    """Steps of the paper's optimisation loop (supplement S3.C) on its own set-up: SPSA over the four
+    complex heights of the smoothed stepwise pulse from the square start, each step two loss
+    evaluations (theta +- c_k Delta) = four trajectories at N = 2000, M = 20 in one adaptive batch, each
+    trajectory split over `parts` workgroups.  Context: the paper quotes about 1.2e4 s for O(100)
+    epochs of two loss evaluations on a laptop CPU."""
+    import numpy as np
+    from paper_2508_18114_amd import serve, transmon
+    nm = transmon.paper_model_normal(5, 100, 4)
+    walls = []
+    t_last = [time.perf_counter()]
+
+    def on_step(rec):
+        torch.cuda.synchronize()
+        now = time.perf_counter()
+        walls.append(now - t_last[0])
+        t_last[0] = now
+        print(f"[paper spsa] step {rec['k']}: {walls[-1]:.1f} s, loss +{rec['loss_plus']:.4f} "
+              f"-{rec['loss_minus']:.4f}", file=sys.stderr, flush=True)
+
+    theta, hist = serve.spsa_optimize(nm, 20, 40.0, 4, epochs, 0.5, 1, sigma=0.5, frame=I.FRAME_DRIVE,
+                                      w_d=transmon.PAPER_W_DRIVE, adaptive=(rtol, atol), parts=parts,
+                                      on_step=on_step)
+    return {"epochs": epochs, "wall_per_epoch_s": walls, "mean_wall_per_epoch_s": float(np.mean(walls[1:] or walls)),
+            "losses": [[h["loss_plus"], h["loss_minus"]] for h in hist],
+            "eps_a": [[h["eps_a_plus"], h["eps_a_minus"]] for h in hist],
+            "theta": [float(x) for x in theta], "parts_per_trajectory": parts,
+            "workload": f"SPSA (supplement S3.C) on the paper's Hamiltonian in its normal-mode basis (N=2000), M=20, "
+                        f"drive frame, tau=40 ns, four stepwise heights, adaptive Dormand-Prince (rtol {rtol}, atol "
+                        f"{atol}), records every 0.5 ns; per step four trajectories in one batch, each over {parts} "
+                        f"workgroups"}
+
+
 def validity_study(lr, I, torch):
     """Supplement S1.B on the small readout model (N=200, flat-top drive, 1e4
     steps, padding weight 1e-5): the control quantity p_M/p_1 and the purity
@@ -760,6 +797,9 @@ def main():
         return
     if a.apply_sample > 0:
         print(json.dumps(apply_sample(lr, I, torch, a.apply_sample)), flush=True)
+        return
+    if a.paper_spsa > 0:
+        print(json.dumps(paper_spsa(lr, I, torch, a.paper_spsa)), flush=True)
         return
     if a.paper_setup > 0:
         print(json.dumps(paper_setup(lr, I, torch, a.paper_setup, parts=a.paper_setup_parts)), flush=True)

@@ -75,7 +75,10 @@ typedef struct { double re, im; } lr_c64;
  *   truncated operators.  In the drive frame every creation term of f carries
  *   e^{i w_d t} and every annihilation term e^{-i w_d t}.  Packed batches
  *   only, fixed RK4 or adaptive steps (LR_ERR_ARG elsewhere), FP64,
- *   d_q <= LR_MAX_DQ.
+ *   d_q <= LR_MAX_DQ.  Its records hold <c_l> in the <a> columns and the
+ *   filter field <f> (f as above, the field of the readout separation) in the
+ *   <f> columns; in the drive frame <f> is e^{i w_d t} times its lab-frame
+ *   value, as for the other kinds, t the record's time.
  * Kinds 0 and 1: L_1 = sqrt(kappa_f) f; every kind: L_2 = sqrt(gamma_1) b, b
  * the ladder sum_n sqrt(n) |n-1><n| of the transmon levels. */
 #define LR_MODEL_DUFFING 0

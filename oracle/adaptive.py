@@ -110,7 +110,7 @@ def integrate(model, pulse, t0, grid, nsteps, B0, rtol, atol, obs_stride=0, dt0=
     ys, acc, rej = integrate_ode(fun, t0, B0, t_out, grid if dt0 is None else dt0, rtol, atol)
     rec = []
     if obs_stride > 0:
-        rec.append(lowrank.observables(model, np.asarray(B0)))
-        rec += [lowrank.observables(model, y) for y in ys[:n_out]]
+        rec.append(lowrank.observables(model, np.asarray(B0), pulse=pulse, t=t0))
+        rec += [lowrank.observables(model, y, pulse=pulse, t=tk) for y, tk in zip(ys[:n_out], t_out)]
     obs = np.array(rec) if rec else np.zeros((0, 6 + model.d_q))
     return ys[-1], obs, acc, rej

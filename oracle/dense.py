@@ -107,21 +107,28 @@ def frame_hamiltonian(model, pulse, t):
     return hamiltonian(model, d_t)
 
 
-def jump_operators(model, pulse=None, t=0.0):
-    """sqrt(kappa_f) f and sqrt(gamma_1) b.  kind 2: f = s_21 c_u^ + s_22 c_l^ + s_23 c_l + s_24 c_u in the
+def filter_operator(model, pulse=None, t=0.0):
+    """Kind 2: the filter's annihilation operator f = s_21 c_u^ + s_22 c_l^ + s_23 c_l + s_24 c_u in the
     normal-mode basis, turned into the frame of the pulse as U f U^ (U = exp(i w_d t n), n = q + n_r +
-    n_f) in the drive frame; for kinds 0 and 1 that rotation is a global phase, which leaves the
-    dissipator unchanged."""
+    n_f) in the drive frame."""
+    b, a, f = operators(model)
+    S = _normal_constants(model)[0]
+    fn = S[1, 0] * f.conj().T + S[1, 1] * a.conj().T + S[1, 2] * a + S[1, 3] * f
+    if pulse is not None and getattr(pulse, "frame", 0) == 1:
+        n = np.array([q + r + k for q in range(model.d_q) for r in range(model.d_r) for k in range(model.d_f)],
+                     dtype=np.float64)
+        u = np.exp(1j * pulse.w_d * t * n)
+        fn = u[:, None] * fn * np.conj(u)[None, :]
+    return fn
+
+
+def jump_operators(model, pulse=None, t=0.0):
+    """sqrt(kappa_f) f and sqrt(gamma_1) b.  kind 2: f in the normal-mode basis and the frame of the
+    pulse (filter_operator); for kinds 0 and 1 the frame rotation of f is a global phase, which leaves
+    the dissipator unchanged."""
     b, a, f = operators(model)
     if getattr(model, "kind", 0) == 2:
-        S = _normal_constants(model)[0]
-        fn = S[1, 0] * f.conj().T + S[1, 1] * a.conj().T + S[1, 2] * a + S[1, 3] * f
-        if pulse is not None and getattr(pulse, "frame", 0) == 1:
-            n = np.array([q + r + k for q in range(model.d_q) for r in range(model.d_r) for k in range(model.d_f)],
-                         dtype=np.float64)
-            u = np.exp(1j * pulse.w_d * t * n)
-            fn = u[:, None] * fn * np.conj(u)[None, :]
-        return [np.sqrt(model.kappa_f) * fn, np.sqrt(model.gamma_1) * b]
+        return [np.sqrt(model.kappa_f) * filter_operator(model, pulse, t), np.sqrt(model.gamma_1) * b]
     return [np.sqrt(model.kappa_f) * f, np.sqrt(model.gamma_1) * b]
 
 
@@ -147,11 +154,16 @@ def lowrank_rhs_pinv(model, pulse, t, B):
     return out
 
 
-def observables(model, rho):
-    """Same record as lowrank.observables, computed from a dense rho."""
+def observables(model, rho, pulse=None, t=0.0):
+    """Same record as lowrank.observables, computed from a dense rho (kind 2: <f> = e1 tr(U f U^ rho)
+    with the filter operator of filter_operator, e1 = e^{i w_d t} in the drive frame, 1 in the lab
+    frame)."""
     b, a, f = operators(model)
     ea = np.trace(a @ rho)
     ef = np.trace(f @ rho)
+    if getattr(model, "kind", 0) == 2:
+        e1 = np.exp(1j * pulse.w_d * t) if pulse is not None and getattr(pulse, "frame", 0) == 1 else 1.0
+        ef = e1 * np.trace(filter_operator(model, pulse, t) @ rho)
     tr = np.trace(rho).real
     tr2 = np.trace(rho @ rho).real
     Pq = []
@@ -166,7 +178,7 @@ def integrate(model, pulse, t0, dt, nsteps, rho0, obs_stride=0):
     """Classic RK4 on the dense rho with the same stage times as the low-rank path."""
     rho = np.array(rho0, dtype=np.complex128, copy=True)
     fun = lambda t, X: lindbladian(model, pulse, t, X)  # noqa: E731
-    rec = [observables(model, rho)] if obs_stride > 0 else []
+    rec = [observables(model, rho, pulse, t0)] if obs_stride > 0 else []
     for n in range(nsteps):
         t = t0 + n * dt
         k1 = fun(t, rho)
@@ -175,5 +187,5 @@ def integrate(model, pulse, t0, dt, nsteps, rho0, obs_stride=0):
         k4 = fun(t + dt, rho + dt * k3)
         rho = rho + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
         if obs_stride > 0 and (n + 1) % obs_stride == 0:
-            rec.append(observables(model, rho))
+            rec.append(observables(model, rho, pulse, t0 + (n + 1) * dt))
     return rho, (np.array(rec) if rec else np.zeros((0, 6 + model.d_q)))

@@ -335,17 +335,27 @@ def rhs(model, pulse, t, B, sum_order="matmul"):
 OBS_HEADER = ("re_a", "im_a", "re_f", "im_f", "tr_rho", "tr_rho2")
 
 
-def observables(model, B, sum_order="matmul"):
+def observables(model, B, sum_order="matmul", pulse=None, t=0.0):
     """[Re<a>, Im<a>, Re<f>, Im<f>, tr rho, tr rho^2, P_q(0..d_q-1)].
 
     <O> = tr(O rho) = sum_j b_j^ O b_j (unnormalised); tr rho^2 = ||B^ B||_F^2
     (since tr (B B^)^2 = tr (B^ B)^2); P_q(k) = tr(|k><k|_q rho).  The two fields
-    are those of the lowering operators of the resonator and filter slots: for
-    kind 2 the normal-mode fields <c_l>, <c_u>.
+    are those of the lowering operators of the resonator and filter slots, in
+    the frame of the state (in the drive frame e^{i w_d t} times the lab-frame
+    field).  Kind 2 (normal-mode basis): <a> is the lower mode's <c_l>, and <f>
+    is the filter field that the readout separation takes (S2.D: f = s_21 c_u^ +
+    s_22 c_l^ + s_23 c_l + s_24 c_u), e^{i w_d t} <f>_lab in the drive frame,
+    which is s_23 <c_l> + s_24 <c_u> + e^{2 i w_d t} (s_21 <c_u>* + s_22 <c_l>*)
+    in terms of the drive-frame mode fields (pulse, t: the frame and the time of
+    the record).
     """
     T = _as_tensor(model, B)
     a = total(T.conj() * lower(T, 1), sum_order)
     f = total(T.conj() * lower(T, 2), sum_order)
+    if getattr(model, "kind", 0) == 2:
+        s21, s22, s23, s24 = normal_mode_constants(model)[0][1]
+        e2 = _frame_phase(pulse, t) ** 2
+        f = s23 * a + s24 * f + e2 * (s21 * np.conj(f) + s22 * np.conj(a))
     tr = total(np.abs(T) ** 2, sum_order)
     G = inner(B, B, sum_order)
     tr2 = np.sum(np.abs(G) ** 2)
@@ -377,10 +387,10 @@ def integrate(model, pulse, t0, dt, nsteps, B0, obs_stride=0, sum_order="matmul"
     fun = lambda t, X: rhs(model, pulse, t, X, sum_order)  # noqa: E731
     rec = []
     if obs_stride > 0:
-        rec.append(observables(model, B, sum_order))
+        rec.append(observables(model, B, sum_order, pulse, t0))
     for n in range(nsteps):
         B = rk4_step(fun, t0 + n * dt, dt, B)
         if obs_stride > 0 and (n + 1) % obs_stride == 0:
-            rec.append(observables(model, B, sum_order))
+            rec.append(observables(model, B, sum_order, pulse, t0 + (n + 1) * dt))
     obs = np.array(rec) if rec else np.zeros((0, 6 + model.d_q))
     return B, obs

@@ -425,8 +425,25 @@ __global__ __launch_bounds__(kWG) void k_obs(const TrajDev* __restrict__ trajs, 
     if (threadIdx.x == 0) rec[6 + q] = s;
   }
   const double s_ar = block_sum(ar, red), s_ai = block_sum(ai, red);
-  const double s_fr = block_sum(fr, red), s_fi = block_sum(fi, red);
+  double s_fr = block_sum(fr, red), s_fi = block_sum(fi, red);
   const double s_tr = block_sum(tr, red);
+  if (T.mkind == 2) {
+    // normal-mode basis: the filter field f = s21 c_u^ + s22 c_l^ + s23 c_l + s24 c_u (supplement S2.D)
+    // from the mode fields <c_l> (resonator slot) and <c_u> (filter slot); in the drive frame the
+    // creation terms carry e^{2 i w_d t} (the record is e^{i w_d t} times the lab-frame field, as for
+    // the other kinds)
+    double2 e2 = make_double2(1.0, 0.0);
+    if (T.frame) {
+      const double2 e1 = frame_phase(T.w_d, T.t0 + (double)(T.step_base + step) * T.dt);
+      e2 = cmul(e1, e1);
+    }
+    const double2 cl = make_double2(s_ar, s_ai), cu = make_double2(s_fr, s_fi);
+    const double2 cr = make_double2(T.nm[0] * cu.x + T.nm[1] * cl.x, -(T.nm[0] * cu.y + T.nm[1] * cl.y));
+    const double2 an = make_double2(T.nm[2] * cl.x + T.nm[3] * cu.x, T.nm[2] * cl.y + T.nm[3] * cu.y);
+    const double2 fv = cadd(an, cmul(e2, cr));
+    s_fr = fv.x;
+    s_fi = fv.y;
+  }
   if (threadIdx.x == 0) {
     rec[0] = s_ar;
     rec[1] = s_ai;

@@ -399,14 +399,16 @@ def project_heights(theta: np.ndarray, bound: float = I.ghz(0.4) * (1.0 - 1e-9))
 
 def pulse_loss_batch(model: I.ModelParams, M: int, pulses, dt: float, nsteps: int, obs_stride: int,
                      pad_scale: float = I.PAPER_PAD_SCALE, seed: int = 0, stream=None, packed=None,
-                     adaptive=None):
+                     adaptive=None, parts: int = 0):
     """Readout loss Lambda (and its figures of merit) of each pulse: the g and e
     trajectories of every pulse integrated together in one batch, the loss of
     each g/e pair formed on the device.  packed: the packed schedule (default:
-    on for the transmon-eigenbasis model, which runs only there); adaptive:
-    (rtol, atol) for adaptive steps, dt then being the output grid."""
+    on for the paper's models, kinds 1 and 2, which run only there); adaptive:
+    (rtol, atol) for adaptive steps, dt then being the output grid; parts: each
+    FP64 trajectory split over that many workgroups (latency when few pulses
+    are evaluated at once)."""
     if packed is None:
-        packed = getattr(model, "kind", 0) == I.MODEL_TRANSMON
+        packed = getattr(model, "kind", 0) in (I.MODEL_TRANSMON, I.MODEL_NORMAL)
     import torch
     items = []
     nrec = nsteps // obs_stride + 1
@@ -416,7 +418,7 @@ def pulse_loss_batch(model: I.ModelParams, M: int, pulses, dt: float, nsteps: in
             items.append(dict(model=model, M=M, pulse=p, dt=dt, nsteps=nsteps, B=lr.to_device(B0),
                               obs_stride=obs_stride,
                               obs=torch.zeros((nrec, 6 + model.d_q), dtype=torch.float64, device="cuda")))
-    b = lr.Batch(items, stream=stream, packed=packed, adaptive=adaptive)
+    b = lr.Batch(items, stream=stream, packed=packed, adaptive=adaptive, parts=parts)
     b.run()
     rc, codes, steps = b.status()
     if rc != lr.LR_OK:
@@ -442,22 +444,26 @@ def square_start(model: I.ModelParams, nh: int, amp: float = I.ghz(0.15)) -> np.
 
 def spsa_optimize(model: I.ModelParams, M: int, T: float, nh: int, iters: int, dt: float, obs_stride: int,
                   seed: int = 1, a: float = 0.05, c: float = 0.05, sigma: float = 0.5,
-                  frame: int = I.FRAME_DRIVE, stream=None, w_d: float = I.W_DRIVE, adaptive=None):
+                  frame: int = I.FRAME_DRIVE, stream=None, w_d: float = I.W_DRIVE, adaptive=None, parts: int = 0,
+                  on_step=None):
     """The optimisation loop of supplement S3.C on the device: SPSA over the nh
     complex heights of the smoothed stepwise pulse, started from the square shape
     of amplitude 2 pi 150 MHz (square_start), each step evaluating theta +- c_k
-    Delta in one batch of four trajectories.  Returns (theta, history) with the
-    loss at both probes of every step."""
+    Delta in one batch of four trajectories (each split over `parts` workgroups
+    when given).  Returns (theta, history) with the loss at both probes of every
+    step; on_step(record) is called after each step."""
     opt = SPSA(square_start(model, nh), seed, a=a, c=c, project=project_heights)
     hist = []
     for _ in range(iters):
         tp, tm = opt.ask()
         pulses = [I.stepwise_pulse(heights_from(x), T, sigma=sigma, w_d=w_d).replace(frame=frame) for x in (tp, tm)]
         fp, fm = pulse_loss_batch(model, M, pulses, dt, int(round(T / dt)), obs_stride, stream=stream,
-                                  adaptive=adaptive)
+                                  adaptive=adaptive, parts=parts)
         opt.tell(fp["loss"], fm["loss"])
         hist.append({"k": opt.k, "loss_plus": fp["loss"], "loss_minus": fm["loss"],
                      "eps_a_plus": fp["eps_a"], "eps_a_minus": fm["eps_a"]})
+        if on_step is not None:
+            on_step(hist[-1])
     return opt.theta, hist
 
 

@@ -788,6 +788,34 @@ def test_normal_model_drive_frame_is_the_transformed_lab_rhs():
         assert np.max(np.abs(lhs - ref)) <= 1e-11 * np.max(np.abs(ref))
 
 
+def test_normal_model_record_is_the_filter_field():
+    """Kind 2: the record's <f> is the filter field that the readout separation takes (eq. for beta,
+    S2.D: f = s_21 c_u^ + s_22 c_l^ + s_23 c_l + s_24 c_u), brute force from Kronecker-built ladder
+    matrices: tr(f rho) in the lab frame; in the drive frame, for the rotated state B' = U B,
+    e^{i w_d t} tr(f rho) (the convention of the other kinds' fields) with rho the lab-frame state.  The
+    upper mode's own field <c_u> (the slot's lowering operator) is far from it.  Also the dense oracle's
+    record."""
+    m = _normal_model(3, 3, 3)
+    B = _rand_B(m.N, 3, 84)
+    cl, cu = dense.operators(m)[1:]
+    S = np.asarray(m.S).reshape(2, 4)
+    F = S[1, 0] * cu.conj().T + S[1, 1] * cl.conj().T + S[1, 2] * cl + S[1, 3] * cu
+    rho = B @ B.conj().T
+    ref = np.trace(F @ rho)
+    rec = lowrank.observables(m, B, pulse=PULSE, t=0.8)
+    assert abs(complex(rec[2], rec[3]) - ref) <= 1e-12 * abs(ref)
+    assert abs(complex(rec[0], rec[1]) - np.trace(cl @ rho)) <= 1e-12 * abs(ref)
+    assert abs(np.trace(cu @ rho) - ref) > 1e-2 * abs(ref)
+    for t in (0.0, 0.8, 3.3):
+        u, _ = _frame_phase(m, PULSE.w_d, t)
+        Br = u[:, None] * B
+        rec = lowrank.observables(m, Br, pulse=ROT, t=t)
+        want = np.exp(1j * PULSE.w_d * t) * ref
+        assert abs(complex(rec[2], rec[3]) - want) <= 1e-12 * abs(ref)
+        drec = dense.observables(m, Br @ Br.conj().T, ROT, t)
+        assert abs(complex(drec[2], drec[3]) - want) <= 1e-12 * abs(ref)
+
+
 def test_package_normal_modes_match_the_oracle():
     """The package's normal modes (model input for the device) equal the oracle's pinned ones."""
     from paper_2508_18114_amd import transmon
