@@ -419,8 +419,8 @@ int lr_batch_run(lr_batch_t* batch);
  * lr_batch_init); kernel timing (lr_batch_profile_*) is not recorded while on.
  * on = 0 drops the graph.  LR_ERR_STATE before lr_batch_bind, when the batch
  * is bound to the null stream (which cannot be captured), or when a
- * trajectory runs in the spread schedule (its cooperative launches are not
- * captured). */
+ * trajectory runs in the spread schedule or is layer-split
+ * (LR_BATCH_PACKED_PARTS; their cooperative launches are not captured). */
 int lr_batch_graph(lr_batch_t* batch, int32_t on);
 /* Synchronise; per-trajectory status codes and failing step indices
  * (arrays of n, may be NULL).  Returns the first non-OK code or LR_OK. */
@@ -431,10 +431,10 @@ int lr_batch_status(lr_batch_t* batch, int32_t* codes, int64_t* failed_steps);
  * again resets the count).  lr_batch_profile_read synchronises the stream and
  * returns the summed kernel time (ms) and the launch count. */
 int lr_batch_profile_enable(lr_batch_t* batch, int32_t on);
-/* lr_wait_limits for every spread-schedule trajectory of a bound batch
- * (enqueued on the bound stream; applies to later lr_batch_run calls; the
- * packed and adaptive kernels have no group barriers).  LR_ERR_STATE before
- * lr_batch_bind. */
+/* lr_wait_limits for every spread-schedule and layer-split trajectory of a
+ * bound batch (enqueued on the bound stream; applies to later lr_batch_run
+ * calls; the one-workgroup packed and adaptive kernels have no group
+ * barriers).  LR_ERR_STATE before lr_batch_bind. */
 int lr_batch_wait_limits(lr_batch_t* batch, uint32_t spins, int32_t never);
 int lr_batch_profile_read(lr_batch_t* batch, double* ms, int64_t* launches);
 void lr_batch_destroy(lr_batch_t* batch);

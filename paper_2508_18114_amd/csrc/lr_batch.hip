@@ -451,23 +451,18 @@ int lr_batch_bind(lr_batch_t* b, void* d_ws, size_t bytes, void* stream) {
     size_t& m = b->packed[t] ? max_lds_packed : max_lds;
     m = std::max(m, b->lds[t]);
   }
-  for (int kp : lrk::kPackedKP)
-    for (int pro = 0; pro < 2; ++pro)
-      if (max_lds_packed > 0 &&
-          (hipFuncSetAttribute(lrk::packed_kernel(kp, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)max_lds_packed) != hipSuccess ||
-           hipFuncSetAttribute(lrk::packed_kernel(kp, pro != 0, true), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)max_lds_packed) != hipSuccess ||
-
-           hipFuncSetAttribute(lrk::dp5_kernel(kp, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)max_lds_packed) != hipSuccess ||
-           hipFuncSetAttribute(lrk::dp5_kernel(kp, pro != 0, true), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)max_lds_packed) != hipSuccess ||
-           hipFuncSetAttribute(lrk::packed_split_kernel(kp, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)max_lds_packed) != hipSuccess ||
-           hipFuncSetAttribute(lrk::dp5_split_kernel(kp, pro != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)max_lds_packed) != hipSuccess))
-        return LR_ERR_HIP;
+  // every packed kernel (one-workgroup chunk and prologue, layer-split chunk; fixed-step and adaptive;
+  // kinds 0/1 and kind 2) may take the largest packed footprint
+  if (max_lds_packed > 0)
+    for (int kp : lrk::kPackedKP)
+      for (int nm = 0; nm < 2; ++nm) {
+        const void* fns[] = {lrk::packed_kernel(kp, false, nm != 0), lrk::packed_kernel(kp, true, nm != 0),
+                             lrk::dp5_kernel(kp, false, nm != 0),    lrk::dp5_kernel(kp, true, nm != 0),
+                             lrk::packed_split_kernel(kp, nm != 0),  lrk::dp5_split_kernel(kp, nm != 0)};
+        for (const void* fn : fns)
+          if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds_packed) != hipSuccess)
+            return LR_ERR_HIP;
+      }
   for (int gm = 0; gm <= 2; ++gm)  // the matrix-core Gram kernels of the packed schedule
     for (int slots = 2; slots <= 3; ++slots)
       for (int pro = 0; pro < 2; ++pro)

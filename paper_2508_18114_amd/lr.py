@@ -518,7 +518,7 @@ class Batch:
         return lr_batch_status(self.handle, len(self.items))
 
     def wait_limits(self, spins=0, never=False):
-        """lr_batch_wait_limits: bounded waits of the spread schedule's group barriers."""
+        """lr_batch_wait_limits: bounded waits of the group barriers (spread schedule, layer-split trajectories)."""
         rc = _lib.lr_batch_wait_limits(self.handle, int(spins), 1 if never else 0)
         if rc != LR_OK:
             raise LrError(rc, "lr_batch_wait_limits")
