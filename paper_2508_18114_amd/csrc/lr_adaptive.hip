@@ -158,7 +158,8 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
         if (r_hi < d_r) {
           __syncthreads();
           if (wait && !split_wait_above(T, SS, &s_ok)) return -8;
-          for (int e = tid; e < LM; e += kTW) Ot[e] = ldS(upper + (size_t)r_hi * LM + e);
+          double2* const w1[1] = {Ot};
+          split_load_layers<1>(w1, upper, r_hi, d_r, LM);
           __syncthreads();
           packed_terms_q<KP>(acc, PM, Ot, Op, sk * sq[r_hi]);
         }
@@ -265,19 +266,21 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
       Yc = lds + LM;
       Yn = lds + 2 * LM;
     }
-    const g_double2* in0 = in + (size_t)r_lo * LM;
-    for (int e = tid; e < LM; e += kTW) Yc[e] = ldS(in0 + e);
-    if (r_lo + 1 < d_r)
-      for (int e = tid; e < LM; e += kTW) Yn[e] = ldS(in0 + LM + e);
-    if constexpr (SPLIT)
-      if (r_lo > 0)
-        for (int e = tid; e < LM; e += kTW) Yp[e] = ldS(in0 - LM + e);
-    if constexpr (NM) {
-      if (r_lo + 2 < d_r)
-        for (int e = tid; e < LM; e += kTW) Yp2[e] = ldS(in0 + 2 * LM + e);
-      if constexpr (SPLIT)
-        if (r_lo > 1)
-          for (int e = tid; e < LM; e += kTW) Ym2[e] = ldS(in0 - 2 * LM + e);
+    if constexpr (SPLIT) {  // the window around the part's first layer, all loads in flight together
+      if constexpr (NM) {
+        double2* const w5[5] = {Ym2, Yp, Yc, Yn, Yp2};
+        split_load_layers<5>(w5, in, r_lo - 2, d_r, LM);
+      } else {
+        double2* const w3[3] = {Yp, Yc, Yn};
+        split_load_layers<3>(w3, in, r_lo - 1, d_r, LM);
+      }
+    } else {
+      for (int e = tid; e < LM; e += kTW) Yc[e] = ld_g(in + e);
+      if (d_r > 1)
+        for (int e = tid; e < LM; e += kTW) Yn[e] = ld_g(in + LM + e);
+      if constexpr (NM)
+        if (d_r > 2)
+          for (int e = tid; e < LM; e += kTW) Yp2[e] = ld_g(in + 2 * LM + e);
     }
     if constexpr (SPLIT)
       if (s < 7) ++SS.c;
@@ -333,18 +336,18 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
               }
               const double2 kk = make_double2(z.y + 0.5 * a.x, -z.x + 0.5 * a.y);
               const size_t gi = ((size_t)r * L + rl) * M + ej;
-              stS(kout + gi, kk);
+              st_g(kout + gi, kk);  // the stage derivatives' rows are the part's own
               if (s < 7) {
                 double2 sum = cscale(kDpA[s][s - 1], kk);
                 for (int j = 0; j < s - 1; ++j)
-                  if (kDpA[s][j] != 0.0) sum = cfma(kDpA[s][j], ldS(Kbuf(kslot[j]) + gi), sum);
+                  if (kDpA[s][j] != 0.0) sum = cfma(kDpA[s][j], ld_g(Kbuf(kslot[j]) + gi), sum);
                 const double2 o = cfma(hc, sum, ldS(ysrc + gi));
                 stS(out + gi, o);
                 Ot[rl * M + ej] = o;
               } else {
                 double2 ev = cscale(kDpE[6], kk);
                 for (int j = 0; j < 6; ++j)
-                  if (kDpE[j] != 0.0) ev = cfma(kDpE[j], ldS(Kbuf(kslot[j]) + gi), ev);
+                  if (kDpE[j] != 0.0) ev = cfma(kDpE[j], ld_g(Kbuf(kslot[j]) + gi), ev);
                 const double2 yo = ldS(ysrc + gi), yn = Yc[rl * M + ej];
                 const double sc = A.atol + A.rtol * fmax(sqrt(yo.x * yo.x + yo.y * yo.y), sqrt(yn.x * yn.x + yn.y * yn.y));
                 const double ex = hc * ev.x / sc, ey = hc * ev.y / sc;
@@ -361,8 +364,14 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
       // filter jump of layer r + 1
       const int rnx = NM ? r + 3 : r + 2;
       double2* dstl = NM ? Ym2 : Yp;
-      if (rnx < (SPLIT ? min(d_r, r_hi + (NM ? 2 : 1)) : d_r))
-        for (int e = tid; e < LM; e += kTW) dstl[e] = ldS(in + (size_t)rnx * LM + e);
+      if (rnx < (SPLIT ? min(d_r, r_hi + (NM ? 2 : 1)) : d_r)) {
+        if constexpr (SPLIT) {
+          double2* const w1[1] = {dstl};
+          split_load_layers<1>(w1, in, rnx, d_r, LM);
+        } else {
+          for (int e = tid; e < LM; e += kTW) dstl[e] = ld_g(in + (size_t)rnx * LM + e);
+        }
+      }
       if constexpr (NM)
         if (r + 1 < r_hi) jump_tile(Y1n, Yc, Yn, Yp2, r + 1, e1j);
       if (s < 7) add_terms(r);
@@ -433,7 +442,7 @@ __device__ __forceinline__ void dp5_body(const TrajDev& T, const AdaptDev& A, in
           const size_t gi = (size_t)r * LM + e;
           const double2 y = ldS(ysrc + gi);
           if (copy) stS(gBb + gi, y);
-          const double2 o = cfma(hc * kDpA[1][0], ldS(k1 + gi), y);
+          const double2 o = cfma(hc * kDpA[1][0], ld_g(k1 + gi), y);
           stS(gS[0] + gi, o);
           Ot[e] = o;
         }

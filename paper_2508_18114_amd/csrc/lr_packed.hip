@@ -736,6 +736,31 @@ __device__ __forceinline__ int split_lo(int w, int P, int d_r) { return (int)(((
 // Entries of the Gram terms a part publishes (M x 3M; kind 2: M x 4M).
 __host__ __device__ inline int split_npe(int M, int kind) { return M * (kind == 2 ? 4 : 3) * M; }
 
+// Layers r0 .. r0 + NL - 1 of a stage state in global memory into the LDS tiles dst[0 .. NL) (layers
+// outside [0, d_r) are skipped), through agent-coherent loads that are all in flight before the
+// first LDS store of a block (the loads of another part's layers are round trips through memory).
+template <int NL>
+__device__ __forceinline__ void split_load_layers(double2* const (&dst)[NL], const g_double2* src, int r0,
+                                                  int d_r, int LM) {
+  for (int e0 = 0; e0 < LM; e0 += 2 * kTW) {
+    double2 v[NL][2];
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int r = r0 + l, e = e0 + (int)threadIdx.x + u * kTW;
+        v[l][u] = (r >= 0 && r < d_r && e < LM) ? ld_ag(src + (size_t)r * LM + e) : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int r = r0 + l, e = e0 + (int)threadIdx.x + u * kTW;
+        if (r >= 0 && r < d_r && e < LM) dst[l][e] = v[l][u];
+      }
+  }
+}
+
 // Wait until one flag reaches target (bounded; raises the group's abort flag
 // when the wait expires).
 __device__ __forceinline__ bool flag_wait_one(const TrajDev& T, const g_u32* flag, uint32_t target, int* s_ok) {
@@ -785,17 +810,30 @@ __device__ bool split_sum(const TrajDev& T, double2 (&acc)[KP], const PackedMap&
   g_u32* fB = (g_u32*)T.flagB;
   flag_arrive(fA + (size_t)S.w * kFlagStride, ++S.a);
   if (!flag_wait(T, fA, S.a, s_ok)) return false;
-  // slice of the entries: a 16-lane group per entry, lane l adds the parts l,
-  // l + 16, ... in order, then a butterfly over the group (order fixed by P)
+  // slice of the entries: a group of G lanes per entry (G = 1 .. 16, the
+  // smallest power of two with at most 8 parts per lane, else 16), lane l adds
+  // the parts l, l + G, ... in order with up to 8 loads in flight, then a
+  // butterfly over the group; the order depends on P only
   const int cs = (npe + np - 1) / np, e0 = S.w * cs, e1 = min(npe, e0 + cs);
-  const int sub = tid & 15, grp = tid >> 4;
-  for (int e = e0 + grp; e < e1; e += kTW / 16) {
+  int G = 1;
+  while (G < 16 && np > 8 * G) G <<= 1;
+  const int sub = tid & (G - 1), grp = tid / G;
+  for (int e = e0 + grp; e < e1; e += kTW / G) {
     double2 s = make_double2(0.0, 0.0);
-    for (int q = sub; q < np; q += 16) s = cadd(s, ld_ag(part + (size_t)q * npe + e));
+    for (int q0 = sub; q0 < np; q0 += 8 * G) {
+      double2 pv[8];
 #pragma unroll
-    for (int off = 8; off > 0; off >>= 1) {
-      s.x += __shfl_xor(s.x, off, 16);
-      s.y += __shfl_xor(s.y, off, 16);
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + u * G;
+        pv[u] = q < np ? ld_ag(part + (size_t)q * npe + e) : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (q0 + u * G < np) s = cadd(s, pv[u]);
+    }
+    for (int off = G / 2; off > 0; off >>= 1) {
+      s.x += __shfl_xor(s.x, off, G);
+      s.y += __shfl_xor(s.y, off, G);
     }
     if (sub == 0) st_ag(red + e, s);
   }
@@ -1043,19 +1081,23 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
         Yc = lds + LM;
         Yn = lds + 2 * LM;
       }
-      const g_double2* in0 = in + (size_t)r_lo * LM;
-      for (int e = tid; e < LM; e += kTW) Yc[e] = ldS(in0 + e);
-      if (r_lo + 1 < d_r)
-        for (int e = tid; e < LM; e += kTW) Yn[e] = ldS(in0 + LM + e);
-      if constexpr (SPLIT)
-        if (r_lo > 0)
-          for (int e = tid; e < LM; e += kTW) Yp[e] = ldS(in0 - LM + e);
+      if constexpr (SPLIT) {  // the window around the part's first layer, all loads in flight together
+        if constexpr (NM) {
+          double2* const w5[5] = {Ym2, Yp, Yc, Yn, Yp2};
+          split_load_layers<5>(w5, in, r_lo - 2, d_r, LM);
+        } else {
+          double2* const w3[3] = {Yp, Yc, Yn};
+          split_load_layers<3>(w3, in, r_lo - 1, d_r, LM);
+        }
+      } else {
+        for (int e = tid; e < LM; e += kTW) Yc[e] = ld_g(in + e);
+        if (d_r > 1)
+          for (int e = tid; e < LM; e += kTW) Yn[e] = ld_g(in + LM + e);
+        if constexpr (NM)
+          if (d_r > 2)
+            for (int e = tid; e < LM; e += kTW) Yp2[e] = ld_g(in + 2 * LM + e);
+      }
       if constexpr (NM) {
-        if (r_lo + 2 < d_r)
-          for (int e = tid; e < LM; e += kTW) Yp2[e] = ldS(in0 + 2 * LM + e);
-        if constexpr (SPLIT)
-          if (r_lo > 1)
-            for (int e = tid; e < LM; e += kTW) Ym2[e] = ldS(in0 - 2 * LM + e);
         __syncthreads();
         jump_tile(Y1c, Yp, Yc, Yn, r_lo, e1j);
       }
@@ -1077,7 +1119,7 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
                 const int rl = min(rb + k * NGe, L - 1);
                 const size_t gi = ((size_t)r * L + rl) * M + ej;
                 pb[k] = ldS(gBb + gi);
-                pa[k] = ldS(gacc + gi);
+                pa[k] = ld_g(gacc + gi);  // the accumulator rows are the part's own
               }
             }
             double2 a1[kTRowBlock], a2[kTRowBlock];
@@ -1116,13 +1158,13 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
                 const size_t gi = ((size_t)r * L + rl) * M + ej;
                 double2 o;
                 if (s == 0) {
-                  stS(gacc + gi, kk);
+                  st_g(gacc + gi, kk);
                   o = cfma(0.5 * dt, kk, Yc[rl * M + ej]);
                 } else if (s == 1) {
-                  stS(gacc + gi, cfma(2.0, kk, pa[k]));
+                  st_g(gacc + gi, cfma(2.0, kk, pa[k]));
                   o = cfma(0.5 * dt, kk, pb[k]);
                 } else if (s == 2) {
-                  stS(gacc + gi, cfma(2.0, kk, pa[k]));
+                  st_g(gacc + gi, cfma(2.0, kk, pa[k]));
                   o = cfma(dt, kk, pb[k]);
                 } else {
                   o = cfma(dt / 6.0, cadd(pa[k], kk), pb[k]);
@@ -1189,7 +1231,8 @@ __device__ __forceinline__ void packed_body(const TrajDev& T, int prologue, int6
           if (r_hi < d_r) {  // the pair (r_hi - 1, r_hi) across the upper boundary
             ok = split_wait_above(T, SS, &s_ok);
             if (ok) {
-              for (int e = tid; e < LM; e += kTW) Ot[e] = ldS(out + (size_t)r_hi * LM + e);
+              double2* const w1[1] = {Ot};
+              split_load_layers<1>(w1, out, r_hi, d_r, LM);
               __syncthreads();
               packed_terms_q<KP>(acc, PM, Ot, Op, sk * sq[r_hi]);
             }
