@@ -156,38 +156,37 @@ __device__ __forceinline__ void packed_terms_q(double2 (&acc)[KP], const PackedM
   }
 }
 
-// Gauss-Jordan elimination of the M x 3M matrix [G | C_1 | C_2] in Aug into
-// [I | X_1 | X_2], then W_k = X_k^ into Wl; returns 0 or -4 (pivot <= 0).
-__device__ __forceinline__ int packed_eliminate(double2* Aug, double2* Wl, double2* s_prow, int M) {
+// Gauss-Jordan elimination of the M x 3M matrix [G | C_1 | C_2] in Aug, then
+// W_k = X_k^ into Wl (X_k the solved right-hand sides); returns 0 or -4 (pivot
+// <= 0).  Thread t keeps column c = t mod 3M and the rows t / 3M, t / 3M + NG,
+// ... (NG = 256 / 3M row groups).  Pivot p updates every entry right of the
+// pivot column in the rows other than p, x - (Aug[i][p] / Aug[p][p]) Aug[p][c];
+// the pivot row and the pivot column are only read while it runs, so one
+// barrier per pivot suffices, and the rows are divided by their pivots at the
+// end (a pivot row is not changed by later pivots left of its own column).
+__device__ __forceinline__ int packed_eliminate(double2* Aug, double2* Wl, double2* /* unused */, int M) {
   const int tid = threadIdx.x, C3 = 3 * M, MM = M * M;
-  // pivot p: the scaled pivot row goes to s_prow, then every entry right of
-  // the pivot column takes x - Aug[i][p] prow[c] (the pivot row: prow[c]);
-  // the pivot column is only read
-  const int tot = M * C3;
+  const int ng = kTW / C3, c = tid % C3, g = tid / C3;
+  const bool act = g < ng;
   for (int p = 0; p < M; ++p) {
     const double piv = Aug[p * C3 + p].x;
     if (!(piv > 0.0)) return -4;
-    const double rp = pivot_rcp(piv);
-    for (int c = p + 1 + tid; c < C3; c += kTW) s_prow[c] = cscale(rp, Aug[p * C3 + c]);
-    __syncthreads();
-    for (int e = tid; e < tot; e += kTW) {
-      const int i = e / C3, c = e - i * C3;
-      if (c > p) {
-        const double2 pr = s_prow[c];
-        if (i == p) {
-          Aug[e] = pr;
-        } else {
-          const double2 l = Aug[i * C3 + p];
-          Aug[e] = cadd(Aug[e], cmul(make_double2(-l.x, -l.y), pr));
+    if (act && c > p) {
+      const double rp = pivot_rcp(piv);
+      const double2 pr = Aug[p * C3 + c];
+      for (int i = g; i < M; i += ng) {
+        if (i != p) {
+          const double2 l = cscale(rp, Aug[i * C3 + p]);
+          Aug[i * C3 + c] = cadd(Aug[i * C3 + c], cmul(make_double2(-l.x, -l.y), pr));
         }
       }
     }
     __syncthreads();
   }
-  // W_k[i][j] = conj(X_k[j][i]), X_k = columns M (k + 1) .. of the eliminated matrix
+  // W_k[i][j] = conj(X_k[j][i]), X_k[j] = row j of the columns M (k + 1) .. over its pivot
   for (int e = tid; e < 2 * MM; e += kTW) {
     const int k = e / MM, o = e - k * MM, i = o / M, j = o - i * M;
-    const double2 x = Aug[j * C3 + M * (k + 1) + i];
+    const double2 x = cscale(pivot_rcp(Aug[j * C3 + j].x), Aug[j * C3 + M * (k + 1) + i]);
     Wl[e] = make_double2(x.x, -x.y);
   }
   __syncthreads();
