@@ -7,8 +7,8 @@
 //
 //   1. solve G X_k = C_k for the reduced G = S^S, C_k = S^ L_k S of the stage
 //      input (FP64 Gauss-Jordan elimination of the augmented [G | C_1 C_2],
-//      held in the registers of four waves that each eliminate G and a quarter
-//      of the right-hand sides on their own, no barrier per pivot); W_k = X_k^
+//      held in the registers of one wave, a column per lane, the multipliers
+//      read across lanes: no barrier and no LDS traffic per pivot); W_k = X_k^
 //   2. k_s = -i H_eff(t_s) S + 1/2 sum_k (L_k S) W_k for the own rows (banded
 //      stencil with one halo layer up and down, jump assembly), RK4 stage
 //      update in registers
@@ -38,8 +38,9 @@ constexpr int kMaxRowsPerThread = 3;
 constexpr size_t kPersistLdsMax = 159 * 1024;  // dynamic LDS (160 KB less the static part)
 
 // Dynamic LDS bytes of k_persist for rt layers of L rows at rank M and P
-// workgroups: stage input with halos, W, the solver waves' exchange areas
-// (4 x 256 complex), per-row jump coefficients, square-root table.
+// workgroups: stage input with halos, W, an area of 4 x 256 complex (with W,
+// the LDS solver's augmented matrix), per-row jump coefficients, square-root
+// table.
 __host__ __device__ inline size_t persist_lds_bytes(int rt, int L, int M, int /* P */) {
   return (size_t)((rt + 2) * L * M + 2 * M * M + 4 * 256) * 16 + (size_t)(2 * rt * L + L + rt + 1) * 8;
 }
@@ -288,69 +289,34 @@ __device__ __forceinline__ double pivot_rcp(double p) {
 // followed by a product carries cond(G) times more rounding into X_k, and G
 // is ill-conditioned through the rank padding).
 //
-// The elimination runs inside single waves, with no workgroup barrier per
-// pivot: each of the first kSolveWaves waves of the workgroup holds all of G
-// and its own share of the 2M right-hand-side columns, and eliminates that
-// M x (M + share) matrix on its own (the G columns are eliminated identically
-// in every wave).  Within a wave, H consecutive lanes own one column and lane
-// h of a column holds the RPL consecutive rows h RPL .. h RPL + RPL - 1 in
-// registers.  Per pivot the multiplier column (column k) and the pivot row
-// entries are handed between lanes through a small per-wave LDS area (a
-// wave's LDS accesses are performed in order: no barrier).  The four waves'
-// LDS traffic shares the CU's one LDS unit, which bounds a pivot.
+// The elimination runs inside one wave, with no workgroup barrier and no LDS
+// traffic per pivot: lane c of the first wave owns column c of the augmented
+// [G | C_1 | C_2] (3M <= 64 columns) and holds all of its rows in registers.
+// At pivot k the multipliers A[i][k] are the registers of lane k, read as
+// wave-uniform values (v_readlane), and the pivot-row entry A[k][c] of a
+// lane's column is its own register k.  The other waves of the workgroup wait
+// at the caller's barrier.
+constexpr int kWsRows = 20;  // register rows of a solver lane (ranks M <= 20)
 constexpr int kSolveWaves = 4;
-constexpr int kWsLds = 4 * 64;  // LDS (complex entries) per solver wave: multiplier column and pivot row, two each
-constexpr int kWsRows = 10;     // register rows of a solver lane (ranks M <= 20)
+constexpr int kWsLds = 4 * 64;  // LDS (complex entries) kept per former solver wave: the LDS solver's augmented
+                                // matrix reaches into this area (3 M^2 <= 2 M^2 + kSolveWaves kWsLds at M = 32)
+__host__ __device__ inline bool ws_fits(int M) { return M <= kWsRows && 3 * M <= 64; }
 
-// Lane map of a solver wave for rank M.
-struct WsMap {
-  int H, RPL;      // lanes per column, rows per lane
-  int slot, h;     // column slot of the lane (G columns 0..M-1, then the wave's right-hand sides) and row block
-  int cbase;       // first right-hand-side column (0 .. 2M-1 over [C_1 | C_2]) of the wave
-  bool act;        // the lane owns a column
-};
-__host__ __device__ inline int ws_cols_per_wave(int M) { return (2 * M + kSolveWaves - 1) / kSolveWaves; }
-// H = ceil(M / kWsRows) lanes per column, each with kWsRows register rows; the
-// register solver takes ranks whose columns of all lanes fit a wave
-__host__ __device__ inline int ws_lanes_per_col(int M) { return (M + kWsRows - 1) / kWsRows; }
-__host__ __device__ inline bool ws_fits(int M) { return ws_lanes_per_col(M) * (M + ws_cols_per_wave(M)) <= 64; }
-__device__ __forceinline__ WsMap ws_map(int M) {
-  WsMap m;
-  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-  const int ncw = ws_cols_per_wave(M);
-  m.H = ws_lanes_per_col(M);
-  m.RPL = kWsRows;
-  m.slot = lane / m.H;
-  m.h = lane - m.slot * m.H;
-  m.cbase = w * ncw;
-  const int nc = max(0, min(2 * M, m.cbase + ncw) - m.cbase);
-  m.act = w < kSolveWaves && m.slot < M + nc;
-  return m;
-}
-// Offset in the reduced [G | C_1 | C_2] (each M x M row-major) of row 0 of the
-// lane's column (rows are M apart).
-__device__ __forceinline__ int ws_col_offset(const WsMap& m, int M) {
-  if (m.slot < M) return m.slot;
-  const int cc = m.cbase + m.slot - M;
-  return cc < M ? M * M + cc : 2 * M * M + (cc - M);
-}
-
-// RC = register rows per lane (>= ws_rows_per_lane(M)).
-template <int RC>
 struct WsRegs {
-  double2 a[RC];
+  double2 a[kWsRows];
 };
 
-// Loads of the lane's column of the reduced [G | C_1 | C_2] (issued early so
-// that their latency overlaps other work).
-template <int RC>
-__device__ __forceinline__ void wsolve_load(const g_double2* red, int M, const WsMap& m, WsRegs<RC>& R) {
-  const int off = ws_col_offset(m, M);
+// Loads of the lane's column of the reduced [G | C_1 | C_2] (each M x M
+// row-major; issued early so that their latency overlaps other work).
+__device__ __forceinline__ void wsolve_load(const g_double2* red, int M, WsRegs& R) {
+  const int lane = (int)(threadIdx.x & 63);
+  const bool act = threadIdx.x < 64 && lane < 3 * M;
+  const int blk = act ? lane / M : 0, col = act ? lane - blk * M : 0;
+  const g_double2* src = red + (size_t)blk * M * M + col;
 #pragma unroll
-  for (int idx = 0; idx < RC; ++idx) {
-    const int r = m.h * RC + idx;
-    R.a[idx] = make_double2(0.0, 0.0);
-    if (m.act && r < M) R.a[idx] = ld_ag(red + off + (size_t)r * M);
+  for (int r = 0; r < kWsRows; ++r) {
+    R.a[r] = make_double2(0.0, 0.0);
+    if (act && r < M) R.a[r] = ld_ag(src + (size_t)r * M);
   }
 }
 
@@ -361,82 +327,48 @@ __device__ __forceinline__ double ws_readlane(double v, int lane) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Elimination by one solver wave (every lane of the wave calls it).  scratch:
-// the wave's kWsLds LDS entries.  Writes W_k[i][j] = conj(X_k[j][i]) of the
-// wave's right-hand-side columns to Wl (W_1 then W_2, M x M row-major each).
+// Elimination by the solver wave (every lane of wave 0 calls it).  Writes
+// W_k[i][j] = conj(X_k[j][i]) to Wl (W_1 then W_2, M x M row-major each).
 // s_nonfinite (LDS) is set on a non-finite input; *badk receives the first
 // non-positive pivot or -1.  The caller synchronises the workgroup before
-// reading Wl or the flags.  A lane holds RC rows (rows past M are zero and
-// stay zero); the pivots run in blocks of RC, so that within a block the
-// register of the pivot row is known at compile time.  The multiplier column
-// and the pivot row of pivot k + 1 are written to the wave's LDS area by
-// their owners during pivot k and read back by every lane (broadcast reads).
-template <int RC>
-__device__ __forceinline__ void wsolve_run(WsRegs<RC>& R, const WsMap& m, double2* scratch, double2* Wl, int M,
-                                           int* s_nonfinite, int* badk) {
-  double2* mcol = scratch;        // [2][64] multiplier column of the pivot, by row
-  double2* prow = scratch + 128;  // [2][64] pivot row, by column slot
-  const int h = m.h, slot = m.slot;
+// reading Wl or the flags.  Rows past M are zero and stay zero; pivot k and
+// row i are compile-time indices of the unrolled loops, so every register
+// index is static.
+__device__ __forceinline__ void wsolve_run(WsRegs& R, double2* Wl, int M, int* s_nonfinite, int* badk) {
+  const int lane = (int)(threadIdx.x & 63);
   bool bad = false;
 #pragma unroll
-  for (int idx = 0; idx < RC; ++idx) bad = bad || !isfinite(R.a[idx].x) || !isfinite(R.a[idx].y);
+  for (int r = 0; r < kWsRows; ++r) bad = bad || !isfinite(R.a[r].x) || !isfinite(R.a[r].y);
   *badk = -1;
   if (__any(bad)) {  // uniform
     if (bad) *s_nonfinite = 1;
     return;
   }
-  double2* myrows = mcol + h * RC;  // this lane's rows in a multiplier column
-  // pivot 0: column 0 and row 0 (row block 0, register 0)
-  if (slot == 0) {
-#pragma unroll
-    for (int idx = 0; idx < RC; ++idx) myrows[idx] = R.a[idx];
-  }
-  if (h == 0) prow[slot] = R.a[0];
-  // every pivot runs (straight-line code per pivot); the first non-positive one is recorded and the
-  // caller discards the result
+  // every pivot runs; the first non-positive one is recorded and the caller discards the result
   int first_bad = -1;
-  for (int kb = 0, hk = 0; kb < M; kb += RC, ++hk) {  // row block hk: pivots kb .. kb + RC - 1
 #pragma unroll
-    for (int j = 0; j < RC; ++j) {  // j, hence the register of the pivot row, is a constant per copy
-      const int k = kb + j;
-      if (k < M) {  // uniform
-        const int par = k & 1;
-        wave_lds_sync();
-        const double2* mrow = myrows + par * 64;
-        double2 mi[RC];
+  for (int k = 0; k < kWsRows; ++k) {
+    if (k < M) {  // uniform
+      const double piv = ws_readlane(R.a[k].x, k);  // A[k][k]: register k of lane k
+      if (!(piv > 0.0) && first_bad < 0) first_bad = k;
+      const double rinv = pivot_rcp(piv > 0.0 ? piv : 1.0);
+      const double2 pc = make_double2(R.a[k].x * rinv, R.a[k].y * rinv);  // row k of the result, this column
 #pragma unroll
-        for (int idx = 0; idx < RC; ++idx) mi[idx] = mrow[idx];  // A[row][k] of the lane's rows
-        const double2 pr = prow[par * 64 + slot];
-        // the pivot A[k][k] is register j of lane hk (column slot 0, row block hk): a uniform value
-        const double piv = ws_readlane(mi[j].x, hk);
-        if (!(piv > 0.0) && first_bad < 0) first_bad = k;
-        const double rinv = pivot_rcp(piv > 0.0 ? piv : 1.0);
-        const double2 pc = make_double2(pr.x * rinv, pr.y * rinv);  // row k of the result, this column
-#pragma unroll
-        for (int idx = 0; idx < RC; ++idx) {
-          double2 v = R.a[idx];
-          v.x = fma(-mi[idx].x, pc.x, v.x);
-          v.x = fma(mi[idx].y, pc.y, v.x);
-          v.y = fma(-mi[idx].x, pc.y, v.y);
-          v.y = fma(-mi[idx].y, pc.x, v.y);
-          R.a[idx] = v;
+      for (int i = 0; i < kWsRows; ++i) {
+        if (i != k) {  // compile time; rows past M are zero in every lane, their update keeps them zero
+          const double mx = ws_readlane(R.a[i].x, k), my = ws_readlane(R.a[i].y, k);  // A[i][k]
+          double2 v = R.a[i];
+          v.x = fma(-mx, pc.x, v.x);
+          v.x = fma(my, pc.y, v.x);
+          v.y = fma(-mx, pc.y, v.y);
+          v.y = fma(-my, pc.x, v.y);
+          R.a[i] = v;
         }
-        if (h == hk) R.a[j] = pc;  // the pivot row itself
-        // pivot row and multiplier column of the next pivot k + 1 (row block hn, register (j + 1) % RC)
-        const int hn = j + 1 < RC ? hk : hk + 1;
-        if (h == hn) prow[(par ^ 1) * 64 + slot] = R.a[(j + 1) % RC];
-        if (slot == k + 1) {
-          double2* mnext = myrows + (par ^ 1) * 64;
-#pragma unroll
-          for (int idx = 0; idx < RC; ++idx) mnext[idx] = R.a[idx];
-        }
+        // keep the uniform multipliers of a row pair next to their use: hoisted
+        // together they exceed the scalar registers and spill
+        if (i & 1) __builtin_amdgcn_sched_barrier(0);
       }
+      R.a[k] = pc;
     }
   }
   if (first_bad >= 0) {
@@ -444,14 +376,12 @@ __device__ __forceinline__ void wsolve_run(WsRegs<RC>& R, const WsMap& m, double
     return;
   }
   // right-hand-side lanes hold X_k[:, i]: W_k[i][j] = conj(X_k[j][i])
-  if (m.act && slot >= M) {
-    const int cc = m.cbase + slot - M, kk = cc < M ? 0 : 1, i = cc - kk * M;
+  if (lane >= M && lane < 3 * M) {
+    const int cc = lane - M, kk = cc < M ? 0 : 1, i = cc - kk * M;
     double2* dst = Wl + (size_t)kk * M * M + (size_t)i * M;
 #pragma unroll
-    for (int idx = 0; idx < RC; ++idx) {
-      const int j = h * RC + idx;
-      if (j < M) dst[j] = make_double2(R.a[idx].x, -R.a[idx].y);
-    }
+    for (int r = 0; r < kWsRows; ++r)
+      if (r < M) dst[r] = make_double2(R.a[r].x, -R.a[r].y);
   }
 }
 
@@ -568,7 +498,7 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
   double2* SL = lds;                              // (rt + 2) L M: [halo | tile | halo]
   double2* tile = SL + LM;
   double2* Wl = SL + (size_t)(rt + 2) * LM;       // 2 M^2
-  double2* WS = Wl + 2 * MM;                      // kSolveWaves x kWsLds: solver waves' exchange areas
+  double2* WS = Wl + 2 * MM;                      // kSolveWaves x kWsLds: the LDS solver's matrix runs on into it
   double* c1row = reinterpret_cast<double*>(WS + kSolveWaves * kWsLds);
   double* c2row = c1row + rt * L;
   double* sqt = c2row + rt * L;                   // sqrt(n), n < nq; then sqrt(r0 + k), k <= rt
@@ -584,8 +514,6 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
     c2row[rl] = q + 1 < d_q ? sqrt(T.gamma * (double)(q + 1)) : 0.0;
   }
   for (int n = tid; n < nq + rt + 1; n += kPW) sqt[n] = sqrt((double)(n < nq ? n : r0 + (n - nq)));
-
-  const WsMap wsm = ws_map(M);  // solver-wave lane map
 
   // element mapping: column j, rows rg, rg + NG, ...
   const int NG = kPW / M;
@@ -774,11 +702,11 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
       __syncthreads();  // stage input tile and halo, drive table in LDS
       const double drv = s_dtab[ds][0];
 
-      // (1) loads of the reduced G, C_k (solver waves of the register solver) in flight while
+      // (1) loads of the reduced G, C_k (solver wave of the register solver) in flight while
       // Z = H_eff(t) S is formed (with three register rows they are issued after it: registers)
       constexpr bool kWaveSolve = GE == 1, kEarlyLoad = kWaveSolve && ROWS == 2;
-      WsRegs<kWsRows> SR;
-      if constexpr (kEarlyLoad) wsolve_load(REDg + (size_t)p * npe, M, wsm, SR);
+      WsRegs SR;
+      if constexpr (kEarlyLoad) wsolve_load(REDg + (size_t)p * npe, M, SR);
       double2 z[ROWS];
       // Z rows of the thread, in the lab frame or the drive frame (one code
       // path per frame, chosen once per stage).  In the drive frame a
@@ -845,14 +773,14 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
       };
       if (T.frame) stencil(std::true_type{});
       else stencil(std::false_type{});
-      // (2) W_k of this stage input (register solver: solver waves, the others wait at the
+      // (2) W_k of this stage input (register solver: the solver wave, the others wait at the
       // barrier; LDS solver: the whole workgroup)
       {
         if constexpr (kWaveSolve) {
-          if (tid < kSolveWaves * 64) {
+          if (tid < 64) {
             int badk;
-            if constexpr (!kEarlyLoad) wsolve_load(REDg + (size_t)p * npe, M, wsm, SR);
-            wsolve_run<kWsRows>(SR, wsm, WS + (tid >> 6) * kWsLds, Wl, M, &s_nonfinite, &badk);
+            if constexpr (!kEarlyLoad) wsolve_load(REDg + (size_t)p * npe, M, SR);
+            wsolve_run(SR, Wl, M, &s_nonfinite, &badk);
             if (tid == 0) s_bad = badk;
           }
         } else {
@@ -975,7 +903,7 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
 
 // Chunk of RK4 steps (the integrator proper) and prologue, as separate
 // kernels so that timing tools see the step kernel alone.
-// GE selects the solver: in the registers of the solver waves (1) or in LDS (2).
+// GE selects the solver: in the registers of one solver wave (1) or in LDS (2).
 template <int ROWS, int GE, int PREC>
 __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ trajs,
                                                  const int2* __restrict__ tilemap, int64_t step0, int64_t nchunk) {
