@@ -172,7 +172,10 @@ __device__ __forceinline__ bool flag_wait(const TrajDev& T, const g_u32* flags, 
       uint32_t n = 0;
       while (__hip_atomic_load(flags + (size_t)w * kFlagStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
              target) {
-        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++n > limit) {
+        // the abort flag is read on every 16th poll only, so that a poll is one
+        // memory round trip
+        if (++n > limit ||
+            ((n & 15u) == 0u && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
           __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ok = false;
           break;
@@ -327,6 +330,16 @@ __device__ __forceinline__ double ws_readlane(double v, int lane) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// Row update of pivot k in a lane's column: v <- v - A[i][k] pc, the
+// multiplier A[i][k] being the same row's register in lane k.
+__device__ __forceinline__ void ws_update(double2& v, int k, double2 pc) {
+  const double mx = ws_readlane(v.x, k), my = ws_readlane(v.y, k);
+  v.x = fma(-mx, pc.x, v.x);
+  v.x = fma(my, pc.y, v.x);
+  v.y = fma(-mx, pc.y, v.y);
+  v.y = fma(-my, pc.x, v.y);
+}
+
 // Elimination by the solver wave (every lane of wave 0 calls it).  Writes
 // W_k[i][j] = conj(X_k[j][i]) to Wl (W_1 then W_2, M x M row-major each).
 // s_nonfinite (LDS) is set on a non-finite input; *badk receives the first
@@ -344,30 +357,28 @@ __device__ __forceinline__ void wsolve_run(WsRegs& R, double2* Wl, int M, int* s
     if (bad) *s_nonfinite = 1;
     return;
   }
-  // every pivot runs; the first non-positive one is recorded and the caller discards the result
+  // every pivot runs; the first non-positive one is recorded and the caller discards the result.
+  // Row k + 1 is updated first, so that the next pivot and its reciprocal are formed while the
+  // other rows are updated.
   int first_bad = -1;
+  double piv = ws_readlane(R.a[0].x, 0);  // A[0][0]: register 0 of lane 0
+  if (!(piv > 0.0)) first_bad = 0;
+  double rinv = pivot_rcp(piv > 0.0 ? piv : 1.0);
 #pragma unroll
   for (int k = 0; k < kWsRows; ++k) {
     if (k < M) {  // uniform
-      const double piv = ws_readlane(R.a[k].x, k);  // A[k][k]: register k of lane k
-      if (!(piv > 0.0) && first_bad < 0) first_bad = k;
-      const double rinv = pivot_rcp(piv > 0.0 ? piv : 1.0);
       const double2 pc = make_double2(R.a[k].x * rinv, R.a[k].y * rinv);  // row k of the result, this column
-#pragma unroll
-      for (int i = 0; i < kWsRows; ++i) {
-        if (i != k) {  // compile time; rows past M are zero in every lane, their update keeps them zero
-          const double mx = ws_readlane(R.a[i].x, k), my = ws_readlane(R.a[i].y, k);  // A[i][k]
-          double2 v = R.a[i];
-          v.x = fma(-mx, pc.x, v.x);
-          v.x = fma(my, pc.y, v.x);
-          v.y = fma(-mx, pc.y, v.y);
-          v.y = fma(-my, pc.x, v.y);
-          R.a[i] = v;
-        }
-        // keep the uniform multipliers of a row pair next to their use: hoisted
-        // together they exceed the scalar registers and spill
-        if (i & 1) __builtin_amdgcn_sched_barrier(0);
+      if (k + 1 < kWsRows) {
+        ws_update(R.a[k + 1], k, pc);
+        // A[k+1][k+1]: register k + 1 of lane k + 1 (zero past M: a pivot that never runs);
+        // no branch, so that the reciprocal interleaves with the row updates below
+        piv = ws_readlane(R.a[k + 1].x, k + 1);
+        if (k + 1 < M && !(piv > 0.0) && first_bad < 0) first_bad = k + 1;
+        rinv = pivot_rcp(piv > 0.0 ? piv : 1.0);
       }
+#pragma unroll
+      for (int i = 0; i < kWsRows; ++i)
+        if (i != k && i != k + 1) ws_update(R.a[i], k, pc);  // compile time; rows past M are zero and stay zero
       R.a[k] = pc;
     }
   }
