@@ -7,8 +7,9 @@
 //
 //   1. solve G X_k = C_k for the reduced G = S^S, C_k = S^ L_k S of the stage
 //      input (FP64 Gauss-Jordan elimination of the augmented [G | C_1 C_2],
-//      held in the registers of one wave, a column per lane, the multipliers
-//      read across lanes: no barrier and no LDS traffic per pivot); W_k = X_k^
+//      held in the registers of two waves, a column per lane and half of the
+//      rows per wave, the multipliers read across lanes, one barrier per
+//      pivot); W_k = X_k^
 //   2. k_s = -i H_eff(t_s) S + 1/2 sum_k (L_k S) W_k for the own rows (banded
 //      stencil with one halo layer up and down, jump assembly), RK4 stage
 //      update in registers
@@ -292,34 +293,38 @@ __device__ __forceinline__ double pivot_rcp(double p) {
 // followed by a product carries cond(G) times more rounding into X_k, and G
 // is ill-conditioned through the rank padding).
 //
-// The elimination runs inside one wave, with no workgroup barrier and no LDS
-// traffic per pivot: lane c of the first wave owns column c of the augmented
-// [G | C_1 | C_2] (3M <= 64 columns) and holds all of its rows in registers.
-// At pivot k the multipliers A[i][k] are the registers of lane k, read as
-// wave-uniform values (v_readlane), and the pivot-row entry A[k][c] of a
-// lane's column is its own register k.  The other waves of the workgroup wait
-// at the caller's barrier.
-constexpr int kWsRows = 20;  // register rows of a solver lane (ranks M <= 20)
+// The elimination runs in two waves: lane c of wave w (w = 0, 1) holds rows
+// kWsHalf w .. kWsHalf w + kWsHalf - 1 of column c of the augmented
+// [G | C_1 | C_2] (3M <= 64 columns) in registers.  At pivot k the
+// multipliers A[i][k] of a wave's rows are the registers of its lane k, read
+// as wave-uniform values (v_readlane); the pivot row A[k][c] comes from the
+// wave that holds row k, which writes it to LDS right after updating it in the
+// previous pivot; one workgroup barrier per pivot, taken by every wave at the
+// same points (the other waves only pass the barriers).
+constexpr int kWsHalf = 10;           // rows per solver wave
+constexpr int kWsRows = 2 * kWsHalf;  // ranks M <= 20
 constexpr int kSolveWaves = 4;
-constexpr int kWsLds = 4 * 64;  // LDS (complex entries) kept per former solver wave: the LDS solver's augmented
-                                // matrix reaches into this area (3 M^2 <= 2 M^2 + kSolveWaves kWsLds at M = 32)
+constexpr int kWsLds = 4 * 64;  // LDS (complex entries): the pivot-row buffers of the register solver; the LDS
+                                // solver's augmented matrix reaches into this area (3 M^2 <= 2 M^2 + 1024 at M = 32)
 __host__ __device__ inline bool ws_fits(int M) { return M <= kWsRows && 3 * M <= 64; }
 
 struct WsRegs {
-  double2 a[kWsRows];
+  double2 a[kWsHalf];
 };
 
-// Loads of the lane's column of the reduced [G | C_1 | C_2] (each M x M
-// row-major; issued early so that their latency overlaps other work).
+// Loads of the lane's rows of its column of the reduced [G | C_1 | C_2] (each
+// M x M row-major; issued early so that their latency overlaps other work).
+// Every thread calls it; threads outside the two solver waves load nothing.
 __device__ __forceinline__ void wsolve_load(const g_double2* red, int M, WsRegs& R) {
-  const int lane = (int)(threadIdx.x & 63);
-  const bool act = threadIdx.x < 64 && lane < 3 * M;
+  const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const bool act = wv < 2 && lane < 3 * M;
   const int blk = act ? lane / M : 0, col = act ? lane - blk * M : 0;
   const g_double2* src = red + (size_t)blk * M * M + col;
 #pragma unroll
-  for (int r = 0; r < kWsRows; ++r) {
+  for (int r = 0; r < kWsHalf; ++r) {
+    const int row = wv * kWsHalf + r;
     R.a[r] = make_double2(0.0, 0.0);
-    if (act && r < M) R.a[r] = ld_ag(src + (size_t)r * M);
+    if (act && row < M) R.a[r] = ld_ag(src + (size_t)row * M);
   }
 }
 
@@ -340,59 +345,68 @@ __device__ __forceinline__ void ws_update(double2& v, int k, double2 pc) {
   v.y = fma(-my, pc.x, v.y);
 }
 
-// Elimination by the solver wave (every lane of wave 0 calls it).  Writes
+// Elimination (every thread of the workgroup calls it; it passes M workgroup
+// barriers in every thread).  prow: 2 x 64 complex entries of LDS.  Writes
 // W_k[i][j] = conj(X_k[j][i]) to Wl (W_1 then W_2, M x M row-major each).
-// s_nonfinite (LDS) is set on a non-finite input; *badk receives the first
-// non-positive pivot or -1.  The caller synchronises the workgroup before
-// reading Wl or the flags.  Rows past M are zero and stay zero; pivot k and
-// row i are compile-time indices of the unrolled loops, so every register
-// index is static.
-__device__ __forceinline__ void wsolve_run(WsRegs& R, double2* Wl, int M, int* s_nonfinite, int* badk) {
-  const int lane = (int)(threadIdx.x & 63);
+// s_nonfinite (LDS, zero on entry) is set on a non-finite input and then
+// nothing is eliminated; *s_bad receives the first non-positive pivot or -1.
+// The caller synchronises the workgroup before reading Wl or the flags.  Rows
+// past M are zero and stay zero; pivot k and the register rows are
+// compile-time constants of the unrolled loops.
+__device__ __forceinline__ void wsolve_run(WsRegs& R, double2* prow, double2* Wl, int M, int* s_nonfinite,
+                                           int* s_bad) {
+  const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const bool solver = wv < 2;  // uniform per wave
   bool bad = false;
+  if (solver) {
 #pragma unroll
-  for (int r = 0; r < kWsRows; ++r) bad = bad || !isfinite(R.a[r].x) || !isfinite(R.a[r].y);
-  *badk = -1;
-  if (__any(bad)) {  // uniform
-    if (bad) *s_nonfinite = 1;
-    return;
+    for (int r = 0; r < kWsHalf; ++r) bad = bad || !isfinite(R.a[r].x) || !isfinite(R.a[r].y);
   }
-  // every pivot runs; the first non-positive one is recorded and the caller discards the result.
-  // Row k + 1 is updated first, so that the next pivot and its reciprocal are formed while the
-  // other rows are updated.
+  if (bad) *s_nonfinite = 1;
+  if (threadIdx.x == 0) *s_bad = -1;
+  if (wv == 0) prow[lane] = R.a[0];  // row 0 of the pivot-row buffer 0
+  __syncthreads();
+  if (*s_nonfinite) return;  // uniform over the workgroup
+  // every pivot runs; the first non-positive one is recorded and the caller discards the result
   int first_bad = -1;
-  double piv = ws_readlane(R.a[0].x, 0);  // A[0][0]: register 0 of lane 0
-  if (!(piv > 0.0)) first_bad = 0;
-  double rinv = pivot_rcp(piv > 0.0 ? piv : 1.0);
 #pragma unroll
   for (int k = 0; k < kWsRows; ++k) {
     if (k < M) {  // uniform
-      const double2 pc = make_double2(R.a[k].x * rinv, R.a[k].y * rinv);  // row k of the result, this column
-      if (k + 1 < kWsRows) {
-        ws_update(R.a[k + 1], k, pc);
-        // A[k+1][k+1]: register k + 1 of lane k + 1 (zero past M: a pivot that never runs);
-        // no branch, so that the reciprocal interleaves with the row updates below
-        piv = ws_readlane(R.a[k + 1].x, k + 1);
-        if (k + 1 < M && !(piv > 0.0) && first_bad < 0) first_bad = k + 1;
-        rinv = pivot_rcp(piv > 0.0 ? piv : 1.0);
-      }
+      if (k > 0) __syncthreads();  // row k in buffer k & 1
+      if (solver) {
+        const double2 pr = prow[(k & 1) * 64 + lane];  // A[k][c]
+        const double piv = ws_readlane(pr.x, k);        // A[k][k]: lane k
+        if (!(piv > 0.0) && first_bad < 0) first_bad = k;
+        const double rinv = pivot_rcp(piv > 0.0 ? piv : 1.0);
+        const double2 pc = make_double2(pr.x * rinv, pr.y * rinv);  // row k of the result, this column
+        auto body = [&](auto rbc) {
+          constexpr int RB = decltype(rbc)::value;  // first row of the wave
+          // row k + 1 first when the wave holds it: it goes to the other buffer for the next pivot
+          if (k + 1 >= RB && k + 1 < RB + kWsHalf) {  // compile time
+            ws_update(R.a[k + 1 - RB], k, pc);
+            prow[((k + 1) & 1) * 64 + lane] = R.a[k + 1 - RB];
+          }
 #pragma unroll
-      for (int i = 0; i < kWsRows; ++i)
-        if (i != k && i != k + 1) ws_update(R.a[i], k, pc);  // compile time; rows past M are zero and stay zero
-      R.a[k] = pc;
+          for (int r = 0; r < kWsHalf; ++r) {  // compile time; rows past M are zero and stay zero
+            if (RB + r == k) R.a[r] = pc;
+            else if (RB + r != k + 1) ws_update(R.a[r], k, pc);
+          }
+        };
+        if (wv == 0) body(std::integral_constant<int, 0>{});
+        else body(std::integral_constant<int, kWsHalf>{});
+      }
     }
   }
-  if (first_bad >= 0) {
-    *badk = first_bad;
-    return;
-  }
+  if (threadIdx.x == 0) *s_bad = first_bad;
   // right-hand-side lanes hold X_k[:, i]: W_k[i][j] = conj(X_k[j][i])
-  if (lane >= M && lane < 3 * M) {
+  if (solver && first_bad < 0 && lane >= M && lane < 3 * M) {
     const int cc = lane - M, kk = cc < M ? 0 : 1, i = cc - kk * M;
     double2* dst = Wl + (size_t)kk * M * M + (size_t)i * M;
 #pragma unroll
-    for (int r = 0; r < kWsRows; ++r)
-      if (r < M) dst[r] = make_double2(R.a[r].x, -R.a[r].y);
+    for (int r = 0; r < kWsHalf; ++r) {
+      const int row = wv * kWsHalf + r;
+      if (row < M) dst[row] = make_double2(R.a[r].x, -R.a[r].y);
+    }
   }
 }
 
@@ -713,7 +727,7 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
       __syncthreads();  // stage input tile and halo, drive table in LDS
       const double drv = s_dtab[ds][0];
 
-      // (1) loads of the reduced G, C_k (solver wave of the register solver) in flight while
+      // (1) loads of the reduced G, C_k (solver waves of the register solver) in flight while
       // Z = H_eff(t) S is formed (with three register rows they are issued after it: registers)
       constexpr bool kWaveSolve = GE == 1, kEarlyLoad = kWaveSolve && ROWS == 2;
       WsRegs SR;
@@ -784,16 +798,12 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
       };
       if (T.frame) stencil(std::true_type{});
       else stencil(std::false_type{});
-      // (2) W_k of this stage input (register solver: the solver wave, the others wait at the
-      // barrier; LDS solver: the whole workgroup)
+      // (2) W_k of this stage input (register solver: two solver waves, the others pass the
+      // same barriers; LDS solver: the whole workgroup)
       {
         if constexpr (kWaveSolve) {
-          if (tid < 64) {
-            int badk;
-            if constexpr (!kEarlyLoad) wsolve_load(REDg + (size_t)p * npe, M, SR);
-            wsolve_run(SR, Wl, M, &s_nonfinite, &badk);
-            if (tid == 0) s_bad = badk;
-          }
+          if constexpr (!kEarlyLoad) wsolve_load(REDg + (size_t)p * npe, M, SR);
+          wsolve_run(SR, WS, Wl, M, &s_nonfinite, &s_bad);
         } else {
           lsolve_run(REDg + (size_t)p * npe, Wl, Wl, M, &s_nonfinite, &s_bad);
         }
@@ -914,7 +924,7 @@ __device__ __forceinline__ void persist_body(const TrajDev* __restrict__ trajs, 
 
 // Chunk of RK4 steps (the integrator proper) and prologue, as separate
 // kernels so that timing tools see the step kernel alone.
-// GE selects the solver: in the registers of one solver wave (1) or in LDS (2).
+// GE selects the solver: in the registers of two solver waves (1) or in LDS (2).
 template <int ROWS, int GE, int PREC>
 __global__ __launch_bounds__(kPW) void k_persist(const TrajDev* __restrict__ trajs,
                                                  const int2* __restrict__ tilemap, int64_t step0, int64_t nchunk) {
